@@ -1,0 +1,199 @@
+"""Benchmark of the multi-matrix syndrome BP decoder on one MI355X.
+
+One step is one pass of the whole hot path over one batch of frames whose
+inputs (Bob's bits, the per-frame error rates, Alice's syndromes) are already
+resident in HBM: channel LLRs (eq. (5)), staging, the flooding iterations
+with the per-frame stopping test, and the decided bits, iteration counts,
+success flags and soft decisions written back to HBM.
+
+Prints one JSON line: reconciled Mbps (frames x n bits per second), the
+roofline of the dominant kernel (the check-node pass) from HIP events on the
+decode stream, and the FP64 CPU oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "check_kernel_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2001_07979_amd", "csrc", "decode.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
+
+
+def stored_traffic():
+    """HBM bytes per check-node launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha1") != source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def host_threads() -> int:
+    n = os.cpu_count() or 1
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    return max(1, min(n, 16))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--algo", choices=["spa", "nms"], default="spa")
+    ap.add_argument("--frames", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time without the per-launch HIP events (no roofline)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); frames are independent, "
+              "so more GPUs would each decode their own share with no exchange", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2001_07979_amd import mbp
+    from paper_2001_07979_amd.inputs import workloads as W
+
+    log("bench: building inputs")
+    wl = W.qkd_n65536(nframes=args.frames, algo=args.algo)
+    fr = wl.frames()
+    code = wl.code
+    n, E, F = code.n, code.E, fr.nframes
+    dev = torch.device("cuda", 0)
+    ctx = mbp.Context(0)
+    dcode = mbp.Code.from_inputs(ctx, code)
+    y = torch.from_numpy(fr.y).to(dev)
+    e = torch.from_numpy(fr.p).to(dev)
+    z = torch.from_numpy(fr.z).to(dev)
+    llr = torch.empty((F, n), dtype=torch.float32, device=dev)
+    out = dict(bits=torch.empty((F, n), dtype=torch.uint8, device=dev),
+               iters=torch.empty(F, dtype=torch.int32, device=dev),
+               ok=torch.empty(F, dtype=torch.uint8, device=dev),
+               llr=torch.empty((F, n), dtype=torch.float32, device=dev))
+    stream = torch.cuda.current_stream()
+
+    def step():
+        mbp.llr_from_bits(ctx, y, e, dtype="f32", out=llr, stream=stream)
+        mbp.decode(ctx, dcode, llr, z, algo=wl.algo, max_iter=wl.max_iter,
+                   early_exit=wl.early_exit, alpha=wl.alpha, clip=wl.clip, out=out,
+                   stream=stream)
+
+    log(f"bench: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    profile = not args.no_profile
+    ctx.profile_reset()
+    ctx.profile_enable(profile)
+    log(f"bench: timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.profile_enable(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    mbps = F * n / ((t1 - t0) / args.steps) / 1e6
+
+    iters = out["iters"].cpu().numpy()
+    ok = out["ok"].cpu().numpy()
+    bits = out["bits"].cpu().numpy()
+    frame_err = np.any(bits != fr.x, axis=1)
+    fer = float(frame_err.mean())
+    p = float(np.mean(fr.p))
+    from math import log2
+    h = -p * log2(p) - (1 - p) * log2(1 - p)
+    m = code.m[0]
+
+    roofline = None
+    if profile:
+        n_c, ms_c = ctx.profile_get("check")
+        n_v, ms_v = ctx.profile_get("variable")
+        # algorithmic bytes of the check-node pass: for every frame iteration,
+        # read c (E, not at t=1), gather L (n), write c (E); the pass that
+        # detects a frame's convergence needs only its L (n) for the test
+        s = 4
+        per_step = 0
+        for t in range(1, int(iters.max()) + 2):
+            full = int((iters >= t).sum())
+            detect = int((iters == t - 1).sum()) if t >= 2 else 0
+            per_step += full * s * ((2 * E if t >= 2 else E) + n) + detect * s * n
+        launches_per_step = n_c / args.steps
+        bytes_per_launch = per_step / launches_per_step
+        avg_ms = ms_c / n_c
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        traffic = stored_traffic()
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": traffic, "kernel": "k_check (check-node pass)",
+                    "avg_launch_ms": round(avg_ms, 5), "launches": n_c,
+                    "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                    "variable_pass_avg_ms": round(ms_v / max(n_v, 1), 5)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = host_threads()
+        lam = oracle.llr_from_bits(fr.y, fr.p).astype(np.float32).astype(np.float64)
+        sample = min(F, 64)
+        log(f"bench: oracle on {sample} frames with {threads} threads")
+        c0 = time.perf_counter()
+        r = oracle.decode(code, lam[:sample], fr.z[:sample],
+                          algo=oracle.SPA if wl.algo == "spa" else oracle.NMS,
+                          max_iter=wl.max_iter, alpha=wl.alpha, clip=wl.clip, nthreads=threads)
+        c1 = time.perf_counter()
+        cpu = {"value": round(sample * n / (c1 - c0) / 1e6, 3), "unit": "Mbps", "cores": threads,
+               "kind": "oracle",
+               "sample": f"first {sample} of the {F} frames, FP64 {wl.algo}, {threads} threads, "
+                         f"{c1 - c0:.1f} s"}
+
+    rec = {
+        "metric": "reconciled Mbps at FER<=1e-2, f<=1.1; % HBM peak; batched vs plain",
+        "value": round(mbps, 1), "unit": "Mbps", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "frames": F, "n": n, "u": code.u, "m": m, "E": E,
+                   "rate": 1 - m / n, "p": p, "algo": wl.algo, "max_iter": wl.max_iter,
+                   "early_exit": wl.early_exit, "peg": code.name},
+        "fer": fer, "decoder_failures": int((ok == 0).sum()),
+        "avg_iters": float(iters.mean()), "max_iters": int(iters.max()),
+        "f": round(m / (n * h), 4), "f_leak": round(code.u * m / (n * h), 4),
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

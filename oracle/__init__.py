@@ -51,6 +51,9 @@ def lib():
         L.oracle_mbp_decode.restype = ctypes.c_int32
         L.oracle_mbp_decode.argtypes = [ctypes.POINTER(_Code), ctypes.POINTER(_Params),
                                         ctypes.c_int32] + [ctypes.c_void_p] * 7 + [ctypes.c_int32]
+        L.oracle_mbp_decode_nms_f32.restype = ctypes.c_int32
+        L.oracle_mbp_decode_nms_f32.argtypes = [ctypes.POINTER(_Code), ctypes.POINTER(_Params),
+                                                ctypes.c_int32] + [ctypes.c_void_p] * 6 + [ctypes.c_int32]
         L.oracle_unsatisfied.restype = ctypes.c_int32
         L.oracle_unsatisfied.argtypes = [ctypes.POINTER(_Code), ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
@@ -123,6 +126,29 @@ def decode(code, llr: np.ndarray, synd: np.ndarray, algo: int = SPA, max_iter: i
     if rc != 0:
         raise ValueError("oracle_mbp_decode rejected its input")
     return dict(bits=bits, iters=iters, ok=ok, L=L, flag=flag)
+
+
+def decode_nms_f32(code, llr: np.ndarray, synd: np.ndarray, max_iter: int = 50,
+                   early_exit: bool = True, alpha: float = 0.75, clip: float = 20.0,
+                   nthreads: int = 0) -> dict:
+    """Normalized min-sum decode with every operation in binary32 (see the C source)."""
+    llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float64)
+    synd = np.ascontiguousarray(np.atleast_2d(synd), dtype=np.uint8)
+    F, n = llr.shape
+    assert n == code.n and synd.shape[0] == F
+    cs, keep = _pack(code)
+    P = _Params(NMS, int(max_iter), int(bool(early_exit)), float(alpha), float(clip), None, 1e-3)
+    bits = np.zeros((F, n), dtype=np.uint8)
+    iters = np.zeros(F, dtype=np.int32)
+    ok = np.zeros(F, dtype=np.uint8)
+    L = np.zeros((F, n), dtype=np.float64)
+    rc = lib().oracle_mbp_decode_nms_f32(ctypes.byref(cs), ctypes.byref(P), F, llr.ctypes.data,
+                                         synd.ctypes.data, bits.ctypes.data, iters.ctypes.data,
+                                         ok.ctypes.data, L.ctypes.data, int(nthreads))
+    del keep
+    if rc != 0:
+        raise ValueError("oracle_mbp_decode_nms_f32 rejected its input")
+    return dict(bits=bits, iters=iters, ok=ok, L=L)
 
 
 def unsatisfied(code, x: np.ndarray, synd: np.ndarray) -> np.ndarray:

@@ -216,7 +216,7 @@ static int buf_alloc(frame_buf *b, const graph *g, int32_t maxdeg) {
     b->c = malloc(sizeof(double) * (size_t)(g->E > 0 ? g->E : 1));
     b->q = malloc(sizeof(double) * (size_t)(g->E > 0 ? g->E : 1));
     b->L = malloc(sizeof(double) * (size_t)(g->n > 0 ? g->n : 1));
-    b->th = malloc(sizeof(double) * (size_t)(maxdeg > 0 ? maxdeg : 1));
+    b->th = malloc(sizeof(double) * (size_t)(maxdeg > g->n ? maxdeg : (g->n > 0 ? g->n : 1)));
     b->tmp = malloc(sizeof(double) * (size_t)(maxdeg > 0 ? maxdeg : 1));
     b->xhat = malloc((size_t)(g->n > 0 ? g->n : 1));
     return (b->c && b->q && b->L && b->th && b->tmp && b->xhat) ? 0 : -1;
@@ -303,6 +303,62 @@ static void decode_frame(const graph *g, const oracle_params *P, const double *l
     if (flag) *flag = fl;
 }
 
+/* Normalized min-sum in binary32 arithmetic. The same rule and schedule as
+   decode_frame, with every quantity a float and every operation rounded to
+   float in the order the definitions give: q = L - c; |q| capped at C; the
+   smallest other magnitude; c = (-1)^z * alpha * (product of signs) * min;
+   L = lambda + the incoming messages in (matrix, check) order. No near-tie
+   flag is computed. */
+static void decode_frame_nms_f32(const graph *g, const oracle_params *P, const double *lam64,
+                                 const uint8_t *z, frame_buf *b, uint8_t *bits, int32_t *iters,
+                                 uint8_t *ok, double *Lout) {
+    const int32_t n = g->n, E = g->E, M = g->M;
+    float *c = (float *)b->c, *q = (float *)b->q, *L = (float *)b->L, *lam = (float *)b->th;
+    const float C = (float)P->clip;
+    for (int32_t i = 0; i < n; ++i) lam[i] = (float)lam64[i];
+    for (int32_t e = 0; e < E; ++e) c[e] = 0.0f;
+    for (int32_t i = 0; i < n; ++i) L[i] = lam[i];
+    int32_t t_stop = P->max_iter;
+    int stopped = 0;
+    for (int32_t t = 1; t <= P->max_iter; ++t) {
+        for (int32_t e = 0; e < E; ++e) q[e] = L[g->edge_var[e]] - c[e];
+        for (int32_t r = 0; r < M; ++r) {
+            int32_t e0 = g->row_start[r], d = g->row_start[r + 1] - e0;
+            float zs = z[r] ? -1.0f : 1.0f;
+            float alpha = (float)weight_of(P, t, g->row_matrix[r], g->u);
+            float *tmp = (float *)b->tmp;
+            for (int32_t k = 0; k < d; ++k) {
+                float sg = 1.0f, mn = INFINITY;
+                for (int32_t kk = 0; kk < d; ++kk) {
+                    if (kk == k) continue;
+                    sg *= q[e0 + kk] < 0.0f ? -1.0f : 1.0f;
+                    float a = fabsf(q[e0 + kk]);
+                    if (a > C) a = C;
+                    if (a < mn) mn = a;
+                }
+                tmp[k] = zs * alpha * sg * mn;
+            }
+            for (int32_t k = 0; k < d; ++k) c[e0 + k] = tmp[k];
+        }
+        for (int32_t i = 0; i < n; ++i) {
+            float s = lam[i];
+            for (int32_t k = g->var_start[i]; k < g->var_start[i + 1]; ++k) s += c[g->var_edges[k]];
+            L[i] = s;
+        }
+        for (int32_t i = 0; i < n; ++i) b->xhat[i] = L[i] < 0.0f ? 1 : 0;
+        if (P->early_exit && unsatisfied(g, b->xhat, z) == 0) {
+            t_stop = t;
+            stopped = 1;
+            break;
+        }
+    }
+    *ok = stopped ? 1 : (unsatisfied(g, b->xhat, z) == 0 ? 1 : 0);
+    *iters = t_stop;
+    for (int32_t i = 0; i < n; ++i) bits[i] = b->xhat[i];
+    if (Lout)
+        for (int32_t i = 0; i < n; ++i) Lout[i] = (double)L[i];
+}
+
 /* ---------------------------------------------------------------------- */
 typedef struct {
     const graph *g;
@@ -316,6 +372,7 @@ typedef struct {
     double *Lout;
     uint8_t *flag;
     int32_t maxdeg;
+    int f32;    /* decode_frame_nms_f32 instead of decode_frame */
     int next;   /* next frame to take (atomic) */
     int failed; /* allocation failure in a worker (atomic) */
 } job;
@@ -333,9 +390,14 @@ static void *worker(void *arg) {
     for (;;) {
         int f = __atomic_fetch_add(&J->next, 1, __ATOMIC_SEQ_CST);
         if (f >= J->nframes) break;
-        decode_frame(J->g, J->P, J->llr + (size_t)f * n, J->synd + (size_t)f * M, &b,
-                     J->bits + (size_t)f * n, J->iters + f, J->ok + f,
-                     J->Lout ? J->Lout + (size_t)f * n : NULL, J->flag ? J->flag + f : NULL);
+        if (J->f32)
+            decode_frame_nms_f32(J->g, J->P, J->llr + (size_t)f * n, J->synd + (size_t)f * M, &b,
+                                 J->bits + (size_t)f * n, J->iters + f, J->ok + f,
+                                 J->Lout ? J->Lout + (size_t)f * n : NULL);
+        else
+            decode_frame(J->g, J->P, J->llr + (size_t)f * n, J->synd + (size_t)f * M, &b,
+                         J->bits + (size_t)f * n, J->iters + f, J->ok + f,
+                         J->Lout ? J->Lout + (size_t)f * n : NULL, J->flag ? J->flag + f : NULL);
     }
     buf_free(&b);
     return NULL;
@@ -354,10 +416,10 @@ int32_t oracle_default_threads(void) {
  *   flag  [nframes] near-tie flags, or NULL
  *   nthreads <= 0 uses every online core.
  * Returns 0, or -1 on bad input or allocation failure. */
-int32_t oracle_mbp_decode(const oracle_code *code, const oracle_params *P, int32_t nframes,
+static int32_t run_decode(const oracle_code *code, const oracle_params *P, int32_t nframes,
                           const double *llr, const uint8_t *synd, uint8_t *bits,
                           int32_t *iters, uint8_t *ok, double *Lout, uint8_t *flag,
-                          int32_t nthreads) {
+                          int32_t nthreads, int f32) {
     if (!code || !P || nframes < 0 || P->max_iter < 1 || code->u < 1 || code->n < 1) return -1;
     if (nframes == 0) return 0;
     graph g;
@@ -367,7 +429,7 @@ int32_t oracle_mbp_decode(const oracle_code *code, const oracle_params *P, int32
         int32_t d = g.row_start[r + 1] - g.row_start[r];
         if (d > maxdeg) maxdeg = d;
     }
-    job J = {&g, P, nframes, llr, synd, bits, iters, ok, Lout, flag, maxdeg, 0, 0};
+    job J = {&g, P, nframes, llr, synd, bits, iters, ok, Lout, flag, maxdeg, f32, 0, 0};
     if (nthreads <= 0) nthreads = oracle_default_threads();
     if (nthreads > nframes) nthreads = nframes;
     pthread_t *th = malloc(sizeof(pthread_t) * (size_t)nthreads);
@@ -382,6 +444,23 @@ int32_t oracle_mbp_decode(const oracle_code *code, const oracle_params *P, int32
     free(th);
     graph_free(&g);
     return J.failed ? -1 : 0;
+}
+
+int32_t oracle_mbp_decode(const oracle_code *code, const oracle_params *P, int32_t nframes,
+                          const double *llr, const uint8_t *synd, uint8_t *bits,
+                          int32_t *iters, uint8_t *ok, double *Lout, uint8_t *flag,
+                          int32_t nthreads) {
+    return run_decode(code, P, nframes, llr, synd, bits, iters, ok, Lout, flag, nthreads, 0);
+}
+
+/* The same decode with normalized min-sum carried out in binary32 (see
+   decode_frame_nms_f32); llr values are rounded to float on entry. */
+int32_t oracle_mbp_decode_nms_f32(const oracle_code *code, const oracle_params *P,
+                                  int32_t nframes, const double *llr, const uint8_t *synd,
+                                  uint8_t *bits, int32_t *iters, uint8_t *ok, double *Lout,
+                                  int32_t nthreads) {
+    if (!P || P->algo != 1) return -1;
+    return run_decode(code, P, nframes, llr, synd, bits, iters, ok, Lout, NULL, nthreads, 1);
 }
 
 /* Residual syndrome weight of decided bits: per frame, the number of stacked

@@ -1,0 +1,690 @@
+// HIP kernels (gfx950) and the host-side iteration driver of the
+// multi-matrix syndrome BP decoder.
+//
+// Layout in HBM. Frames are processed in groups of 64, one frame per lane of
+// a wavefront, so every lane of a wave works on the same check or variable
+// of the shared code and all graph indices are wave-uniform scalar loads.
+// Per group g (all arrays frame-interleaved, 64 consecutive elements per
+// graph node or edge):
+//   c   [g][E][64]  check-to-variable messages, edges in check-major order
+//   Lp  [g][n][64]  soft decisions L of eq. (2) (posterior LLRs)
+//   lam [g][n][64]  channel LLRs
+//   zb  [g][M]      syndrome bits, bit k = frame g*64+k
+// A variable-to-check message is never stored: it is rebuilt as L - c from
+// the previous iteration's L and c when the check pass reads them.
+//
+// One iteration t (flooding schedule over the stacked graph):
+//   check pass     for every check of every matrix: q = L^{t-1} - c^{t-1} on
+//                  each edge, c^t from the check rule of Sec. 3B eq. (6) (or
+//                  normalized min-sum); it also XORs the decisions of L^{t-1}
+//                  over the check, which is the stopping test of iteration
+//                  t-1, and ORs unmet checks into a per-group lane mask;
+//   variable pass  L^t = lambda + sum of c^t over the variable's edges in
+//                  (matrix, check) order, eq. (2); frames whose test at t-1
+//                  passed keep L^{t-1} and are retired with iters = t-1.
+// After the last iteration a syndrome-only pass tests L^T.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "mbp_internal.h"
+
+namespace mbp {
+namespace {
+
+constexpr int G = kLanes;
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr int kRowsPerWave = 4;
+constexpr int kRowsPerTile = kRowsPerWave * kWaves;
+constexpr int kVarsPerWave = 4;
+constexpr int kVarsPerTile = kVarsPerWave * kWaves;
+constexpr int kVarChunk = 8;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() {
+    return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+}
+
+// phi(x) = -ln tanh(x/2) = ln(1 + 2/(e^x - 1)); phi is its own inverse, so
+// 2 atanh(prod tanh(a_k/2)) = phi(sum phi(a_k)) for magnitudes a_k >= 0.
+// phi(0) = +inf and phi(+inf) = 0 follow from IEEE arithmetic.
+__device__ __forceinline__ float phi(float x) { return log1pf(2.0f / expm1f(x)); }
+
+enum { kNMS = MBP_ALGO_NMS, kSPA = MBP_ALGO_SPA };
+
+struct CheckArgs {
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const void *Lp;
+    void *c;
+    const uint64_t *zb;
+    const uint64_t *act;
+    uint64_t *uns;
+    int64_t E;
+    int32_t n, M, ngroups, ntiles, t, want_syn;
+    double alpha, clip;
+};
+
+// Check-node pass. Each wave handles kRowsPerWave checks of one group; the
+// check degree d <= DMAX is wave-uniform, the messages of a check are held in
+// registers (q[j]) between the gather and the write.
+template <typename T, int ALGO, int DMAX>
+__global__ __launch_bounds__(kBlock) void k_check(CheckArgs a) {
+    __shared__ uint64_t sh_bad[kWaves];
+    const T *__restrict__ Lp = static_cast<const T *>(a.Lp);
+    T *__restrict__ c = static_cast<T *>(a.c);
+    const int lane = lane_id(), wave = wave_id();
+    const T alpha = static_cast<T>(a.alpha), clip = static_cast<T>(a.clip);
+    const int pt = a.t & 1;
+    const bool first = a.t == 1;
+    const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        const int g = static_cast<int>(w / a.ntiles);
+        const int tile = static_cast<int>(w % a.ntiles);
+        const uint64_t act = a.act[2 * g + pt];
+        if (act == 0) continue;  // whole group retired (uniform over the block)
+        const bool on = (act >> lane) & 1;
+        const T *Lg = Lp + static_cast<size_t>(g) * a.n * G + lane;
+        T *cg = c + static_cast<size_t>(g) * a.E * G + lane;
+        const uint64_t *zg = a.zb + static_cast<size_t>(g) * a.M;
+        uint64_t bad = 0;
+        for (int k = 0; k < kRowsPerWave; ++k) {
+            const int r = tile * kRowsPerTile + k * kWaves + wave;
+            if (r >= a.M) break;
+            const int e0 = a.row_ptr[r];
+            const int d = a.row_ptr[r + 1] - e0;
+            const int zbit = static_cast<int>((zg[r] >> lane) & 1);
+            int par = 0;
+            if (on) {
+                T q[DMAX];
+#pragma unroll
+                for (int j = 0; j < DMAX; ++j) {
+                    if (j < d) {
+                        const int v = a.col[e0 + j];
+                        const T Lv = Lg[static_cast<size_t>(v) * G];
+                        const T co = first ? T(0) : cg[static_cast<size_t>(e0 + j) * G];
+                        q[j] = Lv - co;
+                        par ^= (Lv < T(0)) ? 1 : 0;
+                    }
+                }
+                uint64_t neg = 0;
+                int sx = zbit;  // syndrome sign times every message sign
+                if constexpr (ALGO == kNMS) {
+                    T m1 = T(INFINITY), m2 = T(INFINITY);
+                    int i1 = 0;
+#pragma unroll
+                    for (int j = 0; j < DMAX; ++j) {
+                        if (j < d) {
+                            const int s = q[j] < T(0) ? 1 : 0;
+                            sx ^= s;
+                            neg |= static_cast<uint64_t>(s) << j;
+                            T aj = fabs(q[j]);
+                            aj = aj < clip ? aj : clip;
+                            if (aj < m1) {
+                                m2 = m1;
+                                m1 = aj;
+                                i1 = j;
+                            } else if (aj < m2) {
+                                m2 = aj;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < DMAX; ++j) {
+                        if (j < d) {
+                            const T mag = alpha * (j == i1 ? m2 : m1);
+                            const int s = sx ^ static_cast<int>((neg >> j) & 1);
+                            cg[static_cast<size_t>(e0 + j) * G] = s ? -mag : mag;
+                        }
+                    }
+                } else if constexpr (sizeof(T) == 4) {
+                    // sum-product, FP32: phi domain with prefix/suffix exclusion
+                    T f[DMAX];
+#pragma unroll
+                    for (int j = 0; j < DMAX; ++j) {
+                        if (j < d) {
+                            const int s = q[j] < T(0) ? 1 : 0;
+                            sx ^= s;
+                            neg |= static_cast<uint64_t>(s) << j;
+                            T aj = fabs(q[j]);
+                            aj = aj < clip ? aj : clip;
+                            f[j] = phi(aj);
+                        }
+                    }
+                    T run = T(0);
+#pragma unroll
+                    for (int j = 0; j < DMAX; ++j) {
+                        if (j < d) {
+                            q[j] = run;  // sum of phi over edges before j
+                            run += f[j];
+                        }
+                    }
+                    T suf = T(0);
+#pragma unroll
+                    for (int j = DMAX - 1; j >= 0; --j) {
+                        if (j < d) {
+                            const T mag = phi(q[j] + suf);
+                            suf += f[j];
+                            const int s = sx ^ static_cast<int>((neg >> j) & 1);
+                            cg[static_cast<size_t>(e0 + j) * G] = s ? -mag : mag;
+                        }
+                    }
+                } else {
+                    // sum-product, FP64: tanh domain with prefix/suffix products
+                    T th[DMAX];
+#pragma unroll
+                    for (int j = 0; j < DMAX; ++j) {
+                        if (j < d) {
+                            const int s = q[j] < T(0) ? 1 : 0;
+                            sx ^= s;
+                            neg |= static_cast<uint64_t>(s) << j;
+                            T aj = fabs(q[j]);
+                            aj = aj < clip ? aj : clip;
+                            th[j] = tanh(aj * T(0.5));
+                        }
+                    }
+                    T run = T(1);
+#pragma unroll
+                    for (int j = 0; j < DMAX; ++j) {
+                        if (j < d) {
+                            q[j] = run;  // product of tanh over edges before j
+                            run *= th[j];
+                        }
+                    }
+                    T suf = T(1);
+#pragma unroll
+                    for (int j = DMAX - 1; j >= 0; --j) {
+                        if (j < d) {
+                            const T mag = T(2) * atanh(q[j] * suf);
+                            suf *= th[j];
+                            const int s = sx ^ static_cast<int>((neg >> j) & 1);
+                            cg[static_cast<size_t>(e0 + j) * G] = s ? -mag : mag;
+                        }
+                    }
+                }
+            }
+            bad |= __ballot(on && (par != zbit));
+        }
+        if (a.want_syn) {
+            if (lane == 0) sh_bad[wave] = bad;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint64_t b = 0;
+                for (int i = 0; i < kWaves; ++i) b |= sh_bad[i];
+                if (b) atomicOr(reinterpret_cast<unsigned long long *>(&a.uns[2 * g + pt]),
+                                static_cast<unsigned long long>(b));
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Syndrome-only pass: the stopping test of the decisions held in Lp.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_syndrome(CheckArgs a) {
+    __shared__ uint64_t sh_bad[kWaves];
+    const T *__restrict__ Lp = static_cast<const T *>(a.Lp);
+    const int lane = lane_id(), wave = wave_id();
+    const int pt = a.t & 1;
+    const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        const int g = static_cast<int>(w / a.ntiles);
+        const int tile = static_cast<int>(w % a.ntiles);
+        const uint64_t act = a.act[2 * g + pt];
+        if (act == 0) continue;
+        const bool on = (act >> lane) & 1;
+        const T *Lg = Lp + static_cast<size_t>(g) * a.n * G + lane;
+        const uint64_t *zg = a.zb + static_cast<size_t>(g) * a.M;
+        uint64_t bad = 0;
+        for (int k = 0; k < kRowsPerWave; ++k) {
+            const int r = tile * kRowsPerTile + k * kWaves + wave;
+            if (r >= a.M) break;
+            const int e0 = a.row_ptr[r];
+            const int d = a.row_ptr[r + 1] - e0;
+            const int zbit = static_cast<int>((zg[r] >> lane) & 1);
+            int par = 0;
+            if (on)
+                for (int j = 0; j < d; ++j) par ^= (Lg[static_cast<size_t>(a.col[e0 + j]) * G] < T(0)) ? 1 : 0;
+            bad |= __ballot(on && (par != zbit));
+        }
+        if (lane == 0) sh_bad[wave] = bad;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t b = 0;
+            for (int i = 0; i < kWaves; ++i) b |= sh_bad[i];
+            if (b) atomicOr(reinterpret_cast<unsigned long long *>(&a.uns[2 * g + pt]),
+                            static_cast<unsigned long long>(b));
+        }
+        __syncthreads();
+    }
+}
+
+struct VarArgs {
+    const int32_t *var_ptr;
+    const int32_t *var_edge;
+    const void *c;
+    const void *lam;
+    void *Lp;
+    uint64_t *act;
+    uint64_t *uns;
+    uint64_t *status;  // host-visible per-group running masks
+    int32_t *iters_out;
+    uint8_t *ok_out;
+    int64_t E;
+    int32_t n, ngroups, ntiles, t, early_exit;
+};
+
+// Variable-node pass, eq. (2), plus the per-group bookkeeping of the
+// stopping rule.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_variable(VarArgs a) {
+    const T *__restrict__ c = static_cast<const T *>(a.c);
+    const T *__restrict__ lam = static_cast<const T *>(a.lam);
+    T *__restrict__ Lp = static_cast<T *>(a.Lp);
+    const int lane = lane_id(), wave = wave_id();
+    const int pt = a.t & 1, nt = (a.t + 1) & 1;
+    const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        const int g = static_cast<int>(w / a.ntiles);
+        const int tile = static_cast<int>(w % a.ntiles);
+        const uint64_t act = a.act[2 * g + pt];
+        const uint64_t U = (a.early_exit && a.t > 1) ? a.uns[2 * g + pt] : ~0ull;
+        const uint64_t run = act & U;
+        if (tile == 0 && wave == 0) {
+            // Frames whose decisions at t-1 met every syndrome stop here;
+            // nothing else reads these words during this pass.
+            const uint64_t conv = act & ~U;
+            if (lane == 0) {
+                a.act[2 * g + nt] = run;
+                a.uns[2 * g + nt] = 0;
+                __hip_atomic_store(&a.status[g], run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            if ((conv >> lane) & 1) {
+                const int f = g * G + lane;
+                a.iters_out[f] = a.t - 1;
+                a.ok_out[f] = 1;
+            }
+        }
+        if (!((run >> lane) & 1)) continue;
+        const size_t gb = static_cast<size_t>(g) * a.n * G + lane;
+        const T *cg = c + static_cast<size_t>(g) * a.E * G + lane;
+        for (int k = 0; k < kVarsPerWave; ++k) {
+            const int i = tile * kVarsPerTile + k * kWaves + wave;
+            if (i >= a.n) break;
+            const int k0 = a.var_ptr[i], k1 = a.var_ptr[i + 1];
+            T s = lam[gb + static_cast<size_t>(i) * G];
+            for (int kk = k0; kk < k1; kk += kVarChunk) {
+                T v[kVarChunk];
+#pragma unroll
+                for (int j = 0; j < kVarChunk; ++j)
+                    if (kk + j < k1) v[j] = cg[static_cast<size_t>(a.var_edge[kk + j]) * G];
+#pragma unroll
+                for (int j = 0; j < kVarChunk; ++j)
+                    if (kk + j < k1) s += v[j];
+            }
+            Lp[gb + static_cast<size_t>(i) * G] = s;
+        }
+    }
+}
+
+__global__ void k_init_groups(uint64_t *act, uint64_t *uns, uint64_t *status, int32_t nframes,
+                              int32_t ngroups) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngroups) return;
+    const int rem = nframes - g * G;
+    const uint64_t valid = rem >= G ? ~0ull : ((1ull << rem) - 1ull);
+    act[2 * g + 1] = valid;  // iteration 1 reads parity 1
+    act[2 * g + 0] = 0;
+    uns[2 * g + 0] = 0;
+    uns[2 * g + 1] = 0;
+    __hip_atomic_store(&status[g], valid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Frames still running after the last iteration: ok from the syndrome-only
+// pass, iterations = the last one run.
+__global__ void k_finalize(const uint64_t *act, const uint64_t *uns, int32_t *iters_out,
+                           uint8_t *ok_out, int32_t nframes, int32_t tf, int32_t last_iter) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nframes) return;
+    const int g = f / G, lane = f % G, p = tf & 1;
+    if ((act[2 * g + p] >> lane) & 1) {
+        ok_out[f] = ((uns[2 * g + p] >> lane) & 1) ? 0 : 1;
+        iters_out[f] = last_iter;
+    }
+}
+
+// [F][n] -> [g][n][64] for the channel LLRs (also the initial L).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_stage_llr(const T *llr, T *lam, T *Lp, int32_t nframes,
+                                                      int32_t n) {
+    __shared__ T tile[64][65];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int g = blockIdx.y, i0 = blockIdx.x * 64;
+    for (int fy = ty; fy < 64; fy += kWaves) {
+        const int f = g * G + fy, i = i0 + tx;
+        tile[fy][tx] = (f < nframes && i < n) ? llr[static_cast<size_t>(f) * n + i] : T(0);
+    }
+    __syncthreads();
+    for (int iy = ty; iy < 64; iy += kWaves) {
+        const int i = i0 + iy;
+        if (i < n) {
+            const T v = tile[tx][iy];
+            const size_t o = (static_cast<size_t>(g) * n + i) * G + tx;
+            lam[o] = v;
+            Lp[o] = v;
+        }
+    }
+}
+
+// [F][M] syndrome bytes -> [g][M] 64-bit lane masks.
+__global__ __launch_bounds__(kBlock) void k_stage_synd(const uint8_t *z, uint64_t *zb, int32_t nframes,
+                                                       int32_t M) {
+    __shared__ uint8_t s[64][kBlock + 4];
+    const int g = blockIdx.y, r0 = blockIdx.x * kBlock;
+    for (int fy = 0; fy < 64; ++fy) {
+        const int f = g * G + fy, r = r0 + static_cast<int>(threadIdx.x);
+        s[fy][threadIdx.x] = (f < nframes && r < M) ? z[static_cast<size_t>(f) * M + r] : 0;
+    }
+    __syncthreads();
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    for (int k = 0; k < 64; ++k) {
+        const int rr = wave * 64 + k;
+        const uint64_t mask = __ballot(s[lane][rr] != 0);
+        if (lane == 0 && r0 + rr < M) zb[static_cast<size_t>(g) * M + r0 + rr] = mask;
+    }
+}
+
+// [g][n][64] -> decided bits [F][n] and, optionally, L [F][n].
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_output(const T *Lp, uint8_t *bits, T *llr_out,
+                                                   int32_t nframes, int32_t n) {
+    __shared__ T tile[64][65];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int g = blockIdx.y, i0 = blockIdx.x * 64;
+    for (int iy = ty; iy < 64; iy += kWaves) {
+        const int i = i0 + iy;
+        tile[iy][tx] = i < n ? Lp[(static_cast<size_t>(g) * n + i) * G + tx] : T(0);
+    }
+    __syncthreads();
+    for (int fy = ty; fy < 64; fy += kWaves) {
+        const int f = g * G + fy, i = i0 + tx;
+        if (f < nframes && i < n) {
+            const T v = tile[tx][fy];
+            const size_t o = static_cast<size_t>(f) * n + i;
+            bits[o] = v < T(0) ? 1 : 0;
+            if (llr_out) llr_out[o] = v;
+        }
+    }
+}
+
+// Channel LLR (1 - 2y) ln((1 - e)/e), computed in FP64.
+template <typename T>
+__global__ void k_llr(const uint8_t *y, const double *e, T *out, int32_t nframes, int32_t n) {
+    const size_t total = static_cast<size_t>(nframes) * n;
+    for (size_t idx = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
+         idx += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const size_t f = idx / static_cast<size_t>(n);
+        const double ef = e[f];
+        const double lam = log((1.0 - ef) / ef);
+        out[idx] = static_cast<T>(y[idx] ? -lam : lam);
+    }
+}
+
+// ---------------------------------------------------------------- host side
+int blocks_per_cu(const void *fn) {
+    static std::mutex mu;
+    static std::unordered_map<const void *, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(fn);
+    if (it != cache.end()) return it->second;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+    cache[fn] = nb;
+    return nb;
+}
+
+int grid_for(const mbp_ctx *ctx, const void *fn, int64_t items) {
+    const int64_t cap = static_cast<int64_t>(ctx->num_cus) * blocks_per_cu(fn);
+    return static_cast<int>(std::max<int64_t>(1, std::min(items, cap)));
+}
+
+struct Timer {
+    mbp_ctx *ctx;
+    hipStream_t stream;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+    size_t used = 0;
+
+    hipError_t event(hipEvent_t *ev) {
+        if (used == ctx->timing_events.size()) {
+            hipEvent_t e;
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) return err;
+            ctx->timing_events.push_back(e);
+        }
+        *ev = ctx->timing_events[used++];
+        return hipSuccess;
+    }
+    template <typename F>
+    hipError_t run(int which, F &&launch) {
+        if (!ctx->profiling) {
+            launch();
+            return hipGetLastError();
+        }
+        hipEvent_t a, b;
+        hipError_t err;
+        if ((err = event(&a)) != hipSuccess || (err = event(&b)) != hipSuccess) return err;
+        if ((err = hipEventRecord(a, stream)) != hipSuccess) return err;
+        launch();
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        if ((err = hipEventRecord(b, stream)) != hipSuccess) return err;
+        marks.push_back({which, {a, b}});
+        return hipSuccess;
+    }
+    hipError_t collect() {
+        for (auto &m : marks) {
+            float ms = 0.f;
+            hipError_t err = hipEventElapsedTime(&ms, m.second.first, m.second.second);
+            if (err != hipSuccess) return err;
+            ctx->stats[m.first].launches += 1;
+            ctx->stats[m.first].total_ms += ms;
+        }
+        marks.clear();
+        return hipSuccess;
+    }
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+int ensure_workspace(mbp_ctx *ctx, size_t bytes) {
+    if (ctx->ws_bytes >= bytes) return MBP_OK;
+    if (ctx->ws) {
+        hipError_t e = hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+        if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
+    }
+    hipError_t e = hipMalloc(&ctx->ws, bytes);
+    if (e != hipSuccess) {
+        ctx->ws = nullptr;
+        return hip_fail(e, "hipMalloc(workspace)");
+    }
+    ctx->ws_bytes = bytes;
+    return MBP_OK;
+}
+
+int ensure_status(mbp_ctx *ctx, int32_t ngroups) {
+    if (ctx->status_cap >= ngroups) return MBP_OK;
+    if (ctx->status_host) (void)hipHostFree(ctx->status_host);
+    ctx->status_host = nullptr;
+    ctx->status_dev = nullptr;
+    ctx->status_cap = 0;
+    const int32_t cap = std::max<int32_t>(ngroups, 64);
+    void *p = nullptr;
+    hipError_t e = hipHostMalloc(&p, sizeof(uint64_t) * cap, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(status)");
+    void *d = nullptr;
+    e = hipHostGetDevicePointer(&d, p, 0);
+    if (e != hipSuccess) {
+        (void)hipHostFree(p);
+        return hip_fail(e, "hipHostGetDevicePointer(status)");
+    }
+    ctx->status_host = static_cast<uint64_t *>(p);
+    ctx->status_dev = static_cast<uint64_t *>(d);
+    ctx->status_cap = cap;
+    return MBP_OK;
+}
+
+template <typename T, int ALGO>
+const void *check_kernel(int dmax) {
+    switch (dmax) {
+        case 8: return reinterpret_cast<const void *>(&k_check<T, ALGO, 8>);
+        case 16: return reinterpret_cast<const void *>(&k_check<T, ALGO, 16>);
+        case 24: return reinterpret_cast<const void *>(&k_check<T, ALGO, 24>);
+        case 32: return reinterpret_cast<const void *>(&k_check<T, ALGO, 32>);
+        case 48: return reinterpret_cast<const void *>(&k_check<T, ALGO, 48>);
+        default: return reinterpret_cast<const void *>(&k_check<T, ALGO, 64>);
+    }
+}
+
+int dmax_for(int d) {
+    for (int c : {8, 16, 24, 32, 48}) if (d <= c) return c;
+    return 64;
+}
+
+template <typename T>
+int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t F,
+               const void *llr, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
+               uint8_t *ok_out, void *llr_out, hipStream_t stream) {
+    const int32_t n = code->n, M = code->M;
+    const int64_t E = code->E;
+    const int32_t ngroups = (F + G - 1) / G;
+    const size_t s = sizeof(T);
+    const size_t sz_c = align_up(static_cast<size_t>(ngroups) * E * G * s);
+    const size_t sz_L = align_up(static_cast<size_t>(ngroups) * n * G * s);
+    const size_t sz_z = align_up(static_cast<size_t>(ngroups) * M * sizeof(uint64_t));
+    const size_t sz_m = align_up(static_cast<size_t>(ngroups) * 2 * sizeof(uint64_t));
+    int rc = ensure_workspace(ctx, sz_c + 2 * sz_L + sz_z + 2 * sz_m);
+    if (rc != MBP_OK) return rc;
+    if ((rc = ensure_status(ctx, ngroups)) != MBP_OK) return rc;
+    char *base = static_cast<char *>(ctx->ws);
+    T *c = reinterpret_cast<T *>(base);
+    T *Lp = reinterpret_cast<T *>(base + sz_c);
+    T *lam = reinterpret_cast<T *>(base + sz_c + sz_L);
+    uint64_t *zb = reinterpret_cast<uint64_t *>(base + sz_c + 2 * sz_L);
+    uint64_t *act = reinterpret_cast<uint64_t *>(base + sz_c + 2 * sz_L + sz_z);
+    uint64_t *uns = reinterpret_cast<uint64_t *>(base + sz_c + 2 * sz_L + sz_z + sz_m);
+
+    Timer tm{ctx, stream, {}, 0};
+    hipError_t err;
+#define LAUNCH_OR_FAIL(which, ...)                                      \
+    do {                                                                \
+        err = tm.run(which, [&] { __VA_ARGS__; });                      \
+        if (err != hipSuccess) return hip_fail(err, "kernel launch");   \
+    } while (0)
+
+    LAUNCH_OR_FAIL(kStaging, k_init_groups<<<(ngroups + 63) / 64, 64, 0, stream>>>(
+                                 act, uns, ctx->status_dev, F, ngroups));
+    const dim3 tgrid((n + 63) / 64, ngroups);
+    LAUNCH_OR_FAIL(kStaging, k_stage_llr<T><<<tgrid, kBlock, 0, stream>>>(
+                                 static_cast<const T *>(llr), lam, Lp, F, n));
+    LAUNCH_OR_FAIL(kStaging, k_stage_synd<<<dim3((M + kBlock - 1) / kBlock, ngroups), kBlock, 0, stream>>>(
+                                 synd, zb, F, M));
+
+    const int dmax = dmax_for(code->max_check_deg);
+    const void *kc = p->algo == MBP_ALGO_NMS ? check_kernel<T, kNMS>(dmax) : check_kernel<T, kSPA>(dmax);
+    CheckArgs ca{code->d_row_ptr, code->d_col, Lp, c, zb, act, uns, E, n, M, ngroups,
+                 (M + kRowsPerTile - 1) / kRowsPerTile, 0, p->early_exit, p->alpha, p->llr_clip};
+    VarArgs va{code->d_var_ptr, code->d_var_edge, c, lam, Lp, act, uns, ctx->status_dev,
+               iters_out, ok_out, E, n, ngroups, (n + kVarsPerTile - 1) / kVarsPerTile, 0,
+               p->early_exit};
+    const int grid_c = grid_for(ctx, kc, static_cast<int64_t>(ngroups) * ca.ntiles);
+    const void *kv = reinterpret_cast<const void *>(&k_variable<T>);
+    const int grid_v = grid_for(ctx, kv, static_cast<int64_t>(ngroups) * va.ntiles);
+
+    if (ctx->poll_events.size() < 2) {
+        for (size_t k = ctx->poll_events.size(); k < 2; ++k) {
+            hipEvent_t e;
+            if ((err = hipEventCreateWithFlags(&e, hipEventDisableTiming)) != hipSuccess)
+                return hip_fail(err, "hipEventCreate");
+            ctx->poll_events.push_back(e);
+        }
+    }
+
+    void *cargs[] = {&ca};
+    int32_t last = 0;
+    for (int32_t t = 1; t <= p->max_iter; ++t) {
+        ca.t = t;
+        va.t = t;
+        // the stopping test of iteration t-1 rides on check pass t (t >= 2)
+        ca.want_syn = (p->early_exit && t > 1) ? 1 : 0;
+        hipError_t lerr = hipSuccess;
+        LAUNCH_OR_FAIL(kCheckNode, lerr = hipLaunchKernel(kc, dim3(grid_c), dim3(kBlock), cargs, 0, stream));
+        if (lerr != hipSuccess) return hip_fail(lerr, "hipLaunchKernel(check)");
+        LAUNCH_OR_FAIL(kVarNode, k_variable<T><<<grid_v, kBlock, 0, stream>>>(va));
+        last = t;
+        if (p->early_exit) {
+            if ((err = hipEventRecord(ctx->poll_events[t & 1], stream)) != hipSuccess)
+                return hip_fail(err, "hipEventRecord");
+            if (t >= 2) {
+                // wait for iteration t-1 while iteration t runs, then read
+                // the running masks it (or a later iteration) left behind
+                if ((err = hipEventSynchronize(ctx->poll_events[(t - 1) & 1])) != hipSuccess)
+                    return hip_fail(err, "hipEventSynchronize");
+                bool any = false;
+                volatile uint64_t *st = ctx->status_host;
+                for (int32_t g = 0; g < ngroups && !any; ++g) any = st[g] != 0;
+                if (!any) break;
+            }
+        }
+    }
+    // stopping test of the last iteration's decisions for frames still running
+    ca.t = last + 1;
+    ca.want_syn = 1;
+    LAUNCH_OR_FAIL(kSyndrome, k_syndrome<T><<<grid_for(ctx, reinterpret_cast<const void *>(&k_syndrome<T>),
+                                                        static_cast<int64_t>(ngroups) * ca.ntiles),
+                                              kBlock, 0, stream>>>(ca));
+    LAUNCH_OR_FAIL(kStaging, k_finalize<<<(F + 255) / 256, 256, 0, stream>>>(act, uns, iters_out, ok_out, F,
+                                                                            last + 1, last));
+    LAUNCH_OR_FAIL(kStaging, k_output<T><<<tgrid, kBlock, 0, stream>>>(Lp, bits_out, static_cast<T *>(llr_out),
+                                                                      F, n));
+#undef LAUNCH_OR_FAIL
+    if ((err = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(err, "hipStreamSynchronize");
+    if ((err = tm.collect()) != hipSuccess) return hip_fail(err, "hipEventElapsedTime");
+    return MBP_OK;
+}
+
+}  // namespace
+
+int decode_impl(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,
+                const void *llr, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
+                uint8_t *ok_out, void *llr_out, hipStream_t stream) {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (p->dtype == MBP_F32)
+        return run_decode<float>(ctx, code, p, nframes, llr, synd, bits_out, iters_out, ok_out, llr_out,
+                                 stream);
+    return run_decode<double>(ctx, code, p, nframes, llr, synd, bits_out, iters_out, ok_out, llr_out,
+                              stream);
+}
+
+int llr_impl(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y, const double *e,
+             int32_t dtype, void *llr_out, hipStream_t stream) {
+    hipError_t err = hipSetDevice(ctx->device);
+    if (err != hipSuccess) return hip_fail(err, "hipSetDevice");
+    const size_t total = static_cast<size_t>(nframes) * n;
+    const int grid = static_cast<int>(std::min<size_t>((total + 255) / 256, 65536));
+    if (dtype == MBP_F32)
+        k_llr<float><<<grid, 256, 0, stream>>>(y, e, static_cast<float *>(llr_out), nframes, n);
+    else
+        k_llr<double><<<grid, 256, 0, stream>>>(y, e, static_cast<double *>(llr_out), nframes, n);
+    err = hipGetLastError();
+    if (err != hipSuccess) return hip_fail(err, "k_llr launch");
+    return MBP_OK;
+}
+
+}  // namespace mbp

@@ -1,0 +1,75 @@
+// Internal declarations shared by the C-ABI layer (capi.cpp) and the HIP
+// kernels (decode.hip) of the MBP decoder library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mbp.h"
+
+namespace mbp {
+
+// Frames per interleaved group: one frame per lane of a 64-wide wavefront.
+constexpr int kLanes = 64;
+
+// Per-kernel timing totals (see mbp_profile_get).
+enum KernelId { kCheckNode = 0, kVarNode = 1, kSyndrome = 2, kStaging = 3, kNumKernels = 4 };
+
+struct KernelStat {
+    int64_t launches = 0;
+    double total_ms = 0.0;
+};
+
+// Records the last error of the calling thread and returns `code`.
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+}  // namespace mbp
+
+struct mbp_ctx {
+    int32_t device = 0;
+    int32_t num_cus = 0;
+    // Decode workspace: one device allocation, grown on demand.
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    // Per-group "still running" masks the kernels write to host-visible
+    // pinned memory, so the host can stop launching iterations early.
+    uint64_t *status_host = nullptr;
+    uint64_t *status_dev = nullptr;
+    int32_t status_cap = 0;
+    std::vector<hipEvent_t> poll_events;
+    // Profiling.
+    bool profiling = false;
+    mbp::KernelStat stats[mbp::kNumKernels];
+    std::vector<hipEvent_t> timing_events;
+    int32_t live_codes = 0;
+};
+
+struct mbp_code {
+    mbp_ctx *ctx = nullptr;
+    int32_t n = 0, u = 0, M = 0;
+    int64_t E = 0;
+    std::vector<int32_t> m;
+    int32_t max_check_deg = 0, max_var_deg = 0;
+    // Device edge layouts of the stacked graph [H_1; ...; H_u]:
+    // edges in check-major order (matrix, row, column); for each variable its
+    // edges in the same order.
+    int32_t *d_row_ptr = nullptr;   // [M + 1]
+    int32_t *d_col = nullptr;       // [E]
+    int32_t *d_var_ptr = nullptr;   // [n + 1]
+    int32_t *d_var_edge = nullptr;  // [E]
+};
+
+namespace mbp {
+
+// Implemented in decode.hip; arguments are validated by capi.cpp.
+int decode_impl(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,
+                const void *llr, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
+                uint8_t *ok_out, void *llr_out, hipStream_t stream);
+int llr_impl(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y, const double *e,
+             int32_t dtype, void *llr_out, hipStream_t stream);
+
+}  // namespace mbp

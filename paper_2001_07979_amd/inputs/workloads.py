@@ -1,0 +1,84 @@
+"""The decoder's workloads, built from seeded synthetic inputs.
+
+Each one names its code (PEG matrices and degree profile), its frames (key
+bits, BSC noise, syndromes) and its decoder settings. They stand in for the
+paper's QKD keys and PEG matrices (Sec. 3A splits a 2^20-bit sifted key into
+frames of n bits; Sec. 4 runs rates 0.5-0.8 at efficiency 1.1-1.4), neither of
+which is published.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import Code, Frames, bsc_frames, peg_code
+
+IRREGULAR_238 = {2: 0.25, 3: 0.45, 8: 0.30}
+IRREGULAR_2310 = {2: 0.25, 3: 0.45, 10: 0.30}
+
+
+def peg_depth(n: int) -> int:
+    """Breadth-first depth bound of the PEG construction (-1 = none)."""
+    if n <= 8192:
+        return -1
+    if n <= 65536:
+        return 2
+    return 1
+
+
+@dataclass
+class Workload:
+    name: str
+    code: Code
+    nframes: int
+    p: object
+    seed: int
+    algo: str
+    dtype: str
+    max_iter: int
+    early_exit: bool = True
+    alpha: float = 0.75
+    clip: float = 20.0
+    meta: dict = field(default_factory=dict)
+
+    def frames(self, nframes: int | None = None) -> Frames:
+        return bsc_frames(self.code, nframes or self.nframes, self.p, self.seed)
+
+
+def fp64_n4096(nframes: int = 16) -> Workload:
+    """u=2 regular (3,6) PEG matrices, n=4096, rate 1/2, BSC 0.05, FP64 sum-product."""
+    code = peg_code(4096, 2048, 2, {3: 1.0}, seed_base=1000, max_depth=peg_depth(4096),
+                    name="peg-n4096-r050-u2-dv3")
+    return Workload("mbp-spa-f64-n4096-u2-p0.05", code, nframes, 0.05, 1, "spa", "f64", 50)
+
+
+def qkd_n65536(nframes: int = 256, algo: str = "spa") -> Workload:
+    """u=2 irregular {2,3,8} PEG matrices, n=65536, rate 3/4, BSC 0.02, FP32."""
+    code = peg_code(65536, 16384, 2, IRREGULAR_238, seed_base=2000,
+                    max_depth=peg_depth(65536), name="peg-n65536-r075-u2-d238")
+    return Workload(f"mbp-{algo}-f32-n65536-r075-u2-p0.02", code, nframes, 0.02, 2, algo,
+                    "f32", 100)
+
+
+QKD_262K_POINTS = {0.5: 0.08, 0.7: 0.04, 0.85: 0.02}
+
+
+def qkd_n262144(rate: float, nframes: int = 64, algo: str = "spa") -> Workload:
+    """u=3 irregular {2,3,10} PEG matrices, n=2^18, one of three (rate, p) points."""
+    n = 262144
+    m = int(round((1.0 - rate) * n))
+    p = QKD_262K_POINTS[rate]
+    code = peg_code(n, m, 3, IRREGULAR_2310, seed_base=3000 + int(round(rate * 100)),
+                    max_depth=peg_depth(n), name=f"peg-n262144-r{rate}-u3-d2310")
+    return Workload(f"mbp-{algo}-f32-n262144-r{rate}-u3-p{p}", code, nframes, p, 3, algo,
+                    "f32", 100)
+
+
+def unrolled_n16384(nframes: int = 512) -> Workload:
+    """u=2 irregular {2,3,8} PEG matrices, n=16384, rate 1/2, BSC p ~ U[0.04, 0.08]."""
+    code = peg_code(16384, 8192, 2, IRREGULAR_238, seed_base=5000, max_depth=peg_depth(16384),
+                    name="peg-n16384-r050-u2-d238")
+    p = np.random.default_rng(5).uniform(0.04, 0.08, size=nframes)
+    return Workload("mbp-nms-unrolled-k20-n16384-u2", code, nframes, p, 5, "nms", "f32", 20,
+                    early_exit=False)

@@ -1,0 +1,145 @@
+"""Run the HIP decoder and the FP64 oracle on the same seeded inputs, and
+compare them under the parity protocol.
+
+Protocol (GPU against the FP64 oracle):
+* a frame the oracle decodes without a near tie (its flag is 0) must match
+  exactly in success, iteration count and every decided bit;
+* its final soft decisions must agree to `rtol` (1e-4 for FP32) relative,
+  plus ATOL32 = 1e-5 absolute for FP32 (the representation limit of the
+  summed messages where they cancel), wherever |L| >= 1e-3, for frames that stop within LONG_AFTER = 8
+  iterations (the paper reports 3.71 to 6.67 iterations on average,
+  Tables 2 and 3). A longer FP32 trajectory drifts from FP64 by more than
+  that (measured: up to ~2e-3 for sum-product at 27 iterations, and far more
+  for min-sum, whose rounding errors grow by about alpha (d_v - 1) per
+  iteration, enough to move a long decode's stopping iteration); there
+  `long_rtol` applies to sum-product, while min-sum FP32 frames are held bit
+  for bit to the oracle's binary32 min-sum and only counted against FP64;
+* a frame the oracle fails must fail on the GPU too with iters = T;
+* flagged frames (a soft decision within 1e-3 of zero at a point where FP32
+  rounding could change the outcome) are compared and counted; together with
+  failed-frame disagreements they may not exceed 1% of the frames.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+SMALL = 1e-3
+LONG_AFTER = 8
+# FP32 holds a check message of size up to C = 20 only to 20 * 2^-24 = 1.2e-6;
+# a soft decision adds up to ~16 of them, so where they cancel to a small
+# |L| its FP32 value is good to about 1e-5 absolute, not 1e-4 relative.
+ATOL32 = 1e-5
+
+
+def gpu_run(ctx, dcode, frames, algo, dtype, max_iter, early_exit=True, alpha=0.75,
+            clip=20.0, llr=None):
+    import torch
+    from paper_2001_07979_amd import mbp
+    dev = torch.device("cuda", ctx.device)
+    y = torch.from_numpy(frames.y).to(dev)
+    e = torch.from_numpy(frames.p.astype(np.float64)).to(dev)
+    if llr is None:
+        llr = mbp.llr_from_bits(ctx, y, e, dtype=dtype)
+    else:
+        llr = torch.from_numpy(llr).to(dev)
+    z = torch.from_numpy(frames.z).to(dev)
+    out = mbp.decode(ctx, dcode, llr, z, algo=algo, max_iter=max_iter, early_exit=early_exit,
+                     alpha=alpha, clip=clip)
+    torch.cuda.synchronize()
+    return dict(llr_in=llr.cpu().numpy(), bits=out["bits"].cpu().numpy(),
+                iters=out["iters"].cpu().numpy(), ok=out["ok"].cpu().numpy(),
+                L=out["llr"].cpu().numpy().astype(np.float64))
+
+
+def oracle_llr(frames, dtype):
+    lam = oracle.llr_from_bits(frames.y, frames.p)
+    if dtype == "f32":
+        lam = lam.astype(np.float32).astype(np.float64)
+    return lam
+
+
+def oracle_run(code, frames, algo, dtype, max_iter, early_exit=True, alpha=0.75, clip=20.0,
+               idx=None, lam=None):
+    if lam is None:
+        lam = oracle_llr(frames, dtype)
+    z = frames.z
+    if idx is not None:
+        lam, z = lam[idx], z[idx]
+    r = oracle.decode(code, lam, z, algo=oracle.SPA if algo == "spa" else oracle.NMS,
+                      max_iter=max_iter, early_exit=early_exit, alpha=alpha, clip=clip)
+    r["llr_in"] = lam
+    return r
+
+
+def compare(gpu, orc, max_iter, rtol, idx=None, exact_all=False, long_rtol=1e-2, atol=0.0):
+    """Apply the protocol; returns a summary dict, raising AssertionError on a bug.
+
+    long_rtol=None marks a run whose frames beyond LONG_AFTER iterations are
+    held bit for bit to the binary32 oracle instead (FP32 min-sum): against
+    FP64 they are only counted.
+    """
+    sel = (lambda a: a[idx]) if idx is not None else (lambda a: a)
+    g = {k: sel(v) for k, v in gpu.items() if k != "llr_in"}
+    F = len(orc["ok"])
+    summary = dict(frames=F, oracle_ok=int(orc["ok"].sum()), flagged=int(orc["flag"].sum()),
+                   flagged_mismatch=0, failed_mismatch=0, long_mismatch=0, max_rel=0.0,
+                   hamming_failed=[])
+    for f in range(F):
+        o_ok, o_it = int(orc["ok"][f]), int(orc["iters"][f])
+        g_ok, g_it = int(g["ok"][f]), int(g["iters"][f])
+        same_bits = np.array_equal(orc["bits"][f], g["bits"][f])
+        same = g_ok == o_ok and g_it == o_it and same_bits
+        if long_rtol is None and o_it > LONG_AFTER and not exact_all:
+            summary["long_mismatch"] += int(not same)
+            continue
+        strict = exact_all or (o_ok and not orc["flag"][f])
+        if strict:
+            assert g_ok == o_ok and g_it == o_it, (
+                f"frame {f}: gpu ok={g_ok} iters={g_it}, oracle ok={o_ok} iters={o_it}")
+            assert same_bits, f"frame {f}: {int((orc['bits'][f] != g['bits'][f]).sum())} bits differ"
+            Lo, Lg = orc["L"][f], g["L"][f]
+            tol = rtol if o_it <= LONG_AFTER else long_rtol
+            mask = np.abs(Lo) >= SMALL
+            err = np.abs(Lg[mask] - Lo[mask])
+            rel = err / np.abs(Lo[mask])
+            if rel.size:
+                summary["max_rel"] = max(summary["max_rel"], float(rel.max()))
+                k = int(np.argmax(err - tol * np.abs(Lo[mask])))
+                Lo_k, Lg_k = Lo[mask][k], Lg[mask][k]
+                assert np.all(err <= tol * np.abs(Lo[mask]) + atol), (
+                    f"frame {f} (iters {o_it}): L differs by {rel.max():.3g} relative at "
+                    f"L={Lo_k:.6g} (gpu {Lg_k:.6g}, abs {abs(Lg_k - Lo_k):.3g}); "
+                    f"median rel {np.median(rel):.3g}, 99th pct {np.percentile(rel, 99):.3g}, "
+                    f"max |L| {np.abs(Lo).max():.4g}")
+        elif not o_ok:
+            if g_ok or g_it != max_iter:
+                summary["failed_mismatch"] += 1
+            summary["hamming_failed"].append(int((orc["bits"][f] != g["bits"][f]).sum()))
+        else:
+            summary["flagged_mismatch"] += int(not same)
+    bad = summary["flagged_mismatch"] + summary["failed_mismatch"]
+    assert bad <= 0.01 * F, f"{bad} of {F} frames disagree: {summary}"
+    return summary
+
+
+def oracle_f32_run(code, frames, max_iter, early_exit=True, alpha=0.75, clip=20.0, idx=None,
+                   lam=None):
+    if lam is None:
+        lam = oracle_llr(frames, "f32")
+    z = frames.z
+    if idx is not None:
+        lam, z = lam[idx], z[idx]
+    return oracle.decode_nms_f32(code, lam, z, max_iter=max_iter, early_exit=early_exit,
+                                 alpha=alpha, clip=clip)
+
+
+def assert_bitwise(gpu, ref, idx=None):
+    """GPU outputs equal to a reference bit for bit (bits, iters, ok, L)."""
+    sel = (lambda a: a[idx]) if idx is not None else (lambda a: a)
+    for k in ("bits", "iters", "ok", "L"):
+        a, b = sel(gpu[k]), ref[k]
+        if not np.array_equal(a, b):
+            bad = np.nonzero(np.any((a != b).reshape(a.shape[0], -1), axis=1))[0]
+            raise AssertionError(f"{k} differs on frames {bad[:10].tolist()} ({bad.size} in all)")

@@ -1,0 +1,60 @@
+"""The C-ABI library loads and exports what include/mbp.h declares (CPU only).
+
+No call here reaches a GPU: only symbol lookups, the version, and argument
+checks that fail before any device work.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mbp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(mbp_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for fn in ("mbp_ctx_create", "mbp_code_create", "mbp_decode", "mbp_llr_from_bits",
+               "mbp_last_error"):
+        assert fn in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2001_07979_amd import mbp
+    L = mbp.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version_and_error_paths_without_device():
+    from paper_2001_07979_amd import mbp
+    L = mbp.lib()
+    assert L.mbp_version() == 1
+    h = ctypes.c_void_p()
+    assert L.mbp_ctx_create(0, None) == mbp.MBP_EINVAL
+    assert "NULL" in mbp.last_error()
+    assert L.mbp_code_create(None, 8, 1, None, None, None, ctypes.byref(h)) == mbp.MBP_EINVAL
+    assert "ctx" in mbp.last_error()
+    p = mbp.mbp_params(0, 0, 10, 1, 0.75, 20.0)
+    assert L.mbp_decode(None, None, ctypes.byref(p), 1, *([None] * 7)) == mbp.MBP_EINVAL
+    assert L.mbp_llr_from_bits(None, 1, 1, None, None, 0, None, None) == mbp.MBP_EINVAL
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    assert L.mbp_profile_get(None, 0, ctypes.byref(n), ctypes.byref(ms)) == mbp.MBP_EINVAL
+    L.mbp_ctx_destroy(None)
+    L.mbp_code_destroy(None)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2001_07979_amd import mbp
+    monkeypatch.setattr(mbp, "_lib", None)
+    monkeypatch.setattr(mbp, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        mbp.lib()

@@ -1,0 +1,225 @@
+"""GPU parity: the HIP decoder (through the C-ABI) against the FP64 oracle.
+
+Sizes run from tiny ragged codes (several tiles, a partial frame group) up to
+the n = 65536, 256-frame workload the benchmark times, where the oracle
+decodes a sample of frames and properties that hold at any size are checked
+on all of them.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_07979_amd.inputs import bsc_frames, code_from_dense, peg_code, syndromes
+from paper_2001_07979_amd.inputs import workloads as W
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+RTOL32 = 1e-4
+RTOL64 = 1e-9
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2001_07979_amd import mbp
+    c = mbp.Context(0)
+    yield c
+    c.close()
+
+
+def upload(ctx, code):
+    from paper_2001_07979_amd import mbp
+    return mbp.Code.from_inputs(ctx, code)
+
+
+@pytest.fixture(scope="module")
+def ragged_code():
+    # n not a multiple of 64 or of the tile sizes; two matrices; irregular
+    return peg_code(1000, 260, 2, W.IRREGULAR_238, seed_base=7100, name="peg-n1000")
+
+
+def test_llr_kernel_matches_oracle(ctx):
+    rng = np.random.default_rng(0)
+    code = code_from_dense([np.array([[1, 1, 0], [0, 1, 1]], np.uint8)])
+    fr = bsc_frames(code, 1, 0.1, seed=0)
+    fr.y = rng.integers(0, 2, (7, 1000)).astype(np.uint8)
+    fr.p = rng.uniform(0.005, 0.3, 7)
+    import torch
+    from paper_2001_07979_amd import mbp
+    y = torch.from_numpy(fr.y).cuda()
+    e = torch.from_numpy(fr.p).cuda()
+    lam32 = mbp.llr_from_bits(ctx, y, e, dtype="f32").cpu().numpy()
+    lam64 = mbp.llr_from_bits(ctx, y, e, dtype="f64").cpu().numpy()
+    ref = oracle.llr_from_bits(fr.y, fr.p)
+    assert np.array_equal(lam32, ref.astype(np.float32))
+    # the oracle forms P1 = e + y(1-2e) and P0 = 1 - P1 before the logarithm,
+    # the kernel (1-2y) ln((1-e)/e): equal up to a few ulp in FP64
+    np.testing.assert_allclose(lam64, ref, rtol=2e-15, atol=0)
+
+
+@pytest.mark.parametrize("algo,dtype", [("nms", "f32"), ("spa", "f32"), ("spa", "f64"),
+                                        ("nms", "f64")])
+@pytest.mark.parametrize("F", [1, 64, 65, 130])
+def test_ragged_parity(ctx, ragged_code, algo, dtype, F):
+    fr = bsc_frames(ragged_code, F, np.linspace(0.01, 0.035, F), seed=100 + F)
+    dc = upload(ctx, ragged_code)
+    lam = parity.oracle_llr(fr, dtype)
+    if dtype == "f32":
+        # the GPU computes its own LLRs: identical to the oracle's in FP32
+        g = parity.gpu_run(ctx, dc, fr, algo, dtype, 40)
+        assert np.array_equal(g["llr_in"].astype(np.float64), lam)
+    else:
+        # in FP64 the two LLR formulas differ by a few ulp (checked in
+        # test_llr_kernel_matches_oracle); both decoders start from one input
+        g = parity.gpu_run(ctx, dc, fr, algo, dtype, 40, llr=lam)
+    o = parity.oracle_run(ragged_code, fr, algo, dtype, 40, lam=lam)
+    long_rtol = {("spa", "f32"): 1e-2, ("nms", "f32"): None}.get((algo, dtype), 1e-6)
+    s = parity.compare(g, o, 40, RTOL32 if dtype == "f32" else RTOL64, long_rtol=long_rtol,
+                       atol=parity.ATOL32 if dtype == "f32" else 0.0)
+    assert s["oracle_ok"] >= F // 2
+    if (algo, dtype) == ("nms", "f32"):
+        parity.assert_bitwise(g, parity.oracle_f32_run(ragged_code, fr, 40, lam=lam))
+    if (algo, dtype) == ("nms", "f64"):
+        # the same FP64 operations in the same order on both sides
+        parity.assert_bitwise(g, o)
+
+
+@pytest.mark.parametrize("algo", ["nms", "spa"])
+def test_fixed_iterations_parity(ctx, ragged_code, algo):
+    """Without early exit every frame runs T iterations."""
+    fr = bsc_frames(ragged_code, 70, 0.04, seed=9)
+    dc = upload(ctx, ragged_code)
+    g = parity.gpu_run(ctx, dc, fr, algo, "f32", 7, early_exit=False)
+    o = parity.oracle_run(ragged_code, fr, algo, "f32", 7, early_exit=False)
+    assert np.all(g["iters"] == 7)
+    parity.compare(g, o, 7, RTOL32, atol=parity.ATOL32)
+    if algo == "nms":
+        parity.assert_bitwise(g, parity.oracle_f32_run(ragged_code, fr, 7, early_exit=False))
+
+
+def test_fp64_n4096_every_frame_exact(ctx):
+    """u=2 regular (3,6) codes, n=4096, 16 frames, BSC 0.05, FP64 sum-product."""
+    wl = W.fp64_n4096()
+    fr = wl.frames()
+    dc = upload(ctx, wl.code)
+    g = parity.gpu_run(ctx, dc, fr, "spa", "f64", wl.max_iter)
+    o = parity.oracle_run(wl.code, fr, "spa", "f64", wl.max_iter)
+    s = parity.compare(g, o, wl.max_iter, RTOL64, exact_all=True)
+    assert s["oracle_ok"] == 16
+    assert np.array_equal(g["bits"], fr.x)
+
+
+@pytest.mark.parametrize("algo", ["spa", "nms"])
+def test_n65536_full_batch_sampled(ctx, algo):
+    """The benchmarked workload: 256 frames decoded together; the oracle
+    decodes a sample of frames one by one; every frame is checked for the
+    properties that hold at any size."""
+    wl = W.qkd_n65536(algo=algo)
+    fr = wl.frames()
+    dc = upload(ctx, wl.code)
+    g = parity.gpu_run(ctx, dc, fr, algo, "f32", wl.max_iter, alpha=wl.alpha)
+    idx = np.array([0, 1, 63, 64, 127, 128, 200, 255])
+    o = parity.oracle_run(wl.code, fr, algo, "f32", wl.max_iter, alpha=wl.alpha, idx=idx)
+    parity.compare(g, o, wl.max_iter, RTOL32, idx=idx, atol=parity.ATOL32)
+    if algo == "nms":
+        parity.assert_bitwise(g, parity.oracle_f32_run(wl.code, fr, wl.max_iter, idx=idx), idx=idx)
+    # every declared success meets all u syndromes (recomputed here)
+    okf = g["ok"] == 1
+    assert np.array_equal(syndromes(wl.code, g["bits"][okf]), fr.z[okf])
+    assert np.all(g["iters"][~okf] == wl.max_iter)
+    assert okf.mean() > 0.99 and np.array_equal(g["bits"][okf], fr.x[okf])
+
+
+def test_edge_cases(ctx, ragged_code):
+    import torch
+    from paper_2001_07979_amd import mbp
+    dc = upload(ctx, ragged_code)
+    # error-free frames stop after one iteration
+    fr = bsc_frames(ragged_code, 5, 0.0, seed=1)
+    fr.p[:] = 0.03
+    g = parity.gpu_run(ctx, dc, fr, "nms", "f32", 30)
+    assert np.all(g["ok"] == 1) and np.all(g["iters"] == 1) and np.array_equal(g["bits"], fr.x)
+    # random syndromes cannot be met near y: failure at T
+    fr = bsc_frames(ragged_code, 66, 0.02, seed=2)
+    fr.z = np.random.default_rng(3).integers(0, 2, fr.z.shape).astype(np.uint8)
+    g = parity.gpu_run(ctx, dc, fr, "spa", "f32", 9)
+    assert np.all(g["ok"] == 0) and np.all(g["iters"] == 9)
+    # a single iteration
+    fr = bsc_frames(ragged_code, 3, 0.03, seed=4)
+    g = parity.gpu_run(ctx, dc, fr, "spa", "f32", 1)
+    o = parity.oracle_run(ragged_code, fr, "spa", "f32", 1)
+    assert np.array_equal(g["ok"], o["ok"]) and np.all(g["iters"] == 1)
+    # no frames
+    e = torch.empty((0, ragged_code.n), dtype=torch.float32, device="cuda")
+    z = torch.empty((0, ragged_code.M), dtype=torch.uint8, device="cuda")
+    out = mbp.decode(ctx, dc, e, z)
+    assert out["bits"].shape == (0, ragged_code.n)
+
+
+def test_runs_are_bitwise_deterministic(ctx, ragged_code):
+    fr = bsc_frames(ragged_code, 100, 0.045, seed=21)
+    dc = upload(ctx, ragged_code)
+    a = parity.gpu_run(ctx, dc, fr, "spa", "f32", 40)
+    b = parity.gpu_run(ctx, dc, fr, "spa", "f32", 40)
+    for k in ("bits", "iters", "ok", "L"):
+        assert np.array_equal(a[k], b[k])
+
+
+@pytest.mark.parametrize("algo", ["spa", "nms"])
+def test_coset_invariant_on_gpu(ctx, ragged_code, algo):
+    fr = bsc_frames(ragged_code, 64, 0.04, seed=22)
+    dc = upload(ctx, ragged_code)
+    a = parity.gpu_run(ctx, dc, fr, algo, "f32", 40)
+    fr2 = bsc_frames(ragged_code, 64, 0.04, seed=22)
+    fr2.z = fr.z ^ syndromes(ragged_code, fr.y)
+    b = parity.gpu_run(ctx, dc, fr2, algo, "f32", 40, llr=np.abs(a["llr_in"]))
+    assert np.array_equal(a["ok"], b["ok"]) and np.array_equal(a["iters"], b["iters"])
+    nz = np.all(a["L"] != 0, axis=1)
+    assert np.array_equal((a["bits"] ^ fr.y)[nz], b["bits"][nz])
+    assert np.array_equal(np.abs(a["L"])[nz], np.abs(b["L"])[nz])
+
+
+def test_stack_equivalence_on_gpu(ctx, ragged_code):
+    fr = bsc_frames(ragged_code, 64, 0.04, seed=23)
+    rp, ci = ragged_code.stacked()
+    one = type(ragged_code)(n=ragged_code.n, row_ptr=[rp], col_idx=[ci])
+    a = parity.gpu_run(ctx, upload(ctx, ragged_code), fr, "spa", "f32", 40)
+    b = parity.gpu_run(ctx, upload(ctx, one), fr, "spa", "f32", 40)
+    for k in ("bits", "iters", "ok", "L"):
+        assert np.array_equal(a[k], b[k])
+
+
+def test_invalid_arguments_are_rejected(ctx, ragged_code):
+    import ctypes
+    import torch
+    from paper_2001_07979_amd import mbp
+    bad = code_from_dense([np.array([[1, 1, 0], [0, 0, 1]], np.uint8)])  # degree-1 check
+    with pytest.raises(mbp.MbpError) as ei:
+        upload(ctx, bad)
+    assert ei.value.code == mbp.MBP_EINVAL
+    wide = code_from_dense([np.ones((1, 65), np.uint8)])
+    with pytest.raises(mbp.MbpError) as ei:
+        upload(ctx, wide)
+    assert ei.value.code == mbp.MBP_EUNSUPPORTED
+    dc = upload(ctx, ragged_code)
+    llr = torch.zeros((2, ragged_code.n), device="cuda")
+    z = torch.zeros((2, ragged_code.M), dtype=torch.uint8, device="cuda")
+    for kw in (dict(max_iter=0), dict(clip=31.0), dict(algo="nms", alpha=0.0),
+               dict(clip=float("nan"))):
+        with pytest.raises(mbp.MbpError) as ei:
+            mbp.decode(ctx, dc, llr, z, **kw)
+        assert ei.value.code == mbp.MBP_EINVAL
+
+
+def test_profiling_counts_launches(ctx, ragged_code):
+    dc = upload(ctx, ragged_code)
+    fr = bsc_frames(ragged_code, 64, 0.03, seed=5)
+    ctx.profile_reset()
+    ctx.profile_enable(True)
+    g = parity.gpu_run(ctx, dc, fr, "nms", "f32", 40)
+    ctx.profile_enable(False)
+    n_c, ms_c = ctx.profile_get("check")
+    n_v, ms_v = ctx.profile_get("variable")
+    assert n_c == n_v >= int(g["iters"].max()) and ms_c > 0 and ms_v > 0

@@ -386,3 +386,45 @@ def test_worked_tie_decides_zero():
     assert r["L"][0].tolist() == g["L_t1"]
     assert r["L"][0, 1] == 0.0
     assert r["bits"][0].tolist() == g["bits_t1"] and r["ok"][0] == 0
+
+
+# --------------------------------------------- binary32 min-sum variant
+def test_nms_f32_worked_example_is_exact():
+    """Dyadic inputs: the binary32 decoder gives the hand-worked values exactly."""
+    g = json.load(open(GOLDEN))["nms_single_check"]
+    code = code_from_dense([np.array(h) for h in g["H"]])
+    r = oracle.decode_nms_f32(code, np.array([g["lambda"]]), np.array([g["z"]], np.uint8),
+                              max_iter=1, early_exit=False, alpha=g["alpha"])
+    assert r["L"][0].tolist() == g["L_t1"]
+    t = json.load(open(GOLDEN))["path_u2_tie"]
+    code = code_from_dense([np.array(h) for h in t["H"]])
+    r = oracle.decode_nms_f32(code, np.array([t["lambda"]]), np.array([t["z"]], np.uint8),
+                              max_iter=1, early_exit=True, alpha=1.0)
+    assert r["L"][0].tolist() == t["L_t1"] and r["bits"][0].tolist() == t["bits_t1"]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_nms_f32_tracks_fp64_on_trees(seed):
+    """alpha = 1 on a tree: within binary32 rounding of the max-marginals."""
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(8, 15))
+    Hs = brute.random_tree_code(rng, n, u=2)
+    code = code_from_dense(Hs)
+    H = np.concatenate(Hs)
+    z = syndromes(code, rng.integers(0, 2, n).astype(np.uint8)[None])[0]
+    lam = rng.normal(0, 2.5, size=n).astype(np.float32).astype(np.float64)
+    r = oracle.decode_nms_f32(code, lam[None], z[None], max_iter=n, early_exit=False, alpha=1.0,
+                              clip=1e6)
+    np.testing.assert_allclose(r["L"][0], brute.max_marginal(H, z, lam), rtol=1e-5, atol=1e-5)
+
+
+def test_nms_f32_agrees_with_fp64_on_short_decodes(small_peg):
+    fr = bsc_frames(small_peg, 24, 0.04, seed=61)
+    lam = oracle.llr_from_bits(fr.y, fr.p).astype(np.float32).astype(np.float64)
+    a = oracle.decode(small_peg, lam, fr.z, algo=oracle.NMS, max_iter=30)
+    b = oracle.decode_nms_f32(small_peg, lam, fr.z, max_iter=30)
+    short = (a["iters"] <= 5) & (a["ok"] == 1) & (a["flag"] == 0)
+    assert short.sum() >= 12
+    assert np.array_equal(a["iters"][short], b["iters"][short])
+    assert np.array_equal(a["bits"][short], b["bits"][short])
+    np.testing.assert_allclose(b["L"][short], a["L"][short], rtol=1e-5, atol=1e-4)
