@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-launch HIP events (no roofline)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before timing, copy a buffer of this size once (calibrates "
+                         "rocprofv3 byte counters against a transfer of known size)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); frames are independent, "
@@ -108,6 +111,14 @@ def main():
         mbp.decode(ctx, dcode, llr, z, algo=wl.algo, max_iter=wl.max_iter,
                    early_exit=wl.early_exit, alpha=wl.alpha, clip=wl.clip, out=out,
                    stream=stream)
+
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copy probe of {args.copy_probe_mib} MiB done")
+        del src, dst
 
     log(f"bench: warmup {args.warmup}")
     for _ in range(args.warmup):

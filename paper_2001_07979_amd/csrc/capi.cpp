@@ -150,17 +150,21 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
     hipError_t he;
     if ((he = hipSetDevice(ctx->device)) != hipSuccess) return cleanup(hip_fail(he, "hipSetDevice"));
     if ((he = hipMalloc(&code->d_row_ptr, sizeof(int32_t) * (M + 1))) != hipSuccess ||
-        (he = hipMalloc(&code->d_col, sizeof(int32_t) * std::max<int64_t>(E, 1))) != hipSuccess ||
+        (he = hipMalloc(&code->d_col, sizeof(int32_t) * (E + mbp::kIndexPad))) != hipSuccess ||
         (he = hipMalloc(&code->d_var_ptr, sizeof(int32_t) * (n + 1))) != hipSuccess ||
-        (he = hipMalloc(&code->d_var_edge, sizeof(int32_t) * std::max<int64_t>(E, 1))) != hipSuccess)
+        (he = hipMalloc(&code->d_var_edge, sizeof(int32_t) * (E + mbp::kIndexPad))) != hipSuccess)
         return cleanup(hip_fail(he, "mbp_code_create: hipMalloc"));
+    // the kernels read edge indices in fixed-size blocks that may run past the
+    // last edge; the padding holds valid (zero) indices
+    h_col.resize(E + mbp::kIndexPad, 0);
+    h_var_edge.resize(E + mbp::kIndexPad, 0);
     if ((he = hipMemcpy(code->d_row_ptr, h_row_ptr.data(), sizeof(int32_t) * (M + 1),
                         hipMemcpyHostToDevice)) != hipSuccess ||
-        (he = hipMemcpy(code->d_col, h_col.data(), sizeof(int32_t) * E, hipMemcpyHostToDevice)) !=
-            hipSuccess ||
+        (he = hipMemcpy(code->d_col, h_col.data(), sizeof(int32_t) * (E + mbp::kIndexPad),
+                        hipMemcpyHostToDevice)) != hipSuccess ||
         (he = hipMemcpy(code->d_var_ptr, var_cnt.data(), sizeof(int32_t) * (n + 1),
                         hipMemcpyHostToDevice)) != hipSuccess ||
-        (he = hipMemcpy(code->d_var_edge, h_var_edge.data(), sizeof(int32_t) * E,
+        (he = hipMemcpy(code->d_var_edge, h_var_edge.data(), sizeof(int32_t) * (E + mbp::kIndexPad),
                         hipMemcpyHostToDevice)) != hipSuccess)
         return cleanup(hip_fail(he, "mbp_code_create: hipMemcpy"));
     ctx->live_codes++;

@@ -43,42 +43,96 @@ constexpr int kRowsPerWave = 4;
 constexpr int kRowsPerTile = kRowsPerWave * kWaves;
 constexpr int kVarsPerWave = 4;
 constexpr int kVarsPerTile = kVarsPerWave * kWaves;
-constexpr int kVarChunk = 8;
+constexpr int kIdxChunk = 8;  // edge indices read per scalar batch
 
-__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ unsigned lane_id() { return threadIdx.x & 63u; }
 __device__ __forceinline__ int wave_id() {
     return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
 }
 
-// phi(x) = -ln tanh(x/2) = ln(1 + 2/(e^x - 1)); phi is its own inverse, so
-// 2 atanh(prod tanh(a_k/2)) = phi(sum phi(a_k)) for magnitudes a_k >= 0.
-// phi(0) = +inf and phi(+inf) = 0 follow from IEEE arithmetic.
-__device__ __forceinline__ float phi(float x) { return log1pf(2.0f / expm1f(x)); }
+// phi(x) = -ln tanh(x/2) = 2 atanh(e^-x) for x >= 0; phi is its own inverse,
+// so 2 atanh(prod tanh(a_k/2)) = phi(sum phi(a_k)) for magnitudes a_k >= 0.
+// Evaluated with the hardware exp2 / log2 / reciprocal and short polynomials
+// (about 4e-7 relative error over [0, 80]):
+//   v = e^-x, with -x log2(e) split into a rounded part and its residual;
+//   x >= ln 4:  2 atanh(v) = 2v (1 + v^2/3 + v^4/5 + ... + v^12/13), v <= 1/4;
+//   x <  ln 4:  ln((2 - w)/w) with w = 1 - e^-x (Taylor series below 0.35,
+//               where 1 - v would cancel).
+// phi(0) = +inf, and phi(x) = 0 for x >= 80 (true value below 4e-35).
+__device__ __forceinline__ float phi(float x) {
+    constexpr float kL2E = 1.44269504088896340736f;
+    constexpr float kL2ELo = 1.925963033500011e-08f;  // log2(e) - kL2E
+    constexpr float kLn2 = 0.693147180559945309f;
+    constexpr float kLn4 = 1.38629436111989061883f;
+    const float y = -x * kL2E;
+    const float ylo = fmaf(-x, kL2E, -y) + (-x) * kL2ELo;
+    float v = __builtin_amdgcn_exp2f(y);
+    v = fmaf(v, ylo * kLn2, v);
+    const float s = v * v;
+    float p = fmaf(s, 1.0f / 13.0f, 1.0f / 11.0f);
+    p = fmaf(s, p, 1.0f / 9.0f);
+    p = fmaf(s, p, 1.0f / 7.0f);
+    p = fmaf(s, p, 1.0f / 5.0f);
+    p = fmaf(s, p, 1.0f / 3.0f);
+    p = fmaf(s, p, 1.0f);
+    float res = 2.0f * v * p;
+    if (__ballot(x < kLn4)) {
+        float q = fmaf(x, -1.0f / 40320.0f, 1.0f / 5040.0f);
+        q = fmaf(x, q, -1.0f / 720.0f);
+        q = fmaf(x, q, 1.0f / 120.0f);
+        q = fmaf(x, q, -1.0f / 24.0f);
+        q = fmaf(x, q, 1.0f / 6.0f);
+        q = fmaf(x, q, -0.5f);
+        q = fmaf(x, q, 1.0f);
+        const float w = x < 0.35f ? x * q : 1.0f - v;
+        const float r = (2.0f - w) * __builtin_amdgcn_rcpf(w);
+        const float b = __builtin_amdgcn_logf(r) * kLn2;
+        res = x < kLn4 ? b : res;
+    }
+    return x < 80.0f ? res : 0.0f;
+}
 
 enum { kNMS = MBP_ALGO_NMS, kSPA = MBP_ALGO_SPA };
 
-struct CheckArgs {
-    const int32_t *row_ptr;
-    const int32_t *col;
-    const void *Lp;
-    void *c;
-    const uint64_t *zb;
-    const uint64_t *act;
-    uint64_t *uns;
+// Per-group status words (running mask and unmet-check mask, by iteration
+// parity) sit kStride words apart, one 256-byte line per group.
+constexpr int kStride = 32;
+
+// OR lanes with an unmet check into a group's mask. A coherent read first
+// skips the atomic when those lanes are already marked, which is the common
+// case: the mask saturates after a few tiles in early iterations and stays
+// near empty late, so few atomics reach the shared word.
+__device__ __forceinline__ void or_unmet(uint64_t *word, uint64_t bits) {
+    if (!bits) return;
+    const uint64_t cur = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (bits & ~cur)
+        atomicOr(reinterpret_cast<unsigned long long *>(word), static_cast<unsigned long long>(bits));
+}
+
+// Scalars shared by the iteration kernels.
+struct Dims {
     int64_t E;
-    int32_t n, M, ngroups, ntiles, t, want_syn;
+    int32_t n, M, ngroups, ntiles;
+    int32_t t;     // iteration (1-based); the syndrome-only pass uses last + 1
+    int32_t flag;  // check pass: test the incoming decisions; variable pass: early exit
     double alpha, clip;
 };
 
-// Check-node pass. Each wave handles kRowsPerWave checks of one group; the
-// check degree d <= DMAX is wave-uniform, the messages of a check are held in
-// registers (q[j]) between the gather and the write.
+// Check-node pass, iteration t. Each wave handles kRowsPerWave checks of one
+// group. The check's edge indices are read up front as scalars (the column
+// array is padded by 64 entries so a full DMAX block is always in bounds),
+// then all gathers of the check are issued before any is consumed; the
+// messages stay in registers (q[j]) between the gather and the write.
 template <typename T, int ALGO, int DMAX>
-__global__ __launch_bounds__(kBlock) void k_check(CheckArgs a) {
+__global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ row_ptr,
+                                                  const int32_t *__restrict__ col,
+                                                  const uint64_t *__restrict__ zb,
+                                                  const uint64_t *__restrict__ act,
+                                                  const T *__restrict__ Lp, T *__restrict__ c,
+                                                  uint64_t *__restrict__ uns, const Dims a) {
     __shared__ uint64_t sh_bad[kWaves];
-    const T *__restrict__ Lp = static_cast<const T *>(a.Lp);
-    T *__restrict__ c = static_cast<T *>(a.c);
-    const int lane = lane_id(), wave = wave_id();
+    const unsigned lane = lane_id();
+    const int wave = wave_id();
     const T alpha = static_cast<T>(a.alpha), clip = static_cast<T>(a.clip);
     const int pt = a.t & 1;
     const bool first = a.t == 1;
@@ -86,30 +140,40 @@ __global__ __launch_bounds__(kBlock) void k_check(CheckArgs a) {
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
         const int g = static_cast<int>(w / a.ntiles);
         const int tile = static_cast<int>(w % a.ntiles);
-        const uint64_t act = a.act[2 * g + pt];
-        if (act == 0) continue;  // whole group retired (uniform over the block)
-        const bool on = (act >> lane) & 1;
-        const T *Lg = Lp + static_cast<size_t>(g) * a.n * G + lane;
-        T *cg = c + static_cast<size_t>(g) * a.E * G + lane;
-        const uint64_t *zg = a.zb + static_cast<size_t>(g) * a.M;
+        const uint64_t gact = act[kStride * g + pt];
+        if (gact == 0) continue;  // whole group retired (uniform over the block)
+        const bool on = (gact >> lane) & 1;
+        // wave-uniform bases; every access below is base[lane], so addresses
+        // are a scalar base plus one per-lane offset
+        const T *Lg = Lp + static_cast<size_t>(g) * a.n * G;
+        const uint64_t *zg = zb + static_cast<size_t>(g) * a.M;
         uint64_t bad = 0;
         for (int k = 0; k < kRowsPerWave; ++k) {
             const int r = tile * kRowsPerTile + k * kWaves + wave;
             if (r >= a.M) break;
-            const int e0 = a.row_ptr[r];
-            const int d = a.row_ptr[r + 1] - e0;
+            const int e0 = row_ptr[r];
+            const int d = row_ptr[r + 1] - e0;
             const int zbit = static_cast<int>((zg[r] >> lane) & 1);
+            T *cg = c + (static_cast<size_t>(g) * a.E + e0) * G;
+            int v[DMAX];
+#pragma unroll
+            for (int j = 0; j < DMAX; ++j) v[j] = col[e0 + j];
             int par = 0;
             if (on) {
-                T q[DMAX];
+                // issue every gather of the check before using any of them
+                T q[DMAX], co[DMAX];
 #pragma unroll
                 for (int j = 0; j < DMAX; ++j) {
                     if (j < d) {
-                        const int v = a.col[e0 + j];
-                        const T Lv = Lg[static_cast<size_t>(v) * G];
-                        const T co = first ? T(0) : cg[static_cast<size_t>(e0 + j) * G];
-                        q[j] = Lv - co;
-                        par ^= (Lv < T(0)) ? 1 : 0;
+                        q[j] = (Lg + static_cast<size_t>(v[j]) * G)[lane];
+                        co[j] = first ? T(0) : (cg + j * G)[lane];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < DMAX; ++j) {
+                    if (j < d) {
+                        par ^= (q[j] < T(0)) ? 1 : 0;
+                        q[j] -= co[j];
                     }
                 }
                 uint64_t neg = 0;
@@ -139,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_check(CheckArgs a) {
                         if (j < d) {
                             const T mag = alpha * (j == i1 ? m2 : m1);
                             const int s = sx ^ static_cast<int>((neg >> j) & 1);
-                            cg[static_cast<size_t>(e0 + j) * G] = s ? -mag : mag;
+                            (cg + j * G)[lane] = s ? -mag : mag;
                         }
                     }
                 } else if constexpr (sizeof(T) == 4) {
@@ -171,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_check(CheckArgs a) {
                             const T mag = phi(q[j] + suf);
                             suf += f[j];
                             const int s = sx ^ static_cast<int>((neg >> j) & 1);
-                            cg[static_cast<size_t>(e0 + j) * G] = s ? -mag : mag;
+                            (cg + j * G)[lane] = s ? -mag : mag;
                         }
                     }
                 } else {
@@ -203,21 +267,20 @@ __global__ __launch_bounds__(kBlock) void k_check(CheckArgs a) {
                             const T mag = T(2) * atanh(q[j] * suf);
                             suf *= th[j];
                             const int s = sx ^ static_cast<int>((neg >> j) & 1);
-                            cg[static_cast<size_t>(e0 + j) * G] = s ? -mag : mag;
+                            (cg + j * G)[lane] = s ? -mag : mag;
                         }
                     }
                 }
             }
             bad |= __ballot(on && (par != zbit));
         }
-        if (a.want_syn) {
+        if (a.flag) {
             if (lane == 0) sh_bad[wave] = bad;
             __syncthreads();
             if (threadIdx.x == 0) {
                 uint64_t b = 0;
                 for (int i = 0; i < kWaves; ++i) b |= sh_bad[i];
-                if (b) atomicOr(reinterpret_cast<unsigned long long *>(&a.uns[2 * g + pt]),
-                                static_cast<unsigned long long>(b));
+                or_unmet(&uns[kStride * g + pt], b);
             }
             __syncthreads();
         }
@@ -226,30 +289,43 @@ __global__ __launch_bounds__(kBlock) void k_check(CheckArgs a) {
 
 // Syndrome-only pass: the stopping test of the decisions held in Lp.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_syndrome(CheckArgs a) {
+__global__ __launch_bounds__(kBlock) void k_syndrome(const int32_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col,
+                                                     const uint64_t *__restrict__ zb,
+                                                     const uint64_t *__restrict__ act,
+                                                     const T *__restrict__ Lp,
+                                                     uint64_t *__restrict__ uns, const Dims a) {
     __shared__ uint64_t sh_bad[kWaves];
-    const T *__restrict__ Lp = static_cast<const T *>(a.Lp);
-    const int lane = lane_id(), wave = wave_id();
+    const unsigned lane = lane_id();
+    const int wave = wave_id();
     const int pt = a.t & 1;
     const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
         const int g = static_cast<int>(w / a.ntiles);
         const int tile = static_cast<int>(w % a.ntiles);
-        const uint64_t act = a.act[2 * g + pt];
-        if (act == 0) continue;
-        const bool on = (act >> lane) & 1;
-        const T *Lg = Lp + static_cast<size_t>(g) * a.n * G + lane;
-        const uint64_t *zg = a.zb + static_cast<size_t>(g) * a.M;
+        const uint64_t gact = act[kStride * g + pt];
+        if (gact == 0) continue;
+        const bool on = (gact >> lane) & 1;
+        const T *Lg = Lp + static_cast<size_t>(g) * a.n * G;
+        const uint64_t *zg = zb + static_cast<size_t>(g) * a.M;
         uint64_t bad = 0;
         for (int k = 0; k < kRowsPerWave; ++k) {
             const int r = tile * kRowsPerTile + k * kWaves + wave;
             if (r >= a.M) break;
-            const int e0 = a.row_ptr[r];
-            const int d = a.row_ptr[r + 1] - e0;
+            const int e0 = row_ptr[r];
+            const int d = row_ptr[r + 1] - e0;
             const int zbit = static_cast<int>((zg[r] >> lane) & 1);
             int par = 0;
-            if (on)
-                for (int j = 0; j < d; ++j) par ^= (Lg[static_cast<size_t>(a.col[e0 + j]) * G] < T(0)) ? 1 : 0;
+            for (int j0 = 0; j0 < d; j0 += kIdxChunk) {
+                int v[kIdxChunk];
+#pragma unroll
+                for (int j = 0; j < kIdxChunk; ++j) v[j] = col[e0 + j0 + j];
+                if (on) {
+#pragma unroll
+                    for (int j = 0; j < kIdxChunk; ++j)
+                        if (j0 + j < d) par ^= ((Lg + static_cast<size_t>(v[j]) * G)[lane] < T(0)) ? 1 : 0;
+                }
+            }
             bad |= __ballot(on && (par != zbit));
         }
         if (lane == 0) sh_bad[wave] = bad;
@@ -257,77 +333,71 @@ __global__ __launch_bounds__(kBlock) void k_syndrome(CheckArgs a) {
         if (threadIdx.x == 0) {
             uint64_t b = 0;
             for (int i = 0; i < kWaves; ++i) b |= sh_bad[i];
-            if (b) atomicOr(reinterpret_cast<unsigned long long *>(&a.uns[2 * g + pt]),
-                            static_cast<unsigned long long>(b));
+            or_unmet(&uns[kStride * g + pt], b);
         }
         __syncthreads();
     }
 }
 
-struct VarArgs {
-    const int32_t *var_ptr;
-    const int32_t *var_edge;
-    const void *c;
-    const void *lam;
-    void *Lp;
-    uint64_t *act;
-    uint64_t *uns;
-    uint64_t *status;  // host-visible per-group running masks
-    int32_t *iters_out;
-    uint8_t *ok_out;
-    int64_t E;
-    int32_t n, ngroups, ntiles, t, early_exit;
-};
-
 // Variable-node pass, eq. (2), plus the per-group bookkeeping of the
-// stopping rule.
+// stopping rule. act_in / uns_in are this iteration's words, act_out /
+// uns_out the next iteration's (the same arrays at the other parity).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_variable(VarArgs a) {
-    const T *__restrict__ c = static_cast<const T *>(a.c);
-    const T *__restrict__ lam = static_cast<const T *>(a.lam);
-    T *__restrict__ Lp = static_cast<T *>(a.Lp);
-    const int lane = lane_id(), wave = wave_id();
-    const int pt = a.t & 1, nt = (a.t + 1) & 1;
+__global__ __launch_bounds__(kBlock) void k_variable(
+    const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_edge,
+    const T *__restrict__ c, const T *__restrict__ lam, T *__restrict__ Lp,
+    const uint64_t *__restrict__ act_in, const uint64_t *__restrict__ uns_in,
+    uint64_t *__restrict__ act_out, uint64_t *__restrict__ uns_out,
+    uint64_t *__restrict__ status, int32_t *__restrict__ iters_out, uint8_t *__restrict__ ok_out,
+    const Dims a) {
+    const unsigned lane = lane_id();
+    const int wave = wave_id();
     const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
         const int g = static_cast<int>(w / a.ntiles);
         const int tile = static_cast<int>(w % a.ntiles);
-        const uint64_t act = a.act[2 * g + pt];
-        const uint64_t U = (a.early_exit && a.t > 1) ? a.uns[2 * g + pt] : ~0ull;
-        const uint64_t run = act & U;
+        const uint64_t gact = act_in[kStride * g];
+        const uint64_t U = (a.flag && a.t > 1) ? uns_in[kStride * g] : ~0ull;
+        const uint64_t run = gact & U;
         if (tile == 0 && wave == 0) {
             // Frames whose decisions at t-1 met every syndrome stop here;
             // nothing else reads these words during this pass.
-            const uint64_t conv = act & ~U;
+            const uint64_t conv = gact & ~U;
             if (lane == 0) {
-                a.act[2 * g + nt] = run;
-                a.uns[2 * g + nt] = 0;
-                __hip_atomic_store(&a.status[g], run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                act_out[kStride * g] = run;
+                uns_out[kStride * g] = 0;
+                __hip_atomic_store(&status[g], run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             }
             if ((conv >> lane) & 1) {
                 const int f = g * G + lane;
-                a.iters_out[f] = a.t - 1;
-                a.ok_out[f] = 1;
+                iters_out[f] = a.t - 1;
+                ok_out[f] = 1;
             }
         }
-        if (!((run >> lane) & 1)) continue;
-        const size_t gb = static_cast<size_t>(g) * a.n * G + lane;
-        const T *cg = c + static_cast<size_t>(g) * a.E * G + lane;
+        if (run == 0) continue;
+        const bool on = (run >> lane) & 1;
+        const size_t gb = static_cast<size_t>(g) * a.n * G;
+        const T *cg = c + static_cast<size_t>(g) * a.E * G;
         for (int k = 0; k < kVarsPerWave; ++k) {
             const int i = tile * kVarsPerTile + k * kWaves + wave;
             if (i >= a.n) break;
-            const int k0 = a.var_ptr[i], k1 = a.var_ptr[i + 1];
-            T s = lam[gb + static_cast<size_t>(i) * G];
-            for (int kk = k0; kk < k1; kk += kVarChunk) {
-                T v[kVarChunk];
+            const int k0 = var_ptr[i], k1 = var_ptr[i + 1];
+            T s = on ? (lam + gb + static_cast<size_t>(i) * G)[lane] : T(0);
+            for (int kk = k0; kk < k1; kk += kIdxChunk) {
+                int ev[kIdxChunk];
 #pragma unroll
-                for (int j = 0; j < kVarChunk; ++j)
-                    if (kk + j < k1) v[j] = cg[static_cast<size_t>(a.var_edge[kk + j]) * G];
+                for (int j = 0; j < kIdxChunk; ++j) ev[j] = var_edge[kk + j];
+                if (on) {
+                    T x[kIdxChunk];
 #pragma unroll
-                for (int j = 0; j < kVarChunk; ++j)
-                    if (kk + j < k1) s += v[j];
+                    for (int j = 0; j < kIdxChunk; ++j)
+                        if (kk + j < k1) x[j] = (cg + static_cast<size_t>(ev[j]) * G)[lane];
+#pragma unroll
+                    for (int j = 0; j < kIdxChunk; ++j)
+                        if (kk + j < k1) s += x[j];
+                }
             }
-            Lp[gb + static_cast<size_t>(i) * G] = s;
+            if (on) (Lp + gb + static_cast<size_t>(i) * G)[lane] = s;
         }
     }
 }
@@ -338,10 +408,10 @@ __global__ void k_init_groups(uint64_t *act, uint64_t *uns, uint64_t *status, in
     if (g >= ngroups) return;
     const int rem = nframes - g * G;
     const uint64_t valid = rem >= G ? ~0ull : ((1ull << rem) - 1ull);
-    act[2 * g + 1] = valid;  // iteration 1 reads parity 1
-    act[2 * g + 0] = 0;
-    uns[2 * g + 0] = 0;
-    uns[2 * g + 1] = 0;
+    act[kStride * g + 1] = valid;  // iteration 1 reads parity 1
+    act[kStride * g + 0] = 0;
+    uns[kStride * g + 0] = 0;
+    uns[kStride * g + 1] = 0;
     __hip_atomic_store(&status[g], valid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
@@ -352,8 +422,8 @@ __global__ void k_finalize(const uint64_t *act, const uint64_t *uns, int32_t *it
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nframes) return;
     const int g = f / G, lane = f % G, p = tf & 1;
-    if ((act[2 * g + p] >> lane) & 1) {
-        ok_out[f] = ((uns[2 * g + p] >> lane) & 1) ? 0 : 1;
+    if ((act[kStride * g + p] >> lane) & 1) {
+        ok_out[f] = ((uns[kStride * g + p] >> lane) & 1) ? 0 : 1;
         iters_out[f] = last_iter;
     }
 }
@@ -539,15 +609,19 @@ int ensure_status(mbp_ctx *ctx, int32_t ngroups) {
     return MBP_OK;
 }
 
+template <typename T>
+using CheckFn = void (*)(const int32_t *, const int32_t *, const uint64_t *, const uint64_t *,
+                         const T *, T *, uint64_t *, Dims);
+
 template <typename T, int ALGO>
-const void *check_kernel(int dmax) {
+CheckFn<T> check_kernel(int dmax) {
     switch (dmax) {
-        case 8: return reinterpret_cast<const void *>(&k_check<T, ALGO, 8>);
-        case 16: return reinterpret_cast<const void *>(&k_check<T, ALGO, 16>);
-        case 24: return reinterpret_cast<const void *>(&k_check<T, ALGO, 24>);
-        case 32: return reinterpret_cast<const void *>(&k_check<T, ALGO, 32>);
-        case 48: return reinterpret_cast<const void *>(&k_check<T, ALGO, 48>);
-        default: return reinterpret_cast<const void *>(&k_check<T, ALGO, 64>);
+        case 8: return &k_check<T, ALGO, 8>;
+        case 16: return &k_check<T, ALGO, 16>;
+        case 24: return &k_check<T, ALGO, 24>;
+        case 32: return &k_check<T, ALGO, 32>;
+        case 48: return &k_check<T, ALGO, 48>;
+        default: return &k_check<T, ALGO, 64>;
     }
 }
 
@@ -567,7 +641,7 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     const size_t sz_c = align_up(static_cast<size_t>(ngroups) * E * G * s);
     const size_t sz_L = align_up(static_cast<size_t>(ngroups) * n * G * s);
     const size_t sz_z = align_up(static_cast<size_t>(ngroups) * M * sizeof(uint64_t));
-    const size_t sz_m = align_up(static_cast<size_t>(ngroups) * 2 * sizeof(uint64_t));
+    const size_t sz_m = align_up(static_cast<size_t>(ngroups) * kStride * sizeof(uint64_t));
     int rc = ensure_workspace(ctx, sz_c + 2 * sz_L + sz_z + 2 * sz_m);
     if (rc != MBP_OK) return rc;
     if ((rc = ensure_status(ctx, ngroups)) != MBP_OK) return rc;
@@ -596,15 +670,14 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
                                  synd, zb, F, M));
 
     const int dmax = dmax_for(code->max_check_deg);
-    const void *kc = p->algo == MBP_ALGO_NMS ? check_kernel<T, kNMS>(dmax) : check_kernel<T, kSPA>(dmax);
-    CheckArgs ca{code->d_row_ptr, code->d_col, Lp, c, zb, act, uns, E, n, M, ngroups,
-                 (M + kRowsPerTile - 1) / kRowsPerTile, 0, p->early_exit, p->alpha, p->llr_clip};
-    VarArgs va{code->d_var_ptr, code->d_var_edge, c, lam, Lp, act, uns, ctx->status_dev,
-               iters_out, ok_out, E, n, ngroups, (n + kVarsPerTile - 1) / kVarsPerTile, 0,
-               p->early_exit};
-    const int grid_c = grid_for(ctx, kc, static_cast<int64_t>(ngroups) * ca.ntiles);
-    const void *kv = reinterpret_cast<const void *>(&k_variable<T>);
-    const int grid_v = grid_for(ctx, kv, static_cast<int64_t>(ngroups) * va.ntiles);
+    const CheckFn<T> kc = p->algo == MBP_ALGO_NMS ? check_kernel<T, kNMS>(dmax) : check_kernel<T, kSPA>(dmax);
+    Dims dc{E, n, M, ngroups, (M + kRowsPerTile - 1) / kRowsPerTile, 0, 0, p->alpha, p->llr_clip};
+    Dims dv{E, n, M, ngroups, (n + kVarsPerTile - 1) / kVarsPerTile, 0, p->early_exit, p->alpha,
+            p->llr_clip};
+    const int grid_c = grid_for(ctx, reinterpret_cast<const void *>(kc),
+                                static_cast<int64_t>(ngroups) * dc.ntiles);
+    const int grid_v = grid_for(ctx, reinterpret_cast<const void *>(&k_variable<T>),
+                                static_cast<int64_t>(ngroups) * dv.ntiles);
 
     if (ctx->poll_events.size() < 2) {
         for (size_t k = ctx->poll_events.size(); k < 2; ++k) {
@@ -615,17 +688,18 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
         }
     }
 
-    void *cargs[] = {&ca};
     int32_t last = 0;
     for (int32_t t = 1; t <= p->max_iter; ++t) {
-        ca.t = t;
-        va.t = t;
+        dc.t = t;
+        dv.t = t;
         // the stopping test of iteration t-1 rides on check pass t (t >= 2)
-        ca.want_syn = (p->early_exit && t > 1) ? 1 : 0;
-        hipError_t lerr = hipSuccess;
-        LAUNCH_OR_FAIL(kCheckNode, lerr = hipLaunchKernel(kc, dim3(grid_c), dim3(kBlock), cargs, 0, stream));
-        if (lerr != hipSuccess) return hip_fail(lerr, "hipLaunchKernel(check)");
-        LAUNCH_OR_FAIL(kVarNode, k_variable<T><<<grid_v, kBlock, 0, stream>>>(va));
+        dc.flag = (p->early_exit && t > 1) ? 1 : 0;
+        const int pt = t & 1, nt = (t + 1) & 1;
+        LAUNCH_OR_FAIL(kCheckNode, kc<<<grid_c, kBlock, 0, stream>>>(
+                                       code->d_row_ptr, code->d_col, zb, act, Lp, c, uns, dc));
+        LAUNCH_OR_FAIL(kVarNode, k_variable<T><<<grid_v, kBlock, 0, stream>>>(
+                                     code->d_var_ptr, code->d_var_edge, c, lam, Lp, act + pt, uns + pt,
+                                     act + nt, uns + nt, ctx->status_dev, iters_out, ok_out, dv));
         last = t;
         if (p->early_exit) {
             if ((err = hipEventRecord(ctx->poll_events[t & 1], stream)) != hipSuccess)
@@ -643,11 +717,12 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
         }
     }
     // stopping test of the last iteration's decisions for frames still running
-    ca.t = last + 1;
-    ca.want_syn = 1;
-    LAUNCH_OR_FAIL(kSyndrome, k_syndrome<T><<<grid_for(ctx, reinterpret_cast<const void *>(&k_syndrome<T>),
-                                                        static_cast<int64_t>(ngroups) * ca.ntiles),
-                                              kBlock, 0, stream>>>(ca));
+    dc.t = last + 1;
+    dc.flag = 1;
+    LAUNCH_OR_FAIL(kSyndrome,
+                   k_syndrome<T><<<grid_for(ctx, reinterpret_cast<const void *>(&k_syndrome<T>),
+                                            static_cast<int64_t>(ngroups) * dc.ntiles),
+                                   kBlock, 0, stream>>>(code->d_row_ptr, code->d_col, zb, act, Lp, uns, dc));
     LAUNCH_OR_FAIL(kStaging, k_finalize<<<(F + 255) / 256, 256, 0, stream>>>(act, uns, iters_out, ok_out, F,
                                                                             last + 1, last));
     LAUNCH_OR_FAIL(kStaging, k_output<T><<<tgrid, kBlock, 0, stream>>>(Lp, bits_out, static_cast<T *>(llr_out),

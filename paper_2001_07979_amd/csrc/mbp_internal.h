@@ -15,6 +15,10 @@ namespace mbp {
 // Frames per interleaved group: one frame per lane of a 64-wide wavefront.
 constexpr int kLanes = 64;
 
+// Extra zero entries after the device edge-index arrays, so kernels can read
+// indices in fixed blocks (up to the largest check degree, 64) past the end.
+constexpr int kIndexPad = 64;
+
 // Per-kernel timing totals (see mbp_profile_get).
 enum KernelId { kCheckNode = 0, kVarNode = 1, kSyndrome = 2, kStaging = 3, kNumKernels = 4 };
 
