@@ -136,6 +136,7 @@ int mbp_llr_from_bits(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y
  * decisions meet every syndrome, and bits_out / llr_out are that
  * iteration's. Work is enqueued on `stream`; the call polls the device for
  * convergence, so it returns once the whole decode has completed.
+ * nframes may be 0 (nothing happens) and at most 65535 * 64.
  * Errors: EINVAL (bad parameters, sizes or null pointers), ENOMEM (the
  * workspace of 4 ceil(nframes/64) 64 (E + 2n) sizeof(dtype) bytes and
  * more could not be allocated), EDEVICE. */

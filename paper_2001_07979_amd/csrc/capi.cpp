@@ -226,6 +226,8 @@ int mbp_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     if (p->algo == MBP_ALGO_NMS && (!std::isfinite(p->alpha) || p->alpha <= 0.0))
         return fail(MBP_EINVAL, "mbp_decode: alpha must be finite and > 0");
     if (nframes < 0) return fail(MBP_EINVAL, "mbp_decode: nframes < 0");
+    if (nframes > 65535 * mbp::kLanes)
+        return fail(MBP_EINVAL, "mbp_decode: at most 65535 * 64 frames per call");
     if (nframes == 0) return MBP_OK;
     if (!llr || !synd || !bits_out || !iters_out || !ok_out)
         return fail(MBP_EINVAL, "mbp_decode: null buffer");

@@ -492,16 +492,27 @@ __global__ __launch_bounds__(kBlock) void k_output(const T *Lp, uint8_t *bits, T
     }
 }
 
-// Channel LLR (1 - 2y) ln((1 - e)/e), computed in FP64.
+// Channel LLR (1 - 2y) ln((1 - e)/e), computed in FP64. Block (x, f) covers
+// kLlrPerBlock consecutive bits of frame f; each thread takes the logarithm
+// once and converts kLlrPerThread bits.
+constexpr int kLlrPerThread = 8;
+constexpr int kLlrPerBlock = kBlock * kLlrPerThread;
+
 template <typename T>
-__global__ void k_llr(const uint8_t *y, const double *e, T *out, int32_t nframes, int32_t n) {
-    const size_t total = static_cast<size_t>(nframes) * n;
-    for (size_t idx = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
-         idx += static_cast<size_t>(gridDim.x) * blockDim.x) {
-        const size_t f = idx / static_cast<size_t>(n);
-        const double ef = e[f];
-        const double lam = log((1.0 - ef) / ef);
-        out[idx] = static_cast<T>(y[idx] ? -lam : lam);
+__global__ __launch_bounds__(kBlock) void k_llr(const uint8_t *__restrict__ y,
+                                                const double *__restrict__ e, T *__restrict__ out,
+                                                int32_t n) {
+    const size_t f = blockIdx.y;
+    const double ef = e[f];
+    const double lam = log((1.0 - ef) / ef);
+    const T pos = static_cast<T>(lam), neg = static_cast<T>(-lam);
+    const int i0 = blockIdx.x * kLlrPerBlock + threadIdx.x;
+    const uint8_t *yf = y + f * n;
+    T *of = out + f * n;
+#pragma unroll
+    for (int k = 0; k < kLlrPerThread; ++k) {
+        const int i = i0 + k * kBlock;
+        if (i < n) of[i] = yf[i] ? neg : pos;
     }
 }
 
@@ -751,12 +762,17 @@ int llr_impl(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y, const d
              int32_t dtype, void *llr_out, hipStream_t stream) {
     hipError_t err = hipSetDevice(ctx->device);
     if (err != hipSuccess) return hip_fail(err, "hipSetDevice");
-    const size_t total = static_cast<size_t>(nframes) * n;
-    const int grid = static_cast<int>(std::min<size_t>((total + 255) / 256, 65536));
-    if (dtype == MBP_F32)
-        k_llr<float><<<grid, 256, 0, stream>>>(y, e, static_cast<float *>(llr_out), nframes, n);
-    else
-        k_llr<double><<<grid, 256, 0, stream>>>(y, e, static_cast<double *>(llr_out), nframes, n);
+    constexpr int32_t kMaxGridY = 65535;
+    for (int32_t f0 = 0; f0 < nframes; f0 += kMaxGridY) {
+        const int32_t nf = std::min(kMaxGridY, nframes - f0);
+        const dim3 grid((n + kLlrPerBlock - 1) / kLlrPerBlock, nf);
+        const size_t off = static_cast<size_t>(f0) * n;
+        if (dtype == MBP_F32)
+            k_llr<float><<<grid, kBlock, 0, stream>>>(y + off, e + f0, static_cast<float *>(llr_out) + off, n);
+        else
+            k_llr<double><<<grid, kBlock, 0, stream>>>(y + off, e + f0, static_cast<double *>(llr_out) + off,
+                                                       n);
+    }
     err = hipGetLastError();
     if (err != hipSuccess) return hip_fail(err, "k_llr launch");
     return MBP_OK;
