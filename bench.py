@@ -65,6 +65,186 @@ def host_threads() -> int:
     return max(1, min(n, 16))
 
 
+def h2(p):
+    p = np.asarray(p, dtype=np.float64)
+    return -p * np.log2(p) - (1 - p) * np.log2(1 - p)
+
+
+def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float):
+    """The heterogeneous queue (n, rate, u and p per frame) decoded three ways
+    on the same device-resident inputs: the captured persistent batched
+    decode, one plain decode call per frame in arrival order, and one plain
+    call per code.  All three must give identical outputs.  Then a Poisson
+    arrival trace at `arrival_load` x the batched offline frame rate is served
+    by the batched decode (everything that has arrived, per launch) and by the
+    per-frame plain decode, and the latency from arrival to results on the
+    host is recorded per frame."""
+    import torch
+    from paper_2001_07979_amd import mbp
+    from paper_2001_07979_amd.inputs import workloads as W
+
+    dev = torch.device("cuda", 0)
+    queue = W.mixed_queue(nframes, seed=4)
+    log(f"bench: building the {nframes}-frame queue")
+    groups = W.queue_frames(queue, seed=4)
+    cells = list(groups)
+    pool = {}
+    for cell in cells:
+        code, idx, fr = groups[cell]
+        dc = mbp.Code.from_inputs(ctx, code)
+        y = torch.from_numpy(fr.y).to(dev)
+        e = torch.from_numpy(fr.p).to(dev)
+        lam = mbp.llr_from_bits(ctx, y, e, dtype="f32")
+        z = torch.from_numpy(fr.z).to(dev)
+        pool[cell] = dict(code=code, dc=dc, idx=idx, fr=fr, lam=lam, z=z)
+    torch.cuda.synchronize()
+    total_bits = sum(int(len(P["idx"])) * P["code"].n for P in pool.values())
+    items = [(pool[c]["dc"], pool[c]["lam"], pool[c]["z"]) for c in cells]
+    T = 100
+
+    log("bench: autotuning the batched decode")
+    tune = mbp.autotune(ctx, items, max_iter=T)
+    outs_b = [mbp.batch_outputs(dc, lam) for dc, lam, _ in items]
+    plan = mbp.Plan(ctx, items, outs_b, max_iter=T, tuning=tune)
+    plan.launch()
+    plan.wait()
+    torch.cuda.synchronize()
+    log(f"bench: batched offline x{reps}")
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.launch()
+    plan.wait()
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / reps
+    res_b = [{k: v.cpu() for k, v in o.items()} for o in outs_b]
+
+    # plain, one call per code (frames of a code grouped 64 to a wave)
+    outs_g = [mbp.batch_outputs(dc, lam) for dc, lam, _ in items]
+    for (dc, lam, z), o in zip(items, outs_g):  # warm
+        mbp.decode(ctx, dc, lam, z, algo="nms", max_iter=T, out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (dc, lam, z), o in zip(items, outs_g):
+        mbp.decode(ctx, dc, lam, z, algo="nms", max_iter=T, out=o)
+    torch.cuda.synchronize()
+    t_grouped = time.perf_counter() - t0
+
+    # plain, one call per frame in arrival order
+    where = {}
+    for k, c in enumerate(cells):
+        for j, i in enumerate(pool[c]["idx"]):
+            where[int(i)] = (k, j)
+    outs_p = [mbp.batch_outputs(dc, lam) for dc, lam, _ in items]
+
+    def plain_one(i):
+        k, j = where[i]
+        dc, lam, z = items[k]
+        o = {key: v[j:j + 1] for key, v in outs_p[k].items()}
+        mbp.decode(ctx, dc, lam[j:j + 1], z[j:j + 1], algo="nms", max_iter=T, out=o)
+
+    log("bench: plain per-frame offline")
+    plain_one(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(nframes):
+        plain_one(i)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+
+    identical = True
+    for rb, og, op in zip(res_b, outs_g, outs_p):
+        for key in ("bits", "iters", "ok", "llr"):
+            for other in (og, op):
+                identical &= bool(torch.equal(rb[key], other[key].cpu()))
+
+    # frame quality per cell: FER, and efficiency f of each frame
+    fer_cells, qual_bits, ok_frames, err_frames = {}, 0, 0, 0
+    for (c, P), rb in zip(pool.items(), res_b):
+        x = torch.from_numpy(P["fr"].x)
+        wrong = (rb["bits"] != x).any(dim=1).numpy()
+        n, u = P["code"].n, c[2]
+        m = P["code"].m[0]
+        f = m / (n * h2(P["fr"].p))
+        qual = f <= 1.1
+        nq = int(qual.sum())
+        fer_q = float(wrong[qual].mean()) if nq else None
+        fer_cells[f"n{n}-r{c[1]}-u{u}"] = {"frames": int(len(wrong)), "fer": round(float(wrong.mean()), 4),
+                                           "f<=1.1": nq, "fer_f<=1.1": fer_q}
+        if nq and fer_q <= 1e-2:
+            qual_bits += int((qual & ~wrong).sum()) * n
+        err_frames += int(wrong.sum())
+        ok_frames += int(rb["ok"].sum())
+
+    # online: Poisson arrivals at arrival_load x the batched offline frame rate
+    rate_fps = arrival_load * nframes / t_batched
+    arrivals = np.array([q.arrival_s for q in W.mixed_queue(nframes, seed=4, rate_fps=rate_fps)])
+    cell_of = np.array([cells.index(q.cell) for q in queue])
+
+    def serve_batched():
+        done = np.zeros(nframes)
+        start = time.perf_counter()
+        nxt = 0
+        while nxt < nframes:
+            while time.perf_counter() - start < arrivals[nxt]:
+                pass
+            now = time.perf_counter() - start
+            hi = int(np.searchsorted(arrivals, now, side="right"))
+            its, outs = [], []
+            for k in range(len(cells)):
+                sel = np.nonzero(cell_of[nxt:hi] == k)[0]
+                if len(sel) == 0:
+                    continue
+                j0 = where[nxt + int(sel[0])][1]
+                j1 = j0 + len(sel)
+                dc, lam, z = items[k]
+                its.append((dc, lam[j0:j1], z[j0:j1]))
+                outs.append({key: v[j0:j1] for key, v in outs_b[k].items()})
+            mbp.decode_batched(ctx, its, max_iter=T, tuning=tune, outs=outs)
+            torch.cuda.synchronize()
+            done[nxt:hi] = time.perf_counter() - start
+            nxt = hi
+        return done - arrivals
+
+    def serve_plain():
+        done = np.zeros(nframes)
+        start = time.perf_counter()
+        for i in range(nframes):
+            while time.perf_counter() - start < arrivals[i]:
+                pass
+            plain_one(i)
+            torch.cuda.synchronize()
+            done[i] = time.perf_counter() - start
+        return done - arrivals
+
+    log(f"bench: online batched ({rate_fps:.0f} frames/s Poisson)")
+    lat_b = serve_batched()
+    log("bench: online plain per-frame")
+    lat_p = serve_plain()
+    plan.close()
+
+    def pct(a):
+        return {"p50_ms": round(float(np.percentile(a, 50)) * 1e3, 3),
+                "p99_ms": round(float(np.percentile(a, 99)) * 1e3, 3)}
+
+    return {
+        "workload": f"mixed queue, {nframes} frames: n in {list(W.MIXED_N)}, rate in "
+                    f"{list(W.MIXED_RATES)}, u in [2, 3], p log-uniform [0.01, 0.08]; NMS FP32 "
+                    f"alpha 0.75, T={T}, early exit",
+        "frames": nframes, "bits": total_bits, "tuning": tune,
+        "batched_mbps": round(total_bits / t_batched / 1e6, 1),
+        "plain_per_frame_mbps": round(total_bits / t_plain / 1e6, 1),
+        "plain_per_code_mbps": round(total_bits / t_grouped / 1e6, 1),
+        "speedup_vs_plain_per_frame": round(t_plain / t_batched, 2),
+        "speedup_vs_plain_per_code": round(t_grouped / t_batched, 2),
+        "identical_outputs": identical,
+        "decoder_successes": ok_frames, "frame_errors": err_frames,
+        "qualifying_mbps": round(qual_bits / t_batched / 1e6, 1),
+        "cells": fer_cells,
+        "online": {"arrival_fps": round(rate_fps, 1), "load": arrival_load,
+                   "batched_latency": pct(lat_b), "plain_per_frame_latency": pct(lat_p)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +255,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-launch HIP events (no roofline)")
+    ap.add_argument("--queue-frames", type=int, default=2048,
+                    help="frames of the heterogeneous queue for batched vs plain (0 skips it)")
+    ap.add_argument("--queue-reps", type=int, default=5)
+    ap.add_argument("--arrival-load", type=float, default=0.7,
+                    help="Poisson arrival rate as a fraction of the batched offline frame rate")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, copy a buffer of this size once (calibrates "
                          "rocprofv3 byte counters against a transfer of known size)")
@@ -190,6 +375,10 @@ def main():
                "sample": f"first {sample} of the {F} frames, FP64 {wl.algo}, {threads} threads, "
                          f"{c1 - c0:.1f} s"}
 
+    batched = None
+    if args.queue_frames:
+        batched = batched_vs_plain(ctx, args.queue_frames, args.queue_reps, args.arrival_load)
+
     rec = {
         "metric": "reconciled Mbps at FER<=1e-2, f<=1.1; % HBM peak; batched vs plain",
         "value": round(mbps, 1), "unit": "Mbps", "n_gpus": 1, "steps": args.steps,
@@ -201,7 +390,7 @@ def main():
         "fer": fer, "decoder_failures": int((ok == 0).sum()),
         "avg_iters": float(iters.mean()), "max_iters": int(iters.max()),
         "f": round(m / (n * h), 4), "f_leak": round(code.u * m / (n * h), 4),
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "batched_vs_plain": batched,
     }
     print(json.dumps(rec), flush=True)
 

@@ -138,11 +138,112 @@ int mbp_llr_from_bits(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y
  * convergence, so it returns once the whole decode has completed.
  * nframes may be 0 (nothing happens) and at most 65535 * 64.
  * Errors: EINVAL (bad parameters, sizes or null pointers), ENOMEM (the
- * workspace of 4 ceil(nframes/64) 64 (E + 2n) sizeof(dtype) bytes and
- * more could not be allocated), EDEVICE. */
+ * context's workspace, about 64 ceil(nframes/64) (E + 2n) sizeof(dtype) +
+ * 8 ceil(nframes/64) M bytes, could not be allocated), EDEVICE. */
 int mbp_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,
                const void *llr, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
                uint8_t *ok_out, void *llr_out, void *stream);
+
+/* Unrolled normalized min-sum with a hand-written adjoint (for training the
+ * min-sum weights, or any gradient through the decoder). The forward runs K
+ * flooding iterations of the min-sum check rule of mbp_decode with no
+ * stopping test and weight alpha[t][l] for the checks of matrix l at
+ * iteration t, and returns L^K (eq. (2) after K iterations). The backward
+ * returns dJ/dllr and dJ/dalpha for a given dJ/dL^K: the exact reverse of the
+ * forward, with subgradients sgn' = 0, the derivative of a minimum going to
+ * the smallest other edge (lowest edge position among equal values), and the
+ * clip passing sgn(q) where |q| < C and 0 otherwise.
+ * Only the states of every ckpt_every-th iteration are kept; the backward
+ * recomputes the others segment by segment, so the result does not depend on
+ * ckpt_every. FP32 throughout; results are deterministic.
+ *   nframes, K     frames (>= 1, <= 65535 * 64) and iterations (1..1000)
+ *   ckpt_every     1..K
+ *   llr_clip       C, finite and > 0
+ *   llr            device [nframes][n] f32
+ *   synd           device [nframes][M] syndrome bytes (as mbp_decode)
+ *   alpha          device [K][u] f32 weights
+ *   llr_out        device [nframes][n] f32: L^K
+ *   grad_out       device [nframes][n] f32: dJ/dL^K
+ *   grad_llr       device [nframes][n] f32: dJ/dllr
+ *   grad_alpha     device [K][u] f32: dJ/dalpha, summed over frames
+ *   workspace      device, at least mbp_unrolled_workspace_bytes(...) bytes,
+ *                  owned by the caller; the backward must get the workspace
+ *                  the forward filled, unchanged, with the same inputs.
+ * Both calls only enqueue work on `stream`.
+ * Errors: EINVAL (sizes, pointers, K, ckpt_every, clip), EDEVICE. */
+int mbp_unrolled_workspace_bytes(const mbp_code *code, int32_t nframes, int32_t K,
+                                 int32_t ckpt_every, uint64_t *bytes);
+int mbp_nms_unrolled_fwd(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, int32_t K,
+                         int32_t ckpt_every, double llr_clip, const float *llr, const uint8_t *synd,
+                         const float *alpha, float *llr_out, void *workspace,
+                         uint64_t workspace_bytes, void *stream);
+int mbp_nms_unrolled_bwd(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, int32_t K,
+                         int32_t ckpt_every, double llr_clip, const float *llr, const uint8_t *synd,
+                         const float *alpha, const float *grad_out, float *grad_llr,
+                         float *grad_alpha, void *workspace, uint64_t workspace_bytes,
+                         void *stream);
+
+/* Batched persistent decode of frames of several codes at once.
+ *
+ * Each mbp_batch is one uploaded code and its frames (the same buffers as
+ * mbp_decode: llr and llr_out f32, device memory, borrowed). All batches are
+ * decoded by one persistent kernel that runs every iteration itself (a grid
+ * barrier between the check and variable passes, early exit when every frame
+ * has stopped), so the whole decode is one launch plus staging and output
+ * kernels, and can be captured into a hipGraph (mbp_plan_*). The results equal
+ * mbp_decode's bit for bit for the same parameters. Normalized min-sum in FP32
+ * only (p->algo = MBP_ALGO_NMS, p->dtype = MBP_F32; EUNSUPPORTED otherwise).
+ *
+ * mbp_tuning: work-item shape and schedule of the persistent kernel.
+ *   rows_per_wave, vars_per_wave  checks / variables per wave per work item
+ *                                 (1..64; 4 waves per item)
+ *   blocks_per_cu                 resident blocks per compute unit (1..4)
+ *   schedule                      0: item = block + k * grid (interleaved);
+ *                                 1: each block takes a contiguous run
+ * mbp_autotune times a set of tunings on the given batches (their outputs are
+ * overwritten) and returns the fastest; with cache_path it first looks the
+ * batch mix up in that text file and appends new results to it. */
+typedef struct {
+    const mbp_code *code;
+    int32_t nframes;     /* 1 .. 65535 * 64 */
+    const float *llr;    /* device [nframes][n] */
+    const uint8_t *synd; /* device [nframes][M] */
+    uint8_t *bits_out;   /* device [nframes][n] */
+    int32_t *iters_out;  /* device [nframes] */
+    uint8_t *ok_out;     /* device [nframes] */
+    float *llr_out;      /* device [nframes][n], or NULL */
+} mbp_batch;
+
+typedef struct {
+    int32_t rows_per_wave;
+    int32_t vars_per_wave;
+    int32_t blocks_per_cu;
+    int32_t schedule;
+} mbp_tuning;
+
+typedef struct mbp_plan mbp_plan;
+
+int mbp_tuning_default(mbp_tuning *out);
+
+/* Decode all batches (tuning may be NULL for the default). Uses the
+ * context's workspace; returns when the decode has completed.
+ * Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE (also if a grid barrier timed
+ * out, which only happens if blocks could not all be resident). */
+int mbp_decode_batched(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches,
+                       const mbp_params *p, const mbp_tuning *tuning, void *stream);
+
+/* A captured hipGraph of the same decode for fixed batches: the plan owns its
+ * workspace; each launch re-reads the batches' input buffers and rewrites
+ * their outputs. mbp_plan_launch only enqueues; mbp_plan_wait synchronizes
+ * the stream and reports a barrier timeout of the last launch as EDEVICE. */
+int mbp_plan_create(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches, const mbp_params *p,
+                    const mbp_tuning *tuning, mbp_plan **out);
+int mbp_plan_launch(mbp_plan *plan, void *stream);
+int mbp_plan_wait(mbp_plan *plan, void *stream);
+void mbp_plan_destroy(mbp_plan *plan);
+
+int mbp_autotune(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches, const mbp_params *p,
+                 const char *cache_path, mbp_tuning *out);
 
 /* Kernel timing. When enabled, every decode brackets each launch of its
  * check-node and variable-node kernels with HIP events on the decode's

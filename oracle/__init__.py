@@ -130,14 +130,19 @@ def decode(code, llr: np.ndarray, synd: np.ndarray, algo: int = SPA, max_iter: i
 
 def decode_nms_f32(code, llr: np.ndarray, synd: np.ndarray, max_iter: int = 50,
                    early_exit: bool = True, alpha: float = 0.75, clip: float = 20.0,
-                   nthreads: int = 0) -> dict:
+                   alpha_tl: Optional[np.ndarray] = None, nthreads: int = 0) -> dict:
     """Normalized min-sum decode with every operation in binary32 (see the C source)."""
     llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float64)
     synd = np.ascontiguousarray(np.atleast_2d(synd), dtype=np.uint8)
     F, n = llr.shape
     assert n == code.n and synd.shape[0] == F
     cs, keep = _pack(code)
-    P = _Params(NMS, int(max_iter), int(bool(early_exit)), float(alpha), float(clip), None, 1e-3)
+    atl = None
+    if alpha_tl is not None:
+        atl = np.ascontiguousarray(alpha_tl, dtype=np.float64)
+        assert atl.shape == (max_iter, len(code.row_ptr))
+    P = _Params(NMS, int(max_iter), int(bool(early_exit)), float(alpha), float(clip),
+                atl.ctypes.data if atl is not None else None, 1e-3)
     bits = np.zeros((F, n), dtype=np.uint8)
     iters = np.zeros(F, dtype=np.int32)
     ok = np.zeros(F, dtype=np.uint8)

@@ -26,7 +26,7 @@ HIP_FLAGS = [
     "-I", os.path.join(ROOT, "include"),
 ]
 
-HIP_SOURCES = ["csrc/capi.cpp", "csrc/decode.hip"]
+HIP_SOURCES = ["csrc/capi.cpp", "csrc/decode.hip", "csrc/unrolled.hip", "csrc/batched.hip"]
 
 
 def _run(cmd, cwd=None):

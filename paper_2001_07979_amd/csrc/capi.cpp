@@ -1,9 +1,13 @@
 // C-ABI entry points of the MBP decoder: argument validation, error
 // reporting, contexts and the device edge layouts of uploaded codes.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -96,13 +100,15 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
     if (M >= (int64_t(1) << 31) || E >= (int64_t(1) << 31))
         return fail(MBP_EINVAL, "mbp_code_create: stacked graph too large (M, E < 2^31)");
 
-    std::vector<int32_t> h_row_ptr(M + 1), h_col(E), var_cnt(n + 1, 0);
+    std::vector<int32_t> h_row_ptr(M + 1), h_row_mat(M), h_col(E), var_cnt(n + 1, 0), h_mat_off(u + 1, 0);
+    for (int32_t l = 0; l < u; ++l) h_mat_off[l + 1] = h_mat_off[l] + m[l];
     int32_t maxcd = 0;
     int64_t r = 0, e = 0;
     for (int32_t l = 0; l < u; ++l) {
         const int32_t *rp = row_ptr[l], *ci = col_idx[l];
         for (int32_t j = 0; j < m[l]; ++j, ++r) {
             h_row_ptr[r] = (int32_t)e;
+            h_row_mat[r] = l;
             int32_t prev = -1;
             for (int32_t k = rp[j]; k < rp[j + 1]; ++k) {
                 int32_t v = ci[k];
@@ -141,6 +147,8 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
     code->max_var_deg = maxvd;
     auto cleanup = [&](int rc) {
         (void)hipFree(code->d_row_ptr);
+        (void)hipFree(code->d_row_mat);
+        (void)hipFree(code->d_mat_off);
         (void)hipFree(code->d_col);
         (void)hipFree(code->d_var_ptr);
         (void)hipFree(code->d_var_edge);
@@ -150,6 +158,8 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
     hipError_t he;
     if ((he = hipSetDevice(ctx->device)) != hipSuccess) return cleanup(hip_fail(he, "hipSetDevice"));
     if ((he = hipMalloc(&code->d_row_ptr, sizeof(int32_t) * (M + 1))) != hipSuccess ||
+        (he = hipMalloc(&code->d_row_mat, sizeof(int32_t) * M)) != hipSuccess ||
+        (he = hipMalloc(&code->d_mat_off, sizeof(int32_t) * (u + 1))) != hipSuccess ||
         (he = hipMalloc(&code->d_col, sizeof(int32_t) * (E + mbp::kIndexPad))) != hipSuccess ||
         (he = hipMalloc(&code->d_var_ptr, sizeof(int32_t) * (n + 1))) != hipSuccess ||
         (he = hipMalloc(&code->d_var_edge, sizeof(int32_t) * (E + mbp::kIndexPad))) != hipSuccess)
@@ -159,6 +169,10 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
     h_col.resize(E + mbp::kIndexPad, 0);
     h_var_edge.resize(E + mbp::kIndexPad, 0);
     if ((he = hipMemcpy(code->d_row_ptr, h_row_ptr.data(), sizeof(int32_t) * (M + 1),
+                        hipMemcpyHostToDevice)) != hipSuccess ||
+        (he = hipMemcpy(code->d_row_mat, h_row_mat.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (he = hipMemcpy(code->d_mat_off, h_mat_off.data(), sizeof(int32_t) * (u + 1),
                         hipMemcpyHostToDevice)) != hipSuccess ||
         (he = hipMemcpy(code->d_col, h_col.data(), sizeof(int32_t) * (E + mbp::kIndexPad),
                         hipMemcpyHostToDevice)) != hipSuccess ||
@@ -177,6 +191,8 @@ void mbp_code_destroy(mbp_code *code) {
     (void)hipSetDevice(code->ctx->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(code->d_row_ptr);
+    (void)hipFree(code->d_row_mat);
+    (void)hipFree(code->d_mat_off);
     (void)hipFree(code->d_col);
     (void)hipFree(code->d_var_ptr);
     (void)hipFree(code->d_var_edge);
@@ -233,6 +249,230 @@ int mbp_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
         return fail(MBP_EINVAL, "mbp_decode: null buffer");
     return mbp::decode_impl(ctx, code, p, nframes, llr, synd, bits_out, iters_out, ok_out, llr_out,
                             (hipStream_t)stream);
+}
+
+static int check_unrolled(const char *fn, const mbp_code *code, int32_t nframes, int32_t K,
+                          int32_t ckpt) {
+    if (!code) return fail(MBP_EINVAL, std::string(fn) + ": code is NULL");
+    if (nframes < 1 || nframes > 65535 * mbp::kLanes)
+        return fail(MBP_EINVAL, std::string(fn) + ": nframes must be in [1, 65535 * 64]");
+    if (K < 1 || K > 1000) return fail(MBP_EINVAL, std::string(fn) + ": K must be in [1, 1000]");
+    if (ckpt < 1 || ckpt > K) return fail(MBP_EINVAL, std::string(fn) + ": ckpt_every must be in [1, K]");
+    return MBP_OK;
+}
+
+int mbp_unrolled_workspace_bytes(const mbp_code *code, int32_t nframes, int32_t K,
+                                 int32_t ckpt_every, uint64_t *bytes) {
+    int rc = check_unrolled("mbp_unrolled_workspace_bytes", code, nframes, K, ckpt_every);
+    if (rc != MBP_OK) return rc;
+    if (!bytes) return fail(MBP_EINVAL, "mbp_unrolled_workspace_bytes: bytes is NULL");
+    *bytes = mbp::unrolled_workspace_bytes(code, nframes, K, ckpt_every);
+    return MBP_OK;
+}
+
+static int check_unrolled_call(const char *fn, mbp_ctx *ctx, const mbp_code *code, int32_t nframes,
+                               int32_t K, int32_t ckpt, double clip, void *ws, uint64_t ws_bytes) {
+    if (!ctx) return fail(MBP_EINVAL, std::string(fn) + ": ctx is NULL");
+    int rc = check_unrolled(fn, code, nframes, K, ckpt);
+    if (rc != MBP_OK) return rc;
+    if (code->ctx != ctx) return fail(MBP_EINVAL, std::string(fn) + ": code belongs to another context");
+    if (!std::isfinite(clip) || clip <= 0.0)
+        return fail(MBP_EINVAL, std::string(fn) + ": llr_clip must be finite and > 0");
+    if (!ws || ws_bytes < mbp::unrolled_workspace_bytes(code, nframes, K, ckpt))
+        return fail(MBP_EINVAL, std::string(fn) + ": workspace missing or smaller than "
+                                                  "mbp_unrolled_workspace_bytes");
+    return MBP_OK;
+}
+
+int mbp_nms_unrolled_fwd(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, int32_t K,
+                         int32_t ckpt_every, double llr_clip, const float *llr, const uint8_t *synd,
+                         const float *alpha, float *llr_out, void *workspace,
+                         uint64_t workspace_bytes, void *stream) {
+    int rc = check_unrolled_call("mbp_nms_unrolled_fwd", ctx, code, nframes, K, ckpt_every, llr_clip,
+                                 workspace, workspace_bytes);
+    if (rc != MBP_OK) return rc;
+    if (!llr || !synd || !alpha || !llr_out) return fail(MBP_EINVAL, "mbp_nms_unrolled_fwd: null buffer");
+    return mbp::unrolled_forward(ctx, code, nframes, K, ckpt_every, llr_clip, llr, synd, alpha, llr_out,
+                                 workspace, (hipStream_t)stream);
+}
+
+int mbp_nms_unrolled_bwd(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, int32_t K,
+                         int32_t ckpt_every, double llr_clip, const float *llr, const uint8_t *synd,
+                         const float *alpha, const float *grad_out, float *grad_llr,
+                         float *grad_alpha, void *workspace, uint64_t workspace_bytes,
+                         void *stream) {
+    int rc = check_unrolled_call("mbp_nms_unrolled_bwd", ctx, code, nframes, K, ckpt_every, llr_clip,
+                                 workspace, workspace_bytes);
+    if (rc != MBP_OK) return rc;
+    if (!llr || !synd || !alpha || !grad_out || !grad_llr || !grad_alpha)
+        return fail(MBP_EINVAL, "mbp_nms_unrolled_bwd: null buffer");
+    return mbp::unrolled_backward(ctx, code, nframes, K, ckpt_every, llr_clip, llr, synd, alpha, grad_out,
+                                  grad_llr, grad_alpha, workspace, (hipStream_t)stream);
+}
+
+int mbp_tuning_default(mbp_tuning *out) {
+    if (!out) return fail(MBP_EINVAL, "mbp_tuning_default: out is NULL");
+    *out = mbp::default_tuning();
+    return MBP_OK;
+}
+
+static int check_batches(const char *fn, mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_params *p,
+                         const mbp_tuning *tu) {
+    const std::string f(fn);
+    if (!ctx || !p) return fail(MBP_EINVAL, f + ": null ctx or params");
+    if (nb < 1 || !b) return fail(MBP_EINVAL, f + ": need at least one batch");
+    if (p->algo != MBP_ALGO_NMS || p->dtype != MBP_F32)
+        return fail(MBP_EUNSUPPORTED, f + ": the batched decode runs normalized min-sum in FP32 only");
+    if (p->max_iter < 1 || p->max_iter > 10000) return fail(MBP_EINVAL, f + ": max_iter must be in [1, 10000]");
+    if (p->early_exit != 0 && p->early_exit != 1) return fail(MBP_EINVAL, f + ": early_exit must be 0 or 1");
+    if (!std::isfinite(p->llr_clip) || p->llr_clip <= 0.0)
+        return fail(MBP_EINVAL, f + ": llr_clip must be finite and > 0");
+    if (!std::isfinite(p->alpha) || p->alpha <= 0.0) return fail(MBP_EINVAL, f + ": alpha must be finite and > 0");
+    int64_t groups = 0;
+    for (int32_t i = 0; i < nb; ++i) {
+        const mbp_batch &x = b[i];
+        if (!x.code || x.code->ctx != ctx) return fail(MBP_EINVAL, f + ": batch code missing or of another context");
+        if (x.nframes < 1 || x.nframes > 65535 * mbp::kLanes)
+            return fail(MBP_EINVAL, f + ": batch nframes must be in [1, 65535 * 64]");
+        if (!x.llr || !x.synd || !x.bits_out || !x.iters_out || !x.ok_out)
+            return fail(MBP_EINVAL, f + ": null batch buffer");
+        groups += (x.nframes + mbp::kLanes - 1) / mbp::kLanes;
+    }
+    if (groups > (1 << 24)) return fail(MBP_EINVAL, f + ": too many frame groups");
+    if (tu) return mbp::check_tuning(*tu);
+    return MBP_OK;
+}
+
+int mbp_decode_batched(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches, const mbp_params *p,
+                       const mbp_tuning *tuning, void *stream) {
+    int rc = check_batches("mbp_decode_batched", ctx, nbatches, batches, p, tuning);
+    if (rc != MBP_OK) return rc;
+    return mbp::batched_decode(ctx, nbatches, batches, p, tuning ? *tuning : mbp::default_tuning(),
+                               (hipStream_t)stream);
+}
+
+int mbp_plan_create(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches, const mbp_params *p,
+                    const mbp_tuning *tuning, mbp_plan **out) {
+    if (!out) return fail(MBP_EINVAL, "mbp_plan_create: out is NULL");
+    *out = nullptr;
+    int rc = check_batches("mbp_plan_create", ctx, nbatches, batches, p, tuning);
+    if (rc != MBP_OK) return rc;
+    const mbp_tuning tu = tuning ? *tuning : mbp::default_tuning();
+    mbp_plan *plan = new (std::nothrow) mbp_plan();
+    if (!plan) return fail(MBP_ENOMEM, "mbp_plan_create: out of host memory");
+    plan->ctx = ctx;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = hipMalloc(&plan->ws, mbp::batched_workspace_bytes(nbatches, batches, tu));
+    if (e != hipSuccess) {
+        delete plan;
+        return hip_fail(e, "mbp_plan_create: workspace");
+    }
+    rc = mbp::batched_plan_capture(ctx, nbatches, batches, p, tu, plan->ws, &plan->exec, &plan->err_dev);
+    if (rc != MBP_OK) {
+        (void)hipFree(plan->ws);
+        delete plan;
+        return rc;
+    }
+    *out = plan;
+    return MBP_OK;
+}
+
+int mbp_plan_launch(mbp_plan *plan, void *stream) {
+    if (!plan) return fail(MBP_EINVAL, "mbp_plan_launch: plan is NULL");
+    hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    return e == hipSuccess ? MBP_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+int mbp_plan_wait(mbp_plan *plan, void *stream) {
+    if (!plan) return fail(MBP_EINVAL, "mbp_plan_wait: plan is NULL");
+    int32_t flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, plan->err_dev, sizeof(flag), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mbp_plan_wait");
+    if (flag) return fail(MBP_EDEVICE, "mbp_plan_wait: a grid barrier timed out");
+    return MBP_OK;
+}
+
+void mbp_plan_destroy(mbp_plan *plan) {
+    if (!plan) return;
+    (void)hipSetDevice(plan->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    (void)hipFree(plan->ws);
+    delete plan;
+}
+
+// Text cache of autotuned settings: one line per batch mix,
+// "<key> <rows_per_wave> <vars_per_wave> <blocks_per_cu> <schedule> <ms>".
+static std::string tune_key(int32_t nb, const mbp_batch *b, const mbp_params *p) {
+    std::ostringstream k;
+    k << "T" << p->max_iter << "e" << p->early_exit;
+    for (int32_t i = 0; i < nb; ++i)
+        k << "|n" << b[i].code->n << "M" << b[i].code->M << "E" << b[i].code->E << "u" << b[i].code->u << "f"
+          << b[i].nframes;
+    return k.str();
+}
+
+int mbp_autotune(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches, const mbp_params *p,
+                 const char *cache_path, mbp_tuning *out) {
+    if (!out) return fail(MBP_EINVAL, "mbp_autotune: out is NULL");
+    int rc = check_batches("mbp_autotune", ctx, nbatches, batches, p, nullptr);
+    if (rc != MBP_OK) return rc;
+    const std::string key = tune_key(nbatches, batches, p);
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string k;
+            mbp_tuning t{};
+            double ms = 0;
+            if ((ls >> k >> t.rows_per_wave >> t.vars_per_wave >> t.blocks_per_cu >> t.schedule >> ms) &&
+                k == key && mbp::check_tuning(t) == MBP_OK) {
+                *out = t;
+                return MBP_OK;
+            }
+        }
+    }
+    auto time_one = [&](const mbp_tuning &t, double *ms) {
+        int r = mbp::batched_decode(ctx, nbatches, batches, p, t, nullptr);  // warm
+        if (r != MBP_OK) return r;
+        const auto t0 = std::chrono::steady_clock::now();
+        r = mbp::batched_decode(ctx, nbatches, batches, p, t, nullptr);
+        *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return r;
+    };
+    mbp_tuning best = mbp::default_tuning();
+    double best_ms = 0;
+    if ((rc = time_one(best, &best_ms)) != MBP_OK) return rc;
+    // coordinate descent over each knob, twice
+    const int rows[] = {1, 2, 4, 8}, vars[] = {1, 2, 4, 8}, bpcs[] = {1, 2, 3, 4}, scheds[] = {0, 1};
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int knob = 0; knob < 4; ++knob) {
+            const int *vals = knob == 0 ? rows : knob == 1 ? vars : knob == 2 ? bpcs : scheds;
+            const int nv = knob == 0 ? 4 : knob == 1 ? 4 : knob == 2 ? 4 : 2;
+            for (int i = 0; i < nv; ++i) {
+                mbp_tuning t = best;
+                int *field = knob == 0 ? &t.rows_per_wave : knob == 1 ? &t.vars_per_wave
+                                                          : knob == 2 ? &t.blocks_per_cu : &t.schedule;
+                if (*field == vals[i]) continue;
+                *field = vals[i];
+                double ms = 0;
+                if ((rc = time_one(t, &ms)) != MBP_OK) return rc;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
+            }
+        }
+    }
+    *out = best;
+    if (cache_path) {
+        std::ofstream o(cache_path, std::ios::app);
+        o << key << " " << best.rows_per_wave << " " << best.vars_per_wave << " " << best.blocks_per_cu << " "
+          << best.schedule << " " << best_ms << "\n";
+    }
+    return MBP_OK;
 }
 
 int mbp_profile_enable(mbp_ctx *ctx, int32_t enable) {

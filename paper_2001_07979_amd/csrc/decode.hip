@@ -1,628 +1,15 @@
-// HIP kernels (gfx950) and the host-side iteration driver of the
-// multi-matrix syndrome BP decoder.
-//
-// Layout in HBM. Frames are processed in groups of 64, one frame per lane of
-// a wavefront, so every lane of a wave works on the same check or variable
-// of the shared code and all graph indices are wave-uniform scalar loads.
-// Per group g (all arrays frame-interleaved, 64 consecutive elements per
-// graph node or edge):
-//   c   [g][E][64]  check-to-variable messages, edges in check-major order
-//   Lp  [g][n][64]  soft decisions L of eq. (2) (posterior LLRs)
-//   lam [g][n][64]  channel LLRs
-//   zb  [g][M]      syndrome bits, bit k = frame g*64+k
-// A variable-to-check message is never stored: it is rebuilt as L - c from
-// the previous iteration's L and c when the check pass reads them.
-//
-// One iteration t (flooding schedule over the stacked graph):
-//   check pass     for every check of every matrix: q = L^{t-1} - c^{t-1} on
-//                  each edge, c^t from the check rule of Sec. 3B eq. (6) (or
-//                  normalized min-sum); it also XORs the decisions of L^{t-1}
-//                  over the check, which is the stopping test of iteration
-//                  t-1, and ORs unmet checks into a per-group lane mask;
-//   variable pass  L^t = lambda + sum of c^t over the variable's edges in
-//                  (matrix, check) order, eq. (2); frames whose test at t-1
-//                  passed keep L^{t-1} and are retired with iters = t-1.
-// After the last iteration a syndrome-only pass tests L^T.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cmath>
-#include <mutex>
-#include <unordered_map>
-#include <vector>
-
-#include "mbp_internal.h"
+// Host-side iteration driver of the plain multi-matrix syndrome BP decode
+// (mbp_decode) and the channel-LLR entry (mbp_llr_from_bits). The kernels are
+// in mbp_kernels.h.
+#include "mbp_kernels.h"
 
 namespace mbp {
 namespace {
 
-constexpr int G = kLanes;
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
-constexpr int kRowsPerWave = 4;
-constexpr int kRowsPerTile = kRowsPerWave * kWaves;
-constexpr int kVarsPerWave = 4;
-constexpr int kVarsPerTile = kVarsPerWave * kWaves;
-constexpr int kIdxChunk = 8;  // edge indices read per scalar batch
-
-__device__ __forceinline__ unsigned lane_id() { return threadIdx.x & 63u; }
-__device__ __forceinline__ int wave_id() {
-    return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-}
-
-// phi(x) = -ln tanh(x/2) = 2 atanh(e^-x) for x >= 0; phi is its own inverse,
-// so 2 atanh(prod tanh(a_k/2)) = phi(sum phi(a_k)) for magnitudes a_k >= 0.
-// Evaluated with the hardware exp2 / log2 / reciprocal and short polynomials
-// (about 4e-7 relative error over [0, 80]):
-//   v = e^-x, with -x log2(e) split into a rounded part and its residual;
-//   x >= ln 4:  2 atanh(v) = 2v (1 + v^2/3 + v^4/5 + ... + v^12/13), v <= 1/4;
-//   x <  ln 4:  ln((2 - w)/w) with w = 1 - e^-x (Taylor series below 0.35,
-//               where 1 - v would cancel).
-// phi(0) = +inf, and phi(x) = 0 for x >= 80 (true value below 4e-35).
-__device__ __forceinline__ float phi(float x) {
-    constexpr float kL2E = 1.44269504088896340736f;
-    constexpr float kL2ELo = 1.925963033500011e-08f;  // log2(e) - kL2E
-    constexpr float kLn2 = 0.693147180559945309f;
-    constexpr float kLn4 = 1.38629436111989061883f;
-    const float y = -x * kL2E;
-    const float ylo = fmaf(-x, kL2E, -y) + (-x) * kL2ELo;
-    float v = __builtin_amdgcn_exp2f(y);
-    v = fmaf(v, ylo * kLn2, v);
-    const float s = v * v;
-    float p = fmaf(s, 1.0f / 13.0f, 1.0f / 11.0f);
-    p = fmaf(s, p, 1.0f / 9.0f);
-    p = fmaf(s, p, 1.0f / 7.0f);
-    p = fmaf(s, p, 1.0f / 5.0f);
-    p = fmaf(s, p, 1.0f / 3.0f);
-    p = fmaf(s, p, 1.0f);
-    float res = 2.0f * v * p;
-    if (__ballot(x < kLn4)) {
-        float q = fmaf(x, -1.0f / 40320.0f, 1.0f / 5040.0f);
-        q = fmaf(x, q, -1.0f / 720.0f);
-        q = fmaf(x, q, 1.0f / 120.0f);
-        q = fmaf(x, q, -1.0f / 24.0f);
-        q = fmaf(x, q, 1.0f / 6.0f);
-        q = fmaf(x, q, -0.5f);
-        q = fmaf(x, q, 1.0f);
-        const float w = x < 0.35f ? x * q : 1.0f - v;
-        const float r = (2.0f - w) * __builtin_amdgcn_rcpf(w);
-        const float b = __builtin_amdgcn_logf(r) * kLn2;
-        res = x < kLn4 ? b : res;
-    }
-    return x < 80.0f ? res : 0.0f;
-}
-
-enum { kNMS = MBP_ALGO_NMS, kSPA = MBP_ALGO_SPA };
-
-// Per-group status words (running mask and unmet-check mask, by iteration
-// parity) sit kStride words apart, one 256-byte line per group.
-constexpr int kStride = 32;
-
-// OR lanes with an unmet check into a group's mask. A coherent read first
-// skips the atomic when those lanes are already marked, which is the common
-// case: the mask saturates after a few tiles in early iterations and stays
-// near empty late, so few atomics reach the shared word.
-__device__ __forceinline__ void or_unmet(uint64_t *word, uint64_t bits) {
-    if (!bits) return;
-    const uint64_t cur = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (bits & ~cur)
-        atomicOr(reinterpret_cast<unsigned long long *>(word), static_cast<unsigned long long>(bits));
-}
-
-// Scalars shared by the iteration kernels.
-struct Dims {
-    int64_t E;
-    int32_t n, M, ngroups, ntiles;
-    int32_t t;     // iteration (1-based); the syndrome-only pass uses last + 1
-    int32_t flag;  // check pass: test the incoming decisions; variable pass: early exit
-    double alpha, clip;
-};
-
-// Check-node pass, iteration t. Each wave handles kRowsPerWave checks of one
-// group. The check's edge indices are read up front as scalars (the column
-// array is padded by 64 entries so a full DMAX block is always in bounds),
-// then all gathers of the check are issued before any is consumed; the
-// messages stay in registers (q[j]) between the gather and the write.
-template <typename T, int ALGO, int DMAX>
-__global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ row_ptr,
-                                                  const int32_t *__restrict__ col,
-                                                  const uint64_t *__restrict__ zb,
-                                                  const uint64_t *__restrict__ act,
-                                                  const T *__restrict__ Lp, T *__restrict__ c,
-                                                  uint64_t *__restrict__ uns, const Dims a) {
-    __shared__ uint64_t sh_bad[kWaves];
-    const unsigned lane = lane_id();
-    const int wave = wave_id();
-    const T alpha = static_cast<T>(a.alpha), clip = static_cast<T>(a.clip);
-    const int pt = a.t & 1;
-    const bool first = a.t == 1;
-    const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
-    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-        const int g = static_cast<int>(w / a.ntiles);
-        const int tile = static_cast<int>(w % a.ntiles);
-        const uint64_t gact = act[kStride * g + pt];
-        if (gact == 0) continue;  // whole group retired (uniform over the block)
-        const bool on = (gact >> lane) & 1;
-        // wave-uniform bases; every access below is base[lane], so addresses
-        // are a scalar base plus one per-lane offset
-        const T *Lg = Lp + static_cast<size_t>(g) * a.n * G;
-        const uint64_t *zg = zb + static_cast<size_t>(g) * a.M;
-        uint64_t bad = 0;
-        for (int k = 0; k < kRowsPerWave; ++k) {
-            const int r = tile * kRowsPerTile + k * kWaves + wave;
-            if (r >= a.M) break;
-            const int e0 = row_ptr[r];
-            const int d = row_ptr[r + 1] - e0;
-            const int zbit = static_cast<int>((zg[r] >> lane) & 1);
-            T *cg = c + (static_cast<size_t>(g) * a.E + e0) * G;
-            int v[DMAX];
-#pragma unroll
-            for (int j = 0; j < DMAX; ++j) v[j] = col[e0 + j];
-            int par = 0;
-            if (on) {
-                // issue every gather of the check before using any of them
-                T q[DMAX], co[DMAX];
-#pragma unroll
-                for (int j = 0; j < DMAX; ++j) {
-                    if (j < d) {
-                        q[j] = (Lg + static_cast<size_t>(v[j]) * G)[lane];
-                        co[j] = first ? T(0) : (cg + j * G)[lane];
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < DMAX; ++j) {
-                    if (j < d) {
-                        par ^= (q[j] < T(0)) ? 1 : 0;
-                        q[j] -= co[j];
-                    }
-                }
-                uint64_t neg = 0;
-                int sx = zbit;  // syndrome sign times every message sign
-                if constexpr (ALGO == kNMS) {
-                    T m1 = T(INFINITY), m2 = T(INFINITY);
-                    int i1 = 0;
-#pragma unroll
-                    for (int j = 0; j < DMAX; ++j) {
-                        if (j < d) {
-                            const int s = q[j] < T(0) ? 1 : 0;
-                            sx ^= s;
-                            neg |= static_cast<uint64_t>(s) << j;
-                            T aj = fabs(q[j]);
-                            aj = aj < clip ? aj : clip;
-                            if (aj < m1) {
-                                m2 = m1;
-                                m1 = aj;
-                                i1 = j;
-                            } else if (aj < m2) {
-                                m2 = aj;
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int j = 0; j < DMAX; ++j) {
-                        if (j < d) {
-                            const T mag = alpha * (j == i1 ? m2 : m1);
-                            const int s = sx ^ static_cast<int>((neg >> j) & 1);
-                            (cg + j * G)[lane] = s ? -mag : mag;
-                        }
-                    }
-                } else if constexpr (sizeof(T) == 4) {
-                    // sum-product, FP32: phi domain with prefix/suffix exclusion
-                    T f[DMAX];
-#pragma unroll
-                    for (int j = 0; j < DMAX; ++j) {
-                        if (j < d) {
-                            const int s = q[j] < T(0) ? 1 : 0;
-                            sx ^= s;
-                            neg |= static_cast<uint64_t>(s) << j;
-                            T aj = fabs(q[j]);
-                            aj = aj < clip ? aj : clip;
-                            f[j] = phi(aj);
-                        }
-                    }
-                    T run = T(0);
-#pragma unroll
-                    for (int j = 0; j < DMAX; ++j) {
-                        if (j < d) {
-                            q[j] = run;  // sum of phi over edges before j
-                            run += f[j];
-                        }
-                    }
-                    T suf = T(0);
-#pragma unroll
-                    for (int j = DMAX - 1; j >= 0; --j) {
-                        if (j < d) {
-                            const T mag = phi(q[j] + suf);
-                            suf += f[j];
-                            const int s = sx ^ static_cast<int>((neg >> j) & 1);
-                            (cg + j * G)[lane] = s ? -mag : mag;
-                        }
-                    }
-                } else {
-                    // sum-product, FP64: tanh domain with prefix/suffix products
-                    T th[DMAX];
-#pragma unroll
-                    for (int j = 0; j < DMAX; ++j) {
-                        if (j < d) {
-                            const int s = q[j] < T(0) ? 1 : 0;
-                            sx ^= s;
-                            neg |= static_cast<uint64_t>(s) << j;
-                            T aj = fabs(q[j]);
-                            aj = aj < clip ? aj : clip;
-                            th[j] = tanh(aj * T(0.5));
-                        }
-                    }
-                    T run = T(1);
-#pragma unroll
-                    for (int j = 0; j < DMAX; ++j) {
-                        if (j < d) {
-                            q[j] = run;  // product of tanh over edges before j
-                            run *= th[j];
-                        }
-                    }
-                    T suf = T(1);
-#pragma unroll
-                    for (int j = DMAX - 1; j >= 0; --j) {
-                        if (j < d) {
-                            const T mag = T(2) * atanh(q[j] * suf);
-                            suf *= th[j];
-                            const int s = sx ^ static_cast<int>((neg >> j) & 1);
-                            (cg + j * G)[lane] = s ? -mag : mag;
-                        }
-                    }
-                }
-            }
-            bad |= __ballot(on && (par != zbit));
-        }
-        if (a.flag) {
-            if (lane == 0) sh_bad[wave] = bad;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                uint64_t b = 0;
-                for (int i = 0; i < kWaves; ++i) b |= sh_bad[i];
-                or_unmet(&uns[kStride * g + pt], b);
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// Syndrome-only pass: the stopping test of the decisions held in Lp.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_syndrome(const int32_t *__restrict__ row_ptr,
-                                                     const int32_t *__restrict__ col,
-                                                     const uint64_t *__restrict__ zb,
-                                                     const uint64_t *__restrict__ act,
-                                                     const T *__restrict__ Lp,
-                                                     uint64_t *__restrict__ uns, const Dims a) {
-    __shared__ uint64_t sh_bad[kWaves];
-    const unsigned lane = lane_id();
-    const int wave = wave_id();
-    const int pt = a.t & 1;
-    const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
-    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-        const int g = static_cast<int>(w / a.ntiles);
-        const int tile = static_cast<int>(w % a.ntiles);
-        const uint64_t gact = act[kStride * g + pt];
-        if (gact == 0) continue;
-        const bool on = (gact >> lane) & 1;
-        const T *Lg = Lp + static_cast<size_t>(g) * a.n * G;
-        const uint64_t *zg = zb + static_cast<size_t>(g) * a.M;
-        uint64_t bad = 0;
-        for (int k = 0; k < kRowsPerWave; ++k) {
-            const int r = tile * kRowsPerTile + k * kWaves + wave;
-            if (r >= a.M) break;
-            const int e0 = row_ptr[r];
-            const int d = row_ptr[r + 1] - e0;
-            const int zbit = static_cast<int>((zg[r] >> lane) & 1);
-            int par = 0;
-            for (int j0 = 0; j0 < d; j0 += kIdxChunk) {
-                int v[kIdxChunk];
-#pragma unroll
-                for (int j = 0; j < kIdxChunk; ++j) v[j] = col[e0 + j0 + j];
-                if (on) {
-#pragma unroll
-                    for (int j = 0; j < kIdxChunk; ++j)
-                        if (j0 + j < d) par ^= ((Lg + static_cast<size_t>(v[j]) * G)[lane] < T(0)) ? 1 : 0;
-                }
-            }
-            bad |= __ballot(on && (par != zbit));
-        }
-        if (lane == 0) sh_bad[wave] = bad;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint64_t b = 0;
-            for (int i = 0; i < kWaves; ++i) b |= sh_bad[i];
-            or_unmet(&uns[kStride * g + pt], b);
-        }
-        __syncthreads();
-    }
-}
-
-// Variable-node pass, eq. (2), plus the per-group bookkeeping of the
-// stopping rule. act_in / uns_in are this iteration's words, act_out /
-// uns_out the next iteration's (the same arrays at the other parity).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_variable(
-    const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_edge,
-    const T *__restrict__ c, const T *__restrict__ lam, T *__restrict__ Lp,
-    const uint64_t *__restrict__ act_in, const uint64_t *__restrict__ uns_in,
-    uint64_t *__restrict__ act_out, uint64_t *__restrict__ uns_out,
-    uint64_t *__restrict__ status, int32_t *__restrict__ iters_out, uint8_t *__restrict__ ok_out,
-    const Dims a) {
-    const unsigned lane = lane_id();
-    const int wave = wave_id();
-    const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
-    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-        const int g = static_cast<int>(w / a.ntiles);
-        const int tile = static_cast<int>(w % a.ntiles);
-        const uint64_t gact = act_in[kStride * g];
-        const uint64_t U = (a.flag && a.t > 1) ? uns_in[kStride * g] : ~0ull;
-        const uint64_t run = gact & U;
-        if (tile == 0 && wave == 0) {
-            // Frames whose decisions at t-1 met every syndrome stop here;
-            // nothing else reads these words during this pass.
-            const uint64_t conv = gact & ~U;
-            if (lane == 0) {
-                act_out[kStride * g] = run;
-                uns_out[kStride * g] = 0;
-                __hip_atomic_store(&status[g], run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            }
-            if ((conv >> lane) & 1) {
-                const int f = g * G + lane;
-                iters_out[f] = a.t - 1;
-                ok_out[f] = 1;
-            }
-        }
-        if (run == 0) continue;
-        const bool on = (run >> lane) & 1;
-        const size_t gb = static_cast<size_t>(g) * a.n * G;
-        const T *cg = c + static_cast<size_t>(g) * a.E * G;
-        for (int k = 0; k < kVarsPerWave; ++k) {
-            const int i = tile * kVarsPerTile + k * kWaves + wave;
-            if (i >= a.n) break;
-            const int k0 = var_ptr[i], k1 = var_ptr[i + 1];
-            T s = on ? (lam + gb + static_cast<size_t>(i) * G)[lane] : T(0);
-            for (int kk = k0; kk < k1; kk += kIdxChunk) {
-                int ev[kIdxChunk];
-#pragma unroll
-                for (int j = 0; j < kIdxChunk; ++j) ev[j] = var_edge[kk + j];
-                if (on) {
-                    T x[kIdxChunk];
-#pragma unroll
-                    for (int j = 0; j < kIdxChunk; ++j)
-                        if (kk + j < k1) x[j] = (cg + static_cast<size_t>(ev[j]) * G)[lane];
-#pragma unroll
-                    for (int j = 0; j < kIdxChunk; ++j)
-                        if (kk + j < k1) s += x[j];
-                }
-            }
-            if (on) (Lp + gb + static_cast<size_t>(i) * G)[lane] = s;
-        }
-    }
-}
-
-__global__ void k_init_groups(uint64_t *act, uint64_t *uns, uint64_t *status, int32_t nframes,
-                              int32_t ngroups) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ngroups) return;
-    const int rem = nframes - g * G;
-    const uint64_t valid = rem >= G ? ~0ull : ((1ull << rem) - 1ull);
-    act[kStride * g + 1] = valid;  // iteration 1 reads parity 1
-    act[kStride * g + 0] = 0;
-    uns[kStride * g + 0] = 0;
-    uns[kStride * g + 1] = 0;
-    __hip_atomic_store(&status[g], valid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
-// Frames still running after the last iteration: ok from the syndrome-only
-// pass, iterations = the last one run.
-__global__ void k_finalize(const uint64_t *act, const uint64_t *uns, int32_t *iters_out,
-                           uint8_t *ok_out, int32_t nframes, int32_t tf, int32_t last_iter) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nframes) return;
-    const int g = f / G, lane = f % G, p = tf & 1;
-    if ((act[kStride * g + p] >> lane) & 1) {
-        ok_out[f] = ((uns[kStride * g + p] >> lane) & 1) ? 0 : 1;
-        iters_out[f] = last_iter;
-    }
-}
-
-// [F][n] -> [g][n][64] for the channel LLRs (also the initial L).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_stage_llr(const T *llr, T *lam, T *Lp, int32_t nframes,
-                                                      int32_t n) {
-    __shared__ T tile[64][65];
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int g = blockIdx.y, i0 = blockIdx.x * 64;
-    for (int fy = ty; fy < 64; fy += kWaves) {
-        const int f = g * G + fy, i = i0 + tx;
-        tile[fy][tx] = (f < nframes && i < n) ? llr[static_cast<size_t>(f) * n + i] : T(0);
-    }
-    __syncthreads();
-    for (int iy = ty; iy < 64; iy += kWaves) {
-        const int i = i0 + iy;
-        if (i < n) {
-            const T v = tile[tx][iy];
-            const size_t o = (static_cast<size_t>(g) * n + i) * G + tx;
-            lam[o] = v;
-            Lp[o] = v;
-        }
-    }
-}
-
-// [F][M] syndrome bytes -> [g][M] 64-bit lane masks.
-__global__ __launch_bounds__(kBlock) void k_stage_synd(const uint8_t *z, uint64_t *zb, int32_t nframes,
-                                                       int32_t M) {
-    __shared__ uint8_t s[64][kBlock + 4];
-    const int g = blockIdx.y, r0 = blockIdx.x * kBlock;
-    for (int fy = 0; fy < 64; ++fy) {
-        const int f = g * G + fy, r = r0 + static_cast<int>(threadIdx.x);
-        s[fy][threadIdx.x] = (f < nframes && r < M) ? z[static_cast<size_t>(f) * M + r] : 0;
-    }
-    __syncthreads();
-    const int lane = lane_id(), wave = threadIdx.x >> 6;
-    for (int k = 0; k < 64; ++k) {
-        const int rr = wave * 64 + k;
-        const uint64_t mask = __ballot(s[lane][rr] != 0);
-        if (lane == 0 && r0 + rr < M) zb[static_cast<size_t>(g) * M + r0 + rr] = mask;
-    }
-}
-
-// [g][n][64] -> decided bits [F][n] and, optionally, L [F][n].
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_output(const T *Lp, uint8_t *bits, T *llr_out,
-                                                   int32_t nframes, int32_t n) {
-    __shared__ T tile[64][65];
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int g = blockIdx.y, i0 = blockIdx.x * 64;
-    for (int iy = ty; iy < 64; iy += kWaves) {
-        const int i = i0 + iy;
-        tile[iy][tx] = i < n ? Lp[(static_cast<size_t>(g) * n + i) * G + tx] : T(0);
-    }
-    __syncthreads();
-    for (int fy = ty; fy < 64; fy += kWaves) {
-        const int f = g * G + fy, i = i0 + tx;
-        if (f < nframes && i < n) {
-            const T v = tile[tx][fy];
-            const size_t o = static_cast<size_t>(f) * n + i;
-            bits[o] = v < T(0) ? 1 : 0;
-            if (llr_out) llr_out[o] = v;
-        }
-    }
-}
-
-// Channel LLR (1 - 2y) ln((1 - e)/e), computed in FP64. Block (x, f) covers
-// kLlrPerBlock consecutive bits of frame f; each thread takes the logarithm
-// once and converts kLlrPerThread bits.
-constexpr int kLlrPerThread = 8;
-constexpr int kLlrPerBlock = kBlock * kLlrPerThread;
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_llr(const uint8_t *__restrict__ y,
-                                                const double *__restrict__ e, T *__restrict__ out,
-                                                int32_t n) {
-    const size_t f = blockIdx.y;
-    const double ef = e[f];
-    const double lam = log((1.0 - ef) / ef);
-    const T pos = static_cast<T>(lam), neg = static_cast<T>(-lam);
-    const int i0 = blockIdx.x * kLlrPerBlock + threadIdx.x;
-    const uint8_t *yf = y + f * n;
-    T *of = out + f * n;
-#pragma unroll
-    for (int k = 0; k < kLlrPerThread; ++k) {
-        const int i = i0 + k * kBlock;
-        if (i < n) of[i] = yf[i] ? neg : pos;
-    }
-}
-
-// ---------------------------------------------------------------- host side
-int blocks_per_cu(const void *fn) {
-    static std::mutex mu;
-    static std::unordered_map<const void *, int> cache;
-    std::lock_guard<std::mutex> lock(mu);
-    auto it = cache.find(fn);
-    if (it != cache.end()) return it->second;
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
-    cache[fn] = nb;
-    return nb;
-}
-
-int grid_for(const mbp_ctx *ctx, const void *fn, int64_t items) {
-    const int64_t cap = static_cast<int64_t>(ctx->num_cus) * blocks_per_cu(fn);
-    return static_cast<int>(std::max<int64_t>(1, std::min(items, cap)));
-}
-
-struct Timer {
-    mbp_ctx *ctx;
-    hipStream_t stream;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
-    size_t used = 0;
-
-    hipError_t event(hipEvent_t *ev) {
-        if (used == ctx->timing_events.size()) {
-            hipEvent_t e;
-            hipError_t err = hipEventCreate(&e);
-            if (err != hipSuccess) return err;
-            ctx->timing_events.push_back(e);
-        }
-        *ev = ctx->timing_events[used++];
-        return hipSuccess;
-    }
-    template <typename F>
-    hipError_t run(int which, F &&launch) {
-        if (!ctx->profiling) {
-            launch();
-            return hipGetLastError();
-        }
-        hipEvent_t a, b;
-        hipError_t err;
-        if ((err = event(&a)) != hipSuccess || (err = event(&b)) != hipSuccess) return err;
-        if ((err = hipEventRecord(a, stream)) != hipSuccess) return err;
-        launch();
-        if ((err = hipGetLastError()) != hipSuccess) return err;
-        if ((err = hipEventRecord(b, stream)) != hipSuccess) return err;
-        marks.push_back({which, {a, b}});
-        return hipSuccess;
-    }
-    hipError_t collect() {
-        for (auto &m : marks) {
-            float ms = 0.f;
-            hipError_t err = hipEventElapsedTime(&ms, m.second.first, m.second.second);
-            if (err != hipSuccess) return err;
-            ctx->stats[m.first].launches += 1;
-            ctx->stats[m.first].total_ms += ms;
-        }
-        marks.clear();
-        return hipSuccess;
-    }
-};
-
-size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
-
-int ensure_workspace(mbp_ctx *ctx, size_t bytes) {
-    if (ctx->ws_bytes >= bytes) return MBP_OK;
-    if (ctx->ws) {
-        hipError_t e = hipFree(ctx->ws);
-        ctx->ws = nullptr;
-        ctx->ws_bytes = 0;
-        if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
-    }
-    hipError_t e = hipMalloc(&ctx->ws, bytes);
-    if (e != hipSuccess) {
-        ctx->ws = nullptr;
-        return hip_fail(e, "hipMalloc(workspace)");
-    }
-    ctx->ws_bytes = bytes;
-    return MBP_OK;
-}
-
-int ensure_status(mbp_ctx *ctx, int32_t ngroups) {
-    if (ctx->status_cap >= ngroups) return MBP_OK;
-    if (ctx->status_host) (void)hipHostFree(ctx->status_host);
-    ctx->status_host = nullptr;
-    ctx->status_dev = nullptr;
-    ctx->status_cap = 0;
-    const int32_t cap = std::max<int32_t>(ngroups, 64);
-    void *p = nullptr;
-    hipError_t e = hipHostMalloc(&p, sizeof(uint64_t) * cap, hipHostMallocMapped | hipHostMallocCoherent);
-    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(status)");
-    void *d = nullptr;
-    e = hipHostGetDevicePointer(&d, p, 0);
-    if (e != hipSuccess) {
-        (void)hipHostFree(p);
-        return hip_fail(e, "hipHostGetDevicePointer(status)");
-    }
-    ctx->status_host = static_cast<uint64_t *>(p);
-    ctx->status_dev = static_cast<uint64_t *>(d);
-    ctx->status_cap = cap;
-    return MBP_OK;
-}
-
-template <typename T>
-using CheckFn = void (*)(const int32_t *, const int32_t *, const uint64_t *, const uint64_t *,
-                         const T *, T *, uint64_t *, Dims);
+using CheckFn = void (*)(const int32_t *, const int32_t *, const int32_t *, const float *,
+                         const uint64_t *, const uint64_t *, const T *, const T *, T *, uint64_t *,
+                         Dims);
 
 template <typename T, int ALGO>
 CheckFn<T> check_kernel(int dmax) {
@@ -706,8 +93,9 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
         // the stopping test of iteration t-1 rides on check pass t (t >= 2)
         dc.flag = (p->early_exit && t > 1) ? 1 : 0;
         const int pt = t & 1, nt = (t + 1) & 1;
-        LAUNCH_OR_FAIL(kCheckNode, kc<<<grid_c, kBlock, 0, stream>>>(
-                                       code->d_row_ptr, code->d_col, zb, act, Lp, c, uns, dc));
+        LAUNCH_OR_FAIL(kCheckNode, kc<<<grid_c, kBlock, 0, stream>>>(code->d_row_ptr, code->d_col,
+                                                                     code->d_row_mat, nullptr, zb, act,
+                                                                     Lp, c, c, uns, dc));
         LAUNCH_OR_FAIL(kVarNode, k_variable<T><<<grid_v, kBlock, 0, stream>>>(
                                      code->d_var_ptr, code->d_var_edge, c, lam, Lp, act + pt, uns + pt,
                                      act + nt, uns + nt, ctx->status_dev, iters_out, ok_out, dv));
@@ -749,6 +137,7 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
 int decode_impl(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,
                 const void *llr, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
                 uint8_t *ok_out, void *llr_out, hipStream_t stream) {
+    (void)hipGetLastError();  // errors of earlier, unrelated calls are not ours
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if (p->dtype == MBP_F32)
@@ -760,6 +149,7 @@ int decode_impl(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t
 
 int llr_impl(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y, const double *e,
              int32_t dtype, void *llr_out, hipStream_t stream) {
+    (void)hipGetLastError();  // errors of earlier, unrelated calls are not ours
     hipError_t err = hipSetDevice(ctx->device);
     if (err != hipSuccess) return hip_fail(err, "hipSetDevice");
     constexpr int32_t kMaxGridY = 65535;

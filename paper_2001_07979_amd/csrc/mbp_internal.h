@@ -16,8 +16,8 @@ namespace mbp {
 constexpr int kLanes = 64;
 
 // Extra zero entries after the device edge-index arrays, so kernels can read
-// indices in fixed blocks (up to the largest check degree, 64) past the end.
-constexpr int kIndexPad = 64;
+// indices in fixed blocks (up to 64 + 32 entries) past the end.
+constexpr int kIndexPad = 128;
 
 // Per-kernel timing totals (see mbp_profile_get).
 enum KernelId { kCheckNode = 0, kVarNode = 1, kSyndrome = 2, kStaging = 3, kNumKernels = 4 };
@@ -52,6 +52,13 @@ struct mbp_ctx {
     int32_t live_codes = 0;
 };
 
+struct mbp_plan {
+    mbp_ctx *ctx = nullptr;
+    void *ws = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t *err_dev = nullptr;
+};
+
 struct mbp_code {
     mbp_ctx *ctx = nullptr;
     int32_t n = 0, u = 0, M = 0;
@@ -62,6 +69,8 @@ struct mbp_code {
     // edges in check-major order (matrix, row, column); for each variable its
     // edges in the same order.
     int32_t *d_row_ptr = nullptr;   // [M + 1]
+    int32_t *d_row_mat = nullptr;   // [M] matrix of each stacked check
+    int32_t *d_mat_off = nullptr;   // [u + 1] first stacked check of each matrix
     int32_t *d_col = nullptr;       // [E]
     int32_t *d_var_ptr = nullptr;   // [n + 1]
     int32_t *d_var_edge = nullptr;  // [E]
@@ -75,5 +84,24 @@ int decode_impl(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t
                 uint8_t *ok_out, void *llr_out, hipStream_t stream);
 int llr_impl(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y, const double *e,
              int32_t dtype, void *llr_out, hipStream_t stream);
+
+// Batched persistent decode (batched.hip).
+mbp_tuning default_tuning();
+int check_tuning(const mbp_tuning &tu);
+uint64_t batched_workspace_bytes(int32_t nb, const mbp_batch *b, const mbp_tuning &tu);
+int batched_decode(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_params *p, const mbp_tuning &tu,
+                   hipStream_t stream);
+int batched_plan_capture(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_params *p, const mbp_tuning &tu,
+                         void *ws, hipGraphExec_t *exec, int32_t **err_dev);
+
+// Unrolled normalized min-sum (unrolled.hip).
+uint64_t unrolled_workspace_bytes(const mbp_code *code, int32_t nframes, int32_t K, int32_t ckpt);
+int unrolled_forward(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, int32_t K, int32_t ckpt,
+                     double clip, const float *llr, const uint8_t *synd, const float *alpha,
+                     float *llr_out, void *ws, hipStream_t stream);
+int unrolled_backward(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, int32_t K, int32_t ckpt,
+                      double clip, const float *llr, const uint8_t *synd, const float *alpha,
+                      const float *grad_out, float *grad_llr, float *grad_alpha, void *ws,
+                      hipStream_t stream);
 
 }  // namespace mbp

@@ -183,13 +183,13 @@ def syndromes(code: Code, x: np.ndarray) -> np.ndarray:
     x = np.atleast_2d(np.asarray(x, dtype=np.uint8))
     out = []
     for rp, ci in zip(code.row_ptr, code.col_idx):
-        g = x[:, ci]
         starts = rp[:-1]
         nonempty = rp[1:] > starts
         s = np.zeros((x.shape[0], rp.size - 1), dtype=np.uint8)
-        if g.shape[1]:
-            red = np.bitwise_xor.reduceat(g, np.minimum(starts, g.shape[1] - 1), axis=1)
-            s[:, nonempty] = red[:, nonempty]
+        if ci.size:
+            at = np.minimum(starts, ci.size - 1)
+            for f in range(x.shape[0]):  # one row at a time: contiguous gathers
+                s[f, nonempty] = np.bitwise_xor.reduceat(x[f].take(ci), at)[nonempty]
         out.append(s)
     return np.concatenate(out, axis=1)
 

@@ -82,3 +82,55 @@ def unrolled_n16384(nframes: int = 512) -> Workload:
     p = np.random.default_rng(5).uniform(0.04, 0.08, size=nframes)
     return Workload("mbp-nms-unrolled-k20-n16384-u2", code, nframes, p, 5, "nms", "f32", 20,
                     early_exit=False)
+
+
+MIXED_N = (16384, 65536, 262144)
+MIXED_RATES = (0.5, 0.7, 0.85)
+
+
+def mixed_code(n: int, rate: float, u: int) -> Code:
+    """Code of one cell of the mixed queue: the first u of three {2,3,10} PEG
+    matrices of that (n, rate), so u=2 and u=3 frames share matrices."""
+    m = int(round((1.0 - rate) * n))
+    depth = 2 if n <= 16384 else 1
+    full = peg_code(n, m, 3, IRREGULAR_2310, seed_base=4000 + 10 * MIXED_N.index(n)
+                    + MIXED_RATES.index(rate) * 100, max_depth=depth,
+                    name=f"peg-n{n}-r{rate}-u3-d2310")
+    return Code(n=n, row_ptr=full.row_ptr[:u], col_idx=full.col_idx[:u],
+                name=f"peg-n{n}-r{rate}-u{u}-d2310", meta=dict(full.meta, u=u))
+
+
+@dataclass
+class QueueFrame:
+    cell: tuple  # (n, rate, u)
+    p: float
+    arrival_s: float
+
+
+def mixed_queue(nframes: int = 2048, seed: int = 4, rate_fps: float = None):
+    """Frame list of the heterogeneous queue: n, rate and u drawn uniformly,
+    BSC p log-uniform in [0.01, 0.08], Poisson arrivals (rate_fps frames per
+    second; None puts every arrival at t = 0)."""
+    rng = np.random.default_rng(seed)
+    cells = [(n, r, u) for n in MIXED_N for r in MIXED_RATES for u in (2, 3)]
+    pick = rng.integers(0, len(cells), nframes)
+    p = np.exp(rng.uniform(np.log(0.01), np.log(0.08), nframes))
+    if rate_fps:
+        t = np.cumsum(rng.exponential(1.0 / rate_fps, nframes))
+    else:
+        t = np.zeros(nframes)
+    return [QueueFrame(cells[k], float(pp), float(tt)) for k, pp, tt in zip(pick, p, t)]
+
+
+def queue_frames(queue, seed: int = 4):
+    """The queue's frames grouped by cell, each group in arrival order:
+    {cell: (code, queue indices, Frames)}.  A cell draws its frames from
+    SeedSequence(1000 * seed + cell index)."""
+    cells = sorted({q.cell for q in queue})
+    out = {}
+    for k, cell in enumerate(cells):
+        idx = np.array([i for i, q in enumerate(queue) if q.cell == cell], dtype=np.int64)
+        code = mixed_code(*cell)
+        p = np.array([queue[i].p for i in idx])
+        out[cell] = (code, idx, bsc_frames(code, len(idx), p, 1000 * seed + k))
+    return out

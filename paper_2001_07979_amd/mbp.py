@@ -31,6 +31,21 @@ class MbpError(RuntimeError):
         self.code = code
 
 
+class mbp_batch(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_void_p), ("nframes", ctypes.c_int32),
+                ("llr", ctypes.c_void_p), ("synd", ctypes.c_void_p),
+                ("bits_out", ctypes.c_void_p), ("iters_out", ctypes.c_void_p),
+                ("ok_out", ctypes.c_void_p), ("llr_out", ctypes.c_void_p)]
+
+
+class mbp_tuning(ctypes.Structure):
+    _fields_ = [("rows_per_wave", ctypes.c_int32), ("vars_per_wave", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class mbp_params(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("early_exit", ctypes.c_int32),
@@ -55,6 +70,25 @@ def lib():
             "mbp_code_info": (ctypes.c_int, [vp] + [vp] * 6),
             "mbp_llr_from_bits": (ctypes.c_int, [vp, i32, i32, vp, vp, i32, vp, vp]),
             "mbp_decode": (ctypes.c_int, [vp, vp, ctypes.POINTER(mbp_params), i32] + [vp] * 7),
+            "mbp_unrolled_workspace_bytes": (ctypes.c_int, [vp, i32, i32, i32,
+                                                             ctypes.POINTER(ctypes.c_uint64)]),
+            "mbp_nms_unrolled_fwd": (ctypes.c_int, [vp, vp, i32, i32, i32, ctypes.c_double] + [vp] * 5
+                                     + [ctypes.c_uint64, vp]),
+            "mbp_nms_unrolled_bwd": (ctypes.c_int, [vp, vp, i32, i32, i32, ctypes.c_double] + [vp] * 7
+                                     + [ctypes.c_uint64, vp]),
+            "mbp_tuning_default": (ctypes.c_int, [ctypes.POINTER(mbp_tuning)]),
+            "mbp_decode_batched": (ctypes.c_int, [vp, i32, ctypes.POINTER(mbp_batch),
+                                                  ctypes.POINTER(mbp_params),
+                                                  ctypes.POINTER(mbp_tuning), vp]),
+            "mbp_plan_create": (ctypes.c_int, [vp, i32, ctypes.POINTER(mbp_batch),
+                                               ctypes.POINTER(mbp_params), ctypes.POINTER(mbp_tuning),
+                                               ctypes.POINTER(vp)]),
+            "mbp_plan_launch": (ctypes.c_int, [vp, vp]),
+            "mbp_plan_wait": (ctypes.c_int, [vp, vp]),
+            "mbp_plan_destroy": (None, [vp]),
+            "mbp_autotune": (ctypes.c_int, [vp, i32, ctypes.POINTER(mbp_batch),
+                                            ctypes.POINTER(mbp_params), ctypes.c_char_p,
+                                            ctypes.POINTER(mbp_tuning)]),
             "mbp_profile_enable": (ctypes.c_int, [vp, i32]),
             "mbp_profile_reset": (ctypes.c_int, [vp]),
             "mbp_profile_get": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64),
@@ -225,3 +259,189 @@ def decode(ctx: Context, code: Code, llr, synd, algo: str = "spa", max_iter: int
                             _dev_ptr(out["ok"]), _dev_ptr(out.get("llr")), _stream_ptr(stream)),
            "mbp_decode")
     return out
+
+
+# ------------------------------------------------------------ unrolled min-sum
+def unrolled_workspace_bytes(code: Code, nframes: int, K: int, ckpt_every: int) -> int:
+    b = ctypes.c_uint64()
+    _check(lib().mbp_unrolled_workspace_bytes(code.handle, int(nframes), int(K), int(ckpt_every),
+                                              ctypes.byref(b)), "mbp_unrolled_workspace_bytes")
+    return int(b.value)
+
+
+def nms_unrolled_fwd(ctx: Context, code: Code, llr, synd, alpha, ckpt_every: int, clip: float,
+                     workspace, out=None, stream=None):
+    """L^K of K = alpha.shape[0] unrolled min-sum iterations (FP32, GPU tensors)."""
+    import torch
+    F = int(llr.shape[0])
+    K = int(alpha.shape[0])
+    if out is None:
+        out = torch.empty_like(llr)
+    _check(lib().mbp_nms_unrolled_fwd(ctx.handle, code.handle, F, K, int(ckpt_every), float(clip),
+                                      _dev_ptr(llr), _dev_ptr(synd), _dev_ptr(alpha), _dev_ptr(out),
+                                      _dev_ptr(workspace), int(workspace.numel()),
+                                      _stream_ptr(stream)), "mbp_nms_unrolled_fwd")
+    return out
+
+
+def nms_unrolled_bwd(ctx: Context, code: Code, llr, synd, alpha, grad_out, ckpt_every: int,
+                     clip: float, workspace, stream=None):
+    """(dJ/dllr, dJ/dalpha) of the unrolled forward for dJ/dL^K = grad_out."""
+    import torch
+    F = int(llr.shape[0])
+    K = int(alpha.shape[0])
+    grad_llr = torch.empty_like(llr)
+    grad_alpha = torch.empty_like(alpha)
+    _check(lib().mbp_nms_unrolled_bwd(ctx.handle, code.handle, F, K, int(ckpt_every), float(clip),
+                                      _dev_ptr(llr), _dev_ptr(synd), _dev_ptr(alpha),
+                                      _dev_ptr(grad_out), _dev_ptr(grad_llr), _dev_ptr(grad_alpha),
+                                      _dev_ptr(workspace), int(workspace.numel()),
+                                      _stream_ptr(stream)), "mbp_nms_unrolled_bwd")
+    return grad_llr, grad_alpha
+
+
+def _autograd_function():
+    import torch
+
+    class MbpUnrolledNMS(torch.autograd.Function):
+        """L^K = unrolled min-sum(llr, alpha[K, u]); gradients from the HIP adjoint."""
+
+        @staticmethod
+        def forward(fctx, llr, alpha, ctx, code, synd, ckpt_every, clip):
+            llr = llr.contiguous()
+            alpha = alpha.contiguous()
+            nbytes = unrolled_workspace_bytes(code, llr.shape[0], alpha.shape[0], ckpt_every)
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=llr.device)
+            out = nms_unrolled_fwd(ctx, code, llr, synd, alpha, ckpt_every, clip, ws)
+            fctx.save_for_backward(llr, alpha, synd, ws)
+            fctx.meta = (ctx, code, ckpt_every, clip)
+            return out
+
+        @staticmethod
+        def backward(fctx, grad_out):
+            llr, alpha, synd, ws = fctx.saved_tensors
+            ctx, code, ckpt_every, clip = fctx.meta
+            g_llr, g_alpha = nms_unrolled_bwd(ctx, code, llr, synd, alpha, grad_out.contiguous(),
+                                              ckpt_every, clip, ws)
+            return g_llr, g_alpha, None, None, None, None, None
+
+    return MbpUnrolledNMS
+
+
+_unrolled_fn = None
+
+
+def unrolled_nms(ctx: Context, code: Code, llr, synd, alpha, ckpt_every: int = 5,
+                 clip: float = 20.0):
+    """Differentiable unrolled min-sum: returns L^K with autograd to llr and alpha."""
+    global _unrolled_fn
+    if _unrolled_fn is None:
+        _unrolled_fn = _autograd_function()
+    return _unrolled_fn.apply(llr, alpha, ctx, code, synd, int(ckpt_every), float(clip))
+
+
+# ----------------------------------------------------------- batched decode
+def _nms_params(max_iter, early_exit, alpha, clip):
+    return mbp_params(MBP_ALGO_NMS, MBP_F32, int(max_iter), int(bool(early_exit)), float(alpha),
+                      float(clip))
+
+
+def batch_outputs(code: Code, llr, want_llr: bool = True) -> dict:
+    import torch
+    F = int(llr.shape[0])
+    dev = llr.device
+    return dict(bits=torch.empty((F, code.n), dtype=torch.uint8, device=dev),
+                iters=torch.empty(F, dtype=torch.int32, device=dev),
+                ok=torch.empty(F, dtype=torch.uint8, device=dev),
+                llr=torch.empty((F, code.n), dtype=torch.float32, device=dev) if want_llr else None)
+
+
+def _batches(items, outs):
+    arr = (mbp_batch * len(items))()
+    for k, ((code, llr, synd), o) in enumerate(zip(items, outs)):
+        if llr.dtype.is_floating_point and llr.element_size() != 4:
+            raise ValueError("the batched decode takes float32 LLRs")
+        if tuple(llr.shape) != (llr.shape[0], code.n) or tuple(synd.shape) != (llr.shape[0], code.M):
+            raise ValueError("llr must be [F, n] and synd [F, M]")
+        arr[k] = mbp_batch(code.handle.value, int(llr.shape[0]), _dev_ptr(llr), _dev_ptr(synd),
+                           _dev_ptr(o["bits"]), _dev_ptr(o["iters"]), _dev_ptr(o["ok"]),
+                           _dev_ptr(o.get("llr")))
+    return arr
+
+
+def _tuning(t):
+    if t is None:
+        return None
+    if isinstance(t, mbp_tuning):
+        return t
+    return mbp_tuning(int(t["rows_per_wave"]), int(t["vars_per_wave"]), int(t["blocks_per_cu"]),
+                      int(t["schedule"]))
+
+
+def default_tuning() -> dict:
+    t = mbp_tuning()
+    _check(lib().mbp_tuning_default(ctypes.byref(t)), "mbp_tuning_default")
+    return t.as_dict()
+
+
+def decode_batched(ctx: Context, items, max_iter: int = 100, early_exit: bool = True,
+                   alpha: float = 0.75, clip: float = 20.0, tuning=None, outs=None,
+                   want_llr: bool = True, stream=None):
+    """Decode [(Code, llr [F, n] f32, synd [F, M] u8), ...] in one persistent launch
+    (normalized min-sum, FP32). Returns one output dict per item."""
+    if outs is None:
+        outs = [batch_outputs(c, l, want_llr) for c, l, _ in items]
+    arr = _batches(items, outs)
+    p = _nms_params(max_iter, early_exit, alpha, clip)
+    tu = _tuning(tuning)
+    _check(lib().mbp_decode_batched(ctx.handle, len(items), arr, ctypes.byref(p),
+                                    ctypes.byref(tu) if tu is not None else None,
+                                    _stream_ptr(stream)), "mbp_decode_batched")
+    return outs
+
+
+def autotune(ctx: Context, items, max_iter: int = 100, early_exit: bool = True,
+             alpha: float = 0.75, clip: float = 20.0, cache_path: Optional[str] = None,
+             outs=None) -> dict:
+    if outs is None:
+        outs = [batch_outputs(c, l) for c, l, _ in items]
+    arr = _batches(items, outs)
+    p = _nms_params(max_iter, early_exit, alpha, clip)
+    t = mbp_tuning()
+    _check(lib().mbp_autotune(ctx.handle, len(items), arr, ctypes.byref(p),
+                              cache_path.encode() if cache_path else None, ctypes.byref(t)),
+           "mbp_autotune")
+    return t.as_dict()
+
+
+class Plan:
+    """A captured hipGraph of a batched decode over fixed buffers."""
+
+    def __init__(self, ctx: Context, items, outs, max_iter: int = 100, early_exit: bool = True,
+                 alpha: float = 0.75, clip: float = 20.0, tuning=None):
+        arr = _batches(items, outs)
+        p = _nms_params(max_iter, early_exit, alpha, clip)
+        tu = _tuning(tuning)
+        h = ctypes.c_void_p()
+        _check(lib().mbp_plan_create(ctx.handle, len(items), arr, ctypes.byref(p),
+                                     ctypes.byref(tu) if tu is not None else None, ctypes.byref(h)),
+               "mbp_plan_create")
+        self.handle = h
+        self.items, self.outs = items, outs
+
+    def launch(self, stream=None):
+        _check(lib().mbp_plan_launch(self.handle, _stream_ptr(stream)), "mbp_plan_launch")
+
+    def wait(self, stream=None):
+        _check(lib().mbp_plan_wait(self.handle, _stream_ptr(stream)), "mbp_plan_wait")
+
+    def close(self):
+        if self.handle:
+            lib().mbp_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,142 @@
+"""GPU tests of the batched persistent decode: frames of several codes in one
+persistent launch, as eager calls, captured graphs and autotuned settings.
+The reference is the plain decode of each batch alone (itself held to the
+oracle by test_gpu_decode.py) plus the oracle's binary32 min-sum."""
+import numpy as np
+import pytest
+
+from paper_2001_07979_amd.inputs import bsc_frames, peg_code
+from paper_2001_07979_amd.inputs import workloads as W
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2001_07979_amd import mbp
+    c = mbp.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def mix(ctx):
+    """Three codes (n, u, rate and check degree all different) with 1, 70 and
+    64 frames at mixed error rates."""
+    import torch
+    from paper_2001_07979_amd import mbp
+    codes = [peg_code(1000, 260, 2, W.IRREGULAR_238, seed_base=7100, name="peg-n1000"),
+             peg_code(640, 200, 3, {2: 0.3, 3: 0.7}, seed_base=7300, name="peg-n640-u3"),
+             peg_code(2048, 256, 2, W.IRREGULAR_2310, seed_base=7400, name="peg-n2048")]
+    nfr = [1, 70, 64]
+    items, frames = [], []
+    for k, (code, F) in enumerate(zip(codes, nfr)):
+        fr = bsc_frames(code, F, np.geomspace(0.01, 0.06, F), seed=900 + k)
+        dc = mbp.Code.from_inputs(ctx, code)
+        lam = parity.oracle_llr(fr, "f32").astype(np.float32)
+        items.append((dc, torch.from_numpy(lam).cuda(), torch.from_numpy(fr.z).cuda()))
+        frames.append((code, fr, lam))
+    return items, frames
+
+
+def _np(o):
+    return {k: (v.cpu().numpy().astype(np.float64) if k == "llr" else v.cpu().numpy())
+            for k, v in o.items() if v is not None}
+
+
+def _plain(ctx, items, T=60, early_exit=True):
+    from paper_2001_07979_amd import mbp
+    return [_np(mbp.decode(ctx, dc, llr, z, algo="nms", max_iter=T, early_exit=early_exit))
+            for dc, llr, z in items]
+
+
+def _same(a, b):
+    for k in ("bits", "iters", "ok", "llr"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_batched_equals_plain_and_binary32_oracle(ctx, mix):
+    from paper_2001_07979_amd import mbp
+    import torch
+    items, frames = mix
+    outs = mbp.decode_batched(ctx, items, max_iter=60)
+    torch.cuda.synchronize()
+    got = [_np(o) for o in outs]
+    for g, p in zip(got, _plain(ctx, items)):
+        _same(g, p)
+    for g, (code, fr, lam) in zip(got, frames):
+        ref = parity.oracle_f32_run(code, fr, 60, lam=lam.astype(np.float64))
+        parity.assert_bitwise(dict(bits=g["bits"], iters=g["iters"], ok=g["ok"], L=g["llr"]), ref)
+    # the mix holds both outcomes (the oracle decodes 84 of the 135 frames)
+    assert 60 < sum(int(g["ok"].sum()) for g in got) < sum(g["ok"].size for g in got)
+
+
+@pytest.mark.parametrize("tuning", [dict(rows_per_wave=1, vars_per_wave=8, blocks_per_cu=1, schedule=1),
+                                    dict(rows_per_wave=8, vars_per_wave=1, blocks_per_cu=3, schedule=0),
+                                    dict(rows_per_wave=2, vars_per_wave=2, blocks_per_cu=4, schedule=1)])
+def test_tunings_do_not_change_results(ctx, mix, tuning):
+    from paper_2001_07979_amd import mbp
+    items, _ = mix
+    ref = [_np(o) for o in mbp.decode_batched(ctx, items, max_iter=60)]
+    got = [_np(o) for o in mbp.decode_batched(ctx, items, max_iter=60, tuning=tuning)]
+    for a, b in zip(got, ref):
+        _same(a, b)
+
+
+def test_fixed_iterations(ctx, mix):
+    from paper_2001_07979_amd import mbp
+    items, _ = mix
+    got = [_np(o) for o in mbp.decode_batched(ctx, items, max_iter=9, early_exit=False)]
+    for g, p in zip(got, _plain(ctx, items, T=9, early_exit=False)):
+        _same(g, p)
+        assert np.all(g["iters"] == 9)
+
+
+def test_graph_plan_replays(ctx, mix):
+    """A captured plan, replayed three times with eager work in between,
+    matches the eager decode every time."""
+    import torch
+    from paper_2001_07979_amd import mbp
+    items, _ = mix
+    ref = [_np(o) for o in mbp.decode_batched(ctx, items, max_iter=60)]
+    outs = [mbp.batch_outputs(dc, llr) for dc, llr, _ in items]
+    plan = mbp.Plan(ctx, items, outs, max_iter=60)
+    for rep in range(3):
+        for o in outs:
+            for v in o.values():
+                v.zero_()
+        plan.launch()
+        plan.wait()
+        got = [_np(o) for o in outs]
+        for a, b in zip(got, ref):
+            _same(a, b)
+        _plain(ctx, items[:1])  # eager work between replays
+        torch.cuda.synchronize()
+    plan.close()
+
+
+def test_autotune_picks_a_valid_setting(ctx, mix, tmp_path):
+    from paper_2001_07979_amd import mbp
+    items, _ = mix
+    cache = str(tmp_path / "tune.txt")
+    t = mbp.autotune(ctx, items, max_iter=60, cache_path=cache)
+    assert 1 <= t["rows_per_wave"] <= 64 and t["schedule"] in (0, 1)
+    assert mbp.autotune(ctx, items, max_iter=60, cache_path=cache) == t  # cached
+    ref = [_np(o) for o in mbp.decode_batched(ctx, items, max_iter=60)]
+    got = [_np(o) for o in mbp.decode_batched(ctx, items, max_iter=60, tuning=t)]
+    for a, b in zip(got, ref):
+        _same(a, b)
+
+
+def test_batched_rejects_sum_product(ctx, mix):
+    import ctypes
+    from paper_2001_07979_amd import mbp
+    items, _ = mix
+    outs = [mbp.batch_outputs(dc, llr) for dc, llr, _ in items]
+    arr = mbp._batches(items, outs)
+    p = mbp.mbp_params(mbp.MBP_ALGO_SPA, mbp.MBP_F32, 10, 1, 0.75, 20.0)
+    rc = mbp.lib().mbp_decode_batched(ctx.handle, len(items), arr, ctypes.byref(p), None, None)
+    assert rc == mbp.MBP_EUNSUPPORTED

@@ -1,0 +1,194 @@
+"""GPU parity of the unrolled min-sum forward and its hand-written adjoint.
+
+The forward is held bit for bit to the plain decoder and to the oracle's
+binary32 min-sum; the gradients to the FP64 oracle's exact reverse-mode
+gradient, to central differences of the GPU forward, and to themselves under
+a different checkpoint spacing.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_07979_amd.inputs import bsc_frames, peg_code
+from paper_2001_07979_amd.inputs import workloads as W
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2001_07979_amd import mbp
+    c = mbp.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ragged_code():
+    return peg_code(1000, 260, 2, W.IRREGULAR_238, seed_base=7100, name="peg-n1000")
+
+
+def _tensors(fr, alpha):
+    import torch
+    lam = oracle.llr_from_bits(fr.y, fr.p).astype(np.float32)
+    return (torch.from_numpy(lam).cuda(), torch.from_numpy(fr.z).cuda(),
+            torch.from_numpy(alpha.astype(np.float32)).cuda(), lam.astype(np.float64))
+
+
+def _run(ctx, dc, llr, z, alpha, gL=None, ckpt=5, clip=20.0):
+    import torch
+    from paper_2001_07979_amd import mbp
+    K = alpha.shape[0]
+    ws = torch.empty(mbp.unrolled_workspace_bytes(dc, llr.shape[0], K, ckpt), dtype=torch.uint8,
+                     device="cuda")
+    L = mbp.nms_unrolled_fwd(ctx, dc, llr, z, alpha, ckpt, clip, ws)
+    if gL is None:
+        torch.cuda.synchronize()
+        return L.cpu().numpy().astype(np.float64)
+    g_llr, g_alpha = mbp.nms_unrolled_bwd(ctx, dc, llr, z, alpha, gL, ckpt, clip, ws)
+    torch.cuda.synchronize()
+    return (L.cpu().numpy().astype(np.float64), g_llr.cpu().numpy().astype(np.float64),
+            g_alpha.cpu().numpy().astype(np.float64))
+
+
+def test_forward_is_the_plain_decoder_and_binary32_oracle(ctx, ragged_code):
+    from paper_2001_07979_amd import mbp
+    fr = bsc_frames(ragged_code, 70, np.linspace(0.02, 0.05, 70), seed=600)
+    K = 7
+    dc = mbp.Code.from_inputs(ctx, ragged_code)
+    alpha = np.full((K, 2), 0.75)
+    llr, z, a, lam = _tensors(fr, alpha)
+    L = _run(ctx, dc, llr, z, a)
+    g = parity.gpu_run(ctx, dc, fr, "nms", "f32", K, early_exit=False)
+    assert np.array_equal(L, g["L"])
+    alpha = np.random.default_rng(2).uniform(0.5, 1.0, (K, 2)).astype(np.float32).astype(np.float64)
+    llr, z, a, lam = _tensors(fr, alpha)
+    L = _run(ctx, dc, llr, z, a)
+    ref = oracle.decode_nms_f32(ragged_code, lam, fr.z, max_iter=K, early_exit=False, alpha_tl=alpha)
+    assert np.array_equal(L, ref["L"])
+
+
+def test_gradient_matches_fp64_oracle(ctx, ragged_code):
+    from paper_2001_07979_amd import mbp
+    import torch
+    fr = bsc_frames(ragged_code, 32, np.linspace(0.03, 0.06, 32), seed=500)
+    K = 5
+    rng = np.random.default_rng(1)
+    alpha = rng.uniform(0.6, 0.9, (K, 2)).astype(np.float32).astype(np.float64)
+    dc = mbp.Code.from_inputs(ctx, ragged_code)
+    _, z, a, lam = _tensors(fr, alpha)
+    # Channel LLRs of a BSC frame all share one magnitude, so the min-sum
+    # minima are exact ties that FP32 and FP64 rounding later break apart in
+    # different ways (each side then takes a different, equally valid
+    # subgradient).  A continuous random gain on every LLR removes the ties.
+    lam = (lam * rng.uniform(0.7, 1.3, size=lam.shape)).astype(np.float32).astype(np.float64)
+    llr = torch.from_numpy(lam.astype(np.float32)).cuda()
+    w = np.random.default_rng(3).normal(size=lam.shape)  # J = sum w * L^K
+    L, g_llr, g_alpha = _run(ctx, dc, llr, z, a, gL=torch.from_numpy(w.astype(np.float32)).cuda())
+    L64, glam64, galpha64 = oracle.nms_unrolled(ragged_code, K, alpha, lam, fr.z, gL=w)
+    np.testing.assert_allclose(L, L64, rtol=1e-5, atol=1e-5)
+    err = np.abs(g_llr - glam64)
+    scale = np.sqrt(np.mean(glam64 ** 2))
+    close = err <= 1e-4 * np.abs(glam64) + 1e-4 * scale
+    assert close.mean() >= 0.995, f"{(~close).sum()} of {close.size} coordinates differ"
+    assert np.linalg.norm(g_llr - glam64) <= 2e-2 * np.linalg.norm(glam64)
+    np.testing.assert_allclose(g_alpha, galpha64, rtol=2e-2, atol=1e-3 * np.abs(galpha64).max())
+
+
+def test_checkpoint_spacing_does_not_change_gradients(ctx, ragged_code):
+    from paper_2001_07979_amd import mbp
+    import torch
+    fr = bsc_frames(ragged_code, 40, 0.05, seed=501)
+    K = 9
+    alpha = np.random.default_rng(4).uniform(0.6, 0.9, (K, 2))
+    dc = mbp.Code.from_inputs(ctx, ragged_code)
+    llr, z, a, lam = _tensors(fr, alpha)
+    gL = torch.from_numpy(np.random.default_rng(5).normal(size=lam.shape).astype(np.float32)).cuda()
+    ref = _run(ctx, dc, llr, z, a, gL=gL, ckpt=K)
+    for ck in (1, 2, 4, 5):
+        got = _run(ctx, dc, llr, z, a, gL=gL, ckpt=ck)
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y), f"ckpt_every={ck}"
+
+
+def test_gradient_matches_central_differences(ctx):
+    """Central differences of the GPU forward on a small code, where the map
+    is linear across the step (both one-sided slopes agree)."""
+    from paper_2001_07979_amd import mbp
+    import torch
+    code = peg_code(48, 24, 2, {3: 1.0}, seed_base=9100)
+    fr = bsc_frames(code, 2, 0.08, seed=41)
+    K = 5
+    rng = np.random.default_rng(1)
+    alpha = rng.uniform(0.6, 0.9, (K, 2))
+    dc = mbp.Code.from_inputs(ctx, code)
+    llr, z, a, lam = _tensors(fr, alpha)
+    lam = lam * rng.uniform(0.7, 1.3, size=lam.shape)
+    llr = torch.from_numpy(lam.astype(np.float32)).cuda()
+    lam = llr.cpu().numpy().astype(np.float64)
+    w = rng.normal(size=lam.shape)
+    _, g_llr, g_alpha = _run(ctx, dc, llr, z, a, gL=torch.from_numpy(w.astype(np.float32)).cuda())
+
+    def J_lam(x):
+        return float((_run(ctx, dc, torch.from_numpy(x.astype(np.float32)).cuda(), z, a) * w).sum())
+
+    def J_alpha(x):
+        return float((_run(ctx, dc, llr, z, torch.from_numpy(x.astype(np.float32)).cuda()) * w).sum())
+
+    eps = 1e-3
+    checked = 0
+    for i in rng.choice(lam.size, 30, replace=False):
+        xp, xm = lam.copy(), lam.copy()
+        xp.flat[i] += eps
+        xm.flat[i] -= eps
+        jp, j0, jm = J_lam(xp), J_lam(lam), J_lam(xm)
+        right, left = (jp - j0) / eps, (j0 - jm) / eps
+        if abs(right - left) <= 2e-2 * (1 + abs(right)):
+            fd = 0.5 * (right + left)
+            assert g_llr.flat[i] == pytest.approx(fd, rel=2e-2, abs=2e-2)
+            checked += 1
+    assert checked >= 15
+    checked = 0
+    for i in range(alpha.size):
+        xp, xm = alpha.copy(), alpha.copy()
+        xp.flat[i] += eps
+        xm.flat[i] -= eps
+        jp, j0, jm = J_alpha(xp), J_alpha(alpha), J_alpha(xm)
+        right, left = (jp - j0) / eps, (j0 - jm) / eps
+        if abs(right - left) <= 2e-2 * (1 + abs(right)):
+            assert g_alpha.flat[i] == pytest.approx(0.5 * (right + left), rel=2e-2, abs=5e-2)
+            checked += 1
+    assert checked >= 4
+
+
+def test_autograd_bce_training_step(ctx):
+    """K=20 unrolled min-sum on the n=16384 code as a torch autograd op: the
+    BCE loss of sigma(-L^K) against Alice's bits back-propagates through the
+    HIP adjoint into llr and alpha, and matches the FP64 oracle gradient."""
+    import torch
+    from paper_2001_07979_amd import mbp
+    wl = W.unrolled_n16384(nframes=8)
+    fr = wl.frames()
+    K = 20
+    dc = mbp.Code.from_inputs(ctx, wl.code)
+    lam = oracle.llr_from_bits(fr.y, fr.p).astype(np.float32)
+    llr = torch.from_numpy(lam).cuda().requires_grad_(True)
+    alpha = torch.full((K, 2), 0.75, device="cuda", requires_grad=True)
+    z = torch.from_numpy(fr.z).cuda()
+    x = torch.from_numpy(fr.x.astype(np.float32)).cuda()
+    L = mbp.unrolled_nms(ctx, dc, llr, z, alpha, ckpt_every=5)
+    loss = torch.nn.functional.binary_cross_entropy_with_logits(-L, x)
+    loss.backward()
+    L64 = oracle.nms_unrolled(wl.code, K, np.full((K, 2), 0.75), lam.astype(np.float64), fr.z)
+    np.testing.assert_allclose(L.detach().cpu().numpy(), L64, rtol=1e-5, atol=1e-5)
+    sig = 1.0 / (1.0 + np.exp(L64))
+    gL = -(sig - fr.x) / fr.x.size
+    _, glam64, galpha64 = oracle.nms_unrolled(wl.code, K, np.full((K, 2), 0.75),
+                                              lam.astype(np.float64), fr.z, gL=gL)
+    g = llr.grad.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(g - glam64) <= 1e-2 * np.linalg.norm(glam64) + 1e-30
+    np.testing.assert_allclose(alpha.grad.cpu().numpy(), galpha64, rtol=1e-2,
+                               atol=1e-2 * np.abs(galpha64).max() + 1e-30)
