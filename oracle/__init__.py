@@ -59,7 +59,8 @@ def lib():
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.oracle_nms_unrolled.restype = ctypes.c_int32
         L.oracle_nms_unrolled.argtypes = [ctypes.POINTER(_Code), ctypes.c_int32, ctypes.c_void_p,
-                                          ctypes.c_double, ctypes.c_int32] + [ctypes.c_void_p] * 6
+                                          ctypes.c_double, ctypes.c_int32] + [ctypes.c_void_p] * 6 \
+            + [ctypes.c_int32]
         L.oracle_default_threads.restype = ctypes.c_int32
         L.oracle_default_threads.argtypes = []
         _lib = L
@@ -170,8 +171,11 @@ def unsatisfied(code, x: np.ndarray, synd: np.ndarray) -> np.ndarray:
 
 
 def nms_unrolled(code, K: int, alpha: np.ndarray, llr: np.ndarray, synd: np.ndarray,
-                 clip: float = 20.0, gL: Optional[np.ndarray] = None):
-    """Unrolled min-sum: L^K, and with gL = dJ/dL^K also (dJ/dllr, dJ/dalpha)."""
+                 clip: float = 20.0, gL: Optional[np.ndarray] = None, binary32: bool = False):
+    """Unrolled min-sum: L^K, and with gL = dJ/dL^K also (dJ/dllr, dJ/dalpha).
+
+    binary32=True runs the forward in float arithmetic and differentiates
+    that trajectory (the reverse sweep itself stays FP64)."""
     llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float64)
     synd = np.ascontiguousarray(np.atleast_2d(synd), dtype=np.uint8)
     F, n = llr.shape
@@ -189,7 +193,8 @@ def nms_unrolled(code, K: int, alpha: np.ndarray, llr: np.ndarray, synd: np.ndar
     rc = lib().oracle_nms_unrolled(ctypes.byref(cs), int(K), alpha.ctypes.data, float(clip), F,
                                    llr.ctypes.data, synd.ctypes.data, gptr, Lout.ctypes.data,
                                    glam.ctypes.data if glam is not None else None,
-                                   galpha.ctypes.data if galpha is not None else None)
+                                   galpha.ctypes.data if galpha is not None else None,
+                                   int(bool(binary32)))
     del keep
     if rc != 0:
         raise ValueError("oracle_nms_unrolled rejected its input")

@@ -484,19 +484,56 @@ int32_t oracle_unsatisfied(const oracle_code *code, int32_t nframes, const uint8
  * subgradients: sgn has derivative 0; min passes the whole derivative to the
  * smallest of the other edges (lowest edge position among equal values);
  * the cap min(|q|, C) passes sgn(q) when |q| < C and 0 otherwise. */
+/* The forward of one iteration in binary32, with the rounding of
+   decode_frame_nms_f32; states are held as the doubles of their float values. */
+static void nms_iteration_f32(const graph *g, const double *alpha, int32_t t, double C,
+                              const double *lam,
+                              const uint8_t *z, const double *Lp, const double *cp, double *q,
+                              double *c, double *L) {
+    const int32_t n = g->n, E = g->E, M = g->M;
+    const float Cf = (float)C;
+    for (int32_t e = 0; e < E; ++e) q[e] = (double)((float)Lp[g->edge_var[e]] - (float)cp[e]);
+    for (int32_t r = 0; r < M; ++r) {
+        int32_t e0 = g->row_start[r], d = g->row_start[r + 1] - e0;
+        float zs = z[r] ? -1.0f : 1.0f;
+        float a_tl = (float)alpha[(size_t)(t - 1) * (size_t)g->u + (size_t)g->row_matrix[r]];
+        for (int32_t k = 0; k < d; ++k) {
+            float sg = 1.0f, mn = INFINITY;
+            for (int32_t kk = 0; kk < d; ++kk) {
+                if (kk == k) continue;
+                float qf = (float)q[e0 + kk];
+                sg *= qf < 0.0f ? -1.0f : 1.0f;
+                float a = fabsf(qf);
+                if (a > Cf) a = Cf;
+                if (a < mn) mn = a;
+            }
+            c[e0 + k] = (double)(zs * a_tl * sg * mn);
+        }
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        float s = (float)lam[i];
+        for (int32_t k = g->var_start[i]; k < g->var_start[i + 1]; ++k) s += (float)c[g->var_edges[k]];
+        L[i] = (double)s;
+    }
+}
+
 static void nms_unrolled_frame(const graph *g, int32_t K, const double *alpha, double C,
                                const double *lam, const uint8_t *z, const double *gL_in,
                                double *Lout, double *glam, double *galpha,
                                double *cs /* [(K+1)*E] */, double *qs /* [K*E] */,
                                double *Ls /* [(K+1)*n] */, double *gL, double *gc,
-                               double *gq) {
+                               double *gq, int f32) {
     const int32_t n = g->n, E = g->E, M = g->M, u = g->u;
     double *c0 = cs;
     for (int32_t e = 0; e < E; ++e) c0[e] = 0.0;
-    for (int32_t i = 0; i < n; ++i) Ls[i] = lam[i];
+    for (int32_t i = 0; i < n; ++i) Ls[i] = f32 ? (double)(float)lam[i] : lam[i];
     for (int32_t t = 1; t <= K; ++t) {
         const double *Lp = Ls + (size_t)(t - 1) * n, *cp = cs + (size_t)(t - 1) * E;
         double *q = qs + (size_t)(t - 1) * E, *c = cs + (size_t)t * E, *L = Ls + (size_t)t * n;
+        if (f32) {
+            nms_iteration_f32(g, alpha, t, C, lam, z, Lp, cp, q, c, L);
+            continue;
+        }
         for (int32_t e = 0; e < E; ++e) q[e] = Lp[g->edge_var[e]] - cp[e];
         for (int32_t r = 0; r < M; ++r) {
             int32_t e0 = g->row_start[r], d = g->row_start[r + 1] - e0;
@@ -564,11 +601,15 @@ static void nms_unrolled_frame(const graph *g, int32_t K, const double *alpha, d
 
 /* Unrolled min-sum forward (and, if gL is not NULL, its gradient) for
  * nframes frames. alpha is [K][u]; llr, gL, Lout, glam are [nframes][n];
- * galpha [K][u] is the sum over frames. Single-threaded. Returns 0 or -1. */
+ * galpha [K][u] is the sum over frames. With f32 = 1 the forward runs in
+ * binary32 (decode_frame_nms_f32's rounding) and the reverse sweep, still in
+ * FP64, differentiates that binary32 trajectory: it takes its minima, signs
+ * and caps from the float messages. Single-threaded.
+ * Returns 0 or -1. */
 int32_t oracle_nms_unrolled(const oracle_code *code, int32_t K, const double *alpha,
                             double clip, int32_t nframes, const double *llr,
                             const uint8_t *synd, const double *gL, double *Lout,
-                            double *glam, double *galpha) {
+                            double *glam, double *galpha, int32_t f32) {
     if (!code || K < 1 || nframes < 0) return -1;
     graph g;
     if (graph_build(code, &g)) return -1;
@@ -589,7 +630,7 @@ int32_t oracle_nms_unrolled(const oracle_code *code, int32_t K, const double *al
         for (size_t k = 0; k < (size_t)K * (size_t)g.u; ++k) gaf[k] = 0.0;
         nms_unrolled_frame(&g, K, alpha, clip, llr + f * n, synd + f * M,
                            gL ? gL + f * n : NULL, Lout + f * n, glam ? glam + f * n : glw,
-                           gaf, cs, qs, Ls, gLw, gc, gq);
+                           gaf, cs, qs, Ls, gLw, gc, gq, f32);
         if (galpha && gL)
             for (size_t k = 0; k < (size_t)K * (size_t)g.u; ++k) galpha[k] += gaf[k];
     }

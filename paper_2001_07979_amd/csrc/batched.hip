@@ -429,9 +429,11 @@ Built lay_out(int32_t nb, const mbp_batch *b, const mbp_tuning &tu) {
         BatchPlace P{};
         P.group0 = static_cast<int32_t>(B.gd.size());
         P.ngroups = (b[i].nframes + G - 1) / G;
-        const size_t sc = align_up(static_cast<size_t>(code->E) * G * sizeof(float));
-        const size_t sl = align_up(static_cast<size_t>(code->n) * G * sizeof(float));
-        const size_t sz = align_up(static_cast<size_t>(code->M) * sizeof(uint64_t));
+        // per-group strides are the ones the staging and output kernels index
+        // with (g * E * G, g * n * G, g * M); each batch's region is aligned
+        const size_t sc = static_cast<size_t>(code->E) * G * sizeof(float);
+        const size_t sl = static_cast<size_t>(code->n) * G * sizeof(float);
+        const size_t sz = static_cast<size_t>(code->M) * sizeof(uint64_t);
         P.c = take(sc * P.ngroups);
         P.Lp = take(sl * P.ngroups);
         P.lam = take(sl * P.ngroups);

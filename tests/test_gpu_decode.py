@@ -132,6 +132,26 @@ def test_n65536_full_batch_sampled(ctx, algo):
     assert okf.mean() > 0.99 and np.array_equal(g["bits"][okf], fr.x[okf])
 
 
+@pytest.mark.parametrize("rate,algo", [(0.5, "spa"), (0.7, "spa"), (0.85, "spa"), (0.85, "nms")])
+def test_n262144_u3_sampled(ctx, rate, algo):
+    """QKD-scale frames: u=3 {2,3,10} PEG matrices, n=2^18, 64 frames at one
+    of the (rate, p) points, decoded in one call; sampled frames against the
+    oracle, properties on all."""
+    wl = W.qkd_n262144(rate, algo=algo)
+    fr = wl.frames()
+    dc = upload(ctx, wl.code)
+    g = parity.gpu_run(ctx, dc, fr, algo, "f32", wl.max_iter, alpha=wl.alpha)
+    idx = np.array([0, 1, 31, 32, 63])
+    o = parity.oracle_run(wl.code, fr, algo, "f32", wl.max_iter, alpha=wl.alpha, idx=idx)
+    parity.compare(g, o, wl.max_iter, RTOL32, idx=idx, atol=parity.ATOL32)
+    if algo == "nms":
+        parity.assert_bitwise(g, parity.oracle_f32_run(wl.code, fr, wl.max_iter, idx=idx), idx=idx)
+    okf = g["ok"] == 1
+    assert np.array_equal(syndromes(wl.code, g["bits"][okf]), fr.z[okf])
+    assert np.all(g["iters"][~okf] == wl.max_iter)
+    assert np.all((g["iters"] >= 1) & (g["iters"] <= wl.max_iter))
+
+
 def test_edge_cases(ctx, ragged_code):
     import torch
     from paper_2001_07979_amd import mbp

@@ -71,7 +71,20 @@ def test_forward_is_the_plain_decoder_and_binary32_oracle(ctx, ragged_code):
     assert np.array_equal(L, ref["L"])
 
 
-def test_gradient_matches_fp64_oracle(ctx, ragged_code):
+def _grad_close(g, ref, rtol, floor):
+    """Coordinates within rtol of the reference plus floor x its rms."""
+    return np.abs(g - ref) <= rtol * np.abs(ref) + floor * np.sqrt(np.mean(ref ** 2))
+
+
+@pytest.mark.parametrize("ties", [False, True])
+def test_gradient_matches_fp64_oracle(ctx, ragged_code, ties):
+    """Against the oracle's FP64 reverse sweep of the same binary32 forward
+    trajectory (same minima, signs and caps): every coordinate to 1e-4.
+    Against the all-FP64 oracle, whose trajectory rounds differently: tie-free
+    LLRs (a continuous random gain on each) agree on nearly every frame; BSC
+    LLRs, which all share one magnitude per frame, make the minima exact ties
+    that the two trajectories later resolve differently, so there the
+    subgradients differ and only the forward is compared."""
     from paper_2001_07979_amd import mbp
     import torch
     fr = bsc_frames(ragged_code, 32, np.linspace(0.03, 0.06, 32), seed=500)
@@ -80,22 +93,27 @@ def test_gradient_matches_fp64_oracle(ctx, ragged_code):
     alpha = rng.uniform(0.6, 0.9, (K, 2)).astype(np.float32).astype(np.float64)
     dc = mbp.Code.from_inputs(ctx, ragged_code)
     _, z, a, lam = _tensors(fr, alpha)
-    # Channel LLRs of a BSC frame all share one magnitude, so the min-sum
-    # minima are exact ties that FP32 and FP64 rounding later break apart in
-    # different ways (each side then takes a different, equally valid
-    # subgradient).  A continuous random gain on every LLR removes the ties.
-    lam = (lam * rng.uniform(0.7, 1.3, size=lam.shape)).astype(np.float32).astype(np.float64)
+    if not ties:
+        lam = (lam * rng.uniform(0.7, 1.3, size=lam.shape)).astype(np.float32).astype(np.float64)
     llr = torch.from_numpy(lam.astype(np.float32)).cuda()
     w = np.random.default_rng(3).normal(size=lam.shape)  # J = sum w * L^K
     L, g_llr, g_alpha = _run(ctx, dc, llr, z, a, gL=torch.from_numpy(w.astype(np.float32)).cuda())
+
+    L32, glam32, galpha32 = oracle.nms_unrolled(ragged_code, K, alpha, lam, fr.z, gL=w, binary32=True)
+    assert np.array_equal(L, L32)
+    close = _grad_close(g_llr, glam32, 1e-4, 1e-5)
+    assert close.all(), f"{(~close).sum()} of {close.size} coordinates differ"
+    np.testing.assert_allclose(g_alpha, galpha32, rtol=1e-4, atol=1e-5 * np.abs(galpha32).max())
+
     L64, glam64, galpha64 = oracle.nms_unrolled(ragged_code, K, alpha, lam, fr.z, gL=w)
-    np.testing.assert_allclose(L, L64, rtol=1e-5, atol=1e-5)
-    err = np.abs(g_llr - glam64)
-    scale = np.sqrt(np.mean(glam64 ** 2))
-    close = err <= 1e-4 * np.abs(glam64) + 1e-4 * scale
-    assert close.mean() >= 0.995, f"{(~close).sum()} of {close.size} coordinates differ"
-    assert np.linalg.norm(g_llr - glam64) <= 2e-2 * np.linalg.norm(glam64)
-    np.testing.assert_allclose(g_alpha, galpha64, rtol=2e-2, atol=1e-3 * np.abs(galpha64).max())
+    # the FP32 forward drifts from FP64 by rounding amplified over K checks
+    # (measured up to 8.5e-5 at |L| up to 25 here)
+    np.testing.assert_allclose(L, L64, rtol=1e-5, atol=2e-4)
+    if not ties:
+        frames_ok = _grad_close(g_llr, glam64, 1e-4, 1e-4).all(axis=1)
+        assert frames_ok.mean() >= 0.9, f"{(~frames_ok).sum()} of {frames_ok.size} frames differ"
+        assert np.linalg.norm(g_llr - glam64) <= 2e-2 * np.linalg.norm(glam64)
+        np.testing.assert_allclose(g_alpha, galpha64, rtol=1e-1, atol=1e-3 * np.abs(galpha64).max())
 
 
 def test_checkpoint_spacing_does_not_change_gradients(ctx, ragged_code):
@@ -167,7 +185,8 @@ def test_gradient_matches_central_differences(ctx):
 def test_autograd_bce_training_step(ctx):
     """K=20 unrolled min-sum on the n=16384 code as a torch autograd op: the
     BCE loss of sigma(-L^K) against Alice's bits back-propagates through the
-    HIP adjoint into llr and alpha, and matches the FP64 oracle gradient."""
+    HIP adjoint into llr and alpha, and matches the oracle's FP64 reverse sweep of the
+    same binary32 trajectory."""
     import torch
     from paper_2001_07979_amd import mbp
     wl = W.unrolled_n16384(nframes=8)
@@ -182,13 +201,20 @@ def test_autograd_bce_training_step(ctx):
     L = mbp.unrolled_nms(ctx, dc, llr, z, alpha, ckpt_every=5)
     loss = torch.nn.functional.binary_cross_entropy_with_logits(-L, x)
     loss.backward()
-    L64 = oracle.nms_unrolled(wl.code, K, np.full((K, 2), 0.75), lam.astype(np.float64), fr.z)
-    np.testing.assert_allclose(L.detach().cpu().numpy(), L64, rtol=1e-5, atol=1e-5)
-    sig = 1.0 / (1.0 + np.exp(L64))
+    a64 = np.full((K, 2), 0.75)
+    L32 = oracle.nms_unrolled(wl.code, K, a64, lam.astype(np.float64), fr.z, binary32=True)
+    Lg = L.detach().cpu().numpy().astype(np.float64)
+    assert np.array_equal(Lg, L32)
+    # dJ/dL^K of the mean BCE of sigma(-L) against x, from the binary32 L
+    sig = 1.0 / (1.0 + np.exp(L32))
     gL = -(sig - fr.x) / fr.x.size
-    _, glam64, galpha64 = oracle.nms_unrolled(wl.code, K, np.full((K, 2), 0.75),
-                                              lam.astype(np.float64), fr.z, gL=gL)
+    _, glam32, galpha32 = oracle.nms_unrolled(wl.code, K, a64, lam.astype(np.float64), fr.z, gL=gL,
+                                              binary32=True)
     g = llr.grad.cpu().numpy().astype(np.float64)
-    assert np.linalg.norm(g - glam64) <= 1e-2 * np.linalg.norm(glam64) + 1e-30
-    np.testing.assert_allclose(alpha.grad.cpu().numpy(), galpha64, rtol=1e-2,
-                               atol=1e-2 * np.abs(galpha64).max() + 1e-30)
+    # gL itself is computed in FP32 by torch here and in FP64 by the test
+    close = _grad_close(g, glam32, 1e-3, 1e-4)
+    assert close.mean() >= 0.999, f"{(~close).sum()} of {close.size} coordinates differ"
+    np.testing.assert_allclose(alpha.grad.cpu().numpy(), galpha32, rtol=1e-3,
+                               atol=1e-4 * np.abs(galpha32).max() + 1e-30)
+    L64 = oracle.nms_unrolled(wl.code, K, a64, lam.astype(np.float64), fr.z)
+    np.testing.assert_allclose(Lg, L64, rtol=1e-4, atol=1e-3)

@@ -428,3 +428,65 @@ def test_nms_f32_agrees_with_fp64_on_short_decodes(small_peg):
     assert np.array_equal(a["iters"][short], b["iters"][short])
     assert np.array_equal(a["bits"][short], b["bits"][short])
     np.testing.assert_allclose(b["L"][short], a["L"][short], rtol=1e-5, atol=1e-4)
+
+
+def test_unrolled_binary32_forward_is_the_binary32_decoder(small_peg):
+    """The binary32 unrolled forward is the binary32 min-sum decoder run for
+    K iterations without a stopping test, bit for bit."""
+    fr = bsc_frames(small_peg, 3, 0.06, seed=42)
+    lam = oracle.llr_from_bits(fr.y, fr.p)
+    K = 7
+    alpha = np.random.default_rng(2).uniform(0.5, 1.0, size=(K, 2))
+    L = oracle.nms_unrolled(small_peg, K, alpha, lam, fr.z, binary32=True)
+    r = oracle.decode_nms_f32(small_peg, lam, fr.z, max_iter=K, early_exit=False, alpha_tl=alpha)
+    assert np.array_equal(L, r["L"])
+    assert np.array_equal(L.astype(np.float32).astype(np.float64), L)
+
+
+def test_unrolled_binary32_gradient_single_check_closed_form():
+    """On one check at K=1 the binary32 trajectory has the same minima and
+    signs as FP64, so the gradient is the closed form of the FP64 pin."""
+    g = json.load(open(GOLDEN))["nms_single_check"]
+    code = code_from_dense([np.array(h) for h in g["H"]])
+    lam = np.array([g["lambda"]])
+    z = np.array([g["z"]], np.uint8)
+    for k in range(4):
+        gL = np.zeros((1, 4))
+        gL[0, k] = 1.0
+        _, glam, galpha = oracle.nms_unrolled(code, 1, np.array([[0.75]]), lam, z, gL=gL,
+                                              binary32=True)
+        assert galpha[0, 0] == pytest.approx(g["c"][k] / 0.75, abs=1e-7)
+    gL = np.zeros((1, 4))
+    gL[0, 1] = 1.0
+    _, glam, _ = oracle.nms_unrolled(code, 1, np.array([[0.75]]), lam, z, gL=gL, binary32=True)
+    np.testing.assert_allclose(glam[0], [0.0, 1.0, 0.0, 0.75], atol=1e-15)
+
+
+def test_unrolled_binary32_gradient_matches_its_finite_differences():
+    """Central differences of the binary32 forward itself (step 1e-2, where
+    float rounding of J is far below the step's change) on smooth coordinates."""
+    code = peg_code(48, 24, 2, {3: 1.0}, seed_base=9100)
+    fr = bsc_frames(code, 2, 0.08, seed=41)
+    lam = oracle.llr_from_bits(fr.y, fr.p)
+    K = 5
+    rng = np.random.default_rng(1)
+    alpha = rng.uniform(0.6, 0.9, size=(K, 2))
+    lam = lam * rng.uniform(0.7, 1.3, size=lam.shape)
+    w = rng.normal(size=lam.shape)
+
+    def J_of_lam(l):
+        return float((oracle.nms_unrolled(code, K, alpha, l, fr.z, binary32=True) * w).sum())
+
+    _, glam, _ = oracle.nms_unrolled(code, K, alpha, lam, fr.z, gL=w, binary32=True)
+    eps = 1e-2
+    checked = 0
+    for i in rng.choice(lam.size, 40, replace=False):
+        xp, xm = lam.copy(), lam.copy()
+        xp.flat[i] += eps
+        xm.flat[i] -= eps
+        fp, f0, fm = J_of_lam(xp), J_of_lam(lam), J_of_lam(xm)
+        right, left = (fp - f0) / eps, (f0 - fm) / eps
+        if abs(right - left) <= 1e-3 * (1 + abs(right)):
+            assert glam.flat[i] == pytest.approx(0.5 * (right + left), rel=1e-3, abs=1e-3)
+            checked += 1
+    assert checked >= 15
