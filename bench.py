@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "check_kernel_traffic.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2001_07979_amd", "csrc", "decode.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2001_07979_amd", "csrc", f)
+                  for f in ("decode.hip", "mbp_kernels.h")]
 
 
 def log(*a):
@@ -34,8 +35,12 @@ def log(*a):
 
 
 def source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()[:12]
+    """sha1 of the plain decoder's kernel sources (first 12 hex digits)."""
+    h = hashlib.sha1()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:12]
 
 
 def stored_traffic():

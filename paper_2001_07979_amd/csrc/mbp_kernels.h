@@ -53,46 +53,29 @@ __device__ __forceinline__ int wave_id() {
     return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
 }
 
-// phi(x) = -ln tanh(x/2) = 2 atanh(e^-x) for x >= 0; phi is its own inverse,
-// so 2 atanh(prod tanh(a_k/2)) = phi(sum phi(a_k)) for magnitudes a_k >= 0.
-// Evaluated with the hardware exp2 / log2 / reciprocal and short polynomials
-// (about 4e-7 relative error over [0, 80]):
-//   v = e^-x, with -x log2(e) split into a rounded part and its residual;
-//   x >= ln 4:  2 atanh(v) = 2v (1 + v^2/3 + v^4/5 + ... + v^12/13), v <= 1/4;
-//   x <  ln 4:  ln((2 - w)/w) with w = 1 - e^-x (Taylor series below 0.35,
-//               where 1 - v would cancel).
-// phi(0) = +inf, and phi(x) = 0 for x >= 80 (true value below 4e-35).
-__device__ __forceinline__ float phi(float x) {
+// 1 - tanh(a/2) = 2v / (1 + v) with v = e^-a, for a magnitude a >= 0 (at
+// most the clip, so v does not underflow). v comes from the hardware exp2
+// with -a log2(e) split into its rounded value and the residual, which keeps
+// its relative error near one rounding for every a; the complement itself is
+// accurate to a few roundings (relative), including where tanh is near 1.
+__device__ __forceinline__ float tanh_complement(float a) {
     constexpr float kL2E = 1.44269504088896340736f;
     constexpr float kL2ELo = 1.925963033500011e-08f;  // log2(e) - kL2E
     constexpr float kLn2 = 0.693147180559945309f;
-    constexpr float kLn4 = 1.38629436111989061883f;
-    const float y = -x * kL2E;
-    const float ylo = fmaf(-x, kL2E, -y) + (-x) * kL2ELo;
+    const float y = -a * kL2E;
+    const float ylo = fmaf(-a, kL2E, -y) + (-a) * kL2ELo;
     float v = __builtin_amdgcn_exp2f(y);
     v = fmaf(v, ylo * kLn2, v);
-    const float s = v * v;
-    float p = fmaf(s, 1.0f / 13.0f, 1.0f / 11.0f);
-    p = fmaf(s, p, 1.0f / 9.0f);
-    p = fmaf(s, p, 1.0f / 7.0f);
-    p = fmaf(s, p, 1.0f / 5.0f);
-    p = fmaf(s, p, 1.0f / 3.0f);
-    p = fmaf(s, p, 1.0f);
-    float res = 2.0f * v * p;
-    if (__ballot(x < kLn4)) {
-        float q = fmaf(x, -1.0f / 40320.0f, 1.0f / 5040.0f);
-        q = fmaf(x, q, -1.0f / 720.0f);
-        q = fmaf(x, q, 1.0f / 120.0f);
-        q = fmaf(x, q, -1.0f / 24.0f);
-        q = fmaf(x, q, 1.0f / 6.0f);
-        q = fmaf(x, q, -0.5f);
-        q = fmaf(x, q, 1.0f);
-        const float w = x < 0.35f ? x * q : 1.0f - v;
-        const float r = (2.0f - w) * __builtin_amdgcn_rcpf(w);
-        const float b = __builtin_amdgcn_logf(r) * kLn2;
-        res = x < kLn4 ? b : res;
-    }
-    return x < 80.0f ? res : 0.0f;
+    return 2.0f * v * __builtin_amdgcn_rcpf(1.0f + v);
+}
+
+// 2 atanh(1 - E) = ln((2 - E) / E) for a complement E in (0, 1], with two
+// hardware log2: no quotient is rounded, and nothing cancels where E is small
+// (large messages). Where E is near 1 the result is small and carries an
+// absolute error of a few 1e-8.
+__device__ __forceinline__ float atanh2_of_complement(float E) {
+    constexpr float kLn2 = 0.693147180559945309f;
+    return (__builtin_amdgcn_logf(2.0f - E) - __builtin_amdgcn_logf(E)) * kLn2;
 }
 
 enum { kNMS = MBP_ALGO_NMS, kSPA = MBP_ALGO_SPA };
@@ -221,8 +204,12 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                         }
                     }
                 } else if constexpr (sizeof(T) == 4) {
-                    // sum-product, FP32: phi domain with prefix/suffix exclusion
-                    T f[DMAX];
+                    // sum-product, FP32: the tanh product over the other
+                    // edges, carried as complements E = 1 - prod tanh(a/2)
+                    // (a prefix and a suffix, merged per edge), so magnitudes
+                    // near the clip, where tanh rounds to 1, keep their
+                    // precision: 1 - (1 - x)(1 - y) = x + y - xy.
+                    T ep[DMAX];
 #pragma unroll
                     for (int j = 0; j < DMAX; ++j) {
                         if (j < d) {
@@ -231,23 +218,24 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                             neg |= static_cast<uint64_t>(s) << j;
                             T aj = fabs(q[j]);
                             aj = aj < clip ? aj : clip;
-                            f[j] = phi(aj);
+                            ep[j] = tanh_complement(aj);
                         }
                     }
                     T run = T(0);
 #pragma unroll
                     for (int j = 0; j < DMAX; ++j) {
                         if (j < d) {
-                            q[j] = run;  // sum of phi over edges before j
-                            run += f[j];
+                            q[j] = run;  // complement of the product before j
+                            run = fmaf(-run, ep[j], run + ep[j]);
                         }
                     }
                     T suf = T(0);
 #pragma unroll
                     for (int j = DMAX - 1; j >= 0; --j) {
                         if (j < d) {
-                            const T mag = phi(q[j] + suf);
-                            suf += f[j];
+                            const T E = fmaf(-q[j], suf, q[j] + suf);
+                            const T mag = atanh2_of_complement(E);
+                            suf = fmaf(-suf, ep[j], suf + ep[j]);
                             const int s = sx ^ static_cast<int>((neg >> j) & 1);
                             (cg + j * G)[lane] = s ? -mag : mag;
                         }
