@@ -245,15 +245,18 @@ void mbp_plan_destroy(mbp_plan *plan);
 int mbp_autotune(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches, const mbp_params *p,
                  const char *cache_path, mbp_tuning *out);
 
-/* Kernel timing. When enabled, every decode brackets each launch of its
- * check-node and variable-node kernels with HIP events on the decode's
- * stream and adds the elapsed times to per-kernel totals.
- *   mbp_profile_enable  0 / 1
+/* Kernel timing. Every plain decode brackets each launch of the kernels
+ * selected by the mask with HIP events on the decode's stream and adds the
+ * elapsed times to per-kernel totals. Kernel ids: 0 = check-node pass,
+ * 1 = variable-node pass, 2 = stopping test, 3 = staging and output
+ * transposes. Events between launches cost a few microseconds each, so
+ * timing only the kernel of interest disturbs the run least.
+ *   mbp_profile_enable  mask: bit k times kernel id k (0 = off,
+ *                       MBP_PROFILE_ALL = every kernel); EINVAL outside 0..15
  *   mbp_profile_reset   zero the totals
- *   mbp_profile_get     totals of kernel `which` (0 = check-node,
- *                       1 = variable-node, 2 = syndrome-only check,
- *                       3 = staging and output transposes): launches and
- *                       summed milliseconds. */
+ *   mbp_profile_get     totals of kernel id `which`: launches and summed
+ *                       milliseconds. */
+#define MBP_PROFILE_ALL 0xF
 int mbp_profile_enable(mbp_ctx *ctx, int32_t enable);
 int mbp_profile_reset(mbp_ctx *ctx);
 int mbp_profile_get(const mbp_ctx *ctx, int32_t which, int64_t *launches, double *total_ms);

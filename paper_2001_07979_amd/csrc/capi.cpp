@@ -477,7 +477,8 @@ int mbp_autotune(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches, const
 
 int mbp_profile_enable(mbp_ctx *ctx, int32_t enable) {
     if (!ctx) return fail(MBP_EINVAL, "mbp_profile_enable: ctx is NULL");
-    ctx->profiling = enable != 0;
+    if (enable < 0 || enable > 0xF) return fail(MBP_EINVAL, "mbp_profile_enable: mask outside 0..15");
+    ctx->profiling = enable;
     return MBP_OK;
 }
 

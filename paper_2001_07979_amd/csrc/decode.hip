@@ -8,8 +8,7 @@ namespace {
 
 template <typename T>
 using CheckFn = void (*)(const int32_t *, const int32_t *, const int32_t *, const float *,
-                         const uint64_t *, const uint64_t *, const T *, const T *, T *, uint64_t *,
-                         Dims);
+                         const uint64_t *, const uint64_t *, const T *, const T *, T *, Dims);
 
 template <typename T, int ALGO>
 CheckFn<T> check_kernel(int dmax) {
@@ -39,8 +38,10 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     const size_t sz_c = align_up(static_cast<size_t>(ngroups) * E * G * s);
     const size_t sz_L = align_up(static_cast<size_t>(ngroups) * n * G * s);
     const size_t sz_z = align_up(static_cast<size_t>(ngroups) * M * sizeof(uint64_t));
-    const size_t sz_m = align_up(static_cast<size_t>(ngroups) * kStride * sizeof(uint64_t));
-    int rc = ensure_workspace(ctx, sz_c + 2 * sz_L + sz_z + 2 * sz_m);
+    const size_t sz_d = align_up(static_cast<size_t>(ngroups) * n * sizeof(uint64_t));
+    // status words, one 256-byte line per group, then the stopping-test counter
+    const size_t sz_m = align_up(static_cast<size_t>(ngroups) * kStride * sizeof(uint64_t)) + 256;
+    int rc = ensure_workspace(ctx, sz_c + 2 * sz_L + sz_z + sz_d + sz_m);
     if (rc != MBP_OK) return rc;
     if ((rc = ensure_status(ctx, ngroups)) != MBP_OK) return rc;
     char *base = static_cast<char *>(ctx->ws);
@@ -48,8 +49,9 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     T *Lp = reinterpret_cast<T *>(base + sz_c);
     T *lam = reinterpret_cast<T *>(base + sz_c + sz_L);
     uint64_t *zb = reinterpret_cast<uint64_t *>(base + sz_c + 2 * sz_L);
-    uint64_t *act = reinterpret_cast<uint64_t *>(base + sz_c + 2 * sz_L + sz_z);
-    uint64_t *uns = reinterpret_cast<uint64_t *>(base + sz_c + 2 * sz_L + sz_z + sz_m);
+    uint64_t *D = reinterpret_cast<uint64_t *>(base + sz_c + 2 * sz_L + sz_z);
+    uint64_t *words = reinterpret_cast<uint64_t *>(base + sz_c + 2 * sz_L + sz_z + sz_d);
+    uint32_t *done = reinterpret_cast<uint32_t *>(base + sz_c + 2 * sz_L + sz_z + sz_d + sz_m - 256);
 
     Timer tm{ctx, stream, {}, 0};
     hipError_t err;
@@ -59,8 +61,8 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
         if (err != hipSuccess) return hip_fail(err, "kernel launch");   \
     } while (0)
 
-    LAUNCH_OR_FAIL(kStaging, k_init_groups<<<(ngroups + 63) / 64, 64, 0, stream>>>(
-                                 act, uns, ctx->status_dev, F, ngroups));
+    LAUNCH_OR_FAIL(kStaging, k_init_running<<<(ngroups + 63) / 64, 64, 0, stream>>>(
+                                 words, ctx->status_dev, done, F, ngroups));
     const dim3 tgrid((n + 63) / 64, ngroups);
     LAUNCH_OR_FAIL(kStaging, k_stage_llr<T><<<tgrid, kBlock, 0, stream>>>(
                                  static_cast<const T *>(llr), lam, Lp, F, n));
@@ -70,12 +72,14 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     const int dmax = dmax_for(code->max_check_deg);
     const CheckFn<T> kc = p->algo == MBP_ALGO_NMS ? check_kernel<T, kNMS>(dmax) : check_kernel<T, kSPA>(dmax);
     Dims dc{E, n, M, ngroups, (M + kRowsPerTile - 1) / kRowsPerTile, 0, 0, p->alpha, p->llr_clip};
-    Dims dv{E, n, M, ngroups, (n + kVarsPerTile - 1) / kVarsPerTile, 0, p->early_exit, p->alpha,
-            p->llr_clip};
+    Dims dv{E, n, M, ngroups, (n + kVarsPerTile - 1) / kVarsPerTile, 0, 0, p->alpha, p->llr_clip};
+    Dims ds{E, n, M, ngroups, (M + kBlock - 1) / kBlock, 0, 0, p->alpha, p->llr_clip};
     const int grid_c = grid_for(ctx, reinterpret_cast<const void *>(kc),
                                 static_cast<int64_t>(ngroups) * dc.ntiles);
     const int grid_v = grid_for(ctx, reinterpret_cast<const void *>(&k_variable<T>),
                                 static_cast<int64_t>(ngroups) * dv.ntiles);
+    const int grid_s = grid_for(ctx, reinterpret_cast<const void *>(&k_stop_test),
+                                static_cast<int64_t>(ngroups) * ds.ntiles);
 
     if (ctx->poll_events.size() < 2) {
         for (size_t k = ctx->poll_events.size(); k < 2; ++k) {
@@ -86,26 +90,27 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
         }
     }
 
-    int32_t last = 0;
+    // Iteration t: check pass, variable pass (L^t and the decision words),
+    // then, with early exit or on the last iteration, the stopping test,
+    // which retires the frames whose decisions meet every syndrome.
     for (int32_t t = 1; t <= p->max_iter; ++t) {
-        dc.t = t;
-        dv.t = t;
-        // the stopping test of iteration t-1 rides on check pass t (t >= 2)
-        dc.flag = (p->early_exit && t > 1) ? 1 : 0;
-        const int pt = t & 1, nt = (t + 1) & 1;
+        dc.t = dv.t = ds.t = t;
+        ds.flag = t == p->max_iter ? 1 : 0;
         LAUNCH_OR_FAIL(kCheckNode, kc<<<grid_c, kBlock, 0, stream>>>(code->d_row_ptr, code->d_col,
-                                                                     code->d_row_mat, nullptr, zb, act,
-                                                                     Lp, c, c, uns, dc));
+                                                                     code->d_row_mat, nullptr, zb, words,
+                                                                     Lp, c, c, dc));
         LAUNCH_OR_FAIL(kVarNode, k_variable<T><<<grid_v, kBlock, 0, stream>>>(
-                                     code->d_var_ptr, code->d_var_edge, c, lam, Lp, act + pt, uns + pt,
-                                     act + nt, uns + nt, ctx->status_dev, iters_out, ok_out, dv));
-        last = t;
+                                     code->d_var_ptr, code->d_var_edge, c, lam, Lp, words, D, dv));
+        if (!p->early_exit && t < p->max_iter) continue;
+        LAUNCH_OR_FAIL(kSyndrome, k_stop_test<<<grid_s, kBlock, 0, stream>>>(
+                                      code->d_row_ptr, code->d_col, zb, D, words, ctx->status_dev,
+                                      iters_out, ok_out, done, F, ds));
         if (p->early_exit) {
             if ((err = hipEventRecord(ctx->poll_events[t & 1], stream)) != hipSuccess)
                 return hip_fail(err, "hipEventRecord");
             if (t >= 2) {
                 // wait for iteration t-1 while iteration t runs, then read
-                // the running masks it (or a later iteration) left behind
+                // the running sets it (or a later iteration) left behind
                 if ((err = hipEventSynchronize(ctx->poll_events[(t - 1) & 1])) != hipSuccess)
                     return hip_fail(err, "hipEventSynchronize");
                 bool any = false;
@@ -115,15 +120,6 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
             }
         }
     }
-    // stopping test of the last iteration's decisions for frames still running
-    dc.t = last + 1;
-    dc.flag = 1;
-    LAUNCH_OR_FAIL(kSyndrome,
-                   k_syndrome<T><<<grid_for(ctx, reinterpret_cast<const void *>(&k_syndrome<T>),
-                                            static_cast<int64_t>(ngroups) * dc.ntiles),
-                                   kBlock, 0, stream>>>(code->d_row_ptr, code->d_col, zb, act, Lp, uns, dc));
-    LAUNCH_OR_FAIL(kStaging, k_finalize<<<(F + 255) / 256, 256, 0, stream>>>(act, uns, iters_out, ok_out, F,
-                                                                            last + 1, last));
     LAUNCH_OR_FAIL(kStaging, k_output<T><<<tgrid, kBlock, 0, stream>>>(Lp, bits_out, static_cast<T *>(llr_out),
                                                                       F, n));
 #undef LAUNCH_OR_FAIL

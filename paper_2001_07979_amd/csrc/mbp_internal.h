@@ -46,7 +46,7 @@ struct mbp_ctx {
     int32_t status_cap = 0;
     std::vector<hipEvent_t> poll_events;
     // Profiling.
-    bool profiling = false;
+    int32_t profiling = 0;  // bit k: time launches of kernel id k
     mbp::KernelStat stats[mbp::kNumKernels];
     std::vector<hipEvent_t> timing_events;
     int32_t live_codes = 0;

@@ -99,10 +99,15 @@ __device__ __forceinline__ void or_unmet(uint64_t *word, uint64_t bits) {
 struct Dims {
     int64_t E;
     int32_t n, M, ngroups, ntiles;
-    int32_t t;     // iteration (1-based); the syndrome-only pass uses last + 1
-    int32_t flag;  // check pass: test the incoming decisions; variable pass: early exit
+    int32_t t;     // iteration (1-based)
+    int32_t flag;  // stopping test: 1 on the last iteration (settles every frame)
     double alpha, clip;
 };
+
+// Per-group status words for the plain and unrolled decodes: word kRun of
+// group g (at kStride * g) holds the frames still running, word kUnmet the
+// frames with an unmet check in the stopping test under way.
+constexpr int kRun = 0, kUnmet = 1;
 
 // Check-node pass, iteration t. Each wave handles kRowsPerWave checks of one
 // group. The check's edge indices are read up front as scalars (the column
@@ -123,25 +128,22 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                                                   const uint64_t *__restrict__ zb,
                                                   const uint64_t *__restrict__ act,
                                                   const T *__restrict__ Lp, const T *c_in, T *c_out,
-                                                  uint64_t *__restrict__ uns, const Dims a) {
-    __shared__ uint64_t sh_bad[kWaves];
+                                                  const Dims a) {
     const unsigned lane = lane_id();
     const int wave = wave_id();
     const T clip = static_cast<T>(a.clip);
-    const int pt = a.t & 1;
     const bool first = a.t == 1;
     const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
         const int g = static_cast<int>(w / a.ntiles);
         const int tile = static_cast<int>(w % a.ntiles);
-        const uint64_t gact = act[kStride * g + pt];
+        const uint64_t gact = act[kStride * g + kRun];
         if (gact == 0) continue;  // whole group retired (uniform over the block)
         const bool on = (gact >> lane) & 1;
         // wave-uniform bases; every access below is base[lane], so addresses
         // are a scalar base plus one per-lane offset
         const T *Lg = Lp + static_cast<size_t>(g) * a.n * G;
         const uint64_t *zg = zb + static_cast<size_t>(g) * a.M;
-        uint64_t bad = 0;
         for (int k = 0; k < kRowsPerWave; ++k) {
             const int r = tile * kRowsPerTile + k * kWaves + wave;
             if (r >= a.M) break;
@@ -155,7 +157,6 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
             int v[DMAX];
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) v[j] = col[e0 + j];
-            int par = 0;
             if (on) {
                 // issue every gather of the check before using any of them
                 T q[DMAX], co[DMAX];
@@ -167,12 +168,8 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < DMAX; ++j) {
-                    if (j < d) {
-                        par ^= (q[j] < T(0)) ? 1 : 0;
-                        q[j] -= co[j];
-                    }
-                }
+                for (int j = 0; j < DMAX; ++j)
+                    if (j < d) q[j] -= co[j];
                 uint64_t neg = 0;
                 int sx = zbit;  // syndrome sign times every message sign
                 if constexpr (ALGO == kNMS) {
@@ -274,108 +271,113 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                     }
                 }
             }
-            bad |= __ballot(on && (par != zbit));
-        }
-        if (a.flag) {
-            if (lane == 0) sh_bad[wave] = bad;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                uint64_t b = 0;
-                for (int i = 0; i < kWaves; ++i) b |= sh_bad[i];
-                or_unmet(&uns[kStride * g + pt], b);
-            }
-            __syncthreads();
         }
     }
 }
 
-// Syndrome-only pass: the stopping test of the decisions held in Lp.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_syndrome(const int32_t *__restrict__ row_ptr,
-                                                     const int32_t *__restrict__ col,
-                                                     const uint64_t *__restrict__ zb,
-                                                     const uint64_t *__restrict__ act,
-                                                     const T *__restrict__ Lp,
-                                                     uint64_t *__restrict__ uns, const Dims a) {
-    __shared__ uint64_t sh_bad[kWaves];
+// Stopping test of iteration t (Sec. 2: a frame succeeds once z^l = H_l x
+// for every matrix l), on the decision words the variable pass wrote: bit k
+// of D[g][i] is frame 64g+k's decision on bit i. One thread per check: the
+// XOR of the check's decision words and its syndrome word gives, in one
+// 64-bit operation, the frames whose parity differs; they are ORed into the
+// group's kUnmet word. The last block to finish then settles every group:
+// frames of the running set with no unmet check stop at t (ok = 1); on the
+// last iteration (a.flag) the others stop too (ok = 0); the running set and
+// the host-visible status become the frames still running.
+__global__ __launch_bounds__(kBlock) void k_stop_test(const int32_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const uint64_t *__restrict__ zb,
+                                                      const uint64_t *__restrict__ D, uint64_t *words,
+                                                      uint64_t *status, int32_t *iters_out,
+                                                      uint8_t *ok_out, uint32_t *done, int32_t nframes,
+                                                      const Dims a) {
+    __shared__ uint32_t sh_or[2 * kWaves];
+    __shared__ int sh_last;
     const unsigned lane = lane_id();
     const int wave = wave_id();
-    const int pt = a.t & 1;
     const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
         const int g = static_cast<int>(w / a.ntiles);
         const int tile = static_cast<int>(w % a.ntiles);
-        const uint64_t gact = act[kStride * g + pt];
-        if (gact == 0) continue;
-        const bool on = (gact >> lane) & 1;
-        const T *Lg = Lp + static_cast<size_t>(g) * a.n * G;
-        const uint64_t *zg = zb + static_cast<size_t>(g) * a.M;
-        uint64_t bad = 0;
-        for (int k = 0; k < kRowsPerWave; ++k) {
-            const int r = tile * kRowsPerTile + k * kWaves + wave;
-            if (r >= a.M) break;
-            const int e0 = row_ptr[r];
-            const int d = row_ptr[r + 1] - e0;
-            const int zbit = static_cast<int>((zg[r] >> lane) & 1);
-            int par = 0;
-            for (int j0 = 0; j0 < d; j0 += kIdxChunk) {
-                int v[kIdxChunk];
-#pragma unroll
-                for (int j = 0; j < kIdxChunk; ++j) v[j] = col[e0 + j0 + j];
-                if (on) {
-#pragma unroll
-                    for (int j = 0; j < kIdxChunk; ++j)
-                        if (j0 + j < d) par ^= ((Lg + static_cast<size_t>(v[j]) * G)[lane] < T(0)) ? 1 : 0;
-                }
-            }
-            bad |= __ballot(on && (par != zbit));
+        const uint64_t run = words[kStride * g + kRun];
+        if (run == 0) continue;
+        const int r = tile * kBlock + static_cast<int>(threadIdx.x);
+        uint64_t unmet = 0;
+        if (r < a.M) {
+            const uint64_t *Dg = D + static_cast<size_t>(g) * a.n;
+            uint64_t par = zb[static_cast<size_t>(g) * a.M + r];
+            for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) par ^= Dg[col[e]];
+            unmet = par & run;
         }
-        if (lane == 0) sh_bad[wave] = bad;
+        uint32_t lo = static_cast<uint32_t>(unmet), hi = static_cast<uint32_t>(unmet >> 32);
+        for (int o = 32; o > 0; o >>= 1) {
+            lo |= __shfl_xor(lo, o);
+            hi |= __shfl_xor(hi, o);
+        }
+        if (lane == 0) {
+            sh_or[2 * wave] = lo;
+            sh_or[2 * wave + 1] = hi;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             uint64_t b = 0;
-            for (int i = 0; i < kWaves; ++i) b |= sh_bad[i];
-            or_unmet(&uns[kStride * g + pt], b);
+            for (int i = 0; i < kWaves; ++i)
+                b |= static_cast<uint64_t>(sh_or[2 * i]) | (static_cast<uint64_t>(sh_or[2 * i + 1]) << 32);
+            or_unmet(&words[kStride * g + kUnmet], b);
         }
         __syncthreads();
     }
+    // the last block to arrive settles the groups
+    if (threadIdx.x == 0) {
+        __threadfence();
+        sh_last = atomicAdd(done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!sh_last) return;
+    __threadfence();
+    for (int f = threadIdx.x; f < a.ngroups * G; f += kBlock) {
+        const int g = f / G, k = f % G;
+        const uint64_t run = __hip_atomic_load(&words[kStride * g + kRun], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        if (!((run >> k) & 1) || f >= nframes) continue;
+        const uint64_t un = __hip_atomic_load(&words[kStride * g + kUnmet], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        const bool met = !((un >> k) & 1);
+        if (met || a.flag) {
+            iters_out[f] = a.t;
+            ok_out[f] = met ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    for (int g = threadIdx.x; g < a.ngroups; g += kBlock) {
+        const uint64_t run = __hip_atomic_load(&words[kStride * g + kRun], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t un = __hip_atomic_load(&words[kStride * g + kUnmet], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t next = a.flag ? 0 : (run & un);
+        words[kStride * g + kRun] = next;
+        words[kStride * g + kUnmet] = 0;
+        __hip_atomic_store(&status[g], next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    if (threadIdx.x == 0) *done = 0;
 }
 
-// Variable-node pass, eq. (2), plus the per-group bookkeeping of the
-// stopping rule. act_in / uns_in are this iteration's words, act_out /
-// uns_out the next iteration's (the same arrays at the other parity).
+// Variable-node pass, eq. (2): L = lambda + every incoming check message,
+// summed over the variable's edges in edge order (matrix, then check). D, if
+// not null, receives the decision word of each variable (bit k set when
+// frame 64g+k decides 1, i.e. L < 0; frames not running leave 0).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_variable(
     const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_edge,
     const T *__restrict__ c, const T *__restrict__ lam, T *__restrict__ Lp,
-    const uint64_t *__restrict__ act_in, const uint64_t *__restrict__ uns_in,
-    uint64_t *__restrict__ act_out, uint64_t *__restrict__ uns_out,
-    uint64_t *__restrict__ status, int32_t *__restrict__ iters_out, uint8_t *__restrict__ ok_out,
-    const Dims a) {
+    const uint64_t *__restrict__ act, uint64_t *__restrict__ D, const Dims a) {
     const unsigned lane = lane_id();
     const int wave = wave_id();
     const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
         const int g = static_cast<int>(w / a.ntiles);
         const int tile = static_cast<int>(w % a.ntiles);
-        const uint64_t gact = act_in[kStride * g];
-        const uint64_t U = (a.flag && a.t > 1) ? uns_in[kStride * g] : ~0ull;
-        const uint64_t run = gact & U;
-        if (tile == 0 && wave == 0) {
-            // Frames whose decisions at t-1 met every syndrome stop here;
-            // nothing else reads these words during this pass.
-            const uint64_t conv = gact & ~U;
-            if (lane == 0) {
-                act_out[kStride * g] = run;
-                uns_out[kStride * g] = 0;
-                __hip_atomic_store(&status[g], run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            }
-            if ((conv >> lane) & 1) {
-                const int f = g * G + lane;
-                iters_out[f] = a.t - 1;
-                ok_out[f] = 1;
-            }
-        }
+        const uint64_t run = act[kStride * g + kRun];
         if (run == 0) continue;
         const bool on = (run >> lane) & 1;
         const size_t gb = static_cast<size_t>(g) * a.n * G;
@@ -400,12 +402,30 @@ __global__ __launch_bounds__(kBlock) void k_variable(
                 }
             }
             if (on) (Lp + gb + static_cast<size_t>(i) * G)[lane] = s;
+            if (D) {
+                const uint64_t bits = __ballot(on && s < T(0));
+                if (lane == 0) D[static_cast<size_t>(g) * a.n + i] = bits;
+            }
         }
     }
 }
 
-// Per-group masks before the first iteration. Iteration 1 reads parity 1;
-// `both` also marks parity 0 running (a decode that starts at an even t).
+// Running set of the plain and unrolled decodes before the first iteration:
+// every valid frame; the unmet words and the stopping-test counter cleared.
+__global__ void k_init_running(uint64_t *words, uint64_t *status, uint32_t *done, int32_t nframes,
+                               int32_t ngroups) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g == 0) *done = 0;
+    if (g >= ngroups) return;
+    const int rem = nframes - g * G;
+    const uint64_t valid = rem >= G ? ~0ull : ((1ull << rem) - 1ull);
+    words[kStride * g + kRun] = valid;
+    words[kStride * g + kUnmet] = 0;
+    __hip_atomic_store(&status[g], valid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Per-group masks of the batched decode before the first iteration, by
+// iteration parity: iteration 1 reads parity 1; `both` also marks parity 0.
 __global__ void k_init_groups(uint64_t *act, uint64_t *uns, uint64_t *status, int32_t nframes,
                               int32_t ngroups, int32_t both = 0) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -417,19 +437,6 @@ __global__ void k_init_groups(uint64_t *act, uint64_t *uns, uint64_t *status, in
     uns[kStride * g + 0] = 0;
     uns[kStride * g + 1] = 0;
     __hip_atomic_store(&status[g], valid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
-// Frames still running after the last iteration: ok from the syndrome-only
-// pass, iterations = the last one run.
-__global__ void k_finalize(const uint64_t *act, const uint64_t *uns, int32_t *iters_out,
-                           uint8_t *ok_out, int32_t nframes, int32_t tf, int32_t last_iter) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nframes) return;
-    const int g = f / G, lane = f % G, p = tf & 1;
-    if ((act[kStride * g + p] >> lane) & 1) {
-        ok_out[f] = ((uns[kStride * g + p] >> lane) & 1) ? 0 : 1;
-        iters_out[f] = last_iter;
-    }
 }
 
 // [F][n] -> [g][n][64] for the channel LLRs (also the initial L).
@@ -559,7 +566,7 @@ struct Timer {
     }
     template <typename F>
     hipError_t run(int which, F &&launch) {
-        if (!ctx->profiling) {
+        if (!((ctx->profiling >> which) & 1)) {
             launch();
             return hipGetLastError();
         }

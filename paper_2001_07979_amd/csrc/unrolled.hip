@@ -259,8 +259,7 @@ State state_at(char *ws, const Layout &Ly, int32_t t, int32_t K, int32_t ck) {
 }
 
 using FwdFn = void (*)(const int32_t *, const int32_t *, const int32_t *, const float *,
-                       const uint64_t *, const uint64_t *, const float *, const float *, float *,
-                       uint64_t *, Dims);
+                       const uint64_t *, const uint64_t *, const float *, const float *, float *, Dims);
 using AdjPtr = void (*)(const int32_t *, const int32_t *, const int32_t *, const float *,
                         const uint64_t *, const uint64_t *, const float *, const float *,
                         const float *, float *, float *, Dims);
@@ -282,7 +281,7 @@ int dmax_of(int d) {
 }
 
 // Shared set-up of both directions: stage lambda and the syndromes, mark
-// every frame running at both parities.
+// every frame running.
 struct Run {
     mbp_ctx *ctx;
     const mbp_code *code;
@@ -311,7 +310,8 @@ struct Run {
         float *lam = reinterpret_cast<float *>(ws + Ly.lam);
         uint64_t *act = reinterpret_cast<uint64_t *>(ws + Ly.act);
         uint64_t *uns = reinterpret_cast<uint64_t *>(ws + Ly.uns);
-        k_init_groups<<<(ng + 63) / 64, 64, 0, stream>>>(act, uns, ctx->status_dev, F, ng, 1);
+        k_init_running<<<(ng + 63) / 64, 64, 0, stream>>>(act, ctx->status_dev,
+                                                           reinterpret_cast<uint32_t *>(uns), F, ng);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return hip_fail(err, "k_init_groups launch");
         // lam is staged twice into one buffer: k_stage_llr writes both outputs
@@ -326,18 +326,16 @@ struct Run {
     // one forward iteration t: state t-1 -> state t
     void step(int32_t t) {
         const State a = state_at(ws, Ly, t - 1, K, ck), b = state_at(ws, Ly, t, K, ck);
-        uint64_t *act = reinterpret_cast<uint64_t *>(ws + Ly.act);
-        uint64_t *uns = reinterpret_cast<uint64_t *>(ws + Ly.uns);
+        const uint64_t *act = reinterpret_cast<const uint64_t *>(ws + Ly.act);
         const uint64_t *zb = reinterpret_cast<const uint64_t *>(ws + Ly.zb);
         dc.t = t;
         dv.t = t;
         fwd<<<grid_c, kBlock, 0, stream>>>(code->d_row_ptr, code->d_col, code->d_row_mat,
                                            alpha + static_cast<size_t>(t - 1) * code->u, zb, act,
-                                           a.L, a.c ? a.c : b.c, b.c_mut, uns, dc);
-        const int pt = t & 1, nt = (t + 1) & 1;
-        k_variable<float><<<grid_v, kBlock, 0, stream>>>(
-            code->d_var_ptr, code->d_var_edge, b.c, reinterpret_cast<const float *>(ws + Ly.lam), b.L,
-            act + pt, uns + pt, act + nt, uns + nt, ctx->status_dev, nullptr, nullptr, dv);
+                                           a.L, a.c ? a.c : b.c, b.c_mut, dc);
+        k_variable<float><<<grid_v, kBlock, 0, stream>>>(code->d_var_ptr, code->d_var_edge, b.c,
+                                                         reinterpret_cast<const float *>(ws + Ly.lam), b.L,
+                                                         act, nullptr, dv);
     }
 };
 
@@ -381,7 +379,7 @@ int unrolled_backward(mbp_ctx *ctx, const mbp_code *code, int32_t F, int32_t K, 
     float *gA = reinterpret_cast<float *>(w + Ly.gLa), *gB = reinterpret_cast<float *>(w + Ly.gLb);
     float *glam = reinterpret_cast<float *>(w + Ly.glam), *gq = reinterpret_cast<float *>(w + Ly.gq);
     float *galpha = reinterpret_cast<float *>(w + Ly.galpha);
-    const uint64_t *act = reinterpret_cast<const uint64_t *>(w + Ly.act) + 1;
+    const uint64_t *act = reinterpret_cast<const uint64_t *>(w + Ly.act);
     const uint64_t *zb = reinterpret_cast<const uint64_t *>(w + Ly.zb);
     // dJ/dL^K into gA and into the running dJ/dlambda
     k_stage_llr<float><<<dim3((n + 63) / 64, ng), kBlock, 0, stream>>>(grad_out, glam, gA, F, n);

@@ -141,8 +141,18 @@ class Context:
         except Exception:
             pass
 
-    def profile_enable(self, on: bool = True):
-        _check(lib().mbp_profile_enable(self.handle, int(bool(on))), "mbp_profile_enable")
+    def profile_enable(self, on: bool = True, kernels=None):
+        """Time every kernel (on=True), none (on=False), or only the named
+        kernels (a list of KERNEL_IDS keys)."""
+        if not on:
+            mask = 0
+        elif kernels is None:
+            mask = 0xF
+        else:
+            mask = 0
+            for k in kernels:
+                mask |= 1 << KERNEL_IDS[k]
+        _check(lib().mbp_profile_enable(self.handle, mask), "mbp_profile_enable")
 
     def profile_reset(self):
         _check(lib().mbp_profile_reset(self.handle), "mbp_profile_reset")

@@ -243,3 +243,11 @@ def test_profiling_counts_launches(ctx, ragged_code):
     n_c, ms_c = ctx.profile_get("check")
     n_v, ms_v = ctx.profile_get("variable")
     assert n_c == n_v >= int(g["iters"].max()) and ms_c > 0 and ms_v > 0
+    # a mask times only the kernels it names
+    ctx.profile_reset()
+    ctx.profile_enable(True, kernels=["check"])
+    parity.gpu_run(ctx, dc, fr, "nms", "f32", 40)
+    ctx.profile_enable(False)
+    assert ctx.profile_get("check")[0] == n_c and ctx.profile_get("variable")[0] == 0
+    from paper_2001_07979_amd import mbp
+    assert mbp.lib().mbp_profile_enable(ctx.handle, 16) == mbp.MBP_EINVAL
