@@ -96,8 +96,9 @@ void mbp_ctx_destroy(mbp_ctx *ctx);
  *              within each row, each in [0, n)
  * The CSR arrays are copied during the call (the caller keeps them); the
  * library builds and owns the device edge layouts. Every check needs at
- * least two edges, the stacked edge count must be below 2^31, and the
- * largest check degree at most 64 (EUNSUPPORTED above that).
+ * least two edges, the stacked edge count must be below 2^31, and both the
+ * largest check degree and the largest variable degree over all u matrices
+ * at most 64 (EUNSUPPORTED above that).
  * Errors: EINVAL on any violation above, ENOMEM, EDEVICE. */
 int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
                     const int32_t *const *row_ptr, const int32_t *const *col_idx,

@@ -131,6 +131,9 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
                                           " exceeds 64");
     int32_t maxvd = 0;
     for (int32_t i = 0; i < n; ++i) maxvd = std::max(maxvd, var_cnt[i + 1]);
+    if (maxvd > 64)
+        return fail(MBP_EUNSUPPORTED, "mbp_code_create: largest variable degree over all matrices " +
+                                          std::to_string(maxvd) + " exceeds 64");
     for (int32_t i = 0; i < n; ++i) var_cnt[i + 1] += var_cnt[i];
     std::vector<int32_t> h_var_edge(E), fill(var_cnt.begin(), var_cnt.end() - 1);
     for (int64_t k = 0; k < E; ++k) h_var_edge[fill[h_col[k]]++] = (int32_t)k;

@@ -64,19 +64,22 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     LAUNCH_OR_FAIL(kStaging, k_init_running<<<(ngroups + 63) / 64, 64, 0, stream>>>(
                                  words, ctx->status_dev, done, F, ngroups));
     const dim3 tgrid((n + 63) / 64, ngroups);
+    // L^0 = lambda: the first check pass reads lam, so only lam is staged
     LAUNCH_OR_FAIL(kStaging, k_stage_llr<T><<<tgrid, kBlock, 0, stream>>>(
-                                 static_cast<const T *>(llr), lam, Lp, F, n));
+                                 static_cast<const T *>(llr), lam, nullptr, F, n));
     LAUNCH_OR_FAIL(kStaging, k_stage_synd<<<dim3((M + kBlock - 1) / kBlock, ngroups), kBlock, 0, stream>>>(
                                  synd, zb, F, M));
 
     const int dmax = dmax_for(code->max_check_deg);
     const CheckFn<T> kc = p->algo == MBP_ALGO_NMS ? check_kernel<T, kNMS>(dmax) : check_kernel<T, kSPA>(dmax);
     Dims dc{E, n, M, ngroups, (M + kRowsPerTile - 1) / kRowsPerTile, 0, 0, p->alpha, p->llr_clip};
-    Dims dv{E, n, M, ngroups, (n + kVarsPerTile - 1) / kVarsPerTile, 0, 0, p->alpha, p->llr_clip};
+    int vpt = 0;
+    const VarFn<T> kv = variable_kernel<T>(code->max_var_deg, &vpt);
+    Dims dv{E, n, M, ngroups, (n + vpt - 1) / vpt, 0, 0, p->alpha, p->llr_clip};
     Dims ds{E, n, M, ngroups, (M + kBlock - 1) / kBlock, 0, 0, p->alpha, p->llr_clip};
     const int grid_c = grid_for(ctx, reinterpret_cast<const void *>(kc),
                                 static_cast<int64_t>(ngroups) * dc.ntiles);
-    const int grid_v = grid_for(ctx, reinterpret_cast<const void *>(&k_variable<T>),
+    const int grid_v = grid_for(ctx, reinterpret_cast<const void *>(kv),
                                 static_cast<int64_t>(ngroups) * dv.ntiles);
     const int grid_s = grid_for(ctx, reinterpret_cast<const void *>(&k_stop_test),
                                 static_cast<int64_t>(ngroups) * ds.ntiles);
@@ -98,9 +101,9 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
         ds.flag = t == p->max_iter ? 1 : 0;
         LAUNCH_OR_FAIL(kCheckNode, kc<<<grid_c, kBlock, 0, stream>>>(code->d_row_ptr, code->d_col,
                                                                      code->d_row_mat, nullptr, zb, words,
-                                                                     Lp, c, c, dc));
-        LAUNCH_OR_FAIL(kVarNode, k_variable<T><<<grid_v, kBlock, 0, stream>>>(
-                                     code->d_var_ptr, code->d_var_edge, c, lam, Lp, words, D, dv));
+                                                                     t == 1 ? lam : Lp, c, c, dc));
+        LAUNCH_OR_FAIL(kVarNode, kv<<<grid_v, kBlock, 0, stream>>>(code->d_var_ptr, code->d_var_edge, c, lam,
+                                                                   Lp, words, D, dv));
         if (!p->early_exit && t < p->max_iter) continue;
         LAUNCH_OR_FAIL(kSyndrome, k_stop_test<<<grid_s, kBlock, 0, stream>>>(
                                       code->d_row_ptr, code->d_col, zb, D, words, ctx->status_dev,
@@ -153,11 +156,17 @@ int llr_impl(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y, const d
         const int32_t nf = std::min(kMaxGridY, nframes - f0);
         const dim3 grid((n + kLlrPerBlock - 1) / kLlrPerBlock, nf);
         const size_t off = static_cast<size_t>(f0) * n;
-        if (dtype == MBP_F32)
-            k_llr<float><<<grid, kBlock, 0, stream>>>(y + off, e + f0, static_cast<float *>(llr_out) + off, n);
-        else
-            k_llr<double><<<grid, kBlock, 0, stream>>>(y + off, e + f0, static_cast<double *>(llr_out) + off,
-                                                       n);
+        const bool vec = n % kLlrPerThread == 0 && reinterpret_cast<uintptr_t>(y) % 8 == 0 &&
+                         reinterpret_cast<uintptr_t>(llr_out) % 16 == 0;
+        if (dtype == MBP_F32) {
+            float *o = static_cast<float *>(llr_out) + off;
+            if (vec) k_llr<float, true><<<grid, kBlock, 0, stream>>>(y + off, e + f0, o, n);
+            else k_llr<float, false><<<grid, kBlock, 0, stream>>>(y + off, e + f0, o, n);
+        } else {
+            double *o = static_cast<double *>(llr_out) + off;
+            if (vec) k_llr<double, true><<<grid, kBlock, 0, stream>>>(y + off, e + f0, o, n);
+            else k_llr<double, false><<<grid, kBlock, 0, stream>>>(y + off, e + f0, o, n);
+        }
     }
     err = hipGetLastError();
     if (err != hipSuccess) return hip_fail(err, "k_llr launch");

@@ -306,7 +306,18 @@ __global__ __launch_bounds__(kBlock) void k_stop_test(const int32_t *__restrict_
         if (r < a.M) {
             const uint64_t *Dg = D + static_cast<size_t>(g) * a.n;
             uint64_t par = zb[static_cast<size_t>(g) * a.M + r];
-            for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) par ^= Dg[col[e]];
+            const int e1 = row_ptr[r + 1];
+            // indices, then words, a chunk at a time (col is padded past E)
+            for (int e = row_ptr[r]; e < e1; e += kIdxChunk) {
+                int v[kIdxChunk];
+#pragma unroll
+                for (int j = 0; j < kIdxChunk; ++j) v[j] = col[e + j];
+                uint64_t dw[kIdxChunk];
+#pragma unroll
+                for (int j = 0; j < kIdxChunk; ++j) dw[j] = e + j < e1 ? Dg[v[j]] : 0;
+#pragma unroll
+                for (int j = 0; j < kIdxChunk; ++j) par ^= dw[j];
+            }
             unmet = par & run;
         }
         uint32_t lo = static_cast<uint32_t>(unmet), hi = static_cast<uint32_t>(unmet >> 32);
@@ -363,10 +374,12 @@ __global__ __launch_bounds__(kBlock) void k_stop_test(const int32_t *__restrict_
 }
 
 // Variable-node pass, eq. (2): L = lambda + every incoming check message,
-// summed over the variable's edges in edge order (matrix, then check). D, if
-// not null, receives the decision word of each variable (bit k set when
-// frame 64g+k decides 1, i.e. L < 0; frames not running leave 0).
-template <typename T>
+// summed over the variable's edges in edge order (matrix, then check). Each
+// wave takes VPW variables of degree at most DV and issues all their
+// gathers before summing any. D, if not null, receives the decision word of
+// each variable (bit k set when frame 64g+k decides 1, i.e. L < 0; frames
+// not running leave 0).
+template <typename T, int DV, int VPW>
 __global__ __launch_bounds__(kBlock) void k_variable(
     const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_edge,
     const T *__restrict__ c, const T *__restrict__ lam, T *__restrict__ Lp,
@@ -382,32 +395,59 @@ __global__ __launch_bounds__(kBlock) void k_variable(
         const bool on = (run >> lane) & 1;
         const size_t gb = static_cast<size_t>(g) * a.n * G;
         const T *cg = c + static_cast<size_t>(g) * a.E * G;
-        for (int k = 0; k < kVarsPerWave; ++k) {
-            const int i = tile * kVarsPerTile + k * kWaves + wave;
-            if (i >= a.n) break;
-            const int k0 = var_ptr[i], k1 = var_ptr[i + 1];
-            T s = on ? (lam + gb + static_cast<size_t>(i) * G)[lane] : T(0);
-            for (int kk = k0; kk < k1; kk += kIdxChunk) {
-                int ev[kIdxChunk];
+        int i[VPW], k0[VPW], deg[VPW];
+        bool in[VPW];
 #pragma unroll
-                for (int j = 0; j < kIdxChunk; ++j) ev[j] = var_edge[kk + j];
-                if (on) {
-                    T x[kIdxChunk];
+        for (int v = 0; v < VPW; ++v) {
+            i[v] = (tile * VPW + v) * kWaves + wave;
+            in[v] = i[v] < a.n;
+            const int ii = in[v] ? i[v] : a.n - 1;
+            k0[v] = var_ptr[ii];
+            deg[v] = in[v] ? var_ptr[ii + 1] - k0[v] : 0;
+        }
+        T x[VPW][DV], s[VPW];
+        if (on) {
 #pragma unroll
-                    for (int j = 0; j < kIdxChunk; ++j)
-                        if (kk + j < k1) x[j] = (cg + static_cast<size_t>(ev[j]) * G)[lane];
+            for (int v = 0; v < VPW; ++v) {
+                int ev[DV];
 #pragma unroll
-                    for (int j = 0; j < kIdxChunk; ++j)
-                        if (kk + j < k1) s += x[j];
-                }
+                for (int j = 0; j < DV; ++j) ev[j] = var_edge[k0[v] + j];
+                s[v] = in[v] ? (lam + gb + static_cast<size_t>(i[v]) * G)[lane] : T(0);
+#pragma unroll
+                for (int j = 0; j < DV; ++j)
+                    if (j < deg[v]) x[v][j] = (cg + static_cast<size_t>(ev[j]) * G)[lane];
             }
-            if (on) (Lp + gb + static_cast<size_t>(i) * G)[lane] = s;
-            if (D) {
-                const uint64_t bits = __ballot(on && s < T(0));
-                if (lane == 0) D[static_cast<size_t>(g) * a.n + i] = bits;
+#pragma unroll
+            for (int v = 0; v < VPW; ++v) {
+#pragma unroll
+                for (int j = 0; j < DV; ++j)
+                    if (j < deg[v]) s[v] += x[v][j];
+                if (in[v]) (Lp + gb + static_cast<size_t>(i[v]) * G)[lane] = s[v];
+            }
+        }
+        if (D) {
+#pragma unroll
+            for (int v = 0; v < VPW; ++v) {
+                const uint64_t bits = __ballot(on && in[v] && s[v] < T(0));
+                if (lane == 0 && in[v]) D[static_cast<size_t>(g) * a.n + i[v]] = bits;
             }
         }
     }
+}
+
+// The variable-pass instance for a joint variable degree up to dmax, and the
+// variables one block covers (its tile).
+template <typename T>
+using VarFn = void (*)(const int32_t *, const int32_t *, const T *, const T *, T *, const uint64_t *,
+                       uint64_t *, Dims);
+
+template <typename T>
+VarFn<T> variable_kernel(int dmax, int *vars_per_tile) {
+    if (dmax <= 8) { *vars_per_tile = 4 * kWaves; return &k_variable<T, 8, 4>; }
+    if (dmax <= 16) { *vars_per_tile = 4 * kWaves; return &k_variable<T, 16, 4>; }
+    if (dmax <= 32) { *vars_per_tile = 2 * kWaves; return &k_variable<T, 32, 2>; }
+    *vars_per_tile = kWaves;
+    return &k_variable<T, 64, 1>;
 }
 
 // Running set of the plain and unrolled decodes before the first iteration:
@@ -439,7 +479,8 @@ __global__ void k_init_groups(uint64_t *act, uint64_t *uns, uint64_t *status, in
     __hip_atomic_store(&status[g], valid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// [F][n] -> [g][n][64] for the channel LLRs (also the initial L).
+// [F][n] -> [g][n][64] for the channel LLRs, and into Lp as well (the
+// initial L) when Lp is not null.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_stage_llr(const T *llr, T *lam, T *Lp, int32_t nframes,
                                                       int32_t n) {
@@ -457,27 +498,25 @@ __global__ __launch_bounds__(kBlock) void k_stage_llr(const T *llr, T *lam, T *L
             const T v = tile[tx][iy];
             const size_t o = (static_cast<size_t>(g) * n + i) * G + tx;
             lam[o] = v;
-            Lp[o] = v;
+            if (Lp) Lp[o] = v;
         }
     }
 }
 
-// [F][M] syndrome bytes -> [g][M] 64-bit lane masks.
+// [F][M] syndrome bytes -> [g][M] 64-bit lane masks. One thread per check
+// gathers its bit of the group's 64 frames; for each frame the block reads
+// kBlock consecutive bytes.
 __global__ __launch_bounds__(kBlock) void k_stage_synd(const uint8_t *z, uint64_t *zb, int32_t nframes,
                                                        int32_t M) {
-    __shared__ uint8_t s[64][kBlock + 4];
-    const int g = blockIdx.y, r0 = blockIdx.x * kBlock;
-    for (int fy = 0; fy < 64; ++fy) {
-        const int f = g * G + fy, r = r0 + static_cast<int>(threadIdx.x);
-        s[fy][threadIdx.x] = (f < nframes && r < M) ? z[static_cast<size_t>(f) * M + r] : 0;
-    }
-    __syncthreads();
-    const int lane = lane_id(), wave = threadIdx.x >> 6;
-    for (int k = 0; k < 64; ++k) {
-        const int rr = wave * 64 + k;
-        const uint64_t mask = __ballot(s[lane][rr] != 0);
-        if (lane == 0 && r0 + rr < M) zb[static_cast<size_t>(g) * M + r0 + rr] = mask;
-    }
+    const int g = blockIdx.y;
+    const int r = blockIdx.x * kBlock + static_cast<int>(threadIdx.x);
+    if (r >= M) return;
+    const int nf = min(G, nframes - g * G);
+    const uint8_t *zg = z + static_cast<size_t>(g) * G * M + r;
+    uint64_t m = 0;
+#pragma unroll 16
+    for (int k = 0; k < nf; ++k) m |= static_cast<uint64_t>(zg[static_cast<size_t>(k) * M] != 0) << k;
+    zb[static_cast<size_t>(g) * M + r] = m;
 }
 
 // [g][n][64] -> decided bits [F][n] and L [F][n] (either may be null).
@@ -505,11 +544,12 @@ __global__ __launch_bounds__(kBlock) void k_output(const T *Lp, uint8_t *bits, T
 
 // Channel LLR (1 - 2y) ln((1 - e)/e), computed in FP64. Block (x, f) covers
 // kLlrPerBlock consecutive bits of frame f; each thread takes the logarithm
-// once and converts kLlrPerThread bits.
+// once and converts kLlrPerThread consecutive bits. VEC (n a multiple of 8,
+// rows aligned) moves them as one 8-byte load and 16-byte stores.
 constexpr int kLlrPerThread = 8;
 constexpr int kLlrPerBlock = kBlock * kLlrPerThread;
 
-template <typename T>
+template <typename T, bool VEC>
 __global__ __launch_bounds__(kBlock) void k_llr(const uint8_t *__restrict__ y,
                                                 const double *__restrict__ e, T *__restrict__ out,
                                                 int32_t n) {
@@ -517,13 +557,30 @@ __global__ __launch_bounds__(kBlock) void k_llr(const uint8_t *__restrict__ y,
     const double ef = e[f];
     const double lam = log((1.0 - ef) / ef);
     const T pos = static_cast<T>(lam), neg = static_cast<T>(-lam);
-    const int i0 = blockIdx.x * kLlrPerBlock + threadIdx.x;
-    const uint8_t *yf = y + f * n;
-    T *of = out + f * n;
+    const int i0 = blockIdx.x * kLlrPerBlock + static_cast<int>(threadIdx.x) * kLlrPerThread;
+    if (i0 >= n) return;
+    const uint8_t *yf = y + f * n + i0;
+    T *of = out + f * n + i0;
+    if constexpr (VEC) {
+        const uint2 b = *reinterpret_cast<const uint2 *>(yf);
+        T v[kLlrPerThread];
 #pragma unroll
-    for (int k = 0; k < kLlrPerThread; ++k) {
-        const int i = i0 + k * kBlock;
-        if (i < n) of[i] = yf[i] ? neg : pos;
+        for (int k = 0; k < kLlrPerThread; ++k) {
+            const uint32_t w = k < 4 ? b.x : b.y;
+            v[k] = ((w >> (8 * (k & 3))) & 0xffu) ? neg : pos;
+        }
+        constexpr int kPer16 = 16 / static_cast<int>(sizeof(T));
+#pragma unroll
+        for (int k = 0; k < kLlrPerThread; k += kPer16) {
+            if constexpr (sizeof(T) == 4)
+                *reinterpret_cast<float4 *>(of + k) = make_float4(v[k], v[k + 1], v[k + 2], v[k + 3]);
+            else
+                *reinterpret_cast<double2 *>(of + k) = make_double2(v[k], v[k + 1]);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kLlrPerThread; ++k)
+            if (i0 + k < n) of[k] = yf[k] ? neg : pos;
     }
 }
 

@@ -293,6 +293,7 @@ struct Run {
     hipStream_t stream;
     FwdFn fwd;
     AdjPtr adj;
+    VarFn<float> kv;
     Dims dc, dv;
     int grid_c, grid_v, grid_a;
 
@@ -302,10 +303,12 @@ struct Run {
         if (rc != MBP_OK) return rc;
         pick(dmax_of(code->max_check_deg), &fwd, &adj);
         dc = Dims{code->E, n, M, ng, (M + kRowsPerTile - 1) / kRowsPerTile, 0, 0, 0.0, clip};
-        dv = Dims{code->E, n, M, ng, (n + kVarsPerTile - 1) / kVarsPerTile, 0, 0, 0.0, clip};
+        int vpt = 0;
+        kv = variable_kernel<float>(code->max_var_deg, &vpt);
+        dv = Dims{code->E, n, M, ng, (n + vpt - 1) / vpt, 0, 0, 0.0, clip};
         grid_c = grid_for(ctx, reinterpret_cast<const void *>(fwd), static_cast<int64_t>(ng) * dc.ntiles);
         grid_a = grid_for(ctx, reinterpret_cast<const void *>(adj), static_cast<int64_t>(ng) * dc.ntiles);
-        grid_v = grid_for(ctx, reinterpret_cast<const void *>(&k_variable<float>),
+        grid_v = grid_for(ctx, reinterpret_cast<const void *>(kv),
                           static_cast<int64_t>(ng) * dv.ntiles);
         float *lam = reinterpret_cast<float *>(ws + Ly.lam);
         uint64_t *act = reinterpret_cast<uint64_t *>(ws + Ly.act);
@@ -333,9 +336,8 @@ struct Run {
         fwd<<<grid_c, kBlock, 0, stream>>>(code->d_row_ptr, code->d_col, code->d_row_mat,
                                            alpha + static_cast<size_t>(t - 1) * code->u, zb, act,
                                            a.L, a.c ? a.c : b.c, b.c_mut, dc);
-        k_variable<float><<<grid_v, kBlock, 0, stream>>>(code->d_var_ptr, code->d_var_edge, b.c,
-                                                         reinterpret_cast<const float *>(ws + Ly.lam), b.L,
-                                                         act, nullptr, dv);
+        kv<<<grid_v, kBlock, 0, stream>>>(code->d_var_ptr, code->d_var_edge, b.c,
+                                          reinterpret_cast<const float *>(ws + Ly.lam), b.L, act, nullptr, dv);
     }
 };
 
@@ -385,6 +387,7 @@ int unrolled_backward(mbp_ctx *ctx, const mbp_code *code, int32_t F, int32_t K, 
     k_stage_llr<float><<<dim3((n + 63) / 64, ng), kBlock, 0, stream>>>(grad_out, glam, gA, F, n);
     Dims da = R.dc;
     Dims dva = R.dv;
+    dva.ntiles = (n + kVarsPerTile - 1) / kVarsPerTile;  // k_variable_adjoint's tile
     const int grid_va = grid_for(ctx, reinterpret_cast<const void *>(&k_variable_adjoint),
                                  static_cast<int64_t>(ng) * dva.ntiles);
     const int32_t nseg = (K + ck - 1) / ck;

@@ -40,11 +40,14 @@ def ragged_code():
     return peg_code(1000, 260, 2, W.IRREGULAR_238, seed_base=7100, name="peg-n1000")
 
 
-def test_llr_kernel_matches_oracle(ctx):
-    rng = np.random.default_rng(0)
+@pytest.mark.parametrize("n", [1000, 1003, 4099])
+def test_llr_kernel_matches_oracle(ctx, n):
+    """Rows of n = 1000 take the vector path (n a multiple of 8); 1003 and 4099
+    the per-element one."""
+    rng = np.random.default_rng(n)
     code = code_from_dense([np.array([[1, 1, 0], [0, 1, 1]], np.uint8)])
     fr = bsc_frames(code, 1, 0.1, seed=0)
-    fr.y = rng.integers(0, 2, (7, 1000)).astype(np.uint8)
+    fr.y = rng.integers(0, 2, (7, n)).astype(np.uint8)
     fr.p = rng.uniform(0.005, 0.3, 7)
     import torch
     from paper_2001_07979_amd import mbp
