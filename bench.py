@@ -43,9 +43,9 @@ def source_hash() -> str:
     return h.hexdigest()[:12]
 
 
-def stored_traffic():
+def stored_traffic(algo: str):
     """HBM bytes per check-node launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+    summary, if it was taken on the current kernel sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -56,7 +56,7 @@ def stored_traffic():
     if vals.get("kernel_source_sha1") != source_hash():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[f"hbm_bytes_per_launch_{algo}"])
     except (KeyError, ValueError):
         return None
 
@@ -352,7 +352,7 @@ def main():
         bytes_per_launch = per_step / launches_per_step
         avg_ms = ms_c / n_c
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        traffic = stored_traffic()
+        traffic = stored_traffic(wl.algo)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": traffic, "kernel": "k_check (check-node pass)",

@@ -201,6 +201,11 @@ int mbp_nms_unrolled_bwd(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, in
  *   blocks_per_cu                 resident blocks per compute unit (1..4)
  *   schedule                      0: item = block + k * grid (interleaved);
  *                                 1: each block takes a contiguous run
+ *   compact                       1: when a batch's running frames fit into
+ *                                 at most 3/4 of the groups they occupy, move
+ *                                 them (with their state) into the fewest
+ *                                 spare groups; 0: never (results are the
+ *                                 same either way)
  * mbp_autotune times a set of tunings on the given batches (their outputs are
  * overwritten) and returns the fastest; with cache_path it first looks the
  * batch mix up in that text file and appends new results to it. */
@@ -220,6 +225,7 @@ typedef struct {
     int32_t vars_per_wave;
     int32_t blocks_per_cu;
     int32_t schedule;
+    int32_t compact;
 } mbp_tuning;
 
 typedef struct mbp_plan mbp_plan;

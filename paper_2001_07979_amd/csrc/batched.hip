@@ -2,14 +2,25 @@
 // numbers of matrices) decoded by one persistent, cooperatively launched
 // kernel that runs every iteration itself.
 //
-// Each batch is one code with its frames; its frames form 64-frame groups as
-// in the plain decode (same layout, same per-group status words). The kernel
-// walks rounds: the check pass of iteration t over the tiles of every live
-// group of every batch, a grid barrier, the variable pass, a grid barrier;
-// it stops when every group has retired (early exit) or after T iterations,
-// then tests the last decisions of groups still running. Work items (group,
-// tile) are spread over the blocks by a schedule the autotuner picks:
-// interleaved (item = block + k * grid) or in contiguous runs per block.
+// Each batch is one code with its frames, in 64-frame groups as in the plain
+// decode (same interleaved layout). A batch owns twice its groups: the first
+// half holds its frames at the start; the second half are spare groups that
+// frame compaction fills. Every round of the kernel is
+//   check pass t | variable pass t (L^t and decision words) | stopping test
+//   of iteration t | settle (retire the frames that met every syndrome)
+// with a grid barrier after each phase, and, when a batch's running frames
+// fit into clearly fewer groups than they occupy, compaction: its running
+// frames are gathered, with their whole state (c^t, L^t, lambda, syndrome
+// bits), into the fewest spare groups, so the late iterations of frames that
+// converge slowly or not at all stop dragging partly empty groups along. A
+// frame's arithmetic does not depend on its slot, so the results equal the
+// plain decode's bit for bit. Each slot carries the index of the frame it
+// holds (-1 once vacated); iteration counts, flags and outputs go through it.
+//
+// Work inside a phase is spread over the blocks per live group: the tiles of
+// the groups still running form one item space, which the blocks take either
+// interleaved (item = block + k * grid) or in contiguous runs, as the tuning
+// says; retired and unused groups cost one load.
 //
 // The check rule is normalized min-sum in FP32, evaluated in chunks of the
 // check's edges so any check degree up to 64 shares one kernel: the first
@@ -27,10 +38,11 @@
 namespace mbp {
 namespace {
 
-constexpr int kChunk = 16;  // edges of a check gathered per round trip
+constexpr int kChunk = 16;       // edges of a check gathered per round trip
+constexpr int kMovePieces = 64;  // work items per group a compaction fills
 
-// Loads of data that no kernel of the decode writes (graph arrays, group
-// descriptors, syndromes) through the constant address space, so uniform
+// Loads of data that no phase of the kernel writes (graph arrays, group and
+// batch descriptors) through the constant address space, so uniform
 // addresses become scalar loads.
 template <typename T>
 __device__ __forceinline__ T ldc(const T *p, int64_t i) {
@@ -49,22 +61,23 @@ __device__ __forceinline__ void stg(T *p, int64_t i, T v) {
     ((__attribute__((address_space(1))) T *)p)[i] = v;
 }
 
+// A word that a compaction may have rewritten earlier in this launch: a
+// coherent vector load even where the address is uniform.
+__device__ __forceinline__ uint64_t ld_fresh(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 struct GroupDesc {
     const int32_t *row_ptr, *col, *var_ptr, *var_edge;
-    float *c, *Lp;
-    const float *lam;
-    const uint64_t *zb;
-    int32_t *iters_out;  // first frame of the group
-    uint8_t *ok_out;
+    float *c, *Lp, *lam;
+    uint64_t *zb, *D;
     int64_t E;
     int32_t n, M;
-    int32_t cn_tiles, vn_tiles;
-    int64_t cn_first, vn_first;  // first work item of the group in a round
+    int32_t item;  // batch of the group
+    int32_t cn_tiles, vn_tiles, st_tiles;
 };
 
 static_assert(sizeof(GroupDesc) % 8 == 0, "descriptors are copied as 64-bit words");
-constexpr int kCnFirstWord = offsetof(GroupDesc, cn_first) / 8;
-constexpr int kVnFirstWord = offsetof(GroupDesc, vn_first) / 8;
 
 // One descriptor, read word by word through the constant address space.
 __device__ __forceinline__ GroupDesc load_desc(const GroupDesc *gd, int g) {
@@ -76,28 +89,48 @@ __device__ __forceinline__ GroupDesc load_desc(const GroupDesc *gd, int g) {
     return d;
 }
 
+struct ItemDesc {
+    int32_t *iters_out;
+    uint8_t *ok_out;
+    int32_t g0, ng;  // groups [g0, g0 + ng) hold the frames; [g0 + ng, g0 + 2 ng) are spare
+    int32_t nframes, pad;
+};
+
+// Per-batch counters; running and live by round parity (a round writes one
+// parity while the previous round's readers may still read the other).
+struct ItemState {
+    uint32_t running[2], live[2];  // frames / groups still running after settle
+    uint32_t next_spare;           // spare groups filled so far
+    uint32_t pad[3];
+};
+
 struct Barrier {
-    unsigned count, gen, done, err;
-    int32_t last;  // last iteration run (for the finalize kernels)
-    int32_t pad[11];
+    unsigned count, gen, err;
+    unsigned live[2];  // groups still running after settle, by round parity
+    unsigned nnew[2];  // groups compaction filled, by round parity
+    int32_t pad[9];
 };
 
 struct PArgs {
     const GroupDesc *gd;
-    uint64_t *act, *uns;  // [group][kStride]
+    const ItemDesc *items;
+    ItemState *ist;
+    uint64_t *words;  // [group][kStride]: kRun, kUnmet
+    int32_t *fid;     // [group * 64 + lane]: frame (within its batch) the slot holds, or -1
+    int32_t *src;     // [group * 64 + lane]: slot a compaction moves here, or -1
+    int32_t *newg;    // groups filled by the current round's compaction
     Barrier *bar;
-    int64_t cn_items, vn_items;
-    int32_t ngroups, T, early_exit;
-    int32_t rows_per_wave, vars_per_wave, schedule;
+    int32_t ngroups, nitems, T, early_exit;
+    int32_t rows_per_wave, vars_per_wave, schedule, compact;
     float alpha, clip;
 };
 
 // A barrier wait gives up after this long on the 100 MHz real-time clock
-// (2 s); a legitimate wait is one round of work, far shorter.
+// (2 s); a legitimate wait is one phase of work, far shorter.
 constexpr uint64_t kWaitTicks = 200000000ull;
 // Resident blocks per compute unit that the persistent kernel may use: well
-// inside its register-limited occupancy (7 waves per SIMD, one wave of each
-// block per SIMD), so every block of the grid is resident at once.
+// inside its register-limited occupancy (one wave of each block per SIMD),
+// so every block of the grid is resident at once.
 constexpr int kMaxBlocksPerCu = 4;
 
 __device__ bool grid_sync(Barrier *b) {
@@ -130,48 +163,62 @@ __device__ bool grid_sync(Barrier *b) {
     return ok != 0;
 }
 
-// Group of work item w (gd sorted by first item): scalar binary search.
-__device__ __forceinline__ int group_of(const GroupDesc *gd, int ngroups, int64_t w, bool cn) {
-    int lo = 0, hi = ngroups - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        const int64_t *words = reinterpret_cast<const int64_t *>(gd + mid);
-        const int64_t first = ldc(words, cn ? kCnFirstWord : kVnFirstWord);
-        if (first <= w) lo = mid; else hi = mid - 1;
-    }
-    return lo;
+__device__ __forceinline__ uint64_t run_of(const PArgs &a, int g) {
+    return ld_fresh(&a.words[static_cast<size_t>(kStride) * g + kRun]);
 }
 
-// The k-th work item of this block under the schedule, or -1 when done.
-__device__ __forceinline__ int64_t item_at(int64_t k, int64_t total, int schedule) {
-    if (schedule == 0) {
-        const int64_t w = static_cast<int64_t>(blockIdx.x) + k * gridDim.x;
-        return w < total ? w : -1;
+// Calls fn(g, desc, run, tile) for this block's share of the tiles of the
+// groups still running; tiles_of(gd, g) is the phase's tile count of group g.
+// Schedule 0 interleaves the live item space over the blocks; schedule 1
+// gives each block one contiguous run of it.
+template <typename TilesOf, typename Fn>
+__device__ void for_live_tiles(const PArgs &a, TilesOf tiles_of, Fn fn) {
+    const int64_t grid = gridDim.x, b = blockIdx.x;
+    int64_t per = 0;
+    if (a.schedule == 1) {
+        int64_t total = 0;
+        for (int g = 0; g < a.ngroups; ++g)
+            if (run_of(a, g)) total += tiles_of(a.gd, g);
+        per = (total + grid - 1) / grid;
     }
-    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
-    if (k >= per) return -1;
-    const int64_t w = static_cast<int64_t>(blockIdx.x) * per + k;
-    return w < total ? w : -1;
+    int64_t base = 0;
+    for (int g = 0; g < a.ngroups; ++g) {
+        const uint64_t run = run_of(a, g);
+        if (!run) continue;
+        const int64_t nt = tiles_of(a.gd, g);
+        int64_t j0, j1, step;
+        if (a.schedule == 0) {
+            j0 = ((b - base) % grid + grid) % grid;
+            j1 = nt;
+            step = grid;
+        } else {
+            j0 = b * per - base;
+            j1 = j0 + per;
+            j0 = j0 < 0 ? 0 : j0;
+            j1 = j1 > nt ? nt : j1;
+            step = 1;
+        }
+        base += nt;
+        if (j0 >= j1) continue;
+        const GroupDesc G_ = load_desc(a.gd, g);
+        for (int64_t j = j0; j < j1; j += step) fn(g, G_, run, static_cast<int>(j));
+    }
 }
 
-// Min-sum check pass over one tile of a group (rows rpw per wave).
-__device__ void cn_tile(const GroupDesc &G_, int tile, int t, const PArgs &a, uint64_t gact,
-                        uint64_t *uns_word, bool test, uint64_t *sh_bad) {
+// Min-sum check pass over one tile of a group (rows_per_wave rows per wave).
+__device__ void cn_tile(const GroupDesc &G_, int tile, int t, const PArgs &a, uint64_t run) {
     const unsigned lane = lane_id();
     const int wave = wave_id();
-    const bool on = (gact >> lane) & 1;
+    const bool on = (run >> lane) & 1;
     const bool first = t == 1;
     const int rpt = a.rows_per_wave * kWaves;
-    uint64_t bad = 0;
     for (int k = 0; k < a.rows_per_wave; ++k) {
         const int r = tile * rpt + k * kWaves + wave;
         if (r >= G_.M) break;
         const int e0 = ldc(G_.row_ptr, r);
         const int d = ldc(G_.row_ptr, r + 1) - e0;
-        const int zbit = static_cast<int>((ldc(G_.zb, r) >> lane) & 1);
-        const size_t cb = static_cast<size_t>(e0) * G;
-        float *cg = G_.c + cb;
-        int par = 0;
+        const int zbit = static_cast<int>((ld_fresh(G_.zb + r) >> lane) & 1);
+        float *cg = G_.c + static_cast<size_t>(e0) * G;
         uint64_t neg = 0;
         int sx = zbit;
         float m1 = INFINITY, m2 = INFINITY;
@@ -192,7 +239,6 @@ __device__ void cn_tile(const GroupDesc &G_, int tile, int t, const PArgs &a, ui
 #pragma unroll
                 for (int j = 0; j < kChunk; ++j) {
                     if (j0 + j < d) {
-                        par ^= Lv[j] < 0.0f ? 1 : 0;
                         const float q = Lv[j] - cv[j];
                         const int s = q < 0.0f ? 1 : 0;
                         sx ^= s;
@@ -218,173 +264,318 @@ __device__ void cn_tile(const GroupDesc &G_, int tile, int t, const PArgs &a, ui
                 stg(cg, static_cast<int64_t>(j) * G + lane, s ? -mag : mag);
             }
         }
-        bad |= __ballot(on && (par != zbit));
-    }
-    if (test) {
-        if (lane == 0) sh_bad[wave] = bad;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint64_t b = 0;
-            for (int i = 0; i < kWaves; ++i) b |= sh_bad[i];
-            or_unmet(uns_word, b);
-        }
-        __syncthreads();
     }
 }
 
-// Syndrome-only pass over one tile (stopping test of the decisions in Lp).
-__device__ void syn_tile(const GroupDesc &G_, int tile, const PArgs &a, uint64_t gact,
-                         uint64_t *uns_word, uint64_t *sh_bad) {
+// Variable pass over one tile: L^t (eq. (2), in edge order) and the
+// decision word of each variable.
+__device__ void vn_tile(const GroupDesc &G_, int tile, const PArgs &a, uint64_t run) {
     const unsigned lane = lane_id();
     const int wave = wave_id();
-    const bool on = (gact >> lane) & 1;
-    const int rpt = a.rows_per_wave * kWaves;
-    uint64_t bad = 0;
-    for (int k = 0; k < a.rows_per_wave; ++k) {
-        const int r = tile * rpt + k * kWaves + wave;
-        if (r >= G_.M) break;
-        const int e0 = ldc(G_.row_ptr, r);
-        const int d = ldc(G_.row_ptr, r + 1) - e0;
-        const int zbit = static_cast<int>((ldc(G_.zb, r) >> lane) & 1);
-        int par = 0;
-        for (int j0 = 0; j0 < d; j0 += kChunk) {
-            int v[kChunk];
-#pragma unroll
-            for (int j = 0; j < kChunk; ++j) v[j] = ldc(G_.col, e0 + j0 + j);
-            if (on) {
-#pragma unroll
-                for (int j = 0; j < kChunk; ++j)
-                    if (j0 + j < d) par ^= ldg(G_.Lp, static_cast<int64_t>(v[j]) * G + lane) < 0.0f ? 1 : 0;
-            }
-        }
-        bad |= __ballot(on && (par != zbit));
-    }
-    if (lane == 0) sh_bad[wave] = bad;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t b = 0;
-        for (int i = 0; i < kWaves; ++i) b |= sh_bad[i];
-        or_unmet(uns_word, b);
-    }
-    __syncthreads();
-}
-
-// Variable pass over one tile; the tile-0 wave does the group's bookkeeping.
-__device__ void vn_tile(const GroupDesc &G_, int g, int tile, int t, const PArgs &a) {
-    const unsigned lane = lane_id();
-    const int wave = wave_id();
-    const int pt = t & 1, nt = (t + 1) & 1;
-    uint64_t *actg = a.act + static_cast<size_t>(kStride) * g;
-    uint64_t *unsg = a.uns + static_cast<size_t>(kStride) * g;
-    const uint64_t gact = actg[pt];
-    const uint64_t U = (a.early_exit && t > 1) ? unsg[pt] : ~0ull;
-    const uint64_t run = gact & U;
-    if (tile == 0 && wave == 0) {
-        const uint64_t conv = gact & ~U;
-        if (lane == 0) {
-            actg[nt] = run;
-            unsg[nt] = 0;
-            if (gact != 0 && run == 0) atomicAdd(&a.bar->done, 1u);
-        }
-        if ((conv >> lane) & 1) {
-            stg(G_.iters_out, lane, t - 1);
-            stg(G_.ok_out, lane, static_cast<uint8_t>(1));
-        }
-    }
-    if (!((run >> lane) & 1)) return;
+    const bool on = (run >> lane) & 1;
     const int vpt = a.vars_per_wave * kWaves;
     for (int k = 0; k < a.vars_per_wave; ++k) {
         const int i = tile * vpt + k * kWaves + wave;
         if (i >= G_.n) break;
         const int k0 = ldc(G_.var_ptr, i), k1 = ldc(G_.var_ptr, i + 1);
-        float s = ldg(G_.lam, static_cast<int64_t>(i) * G + lane);
+        float s = on ? ldg(G_.lam, static_cast<int64_t>(i) * G + lane) : 0.0f;
         for (int kk = k0; kk < k1; kk += kIdxChunk) {
             int ev[kIdxChunk];
 #pragma unroll
             for (int j = 0; j < kIdxChunk; ++j) ev[j] = ldc(G_.var_edge, kk + j);
-            float x[kIdxChunk];
+            if (on) {
+                float x[kIdxChunk];
 #pragma unroll
-            for (int j = 0; j < kIdxChunk; ++j)
-                if (kk + j < k1) x[j] = ldg(G_.c, static_cast<int64_t>(ev[j]) * G + lane);
+                for (int j = 0; j < kIdxChunk; ++j)
+                    if (kk + j < k1) x[j] = ldg(G_.c, static_cast<int64_t>(ev[j]) * G + lane);
 #pragma unroll
-            for (int j = 0; j < kIdxChunk; ++j)
-                if (kk + j < k1) s += x[j];
+                for (int j = 0; j < kIdxChunk; ++j)
+                    if (kk + j < k1) s += x[j];
+            }
         }
-        stg(G_.Lp, static_cast<int64_t>(i) * G + lane, s);
+        if (on) stg(G_.Lp, static_cast<int64_t>(i) * G + lane, s);
+        const uint64_t bits = __ballot(on && s < 0.0f);
+        if (lane == 0) stg(G_.D, i, bits);
+    }
+}
+
+// Stopping test over one tile of kBlock checks: one thread per check XORs
+// the check's decision words with its syndrome word; the frames whose
+// parity differs are ORed into the group's kUnmet word.
+__device__ void st_tile(const GroupDesc &G_, int g, int tile, const PArgs &a, uint64_t run,
+                        uint32_t *sh_or) {
+    const unsigned lane = lane_id();
+    const int wave = wave_id();
+    const int r = tile * kBlock + static_cast<int>(threadIdx.x);
+    uint64_t unmet = 0;
+    if (r < G_.M) {
+        uint64_t par = ld_fresh(G_.zb + r);
+        const int e1 = ldg(G_.row_ptr, r + 1);
+        for (int e = ldg(G_.row_ptr, r); e < e1; e += kIdxChunk) {
+            int v[kIdxChunk];
+#pragma unroll
+            for (int j = 0; j < kIdxChunk; ++j) v[j] = ldg(G_.col, e + j);
+            uint64_t dw[kIdxChunk];
+#pragma unroll
+            for (int j = 0; j < kIdxChunk; ++j) dw[j] = e + j < e1 ? ldg(G_.D, v[j]) : 0;
+#pragma unroll
+            for (int j = 0; j < kIdxChunk; ++j) par ^= dw[j];
+        }
+        unmet = par & run;
+    }
+    uint32_t lo = static_cast<uint32_t>(unmet), hi = static_cast<uint32_t>(unmet >> 32);
+    for (int o = 32; o > 0; o >>= 1) {
+        lo |= __shfl_xor(lo, o);
+        hi |= __shfl_xor(hi, o);
+    }
+    if (lane == 0) {
+        sh_or[2 * wave] = lo;
+        sh_or[2 * wave + 1] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t bits = 0;
+        for (int i = 0; i < kWaves; ++i)
+            bits |= static_cast<uint64_t>(sh_or[2 * i]) | (static_cast<uint64_t>(sh_or[2 * i + 1]) << 32);
+        or_unmet(&a.words[static_cast<size_t>(kStride) * g + kUnmet], bits);
+    }
+    __syncthreads();
+}
+
+// Settle of round t for one group (one wave): frames with no unmet check
+// stop at t with ok = 1; on the last iteration the others stop with ok = 0.
+__device__ void settle_group(const PArgs &a, int g, int t, int par) {
+    const unsigned lane = lane_id();
+    uint64_t *w = a.words + static_cast<size_t>(kStride) * g;
+    const uint64_t run = ld_fresh(&w[kRun]);
+    if (!run) return;
+    const uint64_t un = ld_fresh(&w[kUnmet]);
+    const bool last = t == a.T;
+    const uint64_t next = last ? 0 : (run & un);
+    const int item = ldc(&a.gd[g].item, 0);
+    if (((run & ~next) >> lane) & 1) {
+        const int f = a.fid[static_cast<size_t>(g) * G + lane];
+        stg(ldc(&a.items[item].iters_out, 0), f, static_cast<int32_t>(t));
+        stg(ldc(&a.items[item].ok_out, 0), f, static_cast<uint8_t>(((un >> lane) & 1) ? 0 : 1));
+    }
+    if (lane == 0) {
+        w[kRun] = next;
+        w[kUnmet] = 0;
+        if (next) {
+            atomicAdd(&a.ist[item].running[par], static_cast<unsigned>(__popcll(next)));
+            atomicAdd(&a.ist[item].live[par], 1u);
+            atomicAdd(&a.bar->live[par], 1u);
+        }
+    }
+}
+
+// Whether batch i compacts after round t: its running frames fit into at
+// most three quarters of the groups they occupy, enough spare groups remain,
+// and at least two iterations remain to profit from it. *K = groups needed.
+__device__ bool wants_compaction(const PArgs &a, int i, int t, int par, int *K) {
+    if (!a.compact || t > a.T - 2) return false;
+    ItemState *s = a.ist + i;
+    const uint32_t R = __hip_atomic_load(&s->running[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t L = __hip_atomic_load(&s->live[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t used = __hip_atomic_load(&s->next_spare, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t ng = static_cast<uint32_t>(ldc(&a.items[i].ng, 0));
+    const uint32_t k = (R + G - 1) / G;
+    *K = static_cast<int>(k);
+    return L >= 2 && 4 * k <= 3 * L && used + k <= ng;
+}
+
+// Compaction plan of batch i (one block): the running frames of its groups,
+// in group and lane order, go to consecutive slots of K fresh spare groups;
+// their old groups stop running.
+__device__ void plan_compaction(const PArgs &a, int i, int K, int par) {
+    __shared__ uint32_t scan[kBlock];
+    __shared__ uint32_t sh_base;
+    const int g0 = ldc(&a.items[i].g0, 0), ng = ldc(&a.items[i].ng, 0);
+    ItemState *s = a.ist + i;
+    const uint32_t used = __hip_atomic_load(&s->next_spare, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int first_new = g0 + ng + static_cast<int>(used);
+    const int ncand = ng + static_cast<int>(used);  // the originals and the spares filled so far
+    if (threadIdx.x == 0) sh_base = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < ncand; c0 += kBlock) {
+        const int ci = c0 + static_cast<int>(threadIdx.x);
+        const int g = g0 + ci;
+        const uint64_t run = ci < ncand ? run_of(a, g) : 0;
+        const uint32_t cnt = static_cast<uint32_t>(__popcll(run));
+        scan[threadIdx.x] = cnt;
+        __syncthreads();
+        for (int o = 1; o < kBlock; o <<= 1) {  // inclusive scan
+            const uint32_t v = threadIdx.x >= static_cast<unsigned>(o) ? scan[threadIdx.x - o] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += v;
+            __syncthreads();
+        }
+        uint32_t k = sh_base + scan[threadIdx.x] - cnt;
+        const uint32_t room = static_cast<uint32_t>(K) * G;  // equals the frames counted at settle
+        for (uint64_t r = run; r && k < room; r &= r - 1) {
+            const int l = __ffsll(static_cast<unsigned long long>(r)) - 1;
+            const size_t from = static_cast<size_t>(g) * G + l;
+            const size_t to = static_cast<size_t>(first_new) * G + k;
+            a.src[to] = static_cast<int32_t>(from);
+            a.fid[to] = a.fid[from];
+            a.fid[from] = -1;
+            ++k;
+        }
+        if (run) a.words[static_cast<size_t>(kStride) * g + kRun] = 0;
+        __syncthreads();
+        if (threadIdx.x == kBlock - 1) sh_base += scan[kBlock - 1];
+        __syncthreads();
+    }
+    const uint32_t R = sh_base;
+    for (int j = threadIdx.x; j < K * G; j += kBlock)
+        if (static_cast<uint32_t>(j) >= R) a.src[static_cast<size_t>(first_new) * G + j] = -1;
+    for (int j = threadIdx.x; j < K; j += kBlock) {
+        const uint32_t lo = static_cast<uint32_t>(j) * G;
+        const uint32_t cnt = R - lo >= static_cast<uint32_t>(G) ? G : R - lo;
+        const uint64_t mask = cnt >= static_cast<uint32_t>(G) ? ~0ull : ((1ull << cnt) - 1ull);
+        uint64_t *w = a.words + static_cast<size_t>(kStride) * (first_new + j);
+        w[kRun] = mask;
+        w[kUnmet] = 0;
+        const unsigned at = atomicAdd(&a.bar->nnew[par], 1u);
+        a.newg[at] = first_new + j;
+    }
+    if (threadIdx.x == 0) s->next_spare = used + static_cast<uint32_t>(K);
+}
+
+// Fills piece p (of kMovePieces) of a group a compaction filled: rows of c
+// (E), L and lambda (n each) and syndrome words (M), each lane from its
+// source slot. One wave per row.
+__device__ void move_piece(const PArgs &a, int g, int p) {
+    const unsigned lane = lane_id();
+    const int wave = wave_id();
+    const GroupDesc G_ = load_desc(a.gd, g);
+    const int32_t s = a.src[static_cast<size_t>(g) * G + lane];
+    const bool has = s >= 0;
+    const int sg = has ? s / G : g, sl = has ? s % G : 0;
+    const float *sc = ldg(&a.gd[sg].c, 0), *sL = ldg(&a.gd[sg].Lp, 0), *slam = ldg(&a.gd[sg].lam, 0);
+    const uint64_t *szb = ldg(&a.gd[sg].zb, 0);
+    auto span = [&](int64_t rows, int64_t *r0, int64_t *r1) {
+        const int64_t per = (rows + kMovePieces - 1) / kMovePieces;
+        *r0 = p * per;
+        *r1 = *r0 + per < rows ? *r0 + per : rows;
+    };
+    int64_t r0, r1;
+    span(G_.E, &r0, &r1);
+    for (int64_t r = r0 + wave; r < r1; r += kWaves)
+        if (has) stg(G_.c, r * G + lane, ldg(sc, r * G + sl));
+    span(G_.n, &r0, &r1);
+    for (int64_t r = r0 + wave; r < r1; r += kWaves) {
+        if (has) {
+            stg(G_.Lp, r * G + lane, ldg(sL, r * G + sl));
+            stg(G_.lam, r * G + lane, ldg(slam, r * G + sl));
+        }
+    }
+    span(G_.M, &r0, &r1);
+    for (int64_t r = r0 + wave; r < r1; r += kWaves) {
+        const uint64_t bits = __ballot(has && ((ld_fresh(szb + r) >> sl) & 1));
+        if (lane == 0) stg(G_.zb, r, bits);
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_persistent(PArgs a) {
-    __shared__ uint64_t sh_bad[kWaves];
-    int32_t t = 1;
-    bool alive = true;
-    for (; t <= a.T && alive; ++t) {
-        const int pt = t & 1;
-        const bool test = a.early_exit && t > 1;
-        for (int64_t k = 0;; ++k) {
-            const int64_t w = item_at(k, a.cn_items, a.schedule);
-            if (w < 0) break;
-            const int g = group_of(a.gd, a.ngroups, w, true);
-            const GroupDesc G_ = load_desc(a.gd, g);
-            const uint64_t gact = a.act[static_cast<size_t>(kStride) * g + pt];
-            if (gact == 0) continue;
-            cn_tile(G_, static_cast<int>(w - G_.cn_first), t, a, gact,
-                    a.uns + static_cast<size_t>(kStride) * g + pt, test, sh_bad);
+    __shared__ uint32_t sh_or[2 * kWaves];
+    for (int t = 1; t <= a.T; ++t) {
+        const int par = t & 1;
+        // clear the next round's counters (their readers finished in round t-1)
+        if (blockIdx.x == 0) {
+            for (int i = threadIdx.x; i < a.nitems; i += kBlock) {
+                a.ist[i].running[par ^ 1] = 0;
+                a.ist[i].live[par ^ 1] = 0;
+            }
+            if (threadIdx.x == 0) {
+                a.bar->live[par ^ 1] = 0;
+                a.bar->nnew[par ^ 1] = 0;
+            }
         }
-        if (!grid_sync(a.bar)) { alive = false; break; }
-        for (int64_t k = 0;; ++k) {
-            const int64_t w = item_at(k, a.vn_items, a.schedule);
-            if (w < 0) break;
-            const int g = group_of(a.gd, a.ngroups, w, false);
-            const GroupDesc G_ = load_desc(a.gd, g);
-            vn_tile(G_, g, static_cast<int>(w - G_.vn_first), t, a);
+        for_live_tiles(a, [](const GroupDesc *gd, int g) { return ldc(&gd[g].cn_tiles, 0); },
+                       [&](int, const GroupDesc &G_, uint64_t run, int tile) { cn_tile(G_, tile, t, a, run); });
+        if (!grid_sync(a.bar)) return;
+        for_live_tiles(a, [](const GroupDesc *gd, int g) { return ldc(&gd[g].vn_tiles, 0); },
+                       [&](int, const GroupDesc &G_, uint64_t run, int tile) { vn_tile(G_, tile, a, run); });
+        if (!grid_sync(a.bar)) return;
+        if (!a.early_exit && t < a.T) continue;
+        for_live_tiles(a, [](const GroupDesc *gd, int g) { return ldc(&gd[g].st_tiles, 0); },
+                       [&](int g, const GroupDesc &G_, uint64_t run, int tile) {
+                           st_tile(G_, g, tile, a, run, sh_or);
+                       });
+        if (!grid_sync(a.bar)) return;
+        for (int g = blockIdx.x * kWaves + wave_id(); g < a.ngroups; g += gridDim.x * kWaves)
+            settle_group(a, g, t, par);
+        if (!grid_sync(a.bar)) return;
+        if (__hip_atomic_load(&a.bar->live[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
+        for (int i = blockIdx.x; i < a.nitems; i += gridDim.x) {
+            int K = 0;
+            if (wants_compaction(a, i, t, par, &K)) plan_compaction(a, i, K, par);
         }
-        if (!grid_sync(a.bar)) { alive = false; break; }
-        if (a.early_exit &&
-            __hip_atomic_load(&a.bar->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-                static_cast<unsigned>(a.ngroups)) {
-            ++t;
-            break;
-        }
+        if (!grid_sync(a.bar)) return;
+        const unsigned nnew =
+            __hip_atomic_load(&a.bar->nnew[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (nnew == 0) continue;
+        for (int64_t w = blockIdx.x; w < static_cast<int64_t>(nnew) * kMovePieces; w += gridDim.x)
+            move_piece(a, a.newg[w / kMovePieces], static_cast<int>(w % kMovePieces));
+        if (!grid_sync(a.bar)) return;
     }
-    if (!alive) return;
-    const int32_t last = t - 1;
-    // stopping test of the last decisions for groups still running
-    const int pf = (last + 1) & 1;
-    for (int64_t k = 0;; ++k) {
-        const int64_t w = item_at(k, a.cn_items, a.schedule);
-        if (w < 0) break;
-        const int g = group_of(a.gd, a.ngroups, w, true);
-        const GroupDesc G_ = load_desc(a.gd, g);
-        const uint64_t gact = a.act[static_cast<size_t>(kStride) * g + pf];
-        if (gact == 0) continue;
-        syn_tile(G_, static_cast<int>(w - G_.cn_first), a, gact, a.uns + static_cast<size_t>(kStride) * g + pf,
-                 sh_bad);
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.bar->last = last;
 }
 
-__global__ void k_reset_barrier(Barrier *b) {
-    if (threadIdx.x == 0) {
+__global__ void k_reset(Barrier *b, ItemState *ist, int32_t nitems) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
         b->count = 0;
         b->gen = 0;
-        b->done = 0;
         b->err = 0;
-        b->last = 0;
+        b->live[0] = b->live[1] = 0;
+        b->nnew[0] = b->nnew[1] = 0;
+    }
+    if (i < nitems) {
+        ist[i].running[0] = ist[i].running[1] = 0;
+        ist[i].live[0] = ist[i].live[1] = 0;
+        ist[i].next_spare = 0;
     }
 }
 
-// ok / iters of frames still running after the last iteration (read from the
-// barrier record, which the persistent kernel filled).
-__global__ void k_finalize_last(const uint64_t *act, const uint64_t *uns, int32_t *iters_out,
-                                uint8_t *ok_out, int32_t nframes, const Barrier *bar) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nframes) return;
-    const int32_t last = bar->last;
-    const int g = f / G, lane = f % G, p = (last + 1) & 1;
-    if ((act[kStride * g + p] >> lane) & 1) {
-        ok_out[f] = ((uns[kStride * g + p] >> lane) & 1) ? 0 : 1;
-        iters_out[f] = last;
+// Slots of a batch's 2 ng groups (originals, then spares) before the decode:
+// running masks of its frames, their frame indices, empty spares.
+__global__ void k_init_slots(uint64_t *words, int32_t *fid, int32_t g0, int32_t ng, int32_t nframes) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= 2 * ng * G) return;
+    const int k = j / G, lane = j % G;
+    const bool orig = k < ng;
+    const int f = k * G + lane;
+    fid[static_cast<size_t>(g0) * G + j] = orig && f < nframes ? f : -1;
+    if (lane == 0) {
+        const int rem = nframes - k * G;
+        const uint64_t valid = !orig ? 0 : rem >= G ? ~0ull : ((1ull << rem) - 1ull);
+        words[static_cast<size_t>(kStride) * (g0 + k) + kRun] = valid;
+        words[static_cast<size_t>(kStride) * (g0 + k) + kUnmet] = 0;
+    }
+}
+
+// [group][n][64] -> bits and L rows [frame][n] of one batch, from every slot
+// that still holds its frame (fid >= 0), i.e. the frame's final state.
+__global__ __launch_bounds__(kBlock) void k_output_slots(const float *Lp, const int32_t *fid, uint8_t *bits,
+                                                         float *llr_out, int32_t n) {
+    __shared__ float tile[64][65];
+    __shared__ int32_t f_of[64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int k = blockIdx.y, i0 = blockIdx.x * 64;
+    if (threadIdx.x < 64) f_of[threadIdx.x] = fid[static_cast<size_t>(k) * G + threadIdx.x];
+    for (int iy = ty; iy < 64; iy += kWaves) {
+        const int i = i0 + iy;
+        tile[iy][tx] = i < n ? Lp[(static_cast<size_t>(k) * n + i) * G + tx] : 0.0f;
+    }
+    __syncthreads();
+    for (int fy = ty; fy < 64; fy += kWaves) {
+        const int f = f_of[fy], i = i0 + tx;
+        if (f < 0 || i >= n) continue;
+        const float v = tile[tx][fy];
+        const size_t o = static_cast<size_t>(f) * n + i;
+        if (bits) bits[o] = v < 0.0f ? 1 : 0;
+        if (llr_out) llr_out[o] = v;
     }
 }
 
@@ -394,15 +585,15 @@ __global__ void k_flag_error(const Barrier *bar, int32_t *err_out) {
 
 // ------------------------------------------------------------------- host
 struct BatchPlace {
-    int32_t group0, ngroups;
-    size_t c, Lp, lam, zb;  // byte offsets of the batch's first group
+    int32_t group0, ngroups;  // first group; groups holding frames (as many spares follow)
+    size_t c, Lp, lam, zb, D;  // byte offsets of the batch's arrays
 };
 
 struct Built {
     std::vector<GroupDesc> gd;
+    std::vector<ItemDesc> items;
     std::vector<BatchPlace> place;
-    size_t off_gd, off_act, off_uns, off_bar, off_err, total;
-    int64_t cn_items, vn_items;
+    size_t off_gd, off_items, off_ist, off_words, off_src, off_newg, off_fid, off_bar, off_err, total;
     int32_t ngroups;
 };
 
@@ -415,30 +606,43 @@ Built lay_out(int32_t nb, const mbp_batch *b, const mbp_tuning &tu) {
         return at;
     };
     int32_t ng = 0;
-    for (int32_t i = 0; i < nb; ++i) ng += (b[i].nframes + G - 1) / G;
+    for (int32_t i = 0; i < nb; ++i) ng += 2 * ((b[i].nframes + G - 1) / G);
     B.ngroups = ng;
     B.off_gd = take(sizeof(GroupDesc) * std::max(ng, 1));
-    B.off_act = take(sizeof(uint64_t) * kStride * std::max(ng, 1));
-    B.off_uns = take(sizeof(uint64_t) * kStride * std::max(ng, 1));
+    B.off_items = take(sizeof(ItemDesc) * std::max(nb, 1));
+    B.off_ist = take(sizeof(ItemState) * std::max(nb, 1));
+    B.off_words = take(sizeof(uint64_t) * kStride * std::max(ng, 1));
+    B.off_src = take(sizeof(int32_t) * G * std::max(ng, 1));
+    B.off_newg = take(sizeof(int32_t) * std::max(ng, 1));
+    B.off_fid = take(sizeof(int32_t) * G * std::max(ng, 1));
     B.off_bar = take(sizeof(Barrier));
     B.off_err = take(sizeof(int32_t));
     const int rpt = tu.rows_per_wave * kWaves, vpt = tu.vars_per_wave * kWaves;
-    int64_t cn = 0, vn = 0;
     for (int32_t i = 0; i < nb; ++i) {
         const mbp_code *code = b[i].code;
         BatchPlace P{};
         P.group0 = static_cast<int32_t>(B.gd.size());
         P.ngroups = (b[i].nframes + G - 1) / G;
+        const int32_t all = 2 * P.ngroups;
         // per-group strides are the ones the staging and output kernels index
         // with (g * E * G, g * n * G, g * M); each batch's region is aligned
         const size_t sc = static_cast<size_t>(code->E) * G * sizeof(float);
         const size_t sl = static_cast<size_t>(code->n) * G * sizeof(float);
         const size_t sz = static_cast<size_t>(code->M) * sizeof(uint64_t);
-        P.c = take(sc * P.ngroups);
-        P.Lp = take(sl * P.ngroups);
-        P.lam = take(sl * P.ngroups);
-        P.zb = take(sz * P.ngroups);
-        for (int32_t k = 0; k < P.ngroups; ++k) {
+        const size_t sd = static_cast<size_t>(code->n) * sizeof(uint64_t);
+        P.c = take(sc * all);
+        P.Lp = take(sl * all);
+        P.lam = take(sl * all);
+        P.zb = take(sz * all);
+        P.D = take(sd * all);
+        ItemDesc it{};
+        it.iters_out = b[i].iters_out;
+        it.ok_out = b[i].ok_out;
+        it.g0 = P.group0;
+        it.ng = P.ngroups;
+        it.nframes = b[i].nframes;
+        B.items.push_back(it);
+        for (int32_t k = 0; k < all; ++k) {
             GroupDesc d{};
             d.row_ptr = code->d_row_ptr;
             d.col = code->d_col;
@@ -447,25 +651,20 @@ Built lay_out(int32_t nb, const mbp_batch *b, const mbp_tuning &tu) {
             // state pointers are filled in once the workspace base is known
             d.c = reinterpret_cast<float *>(P.c + k * sc);
             d.Lp = reinterpret_cast<float *>(P.Lp + k * sl);
-            d.lam = reinterpret_cast<const float *>(P.lam + k * sl);
-            d.zb = reinterpret_cast<const uint64_t *>(P.zb + k * sz);
-            d.iters_out = b[i].iters_out + k * G;
-            d.ok_out = b[i].ok_out + k * G;
+            d.lam = reinterpret_cast<float *>(P.lam + k * sl);
+            d.zb = reinterpret_cast<uint64_t *>(P.zb + k * sz);
+            d.D = reinterpret_cast<uint64_t *>(P.D + k * sd);
             d.E = code->E;
             d.n = code->n;
             d.M = code->M;
+            d.item = i;
             d.cn_tiles = (code->M + rpt - 1) / rpt;
             d.vn_tiles = (code->n + vpt - 1) / vpt;
-            d.cn_first = cn;
-            d.vn_first = vn;
-            cn += d.cn_tiles;
-            vn += d.vn_tiles;
+            d.st_tiles = (code->M + kBlock - 1) / kBlock;
             B.gd.push_back(d);
         }
         B.place.push_back(P);
     }
-    B.cn_items = cn;
-    B.vn_items = vn;
     B.total = o;
     return B;
 }
@@ -474,8 +673,9 @@ void rebase(Built &B, char *base) {
     for (GroupDesc &d : B.gd) {
         d.c = reinterpret_cast<float *>(base + reinterpret_cast<size_t>(d.c));
         d.Lp = reinterpret_cast<float *>(base + reinterpret_cast<size_t>(d.Lp));
-        d.lam = reinterpret_cast<const float *>(base + reinterpret_cast<size_t>(d.lam));
-        d.zb = reinterpret_cast<const uint64_t *>(base + reinterpret_cast<size_t>(d.zb));
+        d.lam = reinterpret_cast<float *>(base + reinterpret_cast<size_t>(d.lam));
+        d.zb = reinterpret_cast<uint64_t *>(base + reinterpret_cast<size_t>(d.zb));
+        d.D = reinterpret_cast<uint64_t *>(base + reinterpret_cast<size_t>(d.D));
     }
 }
 
@@ -494,30 +694,32 @@ int persistent_blocks_per_cu() {
     return cached;
 }
 
-// Upload the group descriptors (synchronous) after pointing them into the
-// workspace at `base`.
+// Upload the group and batch descriptors (synchronous) after pointing them
+// into the workspace at `base`.
 int upload_descriptors(Built &B, char *base) {
     rebase(B, base);
     hipError_t err = hipMemcpy(base + B.off_gd, B.gd.data(), sizeof(GroupDesc) * B.gd.size(),
                                hipMemcpyHostToDevice);
+    if (err == hipSuccess)
+        err = hipMemcpy(base + B.off_items, B.items.data(), sizeof(ItemDesc) * B.items.size(),
+                        hipMemcpyHostToDevice);
     return err == hipSuccess ? MBP_OK : hip_fail(err, "descriptor upload");
 }
 
 // Enqueue the whole batched decode on `stream` (kernels only, so it can be
-// captured into a graph): staging, the persistent decode, finalize, outputs.
-int enqueue_kernels(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_params *p, const mbp_tuning &tu,
-                    const Built &B, char *base, hipStream_t stream, bool cooperative) {
-    uint64_t *act = reinterpret_cast<uint64_t *>(base + B.off_act);
-    uint64_t *uns = reinterpret_cast<uint64_t *>(base + B.off_uns);
+// captured into a graph): staging, the persistent decode, outputs.
+int enqueue_kernels(int32_t nb, const mbp_batch *b, const mbp_params *p, const mbp_tuning &tu, const Built &B,
+                    char *base, int num_cus, hipStream_t stream, bool cooperative) {
+    uint64_t *words = reinterpret_cast<uint64_t *>(base + B.off_words);
+    int32_t *fid = reinterpret_cast<int32_t *>(base + B.off_fid);
     Barrier *bar = reinterpret_cast<Barrier *>(base + B.off_bar);
-    k_reset_barrier<<<1, 64, 0, stream>>>(bar);
+    ItemState *ist = reinterpret_cast<ItemState *>(base + B.off_ist);
+    k_reset<<<(std::max(nb, 1) + 255) / 256, 256, 0, stream>>>(bar, ist, nb);
     for (int32_t i = 0; i < nb; ++i) {
         const BatchPlace &P = B.place[i];
         const mbp_code *code = b[i].code;
         const int32_t F = b[i].nframes, n = code->n, M = code->M;
-        k_init_groups<<<(P.ngroups + 63) / 64, 64, 0, stream>>>(act + static_cast<size_t>(kStride) * P.group0,
-                                                               uns + static_cast<size_t>(kStride) * P.group0,
-                                                               ctx->status_dev + P.group0, F, P.ngroups);
+        k_init_slots<<<(2 * P.ngroups * G + 255) / 256, 256, 0, stream>>>(words, fid, P.group0, P.ngroups, F);
         float *lam = reinterpret_cast<float *>(base + P.lam), *Lp = reinterpret_cast<float *>(base + P.Lp);
         k_stage_llr<float><<<dim3((n + 63) / 64, P.ngroups), kBlock, 0, stream>>>(b[i].llr, lam, Lp, F, n);
         k_stage_synd<<<dim3((M + kBlock - 1) / kBlock, P.ngroups), kBlock, 0, stream>>>(
@@ -525,11 +727,26 @@ int enqueue_kernels(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_para
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return hip_fail(err, "batched staging launch");
-    PArgs a{reinterpret_cast<const GroupDesc *>(base + B.off_gd), act, uns, bar, B.cn_items, B.vn_items,
-            B.ngroups, p->max_iter, p->early_exit, tu.rows_per_wave, tu.vars_per_wave, tu.schedule,
-            static_cast<float>(p->alpha), static_cast<float>(p->llr_clip)};
+    PArgs a{reinterpret_cast<const GroupDesc *>(base + B.off_gd),
+            reinterpret_cast<const ItemDesc *>(base + B.off_items),
+            ist,
+            words,
+            fid,
+            reinterpret_cast<int32_t *>(base + B.off_src),
+            reinterpret_cast<int32_t *>(base + B.off_newg),
+            bar,
+            B.ngroups,
+            nb,
+            p->max_iter,
+            p->early_exit,
+            tu.rows_per_wave,
+            tu.vars_per_wave,
+            tu.schedule,
+            tu.compact,
+            static_cast<float>(p->alpha),
+            static_cast<float>(p->llr_clip)};
     const int bpc = std::max(1, std::min({tu.blocks_per_cu, persistent_blocks_per_cu(), kMaxBlocksPerCu}));
-    const int grid = ctx->num_cus * bpc;
+    const int grid = num_cus * bpc;
     void *args[] = {&a};
     if (cooperative)
         err = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_persistent), dim3(grid), dim3(kBlock),
@@ -540,13 +757,10 @@ int enqueue_kernels(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_para
     if (err != hipSuccess) return hip_fail(err, "persistent decode launch");
     for (int32_t i = 0; i < nb; ++i) {
         const BatchPlace &P = B.place[i];
-        const mbp_code *code = b[i].code;
-        const int32_t F = b[i].nframes, n = code->n;
-        k_finalize_last<<<(F + 255) / 256, 256, 0, stream>>>(act + static_cast<size_t>(kStride) * P.group0,
-                                                            uns + static_cast<size_t>(kStride) * P.group0,
-                                                            b[i].iters_out, b[i].ok_out, F, bar);
-        k_output<float><<<dim3((n + 63) / 64, P.ngroups), kBlock, 0, stream>>>(
-            reinterpret_cast<const float *>(base + P.Lp), b[i].bits_out, b[i].llr_out, F, n);
+        const int32_t n = b[i].code->n;
+        k_output_slots<<<dim3((n + 63) / 64, 2 * P.ngroups), kBlock, 0, stream>>>(
+            reinterpret_cast<const float *>(base + P.Lp), fid + static_cast<size_t>(P.group0) * G, b[i].bits_out,
+            b[i].llr_out, n);
     }
     k_flag_error<<<1, 64, 0, stream>>>(bar, reinterpret_cast<int32_t *>(base + B.off_err));
     if ((err = hipGetLastError()) != hipSuccess) return hip_fail(err, "batched output launch");
@@ -555,13 +769,14 @@ int enqueue_kernels(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_para
 
 }  // namespace
 
-mbp_tuning default_tuning() { return mbp_tuning{4, 4, 2, 0}; }
+mbp_tuning default_tuning() { return mbp_tuning{4, 4, 2, 0, 1}; }
 
 int check_tuning(const mbp_tuning &tu) {
     if (tu.rows_per_wave < 1 || tu.rows_per_wave > 64 || tu.vars_per_wave < 1 || tu.vars_per_wave > 64 ||
-        tu.blocks_per_cu < 1 || tu.blocks_per_cu > kMaxBlocksPerCu || tu.schedule < 0 || tu.schedule > 1)
+        tu.blocks_per_cu < 1 || tu.blocks_per_cu > kMaxBlocksPerCu || tu.schedule < 0 || tu.schedule > 1 ||
+        tu.compact < 0 || tu.compact > 1)
         return fail(MBP_EINVAL, "tuning out of range (rows/vars per wave 1..64, blocks per CU 1..4, "
-                                "schedule 0..1)");
+                                "schedule 0..1, compact 0..1)");
     return MBP_OK;
 }
 
@@ -576,13 +791,12 @@ int batched_decode(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_param
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     Built B = lay_out(nb, b, tu);
     int rc = ensure_workspace(ctx, B.total);
-    if (rc == MBP_OK) rc = ensure_status(ctx, B.ngroups);
     if (rc != MBP_OK) return rc;
     char *base = static_cast<char *>(ctx->ws);
     // the previous user of the workspace may still be running on another stream
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
     if ((rc = upload_descriptors(B, base)) != MBP_OK) return rc;
-    if ((rc = enqueue_kernels(ctx, nb, b, p, tu, B, base, stream, true)) != MBP_OK) return rc;
+    if ((rc = enqueue_kernels(nb, b, p, tu, B, base, ctx->num_cus, stream, true)) != MBP_OK) return rc;
     int32_t flag = 0;
     if ((e = hipMemcpyAsync(&flag, base + B.off_err, sizeof(flag), hipMemcpyDeviceToHost, stream)) !=
             hipSuccess ||
@@ -599,8 +813,7 @@ int batched_plan_capture(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     Built B = lay_out(nb, b, tu);
     char *base = static_cast<char *>(ws);
-    int rc = ensure_status(ctx, B.ngroups);
-    if (rc == MBP_OK) rc = upload_descriptors(B, base);
+    int rc = upload_descriptors(B, base);
     if (rc != MBP_OK) return rc;
     hipStream_t cap;
     if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess)
@@ -610,7 +823,7 @@ int batched_plan_capture(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp
         (void)hipStreamDestroy(cap);
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    rc = enqueue_kernels(ctx, nb, b, p, tu, B, base, cap, false);
+    rc = enqueue_kernels(nb, b, p, tu, B, base, ctx->num_cus, cap, false);
     const hipError_t e2 = hipStreamEndCapture(cap, &graph);
     (void)hipStreamDestroy(cap);
     if (rc != MBP_OK) {

@@ -406,7 +406,7 @@ void mbp_plan_destroy(mbp_plan *plan) {
 }
 
 // Text cache of autotuned settings: one line per batch mix,
-// "<key> <rows_per_wave> <vars_per_wave> <blocks_per_cu> <schedule> <ms>".
+// "<key> <rows_per_wave> <vars_per_wave> <blocks_per_cu> <schedule> <compact> <ms>".
 static std::string tune_key(int32_t nb, const mbp_batch *b, const mbp_params *p) {
     std::ostringstream k;
     k << "T" << p->max_iter << "e" << p->early_exit;
@@ -430,7 +430,8 @@ int mbp_autotune(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches, const
             std::string k;
             mbp_tuning t{};
             double ms = 0;
-            if ((ls >> k >> t.rows_per_wave >> t.vars_per_wave >> t.blocks_per_cu >> t.schedule >> ms) &&
+            if ((ls >> k >> t.rows_per_wave >> t.vars_per_wave >> t.blocks_per_cu >> t.schedule >> t.compact >>
+                 ms) &&
                 k == key && mbp::check_tuning(t) == MBP_OK) {
                 *out = t;
                 return MBP_OK;
@@ -449,15 +450,18 @@ int mbp_autotune(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches, const
     double best_ms = 0;
     if ((rc = time_one(best, &best_ms)) != MBP_OK) return rc;
     // coordinate descent over each knob, twice
-    const int rows[] = {1, 2, 4, 8}, vars[] = {1, 2, 4, 8}, bpcs[] = {1, 2, 3, 4}, scheds[] = {0, 1};
+    const int rows[] = {1, 2, 4, 8}, vars[] = {1, 2, 4, 8}, bpcs[] = {1, 2, 3, 4}, binary[] = {0, 1};
     for (int pass = 0; pass < 2; ++pass) {
-        for (int knob = 0; knob < 4; ++knob) {
-            const int *vals = knob == 0 ? rows : knob == 1 ? vars : knob == 2 ? bpcs : scheds;
-            const int nv = knob == 0 ? 4 : knob == 1 ? 4 : knob == 2 ? 4 : 2;
+        for (int knob = 0; knob < 5; ++knob) {
+            const int *vals = knob == 0 ? rows : knob == 1 ? vars : knob == 2 ? bpcs : binary;
+            const int nv = knob <= 2 ? 4 : 2;
             for (int i = 0; i < nv; ++i) {
                 mbp_tuning t = best;
-                int *field = knob == 0 ? &t.rows_per_wave : knob == 1 ? &t.vars_per_wave
-                                                          : knob == 2 ? &t.blocks_per_cu : &t.schedule;
+                int *field = knob == 0   ? &t.rows_per_wave
+                             : knob == 1 ? &t.vars_per_wave
+                             : knob == 2 ? &t.blocks_per_cu
+                             : knob == 3 ? &t.schedule
+                                         : &t.compact;
                 if (*field == vals[i]) continue;
                 *field = vals[i];
                 double ms = 0;
@@ -473,7 +477,7 @@ int mbp_autotune(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches, const
     if (cache_path) {
         std::ofstream o(cache_path, std::ios::app);
         o << key << " " << best.rows_per_wave << " " << best.vars_per_wave << " " << best.blocks_per_cu << " "
-          << best.schedule << " " << best_ms << "\n";
+          << best.schedule << " " << best.compact << " " << best_ms << "\n";
     }
     return MBP_OK;
 }

@@ -40,7 +40,8 @@ class mbp_batch(ctypes.Structure):
 
 class mbp_tuning(ctypes.Structure):
     _fields_ = [("rows_per_wave", ctypes.c_int32), ("vars_per_wave", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("compact", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -385,7 +386,7 @@ def _tuning(t):
     if isinstance(t, mbp_tuning):
         return t
     return mbp_tuning(int(t["rows_per_wave"]), int(t["vars_per_wave"]), int(t["blocks_per_cu"]),
-                      int(t["schedule"]))
+                      int(t["schedule"]), int(t.get("compact", 1)))
 
 
 def default_tuning() -> dict:

@@ -74,9 +74,10 @@ def test_batched_equals_plain_and_binary32_oracle(ctx, mix):
     assert 60 < sum(int(g["ok"].sum()) for g in got) < sum(g["ok"].size for g in got)
 
 
-@pytest.mark.parametrize("tuning", [dict(rows_per_wave=1, vars_per_wave=8, blocks_per_cu=1, schedule=1),
-                                    dict(rows_per_wave=8, vars_per_wave=1, blocks_per_cu=3, schedule=0),
-                                    dict(rows_per_wave=2, vars_per_wave=2, blocks_per_cu=4, schedule=1)])
+@pytest.mark.parametrize("tuning", [dict(rows_per_wave=1, vars_per_wave=8, blocks_per_cu=1, schedule=1, compact=1),
+                                    dict(rows_per_wave=8, vars_per_wave=1, blocks_per_cu=3, schedule=0, compact=0),
+                                    dict(rows_per_wave=2, vars_per_wave=2, blocks_per_cu=4, schedule=1, compact=0),
+                                    dict(rows_per_wave=4, vars_per_wave=4, blocks_per_cu=2, schedule=0, compact=1)])
 def test_tunings_do_not_change_results(ctx, mix, tuning):
     from paper_2001_07979_amd import mbp
     items, _ = mix
@@ -84,6 +85,52 @@ def test_tunings_do_not_change_results(ctx, mix, tuning):
     got = [_np(o) for o in mbp.decode_batched(ctx, items, max_iter=60, tuning=tuning)]
     for a, b in zip(got, ref):
         _same(a, b)
+
+
+@pytest.fixture(scope="module")
+def stragglers(ctx):
+    """Batches whose frames converge at very different iterations or not at
+    all (BSC p up to beyond the decoding threshold): 300 frames (5 groups) of
+    the n=1000 code and 130 frames (3 groups) of the n=2048 rate-3/4 code, so
+    the running frames shrink into fewer groups than they occupy."""
+    import torch
+    from paper_2001_07979_amd import mbp
+    codes = [peg_code(1000, 260, 2, W.IRREGULAR_238, seed_base=7100, name="peg-n1000"),
+             peg_code(2048, 256, 2, W.IRREGULAR_2310, seed_base=7400, name="peg-n2048")]
+    specs = [(300, (0.02, 0.09), 910), (130, (0.004, 0.035), 911)]
+    items, frames = [], []
+    for code, (F, (p0, p1), seed) in zip(codes, specs):
+        p = np.random.default_rng(seed).permutation(np.geomspace(p0, p1, F))
+        fr = bsc_frames(code, F, p, seed=seed)
+        dc = mbp.Code.from_inputs(ctx, code)
+        lam = parity.oracle_llr(fr, "f32").astype(np.float32)
+        items.append((dc, torch.from_numpy(lam).cuda(), torch.from_numpy(fr.z).cuda()))
+        frames.append((code, fr, lam))
+    return items, frames
+
+
+def test_compaction_keeps_results(ctx, stragglers):
+    """With compaction (running frames regrouped into spare groups as others
+    retire) every output equals the decode without it, the plain decode, and,
+    on sampled frames, the oracle's binary32 min-sum."""
+    from paper_2001_07979_amd import mbp
+    items, frames = stragglers
+    T = 60
+    on = [_np(o) for o in mbp.decode_batched(ctx, items, max_iter=T, tuning=dict(
+        rows_per_wave=4, vars_per_wave=4, blocks_per_cu=2, schedule=0, compact=1))]
+    off = [_np(o) for o in mbp.decode_batched(ctx, items, max_iter=T, tuning=dict(
+        rows_per_wave=4, vars_per_wave=4, blocks_per_cu=2, schedule=0, compact=0))]
+    for a, b in zip(on, off):
+        _same(a, b)
+    for a, b in zip(on, _plain(ctx, items, T=T)):
+        _same(a, b)
+    for g, (code, fr, lam) in zip(on, frames):
+        idx = np.random.default_rng(5).choice(fr.nframes, 12, replace=False)
+        ref = parity.oracle_f32_run(code, fr, T, idx=idx, lam=lam.astype(np.float64))
+        parity.assert_bitwise(dict(bits=g["bits"], iters=g["iters"], ok=g["ok"], L=g["llr"]), ref, idx=idx)
+    # the mix really has stragglers and failures
+    its = np.concatenate([g["iters"] for g in on])
+    assert (its == T).sum() > 100 and (its <= 5).sum() > 80
 
 
 def test_fixed_iterations(ctx, mix):
