@@ -62,7 +62,13 @@ typedef struct mbp_code mbp_code;
  *              every syndrome; 0: every frame runs T iterations.
  *   alpha      min-sum normalization, finite and > 0 (ignored by SPA).
  *   llr_clip   C: variable-to-check messages are clipped to [-C, C] before
- *              the check rule; finite, > 0, and <= 30 for SPA. */
+ *              the check rule; finite, > 0, and <= 30 for SPA.
+ *   compact    mbp_decode with early exit, 1: when the frames still running
+ *              fit into at most 3/4 of the 64-frame groups they occupy, move
+ *              them (with their state) into fewer spare groups so the late
+ *              iterations cost less (the workspace holds a quarter more
+ *              groups); 0: never. Results are the same either way. The
+ *              batched calls use mbp_tuning.compact instead. */
 typedef struct {
     int32_t algo;
     int32_t dtype;
@@ -70,6 +76,8 @@ typedef struct {
     int32_t early_exit;
     double alpha;
     double llr_clip;
+    int32_t compact;
+    int32_t reserved; /* 0 */
 } mbp_params;
 
 /* Message of the last failed call on this thread ("" if none). */

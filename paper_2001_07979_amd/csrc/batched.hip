@@ -38,8 +38,7 @@
 namespace mbp {
 namespace {
 
-constexpr int kChunk = 16;       // edges of a check gathered per round trip
-constexpr int kMovePieces = 64;  // work items per group a compaction fills
+constexpr int kChunk = 16;  // edges of a check gathered per round trip
 
 // Loads of data that no phase of the kernel writes (graph arrays, group and
 // batch descriptors) through the constant address space, so uniform
@@ -442,9 +441,13 @@ __device__ void plan_compaction(const PArgs &a, int i, int K, int par) {
     if (threadIdx.x == 0) s->next_spare = used + static_cast<uint32_t>(K);
 }
 
-// Fills piece p (of kMovePieces) of a group a compaction filled: rows of c
-// (E), L and lambda (n each) and syndrome words (M), each lane from its
-// source slot. One wave per row.
+// Work items per group a compaction fills; each covers a contiguous share
+// of the group's rows, which its waves take in runs of kMovePerWave with all
+// loads of a run issued before its stores.
+constexpr int kBatchMovePieces = 1024;
+
+// Fills piece p of a group a compaction filled: rows of c (E), L and lambda
+// (n each) and syndrome words (M), each lane from its source slot.
 __device__ void move_piece(const PArgs &a, int g, int p) {
     const unsigned lane = lane_id();
     const int wave = wave_id();
@@ -455,25 +458,50 @@ __device__ void move_piece(const PArgs &a, int g, int p) {
     const float *sc = ldg(&a.gd[sg].c, 0), *sL = ldg(&a.gd[sg].Lp, 0), *slam = ldg(&a.gd[sg].lam, 0);
     const uint64_t *szb = ldg(&a.gd[sg].zb, 0);
     auto span = [&](int64_t rows, int64_t *r0, int64_t *r1) {
-        const int64_t per = (rows + kMovePieces - 1) / kMovePieces;
+        const int64_t per = (rows + kBatchMovePieces - 1) / kBatchMovePieces;
         *r0 = p * per;
         *r1 = *r0 + per < rows ? *r0 + per : rows;
     };
+    constexpr int R = kMovePerWave;
     int64_t r0, r1;
     span(G_.E, &r0, &r1);
-    for (int64_t r = r0 + wave; r < r1; r += kWaves)
-        if (has) stg(G_.c, r * G + lane, ldg(sc, r * G + sl));
+    for (int64_t rb = r0 + wave * R; rb < r1; rb += kWaves * R) {
+        float v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (has && rb + j < r1) v[j] = ldg(sc, (rb + j) * G + sl);
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (has && rb + j < r1) stg(G_.c, (rb + j) * G + lane, v[j]);
+    }
     span(G_.n, &r0, &r1);
-    for (int64_t r = r0 + wave; r < r1; r += kWaves) {
-        if (has) {
-            stg(G_.Lp, r * G + lane, ldg(sL, r * G + sl));
-            stg(G_.lam, r * G + lane, ldg(slam, r * G + sl));
+    for (int64_t rb = r0 + wave * R; rb < r1; rb += kWaves * R) {
+        float v[R], u[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (has && rb + j < r1) {
+                v[j] = ldg(sL, (rb + j) * G + sl);
+                u[j] = ldg(slam, (rb + j) * G + sl);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (has && rb + j < r1) {
+                stg(G_.Lp, (rb + j) * G + lane, v[j]);
+                stg(G_.lam, (rb + j) * G + lane, u[j]);
+            }
         }
     }
     span(G_.M, &r0, &r1);
-    for (int64_t r = r0 + wave; r < r1; r += kWaves) {
-        const uint64_t bits = __ballot(has && ((ld_fresh(szb + r) >> sl) & 1));
-        if (lane == 0) stg(G_.zb, r, bits);
+    for (int64_t rb = r0 + wave * R; rb < r1; rb += kWaves * R) {
+        uint64_t v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[j] = has && rb + j < r1 ? ld_fresh(szb + rb + j) : 0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const uint64_t bits = __ballot((v[j] >> sl) & 1);
+            if (lane == 0 && rb + j < r1) stg(G_.zb, rb + j, bits);
+        }
     }
 }
 
@@ -516,8 +544,8 @@ __global__ __launch_bounds__(kBlock) void k_persistent(PArgs a) {
         const unsigned nnew =
             __hip_atomic_load(&a.bar->nnew[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (nnew == 0) continue;
-        for (int64_t w = blockIdx.x; w < static_cast<int64_t>(nnew) * kMovePieces; w += gridDim.x)
-            move_piece(a, a.newg[w / kMovePieces], static_cast<int>(w % kMovePieces));
+        for (int64_t w = blockIdx.x; w < static_cast<int64_t>(nnew) * kBatchMovePieces; w += gridDim.x)
+            move_piece(a, a.newg[w / kBatchMovePieces], static_cast<int>(w % kBatchMovePieces));
         if (!grid_sync(a.bar)) return;
     }
 }
@@ -552,30 +580,6 @@ __global__ void k_init_slots(uint64_t *words, int32_t *fid, int32_t g0, int32_t 
         const uint64_t valid = !orig ? 0 : rem >= G ? ~0ull : ((1ull << rem) - 1ull);
         words[static_cast<size_t>(kStride) * (g0 + k) + kRun] = valid;
         words[static_cast<size_t>(kStride) * (g0 + k) + kUnmet] = 0;
-    }
-}
-
-// [group][n][64] -> bits and L rows [frame][n] of one batch, from every slot
-// that still holds its frame (fid >= 0), i.e. the frame's final state.
-__global__ __launch_bounds__(kBlock) void k_output_slots(const float *Lp, const int32_t *fid, uint8_t *bits,
-                                                         float *llr_out, int32_t n) {
-    __shared__ float tile[64][65];
-    __shared__ int32_t f_of[64];
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int k = blockIdx.y, i0 = blockIdx.x * 64;
-    if (threadIdx.x < 64) f_of[threadIdx.x] = fid[static_cast<size_t>(k) * G + threadIdx.x];
-    for (int iy = ty; iy < 64; iy += kWaves) {
-        const int i = i0 + iy;
-        tile[iy][tx] = i < n ? Lp[(static_cast<size_t>(k) * n + i) * G + tx] : 0.0f;
-    }
-    __syncthreads();
-    for (int fy = ty; fy < 64; fy += kWaves) {
-        const int f = f_of[fy], i = i0 + tx;
-        if (f < 0 || i >= n) continue;
-        const float v = tile[tx][fy];
-        const size_t o = static_cast<size_t>(f) * n + i;
-        if (bits) bits[o] = v < 0.0f ? 1 : 0;
-        if (llr_out) llr_out[o] = v;
     }
 }
 
@@ -758,7 +762,7 @@ int enqueue_kernels(int32_t nb, const mbp_batch *b, const mbp_params *p, const m
     for (int32_t i = 0; i < nb; ++i) {
         const BatchPlace &P = B.place[i];
         const int32_t n = b[i].code->n;
-        k_output_slots<<<dim3((n + 63) / 64, 2 * P.ngroups), kBlock, 0, stream>>>(
+        k_output_slots<float><<<dim3((n + 63) / 64, 2 * P.ngroups), kBlock, 0, stream>>>(
             reinterpret_cast<const float *>(base + P.Lp), fid + static_cast<size_t>(P.group0) * G, b[i].bits_out,
             b[i].llr_out, n);
     }

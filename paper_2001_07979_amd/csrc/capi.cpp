@@ -238,6 +238,7 @@ int mbp_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
         return fail(MBP_EINVAL, "mbp_decode: max_iter must be in [1, 10000]");
     if (p->early_exit != 0 && p->early_exit != 1)
         return fail(MBP_EINVAL, "mbp_decode: early_exit must be 0 or 1");
+    if (p->compact != 0 && p->compact != 1) return fail(MBP_EINVAL, "mbp_decode: compact must be 0 or 1");
     if (!std::isfinite(p->llr_clip) || p->llr_clip <= 0.0)
         return fail(MBP_EINVAL, "mbp_decode: llr_clip must be finite and > 0");
     if (p->algo == MBP_ALGO_SPA && p->llr_clip > 30.0)

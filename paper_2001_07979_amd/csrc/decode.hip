@@ -34,24 +34,37 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     const int32_t n = code->n, M = code->M;
     const int64_t E = code->E;
     const int32_t ngroups = (F + G - 1) / G;
+    // spare groups that compaction may fill: a quarter of the groups (none
+    // for a single group, which has nothing to compact)
+    const int32_t nspare = p->compact && p->early_exit && ngroups >= 2 ? std::max(1, ngroups / 4) : 0;
+    const int32_t ntot = ngroups + nspare;
     const size_t s = sizeof(T);
-    const size_t sz_c = align_up(static_cast<size_t>(ngroups) * E * G * s);
-    const size_t sz_L = align_up(static_cast<size_t>(ngroups) * n * G * s);
-    const size_t sz_z = align_up(static_cast<size_t>(ngroups) * M * sizeof(uint64_t));
-    const size_t sz_d = align_up(static_cast<size_t>(ngroups) * n * sizeof(uint64_t));
-    // status words, one 256-byte line per group, then the stopping-test counter
-    const size_t sz_m = align_up(static_cast<size_t>(ngroups) * kStride * sizeof(uint64_t)) + 256;
-    int rc = ensure_workspace(ctx, sz_c + 2 * sz_L + sz_z + sz_d + sz_m);
+    const size_t sz_c = align_up(static_cast<size_t>(ntot) * E * G * s);
+    const size_t sz_L = align_up(static_cast<size_t>(ntot) * n * G * s);
+    const size_t sz_z = align_up(static_cast<size_t>(ntot) * M * sizeof(uint64_t));
+    const size_t sz_d = align_up(static_cast<size_t>(ntot) * n * sizeof(uint64_t));
+    const size_t sz_f = align_up(static_cast<size_t>(ntot) * G * sizeof(int32_t));
+    // status words, one 256-byte line per group, then the stopping-test counters
+    const size_t sz_m = align_up(static_cast<size_t>(ntot) * kStride * sizeof(uint64_t)) + 256;
+    int rc = ensure_workspace(ctx, sz_c + 2 * sz_L + sz_z + sz_d + 2 * sz_f + sz_m);
     if (rc != MBP_OK) return rc;
-    if ((rc = ensure_status(ctx, ngroups)) != MBP_OK) return rc;
+    if ((rc = ensure_status(ctx, ntot)) != MBP_OK) return rc;
     char *base = static_cast<char *>(ctx->ws);
-    T *c = reinterpret_cast<T *>(base);
-    T *Lp = reinterpret_cast<T *>(base + sz_c);
-    T *lam = reinterpret_cast<T *>(base + sz_c + sz_L);
-    uint64_t *zb = reinterpret_cast<uint64_t *>(base + sz_c + 2 * sz_L);
-    uint64_t *D = reinterpret_cast<uint64_t *>(base + sz_c + 2 * sz_L + sz_z);
-    uint64_t *words = reinterpret_cast<uint64_t *>(base + sz_c + 2 * sz_L + sz_z + sz_d);
-    uint32_t *done = reinterpret_cast<uint32_t *>(base + sz_c + 2 * sz_L + sz_z + sz_d + sz_m - 256);
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        char *at = base + off;
+        off += bytes;
+        return at;
+    };
+    T *c = reinterpret_cast<T *>(carve(sz_c));
+    T *Lp = reinterpret_cast<T *>(carve(sz_L));
+    T *lam = reinterpret_cast<T *>(carve(sz_L));
+    uint64_t *zb = reinterpret_cast<uint64_t *>(carve(sz_z));
+    uint64_t *D = reinterpret_cast<uint64_t *>(carve(sz_d));
+    int32_t *fid = reinterpret_cast<int32_t *>(carve(sz_f));
+    int32_t *src = reinterpret_cast<int32_t *>(carve(sz_f));
+    uint64_t *words = reinterpret_cast<uint64_t *>(carve(sz_m - 256));
+    StopTail *tail = reinterpret_cast<StopTail *>(carve(256));
 
     Timer tm{ctx, stream, {}, 0};
     hipError_t err;
@@ -61,8 +74,8 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
         if (err != hipSuccess) return hip_fail(err, "kernel launch");   \
     } while (0)
 
-    LAUNCH_OR_FAIL(kStaging, k_init_running<<<(ngroups + 63) / 64, 64, 0, stream>>>(
-                                 words, ctx->status_dev, done, F, ngroups));
+    LAUNCH_OR_FAIL(kStaging, k_init_running<<<(ntot * G + 255) / 256, 256, 0, stream>>>(
+                                 words, ctx->status_dev, tail, fid, F, ngroups, nspare));
     const dim3 tgrid((n + 63) / 64, ngroups);
     // L^0 = lambda: the first check pass reads lam, so only lam is staged
     LAUNCH_OR_FAIL(kStaging, k_stage_llr<T><<<tgrid, kBlock, 0, stream>>>(
@@ -72,17 +85,20 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
 
     const int dmax = dmax_for(code->max_check_deg);
     const CheckFn<T> kc = p->algo == MBP_ALGO_NMS ? check_kernel<T, kNMS>(dmax) : check_kernel<T, kSPA>(dmax);
-    Dims dc{E, n, M, ngroups, (M + kRowsPerTile - 1) / kRowsPerTile, 0, 0, p->alpha, p->llr_clip};
+    Dims dc{E, n, M, ntot, (M + kRowsPerTile - 1) / kRowsPerTile, 0, 0, p->alpha, p->llr_clip};
     int vpt = 0;
     const VarFn<T> kv = variable_kernel<T>(code->max_var_deg, &vpt);
-    Dims dv{E, n, M, ngroups, (n + vpt - 1) / vpt, 0, 0, p->alpha, p->llr_clip};
-    Dims ds{E, n, M, ngroups, (M + kBlock - 1) / kBlock, 0, 0, p->alpha, p->llr_clip};
+    Dims dv{E, n, M, ntot, (n + vpt - 1) / vpt, 0, 0, p->alpha, p->llr_clip};
+    Dims ds{E, n, M, ntot, (M + kBlock - 1) / kBlock, 0, 0, p->alpha, p->llr_clip, p->max_iter, ngroups,
+            nspare};
     const int grid_c = grid_for(ctx, reinterpret_cast<const void *>(kc),
                                 static_cast<int64_t>(ngroups) * dc.ntiles);
     const int grid_v = grid_for(ctx, reinterpret_cast<const void *>(kv),
                                 static_cast<int64_t>(ngroups) * dv.ntiles);
     const int grid_s = grid_for(ctx, reinterpret_cast<const void *>(&k_stop_test),
-                                static_cast<int64_t>(ngroups) * ds.ntiles);
+                                static_cast<int64_t>(ntot) * ds.ntiles);
+    const int grid_m = grid_for(ctx, reinterpret_cast<const void *>(&k_move<T>),
+                                static_cast<int64_t>(std::max(nspare, 1)) * (E + 2 * n + M) / kMoveRows);
 
     if (ctx->poll_events.size() < 2) {
         for (size_t k = ctx->poll_events.size(); k < 2; ++k) {
@@ -107,7 +123,11 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
         if (!p->early_exit && t < p->max_iter) continue;
         LAUNCH_OR_FAIL(kSyndrome, k_stop_test<<<grid_s, kBlock, 0, stream>>>(
                                       code->d_row_ptr, code->d_col, zb, D, words, ctx->status_dev,
-                                      iters_out, ok_out, done, F, ds));
+                                      iters_out, ok_out, fid, src, tail, ds));
+        // fills the spare groups the stopping test's compaction planned
+        if (nspare && t <= p->max_iter - 2)
+            LAUNCH_OR_FAIL(kSyndrome, k_move<T><<<grid_m, kBlock, 0, stream>>>(c, Lp, lam, zb, src, tail, E, n,
+                                                                                M));
         if (p->early_exit) {
             if ((err = hipEventRecord(ctx->poll_events[t & 1], stream)) != hipSuccess)
                 return hip_fail(err, "hipEventRecord");
@@ -118,13 +138,13 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
                     return hip_fail(err, "hipEventSynchronize");
                 bool any = false;
                 volatile uint64_t *st = ctx->status_host;
-                for (int32_t g = 0; g < ngroups && !any; ++g) any = st[g] != 0;
+                for (int32_t g = 0; g < ntot && !any; ++g) any = st[g] != 0;
                 if (!any) break;
             }
         }
     }
-    LAUNCH_OR_FAIL(kStaging, k_output<T><<<tgrid, kBlock, 0, stream>>>(Lp, bits_out, static_cast<T *>(llr_out),
-                                                                      F, n));
+    LAUNCH_OR_FAIL(kStaging, k_output_slots<T><<<dim3((n + 63) / 64, ntot), kBlock, 0, stream>>>(
+                                 Lp, fid, bits_out, static_cast<T *>(llr_out), n));
 #undef LAUNCH_OR_FAIL
     if ((err = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(err, "hipStreamSynchronize");
     if ((err = tm.collect()) != hipSuccess) return hip_fail(err, "hipEventElapsedTime");

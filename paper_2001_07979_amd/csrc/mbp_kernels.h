@@ -102,6 +102,17 @@ struct Dims {
     int32_t t;     // iteration (1-based)
     int32_t flag;  // stopping test: 1 on the last iteration (settles every frame)
     double alpha, clip;
+    int32_t T = 0;        // stopping test: the iteration limit
+    int32_t spare0 = 0;   // stopping test: first spare group (= groups holding frames)
+    int32_t nspare = 0;   // stopping test: spare groups compaction may fill (0: none)
+};
+
+// Counters after the plain decode's status words: the stopping test's
+// arrival count, the spare groups filled so far, and the compaction the
+// last stopping test planned (first new group, how many).
+struct StopTail {
+    uint32_t done, spare_used;
+    int32_t move_first, move_count;
 };
 
 // Per-group status words for the plain and unrolled decodes: word kRun of
@@ -277,21 +288,30 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
 
 // Stopping test of iteration t (Sec. 2: a frame succeeds once z^l = H_l x
 // for every matrix l), on the decision words the variable pass wrote: bit k
-// of D[g][i] is frame 64g+k's decision on bit i. One thread per check: the
-// XOR of the check's decision words and its syndrome word gives, in one
-// 64-bit operation, the frames whose parity differs; they are ORed into the
-// group's kUnmet word. The last block to finish then settles every group:
-// frames of the running set with no unmet check stop at t (ok = 1); on the
-// last iteration (a.flag) the others stop too (ok = 0); the running set and
-// the host-visible status become the frames still running.
+// of D[g][i] is the decision on bit i of the frame in slot k of group g. One
+// thread per check: the XOR of the check's decision words and its syndrome
+// word gives, in one 64-bit operation, the frames whose parity differs; they
+// are ORed into the group's kUnmet word. The last block to finish then
+// settles every group: frames of the running set with no unmet check stop at
+// t (ok = 1); on the last iteration (a.flag) the others stop too (ok = 0);
+// the running set and the host-visible status become the frames still
+// running. Slot s holds frame fid[s] (-1: none).
+//
+// Compaction (a.nspare > 0): when the running frames fit into at most 3/4 of
+// the groups they occupy and at least two iterations remain, the same block
+// assigns them, in group and lane order, to consecutive slots of the fewest
+// unused spare groups (src[new slot] = old slot, fid moves along, the old
+// groups stop running) and leaves the plan in the tail for k_move.
 __global__ __launch_bounds__(kBlock) void k_stop_test(const int32_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col,
                                                       const uint64_t *__restrict__ zb,
                                                       const uint64_t *__restrict__ D, uint64_t *words,
                                                       uint64_t *status, int32_t *iters_out,
-                                                      uint8_t *ok_out, uint32_t *done, int32_t nframes,
-                                                      const Dims a) {
+                                                      uint8_t *ok_out, int32_t *fid, int32_t *src,
+                                                      StopTail *tail, const Dims a) {
     __shared__ uint32_t sh_or[2 * kWaves];
+    __shared__ uint32_t scan[kBlock];
+    __shared__ uint32_t sh_base, sh_R, sh_L;
     __shared__ int sh_last;
     const unsigned lane = lane_id();
     const int wave = wave_id();
@@ -341,23 +361,28 @@ __global__ __launch_bounds__(kBlock) void k_stop_test(const int32_t *__restrict_
     // the last block to arrive settles the groups
     if (threadIdx.x == 0) {
         __threadfence();
-        sh_last = atomicAdd(done, 1u) == gridDim.x - 1;
+        sh_last = atomicAdd(&tail->done, 1u) == gridDim.x - 1;
     }
     __syncthreads();
     if (!sh_last) return;
     __threadfence();
-    for (int f = threadIdx.x; f < a.ngroups * G; f += kBlock) {
-        const int g = f / G, k = f % G;
+    for (int s = threadIdx.x; s < a.ngroups * G; s += kBlock) {
+        const int g = s / G, k = s % G;
         const uint64_t run = __hip_atomic_load(&words[kStride * g + kRun], __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
-        if (!((run >> k) & 1) || f >= nframes) continue;
+        if (!((run >> k) & 1)) continue;
         const uint64_t un = __hip_atomic_load(&words[kStride * g + kUnmet], __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
         const bool met = !((un >> k) & 1);
         if (met || a.flag) {
+            const int f = fid[s];
             iters_out[f] = a.t;
             ok_out[f] = met ? 1 : 0;
         }
+    }
+    if (threadIdx.x == 0) {
+        sh_R = 0;
+        sh_L = 0;
     }
     __syncthreads();
     for (int g = threadIdx.x; g < a.ngroups; g += kBlock) {
@@ -368,9 +393,158 @@ __global__ __launch_bounds__(kBlock) void k_stop_test(const int32_t *__restrict_
         const uint64_t next = a.flag ? 0 : (run & un);
         words[kStride * g + kRun] = next;
         words[kStride * g + kUnmet] = 0;
-        __hip_atomic_store(&status[g], next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (next) {
+            atomicAdd(&sh_R, static_cast<uint32_t>(__popcll(next)));
+            atomicAdd(&sh_L, 1u);
+        }
     }
-    if (threadIdx.x == 0) *done = 0;
+    __syncthreads();
+    // compaction plan
+    const uint32_t R = sh_R, L = sh_L, K = (R + G - 1) / G;
+    const uint32_t used = tail->spare_used;
+    const bool compact = a.nspare > 0 && !a.flag && a.t <= a.T - 2 && L >= 2 && 4 * K <= 3 * L &&
+                         used + K <= static_cast<uint32_t>(a.nspare);
+    const int first_new = a.spare0 + static_cast<int>(used);
+    if (compact) {
+        if (threadIdx.x == 0) sh_base = 0;
+        __syncthreads();
+        for (int c0 = 0; c0 < a.ngroups; c0 += kBlock) {
+            const int g = c0 + static_cast<int>(threadIdx.x);
+            const uint64_t run = g < a.ngroups ? words[kStride * g + kRun] : 0;
+            const uint32_t cnt = static_cast<uint32_t>(__popcll(run));
+            scan[threadIdx.x] = cnt;
+            __syncthreads();
+            for (int o = 1; o < kBlock; o <<= 1) {  // inclusive scan
+                const uint32_t v = threadIdx.x >= static_cast<unsigned>(o) ? scan[threadIdx.x - o] : 0;
+                __syncthreads();
+                scan[threadIdx.x] += v;
+                __syncthreads();
+            }
+            uint32_t k = sh_base + scan[threadIdx.x] - cnt;
+            for (uint64_t rr = run; rr && k < K * G; rr &= rr - 1) {
+                const int l = __ffsll(static_cast<unsigned long long>(rr)) - 1;
+                const size_t from = static_cast<size_t>(g) * G + l;
+                const size_t to = static_cast<size_t>(first_new) * G + k;
+                src[to] = static_cast<int32_t>(from);
+                fid[to] = fid[from];
+                fid[from] = -1;
+                ++k;
+            }
+            if (run) words[kStride * g + kRun] = 0;
+            __syncthreads();
+            if (threadIdx.x == kBlock - 1) sh_base += scan[kBlock - 1];
+            __syncthreads();
+        }
+        for (uint32_t j = threadIdx.x; j < K * G; j += kBlock)
+            if (j >= R) src[static_cast<size_t>(first_new) * G + j] = -1;
+        for (uint32_t j = threadIdx.x; j < K; j += kBlock) {
+            const uint32_t lo = j * G, cnt = R - lo >= static_cast<uint32_t>(G) ? G : R - lo;
+            words[kStride * (first_new + j) + kRun] = cnt >= static_cast<uint32_t>(G) ? ~0ull : ((1ull << cnt) - 1ull);
+        }
+        __syncthreads();
+    }
+    for (int g = threadIdx.x; g < a.ngroups; g += kBlock)
+        __hip_atomic_store(&status[g], words[kStride * g + kRun], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (threadIdx.x == 0) {
+        tail->move_first = first_new;
+        tail->move_count = compact ? static_cast<int32_t>(K) : 0;
+        if (compact) tail->spare_used = used + K;
+        tail->done = 0;
+    }
+}
+
+// Rows of one k_move work item (kMoveRows / kWaves per wave, all loads of a
+// wave issued before its stores).
+constexpr int kMoveRows = 64;
+constexpr int kMovePerWave = kMoveRows / kWaves;
+
+// Fills the groups the last stopping test's compaction planned (none: the
+// kernel does nothing): rows of c (E), L and lambda (n each) and syndrome
+// words (M), each lane from its source slot src[]. Work items are runs of
+// kMoveRows rows of one region of one group.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_move(T *c, T *Lp, T *lam, uint64_t *zb, const int32_t *src,
+                                                 const StopTail *tail, int64_t E, int32_t n, int32_t M) {
+    const int count = tail->move_count, first = tail->move_first;
+    if (count == 0) return;
+    const unsigned lane = lane_id();
+    const int wave = wave_id();
+    const int64_t ic = (E + kMoveRows - 1) / kMoveRows, il = (n + kMoveRows - 1) / kMoveRows,
+                  iz = (M + kMoveRows - 1) / kMoveRows, per_group = ic + il + iz;
+    for (int64_t w = blockIdx.x; w < count * per_group; w += gridDim.x) {
+        const int64_t g = first + w / per_group;
+        int64_t item = w % per_group;
+        const int32_t s = src[g * G + lane];
+        const bool has = s >= 0;
+        const int64_t sg = has ? s / G : g, sl = has ? s % G : 0;
+        if (item < ic) {
+            const int64_t r0 = item * kMoveRows + wave * kMovePerWave;
+            T v[kMovePerWave];
+#pragma unroll
+            for (int j = 0; j < kMovePerWave; ++j)
+                if (has && r0 + j < E) v[j] = c[(sg * E + r0 + j) * G + sl];
+#pragma unroll
+            for (int j = 0; j < kMovePerWave; ++j)
+                if (has && r0 + j < E) c[(g * E + r0 + j) * G + lane] = v[j];
+        } else if ((item -= ic) < il) {
+            const int64_t r0 = item * kMoveRows + wave * kMovePerWave;
+            T v[kMovePerWave], u[kMovePerWave];
+#pragma unroll
+            for (int j = 0; j < kMovePerWave; ++j) {
+                if (has && r0 + j < n) {
+                    v[j] = Lp[(sg * n + r0 + j) * G + sl];
+                    u[j] = lam[(sg * n + r0 + j) * G + sl];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kMovePerWave; ++j) {
+                if (has && r0 + j < n) {
+                    Lp[(g * n + r0 + j) * G + lane] = v[j];
+                    lam[(g * n + r0 + j) * G + lane] = u[j];
+                }
+            }
+        } else {
+            item -= il;
+            const int64_t r0 = item * kMoveRows + wave * kMovePerWave;
+            uint64_t v[kMovePerWave];
+#pragma unroll
+            for (int j = 0; j < kMovePerWave; ++j) v[j] = has && r0 + j < M ? zb[sg * M + r0 + j] : 0;
+#pragma unroll
+            for (int j = 0; j < kMovePerWave; ++j) {
+                const uint64_t bits = __ballot((v[j] >> sl) & 1);
+                if (lane == 0 && r0 + j < M) zb[g * M + r0 + j] = bits;
+            }
+        }
+    }
+}
+
+// [group][n][64] -> bits and L rows [frame][n], from every slot that holds a
+// frame (fid >= 0) in its final state.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_output_slots(const T *Lp, const int32_t *fid, uint8_t *bits,
+                                                         T *llr_out, int32_t n) {
+    __shared__ T tile[64][65];
+    __shared__ int32_t f_of[64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int k = blockIdx.y, i0 = blockIdx.x * 64;
+    if (threadIdx.x < 64) f_of[threadIdx.x] = fid[static_cast<size_t>(k) * G + threadIdx.x];
+    __syncthreads();
+    bool any = false;
+    for (int j = 0; j < 64; ++j) any |= f_of[j] >= 0;
+    if (!any) return;  // uniform: an unused or vacated group
+    for (int iy = ty; iy < 64; iy += kWaves) {
+        const int i = i0 + iy;
+        tile[iy][tx] = i < n ? Lp[(static_cast<size_t>(k) * n + i) * G + tx] : T(0);
+    }
+    __syncthreads();
+    for (int fy = ty; fy < 64; fy += kWaves) {
+        const int f = f_of[fy], i = i0 + tx;
+        if (f < 0 || i >= n) continue;
+        const T v = tile[tx][fy];
+        const size_t o = static_cast<size_t>(f) * n + i;
+        if (bits) bits[o] = v < T(0) ? 1 : 0;
+        if (llr_out) llr_out[o] = v;
+    }
 }
 
 // Variable-node pass, eq. (2): L = lambda + every incoming check message,
@@ -451,14 +625,19 @@ VarFn<T> variable_kernel(int dmax, int *vars_per_tile) {
 }
 
 // Running set of the plain and unrolled decodes before the first iteration:
-// every valid frame; the unmet words and the stopping-test counter cleared.
-__global__ void k_init_running(uint64_t *words, uint64_t *status, uint32_t *done, int32_t nframes,
-                               int32_t ngroups) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g == 0) *done = 0;
-    if (g >= ngroups) return;
+// every valid frame of the first ngroups groups (then nspare empty spares);
+// the unmet words and the stopping-test counters cleared; fid, if not null,
+// maps slot 64g+k to frame 64g+k (-1 past the frames and in the spares).
+__global__ void k_init_running(uint64_t *words, uint64_t *status, StopTail *tail, int32_t *fid,
+                               int32_t nframes, int32_t ngroups, int32_t nspare) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s == 0 && tail) *tail = StopTail{0, 0, 0, 0};
+    if (s >= (ngroups + nspare) * G) return;
+    const int g = s / G, k = s % G;
+    if (fid) fid[s] = g < ngroups && s < nframes ? s : -1;
+    if (k) return;
     const int rem = nframes - g * G;
-    const uint64_t valid = rem >= G ? ~0ull : ((1ull << rem) - 1ull);
+    const uint64_t valid = g >= ngroups ? 0 : rem >= G ? ~0ull : ((1ull << rem) - 1ull);
     words[kStride * g + kRun] = valid;
     words[kStride * g + kUnmet] = 0;
     __hip_atomic_store(&status[g], valid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);

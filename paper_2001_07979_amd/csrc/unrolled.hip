@@ -313,8 +313,9 @@ struct Run {
         float *lam = reinterpret_cast<float *>(ws + Ly.lam);
         uint64_t *act = reinterpret_cast<uint64_t *>(ws + Ly.act);
         uint64_t *uns = reinterpret_cast<uint64_t *>(ws + Ly.uns);
-        k_init_running<<<(ng + 63) / 64, 64, 0, stream>>>(act, ctx->status_dev,
-                                                           reinterpret_cast<uint32_t *>(uns), F, ng);
+        k_init_running<<<(ng * G + 255) / 256, 256, 0, stream>>>(act, ctx->status_dev,
+                                                                 reinterpret_cast<StopTail *>(uns), nullptr, F,
+                                                                 ng, 0);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return hip_fail(err, "k_init_groups launch");
         // lam is staged twice into one buffer: k_stage_llr writes both outputs

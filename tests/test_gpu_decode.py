@@ -155,6 +155,42 @@ def test_n262144_u3_sampled(ctx, rate, algo):
     assert np.all((g["iters"] >= 1) & (g["iters"] <= wl.max_iter))
 
 
+@pytest.mark.parametrize("algo,dtype", [("spa", "f32"), ("nms", "f32"), ("spa", "f64")])
+def test_compaction_keeps_results(ctx, ragged_code, algo, dtype):
+    """300 frames (5 groups) whose iteration counts spread from 2 to T: with
+    compaction the frames still running move into spare groups as others
+    stop; every output equals the decode without it, and sampled frames
+    follow the parity protocol against the oracle."""
+    from paper_2001_07979_amd import mbp
+    import torch
+    p = np.random.default_rng(910).permutation(np.geomspace(0.02, 0.09, 300))
+    fr = bsc_frames(ragged_code, 300, p, seed=910)
+    dc = upload(ctx, ragged_code)
+    lam = parity.oracle_llr(fr, dtype)
+    llr = torch.from_numpy(lam.astype(np.float32 if dtype == "f32" else np.float64)).cuda()
+    z = torch.from_numpy(fr.z).cuda()
+    T = 60
+    outs = [mbp.decode(ctx, dc, llr, z, algo=algo, max_iter=T, compact=cp) for cp in (True, False)]
+    torch.cuda.synchronize()
+    a, b = ({k: v.cpu().numpy() for k, v in o.items()} for o in outs)
+    for k in ("bits", "iters", "ok", "llr"):
+        assert np.array_equal(a[k], b[k]), k
+    its = a["iters"]
+    assert (its == T).sum() > 50 and (its <= 5).sum() > 40
+    g = dict(bits=a["bits"], iters=a["iters"], ok=a["ok"], L=a["llr"].astype(np.float64))
+    rng = np.random.default_rng(3)
+    if algo == "nms":
+        # every frame, failed or not, bit for bit against binary32 min-sum
+        idx = rng.choice(300, 16, replace=False)
+        parity.assert_bitwise(g, parity.oracle_f32_run(ragged_code, fr, T, idx=idx, lam=lam), idx=idx)
+    else:
+        # short decodes, where the protocol holds every frame to the oracle
+        idx = rng.choice(np.nonzero(its <= parity.LONG_AFTER)[0], 16, replace=False)
+        o = parity.oracle_run(ragged_code, fr, algo, dtype, T, idx=idx, lam=lam)
+        parity.compare(g, o, T, RTOL32 if dtype == "f32" else RTOL64, idx=idx,
+                       atol=parity.ATOL32 if dtype == "f32" else 0.0)
+
+
 def test_edge_cases(ctx, ragged_code):
     import torch
     from paper_2001_07979_amd import mbp
