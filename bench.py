@@ -75,7 +75,7 @@ def h2(p):
     return -p * np.log2(p) - (1 - p) * np.log2(1 - p)
 
 
-def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float):
+def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_only: bool = False):
     """The heterogeneous queue (n, rate, u and p per frame) decoded three ways
     on the same device-resident inputs: the captured persistent batched
     decode, one plain decode call per frame in arrival order, and one plain
@@ -122,6 +122,10 @@ def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float):
     torch.cuda.synchronize()
     t_batched = (time.perf_counter() - t0) / reps
     res_b = [{k: v.cpu() for k, v in o.items()} for o in outs_b]
+    if batched_only:
+        plan.close()
+        return {"frames": nframes, "bits": total_bits, "tuning": tune,
+                "batched_mbps": round(total_bits / t_batched / 1e6, 1)}
 
     # plain, one call per code (frames of a code grouped 64 to a wave)
     outs_g = [mbp.batch_outputs(dc, lam) for dc, lam, _ in items]
@@ -289,6 +293,53 @@ def qualifying_point(ctx, steps: int, algo: str):
             "note": "FER from these frames only; 64 frames bound FER below about 4.7% (rule of three)"}
 
 
+def unrolled_step(ctx, steps: int):
+    """One training step of the differentiable decoder: K=20 unrolled min-sum
+    iterations (weights per iteration and matrix) on 512 frames of the u=2
+    n=16384 rate-1/2 code, mean BCE of sigma(-L^K) against Alice's bits, and
+    the backward through the hand-written adjoint (checkpoints every 5)."""
+    import torch
+    from paper_2001_07979_amd import mbp
+    from paper_2001_07979_amd.inputs import workloads as W
+
+    wl = W.unrolled_n16384(nframes=512)
+    fr = wl.frames()
+    code = wl.code
+    K = wl.max_iter
+    dev = torch.device("cuda", 0)
+    dcode = mbp.Code.from_inputs(ctx, code)
+    y = torch.from_numpy(fr.y).to(dev)
+    e = torch.from_numpy(fr.p).to(dev)
+    z = torch.from_numpy(fr.z).to(dev)
+    x = torch.from_numpy(fr.x.astype(np.float32)).to(dev)
+    alpha = torch.full((K, code.u), 0.75, device=dev, requires_grad=True)
+
+    def step():
+        llr = mbp.llr_from_bits(ctx, y, e).requires_grad_(True)
+        L = mbp.unrolled_nms(ctx, dcode, llr, z, alpha, ckpt_every=5)
+        loss = torch.nn.functional.binary_cross_entropy_with_logits(-L, x)
+        loss.backward()
+        return loss
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    E, n = code.E, code.n
+    # forward K iterations + recompute of K - K/5 of them: each s(3E + 3n)
+    # bytes per frame (check pass 2E + n, variable pass E + 2n); the adjoint
+    # iterations read q's inputs (L, c), gq and write gq / gL: about s(4E + 3n)
+    fwd_iter = 4 * (3 * E + 3 * n)
+    adj_iter = 4 * (4 * E + 3 * n)
+    bytes_step = fr.nframes * (K * fwd_iter + (K - K // 5) * fwd_iter + K * adj_iter)
+    return {"workload": wl.name, "frames": fr.nframes, "K": K, "ckpt_every": 5,
+            "ms_per_step": round(dt * 1e3, 3), "frames_per_s": round(fr.nframes / dt, 1),
+            "loss": float(loss.item()), "approx_GBps": round(bytes_step / dt / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +353,9 @@ def main():
     ap.add_argument("--queue-frames", type=int, default=2048,
                     help="frames of the heterogeneous queue for batched vs plain (0 skips it)")
     ap.add_argument("--queue-reps", type=int, default=5)
+    ap.add_argument("--queue-batched-only", action="store_true",
+                    help="run only the batched offline leg of the queue (for profiling)")
+    ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled training step")
     ap.add_argument("--no-qualifying", action="store_true",
                     help="skip the f <= 1.1 operating point (n=262144, rate 0.85)")
     ap.add_argument("--arrival-load", type=float, default=0.7,
@@ -422,9 +476,15 @@ def main():
         log("bench: qualifying point (n=262144, rate 0.85, f=1.061)")
         qual = qualifying_point(ctx, 5, args.algo)
 
+    unrolled = None
+    if not args.no_unrolled:
+        log("bench: unrolled K=20 training step")
+        unrolled = unrolled_step(ctx, 5)
+
     batched = None
     if args.queue_frames:
-        batched = batched_vs_plain(ctx, args.queue_frames, args.queue_reps, args.arrival_load)
+        batched = batched_vs_plain(ctx, args.queue_frames, args.queue_reps, args.arrival_load,
+                                   batched_only=args.queue_batched_only)
 
     rec = {
         "metric": "reconciled Mbps at FER<=1e-2, f<=1.1; % HBM peak; batched vs plain",
@@ -437,7 +497,7 @@ def main():
         "fer": fer, "decoder_failures": int((ok == 0).sum()),
         "avg_iters": float(iters.mean()), "max_iters": int(iters.max()),
         "f": round(m / (n * h), 4), "f_leak": round(code.u * m / (n * h), 4),
-        "roofline": roofline, "cpu_baseline": cpu, "qualifying_point": qual,
+        "roofline": roofline, "cpu_baseline": cpu, "qualifying_point": qual, "unrolled_training_step": unrolled,
         "batched_vs_plain": batched,
     }
     print(json.dumps(rec), flush=True)
