@@ -762,9 +762,9 @@ int enqueue_kernels(int32_t nb, const mbp_batch *b, const mbp_params *p, const m
     for (int32_t i = 0; i < nb; ++i) {
         const BatchPlace &P = B.place[i];
         const int32_t n = b[i].code->n;
-        k_output_slots<float><<<dim3((n + 63) / 64, 2 * P.ngroups), kBlock, 0, stream>>>(
-            reinterpret_cast<const float *>(base + P.Lp), fid + static_cast<size_t>(P.group0) * G, b[i].bits_out,
-            b[i].llr_out, n);
+        launch_output_slots<float>(reinterpret_cast<const float *>(base + P.Lp),
+                                   fid + static_cast<size_t>(P.group0) * G, b[i].bits_out, b[i].llr_out, n,
+                                   2 * static_cast<int64_t>(P.ngroups), stream);
     }
     k_flag_error<<<1, 64, 0, stream>>>(bar, reinterpret_cast<int32_t *>(base + B.off_err));
     if ((err = hipGetLastError()) != hipSuccess) return hip_fail(err, "batched output launch");

@@ -143,8 +143,8 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
             }
         }
     }
-    LAUNCH_OR_FAIL(kStaging, k_output_slots<T><<<dim3((n + 63) / 64, ntot), kBlock, 0, stream>>>(
-                                 Lp, fid, bits_out, static_cast<T *>(llr_out), n));
+    LAUNCH_OR_FAIL(kStaging, launch_output_slots<T>(Lp, fid, bits_out, static_cast<T *>(llr_out), n, ntot,
+                                                     stream));
 #undef LAUNCH_OR_FAIL
     if ((err = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(err, "hipStreamSynchronize");
     if ((err = tm.collect()) != hipSuccess) return hip_fail(err, "hipEventElapsedTime");

@@ -519,7 +519,8 @@ __global__ __launch_bounds__(kBlock) void k_move(T *c, T *Lp, T *lam, uint64_t *
 }
 
 // [group][n][64] -> bits and L rows [frame][n], from every slot that holds a
-// frame (fid >= 0) in its final state.
+// frame (fid >= 0) in its final state. Block (x, k): 64 variables of group
+// k (launch_output_slots splits the groups over grids of at most 65535).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_output_slots(const T *Lp, const int32_t *fid, uint8_t *bits,
                                                          T *llr_out, int32_t n) {
@@ -782,6 +783,19 @@ int blocks_per_cu(const void *fn) {
 int grid_for(const mbp_ctx *ctx, const void *fn, int64_t items) {
     const int64_t cap = static_cast<int64_t>(ctx->num_cus) * blocks_per_cu(fn);
     return static_cast<int>(std::max<int64_t>(1, std::min(items, cap)));
+}
+
+// k_output_slots over `groups` groups, in launches of at most 65535 groups
+// (the grid's y limit).
+template <typename T>
+void launch_output_slots(const T *Lp, const int32_t *fid, uint8_t *bits, T *llr_out, int32_t n, int64_t groups,
+                         hipStream_t stream) {
+    constexpr int64_t kMaxY = 65535;
+    for (int64_t g0 = 0; g0 < groups; g0 += kMaxY) {
+        const int64_t ng = std::min(kMaxY, groups - g0);
+        k_output_slots<T><<<dim3((n + 63) / 64, static_cast<unsigned>(ng)), kBlock, 0, stream>>>(
+            Lp + g0 * n * G, fid + g0 * G, bits, llr_out, n);
+    }
 }
 
 struct Timer {
