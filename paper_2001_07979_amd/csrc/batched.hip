@@ -267,34 +267,55 @@ __device__ void cn_tile(const GroupDesc &G_, int tile, int t, const PArgs &a, ui
 }
 
 // Variable pass over one tile: L^t (eq. (2), in edge order) and the
-// decision word of each variable.
+// decision word of each variable. A wave takes its variables two at a time
+// and issues the gathers of both (kVarChunk edges each) before summing.
+constexpr int kVarChunk = 16;
+
+__device__ __forceinline__ void vn_finish(const GroupDesc &G_, int i, float s, bool on, unsigned lane) {
+    if (on) stg(G_.Lp, static_cast<int64_t>(i) * G + lane, s);
+    const uint64_t bits = __ballot(on && s < 0.0f);
+    if (lane == 0) stg(G_.D, i, bits);
+}
+
 __device__ void vn_tile(const GroupDesc &G_, int tile, const PArgs &a, uint64_t run) {
+    constexpr int VC = kVarChunk;
     const unsigned lane = lane_id();
     const int wave = wave_id();
     const bool on = (run >> lane) & 1;
     const int vpt = a.vars_per_wave * kWaves;
-    for (int k = 0; k < a.vars_per_wave; ++k) {
-        const int i = tile * vpt + k * kWaves + wave;
-        if (i >= G_.n) break;
-        const int k0 = ldc(G_.var_ptr, i), k1 = ldc(G_.var_ptr, i + 1);
-        float s = on ? ldg(G_.lam, static_cast<int64_t>(i) * G + lane) : 0.0f;
-        for (int kk = k0; kk < k1; kk += kIdxChunk) {
-            int ev[kIdxChunk];
+    for (int k = 0; k < a.vars_per_wave; k += 2) {
+        const int i0 = tile * vpt + k * kWaves + wave;
+        if (i0 >= G_.n) break;
+        const int i1 = i0 + kWaves;
+        const bool two = k + 1 < a.vars_per_wave && i1 < G_.n;
+        const int p0 = ldc(G_.var_ptr, i0), q0 = ldc(G_.var_ptr, i0 + 1);
+        const int p1 = two ? ldc(G_.var_ptr, i1) : 0, q1 = two ? ldc(G_.var_ptr, i1 + 1) : 0;
+        float s0 = on ? ldg(G_.lam, static_cast<int64_t>(i0) * G + lane) : 0.0f;
+        float s1 = on && two ? ldg(G_.lam, static_cast<int64_t>(i1) * G + lane) : 0.0f;
+        const int dmax = q0 - p0 > q1 - p1 ? q0 - p0 : q1 - p1;
+        for (int c0 = 0; c0 < dmax; c0 += VC) {
+            int e0[VC], e1[VC];
 #pragma unroll
-            for (int j = 0; j < kIdxChunk; ++j) ev[j] = ldc(G_.var_edge, kk + j);
+            for (int j = 0; j < VC; ++j) {
+                e0[j] = ldc(G_.var_edge, p0 + c0 + j);
+                e1[j] = ldc(G_.var_edge, p1 + c0 + j);
+            }
             if (on) {
-                float x[kIdxChunk];
+                float x0[VC], x1[VC];
 #pragma unroll
-                for (int j = 0; j < kIdxChunk; ++j)
-                    if (kk + j < k1) x[j] = ldg(G_.c, static_cast<int64_t>(ev[j]) * G + lane);
+                for (int j = 0; j < VC; ++j) {
+                    if (p0 + c0 + j < q0) x0[j] = ldg(G_.c, static_cast<int64_t>(e0[j]) * G + lane);
+                    if (p1 + c0 + j < q1) x1[j] = ldg(G_.c, static_cast<int64_t>(e1[j]) * G + lane);
+                }
 #pragma unroll
-                for (int j = 0; j < kIdxChunk; ++j)
-                    if (kk + j < k1) s += x[j];
+                for (int j = 0; j < VC; ++j) {
+                    if (p0 + c0 + j < q0) s0 += x0[j];
+                    if (p1 + c0 + j < q1) s1 += x1[j];
+                }
             }
         }
-        if (on) stg(G_.Lp, static_cast<int64_t>(i) * G + lane, s);
-        const uint64_t bits = __ballot(on && s < 0.0f);
-        if (lane == 0) stg(G_.D, i, bits);
+        vn_finish(G_, i0, s0, on, lane);
+        if (two) vn_finish(G_, i1, s1, on, lane);
     }
 }
 

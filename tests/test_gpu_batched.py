@@ -133,6 +133,33 @@ def test_compaction_keeps_results(ctx, stragglers):
     assert (its == T).sum() > 100 and (its <= 5).sum() > 80
 
 
+def test_edge_cases(ctx, mix, stragglers):
+    """Iteration limits 1 and 2 (no room for compaction), a batch whose every
+    frame fails (random syndromes), and many small batches at once: all equal
+    to the plain decode."""
+    import torch
+    from paper_2001_07979_amd import mbp
+    items, _ = mix
+    for T in (1, 2):
+        got = [_np(o) for o in mbp.decode_batched(ctx, items, max_iter=T)]
+        for g, p in zip(got, _plain(ctx, items, T=T)):
+            _same(g, p)
+            assert np.all(g["iters"] <= T)
+    dc, llr, z = stragglers[0][0]
+    bad = torch.from_numpy(np.random.default_rng(8).integers(0, 2, tuple(z.shape)).astype(np.uint8)).cuda()
+    got = _np(mbp.decode_batched(ctx, [(dc, llr, bad)], max_iter=12)[0])
+    assert np.all(got["ok"] == 0) and np.all(got["iters"] == 12)
+    _same(got, _plain(ctx, [(dc, llr, bad)], T=12)[0])
+    many = []
+    for k in range(20):
+        d, l, zz = items[k % len(items)]
+        F = 1 + (k * 7) % 5
+        many.append((d, l[:F].contiguous(), zz[:F].contiguous()))
+    got = [_np(o) for o in mbp.decode_batched(ctx, many, max_iter=30)]
+    for g, p in zip(got, _plain(ctx, many, T=30)):
+        _same(g, p)
+
+
 def test_fixed_iterations(ctx, mix):
     from paper_2001_07979_amd import mbp
     items, _ = mix
