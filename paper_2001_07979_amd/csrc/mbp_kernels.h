@@ -286,6 +286,9 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
     }
 }
 
+// Edges of a check whose decision words the stopping test gathers at once.
+constexpr int kStopChunk = 24;
+
 // Stopping test of iteration t (Sec. 2: a frame succeeds once z^l = H_l x
 // for every matrix l), on the decision words the variable pass wrote: bit k
 // of D[g][i] is the decision on bit i of the frame in slot k of group g. One
@@ -327,16 +330,16 @@ __global__ __launch_bounds__(kBlock) void k_stop_test(const int32_t *__restrict_
             const uint64_t *Dg = D + static_cast<size_t>(g) * a.n;
             uint64_t par = zb[static_cast<size_t>(g) * a.M + r];
             const int e1 = row_ptr[r + 1];
-            // indices, then words, a chunk at a time (col is padded past E)
-            for (int e = row_ptr[r]; e < e1; e += kIdxChunk) {
-                int v[kIdxChunk];
+            // indices, then words, kStopChunk at a time (col is padded past E)
+            for (int e = row_ptr[r]; e < e1; e += kStopChunk) {
+                int v[kStopChunk];
 #pragma unroll
-                for (int j = 0; j < kIdxChunk; ++j) v[j] = col[e + j];
-                uint64_t dw[kIdxChunk];
+                for (int j = 0; j < kStopChunk; ++j) v[j] = col[e + j];
+                uint64_t dw[kStopChunk];
 #pragma unroll
-                for (int j = 0; j < kIdxChunk; ++j) dw[j] = e + j < e1 ? Dg[v[j]] : 0;
+                for (int j = 0; j < kStopChunk; ++j) dw[j] = e + j < e1 ? Dg[v[j]] : 0;
 #pragma unroll
-                for (int j = 0; j < kIdxChunk; ++j) par ^= dw[j];
+                for (int j = 0; j < kStopChunk; ++j) par ^= dw[j];
             }
             unmet = par & run;
         }
