@@ -147,8 +147,9 @@ int mbp_llr_from_bits(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y
  * convergence, so it returns once the whole decode has completed.
  * nframes may be 0 (nothing happens) and at most 65535 * 64.
  * Errors: EINVAL (bad parameters, sizes or null pointers), ENOMEM (the
- * context's workspace, about 64 ceil(nframes/64) (E + 2n) sizeof(dtype) +
- * 8 ceil(nframes/64) M bytes, could not be allocated), EDEVICE. */
+ * context's workspace, about 64 g (E + 2n) sizeof(dtype) + 8 g (M + n)
+ * bytes for g = ceil(nframes/64) groups, plus a quarter more groups with
+ * p->compact and early exit, could not be allocated), EDEVICE. */
 int mbp_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,
                const void *llr, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
                uint8_t *ok_out, void *llr_out, void *stream);

@@ -57,6 +57,7 @@ typedef struct {
     double clip;             /* C: messages entering the check rule lie in [-C, C] */
     const double *alpha_tl;  /* optional [T][u] per-iteration, per-matrix weights (min-sum) */
     double margin;           /* delta for the near-tie flag */
+    int32_t schedule;        /* 0 = flooding; 1 = matrix-serial (see phase_rows) */
 } oracle_params;
 
 /* ---------------------------------------------------------------------- */
@@ -231,13 +232,36 @@ static void buf_free(frame_buf *b) {
     free(b->xhat);
 }
 
-/* One frame of MBP (Algorithm 1 with a flooding schedule over the stacked
-   graph). Writes the decided bits, success flag, iteration count, final
-   soft decisions L and the near-tie flag. */
+/* Rows (stacked checks) updated in phase ph of an iteration. Flooding: one
+   phase, every check of every matrix from the previous iteration's
+   messages. Matrix-serial (Algorithm 1 taken literally: inside an
+   iteration the matrices are visited in turn, and each matrix's
+   check-to-variable then variable-to-check updates finish before the next
+   matrix starts): phase l holds the checks of matrix l, and the soft
+   decisions are recomputed after each phase. */
+static int32_t phase_count(const graph *g, const oracle_params *P) { return P->schedule ? g->u : 1; }
+
+static void phase_rows(const graph *g, const oracle_params *P, int32_t ph, int32_t *r0, int32_t *r1) {
+    if (!P->schedule) {
+        *r0 = 0;
+        *r1 = g->M;
+        return;
+    }
+    int32_t a = 0;
+    while (a < g->M && g->row_matrix[a] < ph) ++a;
+    int32_t b = a;
+    while (b < g->M && g->row_matrix[b] == ph) ++b;
+    *r0 = a;
+    *r1 = b;
+}
+
+/* One frame of MBP (Algorithm 1 over the stacked graph, flooding or
+   matrix-serial). Writes the decided bits, success flag, iteration count,
+   final soft decisions L and the near-tie flag. */
 static void decode_frame(const graph *g, const oracle_params *P, const double *lam,
                          const uint8_t *z, frame_buf *b, uint8_t *bits, int32_t *iters,
                          uint8_t *ok, double *Lout, uint8_t *flag) {
-    const int32_t n = g->n, E = g->E, M = g->M;
+    const int32_t n = g->n, E = g->E;
     /* Algorithm 1, first step: every variable-to-check message starts at the
        channel LLR; equivalently no check message yet (c = 0) and L = lambda. */
     for (int32_t e = 0; e < E; ++e) b->c[e] = 0.0;
@@ -246,26 +270,31 @@ static void decode_frame(const graph *g, const oracle_params *P, const double *l
     int stopped = 0;
     uint8_t fl = 0;
     for (int32_t t = 1; t <= P->max_iter; ++t) {
-        /* variable-to-check messages from the previous iteration: the soft
-           decision minus the message that came in on this edge */
-        for (int32_t e = 0; e < E; ++e) b->q[e] = b->L[g->edge_var[e]] - b->c[e];
-        /* check-to-variable messages of every check of every matrix */
-        for (int32_t r = 0; r < M; ++r) {
-            int32_t e0 = g->row_start[r], d = g->row_start[r + 1] - e0;
-            if (P->algo == 0)
-                check_rule_spa(d, b->q + e0, z[r], P->clip, b->th, b->tmp);
-            else
-                check_rule_nms(d, b->q + e0, z[r], weight_of(P, t, g->row_matrix[r], g->u),
-                               P->clip, b->tmp);
-            for (int32_t k = 0; k < d; ++k) b->c[e0 + k] = b->tmp[k];
-        }
-        /* eq. (2): soft decision = channel LLR + every incoming check
-           message, summed over matrices in order, then checks in order */
-        for (int32_t i = 0; i < n; ++i) {
-            double s = lam[i];
-            for (int32_t k = g->var_start[i]; k < g->var_start[i + 1]; ++k)
-                s += b->c[g->var_edges[k]];
-            b->L[i] = s;
+        for (int32_t ph = 0; ph < phase_count(g, P); ++ph) {
+            int32_t r0, r1;
+            phase_rows(g, P, ph, &r0, &r1);
+            /* variable-to-check messages from the current soft decisions:
+               the soft decision minus the message that came in on this edge */
+            for (int32_t e = g->row_start[r0]; e < g->row_start[r1]; ++e)
+                b->q[e] = b->L[g->edge_var[e]] - b->c[e];
+            /* check-to-variable messages of the phase's checks */
+            for (int32_t r = r0; r < r1; ++r) {
+                int32_t e0 = g->row_start[r], d = g->row_start[r + 1] - e0;
+                if (P->algo == 0)
+                    check_rule_spa(d, b->q + e0, z[r], P->clip, b->th, b->tmp);
+                else
+                    check_rule_nms(d, b->q + e0, z[r], weight_of(P, t, g->row_matrix[r], g->u),
+                                   P->clip, b->tmp);
+                for (int32_t k = 0; k < d; ++k) b->c[e0 + k] = b->tmp[k];
+            }
+            /* eq. (2): soft decision = channel LLR + every incoming check
+               message, summed over matrices in order, then checks in order */
+            for (int32_t i = 0; i < n; ++i) {
+                double s = lam[i];
+                for (int32_t k = g->var_start[i]; k < g->var_start[i + 1]; ++k)
+                    s += b->c[g->var_edges[k]];
+                b->L[i] = s;
+            }
         }
         /* decision: bit 1 iff L < 0 */
         for (int32_t i = 0; i < n; ++i) b->xhat[i] = b->L[i] < 0.0 ? 1 : 0;
@@ -312,7 +341,7 @@ static void decode_frame(const graph *g, const oracle_params *P, const double *l
 static void decode_frame_nms_f32(const graph *g, const oracle_params *P, const double *lam64,
                                  const uint8_t *z, frame_buf *b, uint8_t *bits, int32_t *iters,
                                  uint8_t *ok, double *Lout) {
-    const int32_t n = g->n, E = g->E, M = g->M;
+    const int32_t n = g->n, E = g->E;
     float *c = (float *)b->c, *q = (float *)b->q, *L = (float *)b->L, *lam = (float *)b->th;
     const float C = (float)P->clip;
     for (int32_t i = 0; i < n; ++i) lam[i] = (float)lam64[i];
@@ -321,29 +350,33 @@ static void decode_frame_nms_f32(const graph *g, const oracle_params *P, const d
     int32_t t_stop = P->max_iter;
     int stopped = 0;
     for (int32_t t = 1; t <= P->max_iter; ++t) {
-        for (int32_t e = 0; e < E; ++e) q[e] = L[g->edge_var[e]] - c[e];
-        for (int32_t r = 0; r < M; ++r) {
-            int32_t e0 = g->row_start[r], d = g->row_start[r + 1] - e0;
-            float zs = z[r] ? -1.0f : 1.0f;
-            float alpha = (float)weight_of(P, t, g->row_matrix[r], g->u);
-            float *tmp = (float *)b->tmp;
-            for (int32_t k = 0; k < d; ++k) {
-                float sg = 1.0f, mn = INFINITY;
-                for (int32_t kk = 0; kk < d; ++kk) {
-                    if (kk == k) continue;
-                    sg *= q[e0 + kk] < 0.0f ? -1.0f : 1.0f;
-                    float a = fabsf(q[e0 + kk]);
-                    if (a > C) a = C;
-                    if (a < mn) mn = a;
+        for (int32_t ph = 0; ph < phase_count(g, P); ++ph) {
+            int32_t r0, r1;
+            phase_rows(g, P, ph, &r0, &r1);
+            for (int32_t e = g->row_start[r0]; e < g->row_start[r1]; ++e) q[e] = L[g->edge_var[e]] - c[e];
+            for (int32_t r = r0; r < r1; ++r) {
+                int32_t e0 = g->row_start[r], d = g->row_start[r + 1] - e0;
+                float zs = z[r] ? -1.0f : 1.0f;
+                float alpha = (float)weight_of(P, t, g->row_matrix[r], g->u);
+                float *tmp = (float *)b->tmp;
+                for (int32_t k = 0; k < d; ++k) {
+                    float sg = 1.0f, mn = INFINITY;
+                    for (int32_t kk = 0; kk < d; ++kk) {
+                        if (kk == k) continue;
+                        sg *= q[e0 + kk] < 0.0f ? -1.0f : 1.0f;
+                        float a = fabsf(q[e0 + kk]);
+                        if (a > C) a = C;
+                        if (a < mn) mn = a;
+                    }
+                    tmp[k] = zs * alpha * sg * mn;
                 }
-                tmp[k] = zs * alpha * sg * mn;
+                for (int32_t k = 0; k < d; ++k) c[e0 + k] = tmp[k];
             }
-            for (int32_t k = 0; k < d; ++k) c[e0 + k] = tmp[k];
-        }
-        for (int32_t i = 0; i < n; ++i) {
-            float s = lam[i];
-            for (int32_t k = g->var_start[i]; k < g->var_start[i + 1]; ++k) s += c[g->var_edges[k]];
-            L[i] = s;
+            for (int32_t i = 0; i < n; ++i) {
+                float s = lam[i];
+                for (int32_t k = g->var_start[i]; k < g->var_start[i + 1]; ++k) s += c[g->var_edges[k]];
+                L[i] = s;
+            }
         }
         for (int32_t i = 0; i < n; ++i) b->xhat[i] = L[i] < 0.0f ? 1 : 0;
         if (P->early_exit && unsatisfied(g, b->xhat, z) == 0) {
