@@ -293,6 +293,36 @@ def qualifying_point(ctx, steps: int, algo: str):
             "note": "FER from these frames only; 64 frames bound FER below about 4.7% (rule of three)"}
 
 
+def serial_schedule(ctx, wl, fr, dcode, y, e, z, steps: int):
+    """The main workload decoded with the matrix-serial schedule (Algorithm 1:
+    within an iteration each matrix's check pass is followed by a variable
+    pass): fewer iterations per frame, one more pair of passes per matrix."""
+    import torch
+    from paper_2001_07979_amd import mbp
+
+    code = wl.code
+    llr = torch.empty((fr.nframes, code.n), dtype=torch.float32, device=y.device)
+
+    def step():
+        mbp.llr_from_bits(ctx, y, e, dtype="f32", out=llr)
+        return mbp.decode(ctx, dcode, llr, z, algo=wl.algo, max_iter=wl.max_iter, alpha=wl.alpha,
+                          clip=wl.clip, schedule="serial")
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    bits = out["bits"].cpu().numpy()
+    return {"workload": wl.name, "schedule": "matrix-serial", "frames": fr.nframes,
+            "mbps": round(fr.nframes * code.n / dt / 1e6, 1), "ms_per_step": round(dt * 1e3, 4),
+            "fer": float(np.any(bits != fr.x, axis=1).mean()),
+            "avg_iters": float(out["iters"].float().mean().item()),
+            "max_iters": int(out["iters"].max().item())}
+
+
 def unrolled_step(ctx, steps: int):
     """One training step of the differentiable decoder: K=20 unrolled min-sum
     iterations (weights per iteration and matrix) on 512 frames of the u=2
@@ -358,6 +388,8 @@ def main():
     ap.add_argument("--queue-batched-only", action="store_true",
                     help="run only the batched offline leg of the queue (for profiling)")
     ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled training step")
+    ap.add_argument("--no-serial", action="store_true",
+                    help="skip the main workload under the matrix-serial schedule")
     ap.add_argument("--no-qualifying", action="store_true",
                     help="skip the f <= 1.1 operating point (n=262144, rate 0.85)")
     ap.add_argument("--arrival-load", type=float, default=0.7,
@@ -482,6 +514,11 @@ def main():
         log("bench: qualifying point (n=262144, rate 0.85, f=1.061)")
         qual = qualifying_point(ctx, 5, args.algo)
 
+    serial = None
+    if not args.no_serial:
+        log("bench: main workload, matrix-serial schedule")
+        serial = serial_schedule(ctx, wl, fr, dcode, y, e, z, 5)
+
     unrolled = None
     if not args.no_unrolled:
         log("bench: unrolled K=20 training step")
@@ -503,7 +540,8 @@ def main():
         "fer": fer, "decoder_failures": int((ok == 0).sum()),
         "avg_iters": float(iters.mean()), "max_iters": int(iters.max()),
         "f": round(m / (n * h), 4), "f_leak": round(code.u * m / (n * h), 4),
-        "roofline": roofline, "cpu_baseline": cpu, "qualifying_point": qual, "unrolled_training_step": unrolled,
+        "roofline": roofline, "cpu_baseline": cpu, "qualifying_point": qual, "matrix_serial": serial,
+        "unrolled_training_step": unrolled,
         "batched_vs_plain": batched,
     }
     print(json.dumps(rec), flush=True)

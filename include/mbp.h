@@ -68,7 +68,16 @@ typedef struct mbp_code mbp_code;
  *              them (with their state) into fewer spare groups so the late
  *              iterations cost less (the workspace holds a quarter more
  *              groups); 0: never. Results are the same either way. The
- *              batched calls use mbp_tuning.compact instead. */
+ *              batched calls use mbp_tuning.compact instead.
+ *   schedule   MBP_FLOODING: every check of every matrix from the previous
+ *              iteration's messages, then every variable (the default);
+ *              MBP_MATRIX_SERIAL: Algorithm 1 taken literally, the matrices
+ *              in turn within an iteration, each matrix's check update
+ *              followed by the soft decisions (eq. (2)) before the next
+ *              matrix; the stopping test follows the last matrix. mbp_decode
+ *              only (the batched and unrolled calls are flooding). */
+#define MBP_FLOODING 0
+#define MBP_MATRIX_SERIAL 1
 typedef struct {
     int32_t algo;
     int32_t dtype;
@@ -77,7 +86,7 @@ typedef struct {
     double alpha;
     double llr_clip;
     int32_t compact;
-    int32_t reserved; /* 0 */
+    int32_t schedule;
 } mbp_params;
 
 /* Message of the last failed call on this thread ("" if none). */

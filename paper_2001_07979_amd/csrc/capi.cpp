@@ -146,6 +146,8 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
     code->M = (int32_t)M;
     code->E = E;
     code->m.assign(m, m + u);
+    code->e_off.resize(u + 1);
+    for (int32_t l = 0; l <= u; ++l) code->e_off[l] = h_row_ptr[h_mat_off[l]];
     code->max_check_deg = maxcd;
     code->max_var_deg = maxvd;
     auto cleanup = [&](int rc) {
@@ -239,6 +241,8 @@ int mbp_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     if (p->early_exit != 0 && p->early_exit != 1)
         return fail(MBP_EINVAL, "mbp_decode: early_exit must be 0 or 1");
     if (p->compact != 0 && p->compact != 1) return fail(MBP_EINVAL, "mbp_decode: compact must be 0 or 1");
+    if (p->schedule != MBP_FLOODING && p->schedule != MBP_MATRIX_SERIAL)
+        return fail(MBP_EINVAL, "mbp_decode: unknown schedule");
     if (!std::isfinite(p->llr_clip) || p->llr_clip <= 0.0)
         return fail(MBP_EINVAL, "mbp_decode: llr_clip must be finite and > 0");
     if (p->algo == MBP_ALGO_SPA && p->llr_clip > 30.0)
@@ -327,6 +331,8 @@ static int check_batches(const char *fn, mbp_ctx *ctx, int32_t nb, const mbp_bat
     if (nb < 1 || !b) return fail(MBP_EINVAL, f + ": need at least one batch");
     if (p->algo != MBP_ALGO_NMS || p->dtype != MBP_F32)
         return fail(MBP_EUNSUPPORTED, f + ": the batched decode runs normalized min-sum in FP32 only");
+    if (p->schedule != MBP_FLOODING)
+        return fail(MBP_EUNSUPPORTED, f + ": the batched decode runs the flooding schedule only");
     if (p->max_iter < 1 || p->max_iter > 10000) return fail(MBP_EINVAL, f + ": max_iter must be in [1, 10000]");
     if (p->early_exit != 0 && p->early_exit != 1) return fail(MBP_EINVAL, f + ": early_exit must be 0 or 1");
     if (!std::isfinite(p->llr_clip) || p->llr_clip <= 0.0)

@@ -1,6 +1,8 @@
 // Host-side iteration driver of the plain multi-matrix syndrome BP decode
 // (mbp_decode) and the channel-LLR entry (mbp_llr_from_bits). The kernels are
 // in mbp_kernels.h.
+#include <vector>
+
 #include "mbp_kernels.h"
 
 namespace mbp {
@@ -109,17 +111,52 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
         }
     }
 
+    // The check passes of one iteration: all checks at once (flooding), or
+    // one pass per matrix, each followed by the variable pass (matrix-serial).
+    struct Phase {
+        Dims d;
+        int grid;
+    };
+    std::vector<Phase> phases;
+    if (p->schedule == MBP_MATRIX_SERIAL) {
+        int32_t r0 = 0;
+        for (int32_t l = 0; l < code->u; ++l) {
+            Dims d = dc;
+            d.row0 = r0;
+            d.row1 = r0 + code->m[l];
+            d.ntiles = (code->m[l] + kRowsPerTile - 1) / kRowsPerTile;
+            phases.push_back({d, grid_for(ctx, reinterpret_cast<const void *>(kc),
+                                          static_cast<int64_t>(ngroups) * d.ntiles)});
+            r0 = d.row1;
+        }
+    } else {
+        phases.push_back({dc, grid_c});
+    }
+
     // Iteration t: check pass, variable pass (L^t and the decision words),
-    // then, with early exit or on the last iteration, the stopping test,
-    // which retires the frames whose decisions meet every syndrome.
+    // per phase; then, with early exit or on the last iteration, the
+    // stopping test, which retires the frames whose decisions meet every
+    // syndrome.
     for (int32_t t = 1; t <= p->max_iter; ++t) {
-        dc.t = dv.t = ds.t = t;
+        dv.t = ds.t = t;
         ds.flag = t == p->max_iter ? 1 : 0;
-        LAUNCH_OR_FAIL(kCheckNode, kc<<<grid_c, kBlock, 0, stream>>>(code->d_row_ptr, code->d_col,
-                                                                     code->d_row_mat, nullptr, zb, words,
-                                                                     t == 1 ? lam : Lp, c, c, dc));
-        LAUNCH_OR_FAIL(kVarNode, kv<<<grid_v, kBlock, 0, stream>>>(code->d_var_ptr, code->d_var_edge, c, lam,
-                                                                   Lp, words, D, dv));
+        for (size_t ph = 0; ph < phases.size(); ++ph) {
+            Dims d = phases[ph].d;
+            d.t = t;
+            // L^0 = lambda until the first variable pass has run
+            const T *Lin = t == 1 && ph == 0 ? lam : Lp;
+            LAUNCH_OR_FAIL(kCheckNode, kc<<<phases[ph].grid, kBlock, 0, stream>>>(
+                                           code->d_row_ptr, code->d_col, code->d_row_mat, nullptr, zb, words, Lin,
+                                           c, c, d));
+            // decision words only after the iteration's last phase
+            uint64_t *Dout = ph + 1 == phases.size() ? D : nullptr;
+            // in the first serial iteration only matrices 0..ph have sent
+            // check messages; the others' are zero, so their edges are left out
+            Dims dvp = dv;
+            dvp.emax = t == 1 && phases.size() > 1 ? code->e_off[ph + 1] : -1;
+            LAUNCH_OR_FAIL(kVarNode, kv<<<grid_v, kBlock, 0, stream>>>(code->d_var_ptr, code->d_var_edge, c, lam,
+                                                                       Lp, words, Dout, dvp));
+        }
         if (!p->early_exit && t < p->max_iter) continue;
         LAUNCH_OR_FAIL(kSyndrome, k_stop_test<<<grid_s, kBlock, 0, stream>>>(
                                       code->d_row_ptr, code->d_col, zb, D, words, ctx->status_dev,

@@ -64,6 +64,7 @@ struct mbp_code {
     int32_t n = 0, u = 0, M = 0;
     int64_t E = 0;
     std::vector<int32_t> m;
+    std::vector<int64_t> e_off;  // [u + 1] first stacked edge of each matrix
     int32_t max_check_deg = 0, max_var_deg = 0;
     // Device edge layouts of the stacked graph [H_1; ...; H_u]:
     // edges in check-major order (matrix, row, column); for each variable its

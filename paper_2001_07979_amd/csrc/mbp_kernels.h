@@ -105,6 +105,9 @@ struct Dims {
     int32_t T = 0;        // stopping test: the iteration limit
     int32_t spare0 = 0;   // stopping test: first spare group (= groups holding frames)
     int32_t nspare = 0;   // stopping test: spare groups compaction may fill (0: none)
+    int32_t row0 = 0;     // check pass: first stacked check of the pass
+    int32_t row1 = -1;    // check pass: one past its last check (-1: M)
+    int64_t emax = -1;    // variable pass: sum only edges below this (-1: all)
 };
 
 // Counters after the plain decode's status words: the stopping test's
@@ -156,8 +159,8 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
         const T *Lg = Lp + static_cast<size_t>(g) * a.n * G;
         const uint64_t *zg = zb + static_cast<size_t>(g) * a.M;
         for (int k = 0; k < kRowsPerWave; ++k) {
-            const int r = tile * kRowsPerTile + k * kWaves + wave;
-            if (r >= a.M) break;
+            const int r = a.row0 + tile * kRowsPerTile + k * kWaves + wave;
+            if (r >= (a.row1 < 0 ? a.M : a.row1)) break;
             const int e0 = row_ptr[r];
             const int d = row_ptr[r + 1] - e0;
             const int zbit = static_cast<int>((zg[r] >> lane) & 1);
@@ -585,21 +588,25 @@ __global__ __launch_bounds__(kBlock) void k_variable(
         }
         T x[VPW][DV], s[VPW];
         if (on) {
+            // emax >= 0 restricts the sum to stacked edges below it: the
+            // matrices whose check messages exist so far in the first
+            // iteration of the matrix-serial schedule
+            const int64_t lim = a.emax < 0 ? INT64_MAX : a.emax;
+            int ev[VPW][DV];
 #pragma unroll
             for (int v = 0; v < VPW; ++v) {
-                int ev[DV];
 #pragma unroll
-                for (int j = 0; j < DV; ++j) ev[j] = var_edge[k0[v] + j];
+                for (int j = 0; j < DV; ++j) ev[v][j] = var_edge[k0[v] + j];
                 s[v] = in[v] ? (lam + gb + static_cast<size_t>(i[v]) * G)[lane] : T(0);
 #pragma unroll
                 for (int j = 0; j < DV; ++j)
-                    if (j < deg[v]) x[v][j] = (cg + static_cast<size_t>(ev[j]) * G)[lane];
+                    if (j < deg[v] && ev[v][j] < lim) x[v][j] = (cg + static_cast<size_t>(ev[v][j]) * G)[lane];
             }
 #pragma unroll
             for (int v = 0; v < VPW; ++v) {
 #pragma unroll
                 for (int j = 0; j < DV; ++j)
-                    if (j < deg[v]) s[v] += x[v][j];
+                    if (j < deg[v] && ev[v][j] < lim) s[v] += x[v][j];
                 if (in[v]) (Lp + gb + static_cast<size_t>(i[v]) * G)[lane] = s[v];
             }
         }

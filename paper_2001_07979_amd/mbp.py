@@ -51,7 +51,7 @@ class mbp_params(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("early_exit", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("llr_clip", ctypes.c_double),
-                ("compact", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("compact", ctypes.c_int32), ("schedule", ctypes.c_int32)]
 
 
 def lib():
@@ -245,7 +245,7 @@ def llr_from_bits(ctx: Context, y, e, dtype="f32", out=None, stream=None):
 def decode(ctx: Context, code: Code, llr, synd, algo: str = "spa", max_iter: int = 50,
            early_exit: bool = True, alpha: float = 0.75, clip: float = 20.0,
            want_llr: bool = True, out: Optional[dict] = None, stream=None,
-           compact: bool = True) -> dict:
+           compact: bool = True, schedule: str = "flooding") -> dict:
     """Decode every frame: llr [F, n] (float32/float64, GPU), synd [F, M] (uint8, GPU).
 
     Returns dict(bits [F, n] uint8, iters [F] int32, ok [F] uint8, llr [F, n] or None).
@@ -266,7 +266,8 @@ def decode(ctx: Context, code: Code, llr, synd, algo: str = "spa", max_iter: int
                    ok=torch.empty(F, dtype=torch.uint8, device=dev),
                    llr=torch.empty((F, code.n), dtype=llr.dtype, device=dev) if want_llr else None)
     p = mbp_params(MBP_ALGO_SPA if algo == "spa" else MBP_ALGO_NMS, dt, int(max_iter),
-                   int(bool(early_exit)), float(alpha), float(clip), int(bool(compact)), 0)
+                   int(bool(early_exit)), float(alpha), float(clip), int(bool(compact)),
+                   {"flooding": 0, "serial": 1}[schedule])
     _check(lib().mbp_decode(ctx.handle, code.handle, ctypes.byref(p), F, _dev_ptr(llr),
                             _dev_ptr(synd), _dev_ptr(out["bits"]), _dev_ptr(out["iters"]),
                             _dev_ptr(out["ok"]), _dev_ptr(out.get("llr")), _stream_ptr(stream)),
