@@ -257,7 +257,7 @@ def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_
 def qualifying_point(ctx, steps: int, algo: str):
     """The operating point that meets f <= 1.1: u=3 {2,3,10} PEG matrices,
     n=2^18, rate 0.85, BSC 0.02 (f = 1.061), 64 frames, decoded like the main
-    workload (LLRs + decode per step, inputs resident)."""
+    workload (decoded from Bob's bits and error rates per step, inputs resident)."""
     import torch
     from paper_2001_07979_amd import mbp
     from paper_2001_07979_amd.inputs import workloads as W
@@ -270,11 +270,10 @@ def qualifying_point(ctx, steps: int, algo: str):
     y = torch.from_numpy(fr.y).to(dev)
     e = torch.from_numpy(fr.p).to(dev)
     z = torch.from_numpy(fr.z).to(dev)
-    llr = torch.empty((fr.nframes, code.n), dtype=torch.float32, device=dev)
 
     def step():
-        mbp.llr_from_bits(ctx, y, e, dtype="f32", out=llr)
-        return mbp.decode(ctx, dcode, llr, z, algo=wl.algo, max_iter=wl.max_iter, alpha=wl.alpha, clip=wl.clip)
+        return mbp.decode_from_bits(ctx, dcode, y, e, z, dtype="f32", algo=wl.algo, max_iter=wl.max_iter,
+                                    alpha=wl.alpha, clip=wl.clip)
 
     step()
     torch.cuda.synchronize()
@@ -301,12 +300,10 @@ def serial_schedule(ctx, wl, fr, dcode, y, e, z, steps: int):
     from paper_2001_07979_amd import mbp
 
     code = wl.code
-    llr = torch.empty((fr.nframes, code.n), dtype=torch.float32, device=y.device)
 
     def step():
-        mbp.llr_from_bits(ctx, y, e, dtype="f32", out=llr)
-        return mbp.decode(ctx, dcode, llr, z, algo=wl.algo, max_iter=wl.max_iter, alpha=wl.alpha,
-                          clip=wl.clip, schedule="serial")
+        return mbp.decode_from_bits(ctx, dcode, y, e, z, dtype="f32", algo=wl.algo, max_iter=wl.max_iter,
+                                    alpha=wl.alpha, clip=wl.clip, schedule="serial")
 
     step()
     torch.cuda.synchronize()
@@ -426,6 +423,13 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
+        # Bob's bits and error rates in, the LLRs of eq. (5) formed inside
+        # the decoder (the same outputs as llr_from_bits then decode)
+        mbp.decode_from_bits(ctx, dcode, y, e, z, dtype="f32", algo=wl.algo, max_iter=wl.max_iter,
+                             early_exit=wl.early_exit, alpha=wl.alpha, clip=wl.clip, out=out,
+                             stream=stream)
+
+    def step_two_calls():
         mbp.llr_from_bits(ctx, y, e, dtype="f32", out=llr, stream=stream)
         mbp.decode(ctx, dcode, llr, z, algo=wl.algo, max_iter=wl.max_iter,
                    early_exit=wl.early_exit, alpha=wl.alpha, clip=wl.clip, out=out,
@@ -460,6 +464,16 @@ def main():
     iters = out["iters"].cpu().numpy()
     ok = out["ok"].cpu().numpy()
     bits = out["bits"].cpu().numpy()
+
+    # the same step as two calls (LLR rows stored, then decoded)
+    step_two_calls()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        step_two_calls()
+    torch.cuda.synchronize()
+    two_calls_ms = (time.perf_counter() - t2) * 1e3 / args.steps
+    assert np.array_equal(out["bits"].cpu().numpy(), bits)
     frame_err = np.any(bits != fr.x, axis=1)
     fer = float(frame_err.mean())
     p = float(np.mean(fr.p))
@@ -471,12 +485,13 @@ def main():
     if profile:
         n_c, ms_c = ctx.profile_get("check")
         # algorithmic bytes of the check-node pass: for every iteration a
-        # frame runs, read c (E, not at t=1), gather L (n), write c (E)
+        # frame runs, read c (E) and L (n) and write c (E); at t = 1 there
+        # is no c to read, and lambda comes as one bit per variable
         s = 4
         per_step = 0
         for t in range(1, int(iters.max()) + 1):
             full = int((iters >= t).sum())
-            per_step += full * s * ((2 * E if t >= 2 else E) + n)
+            per_step += full * (s * (2 * E + n) if t >= 2 else s * E + n / 8)
         launches_per_step = n_c / args.steps
         bytes_per_launch = per_step / launches_per_step
         avg_ms = ms_c / n_c
@@ -540,6 +555,8 @@ def main():
         "fer": fer, "decoder_failures": int((ok == 0).sum()),
         "avg_iters": float(iters.mean()), "max_iters": int(iters.max()),
         "f": round(m / (n * h), 4), "f_leak": round(code.u * m / (n * h), 4),
+        "llr_rows_then_decode": {"ms_per_step": round(two_calls_ms, 4),
+                                 "mbps": round(F * n / (two_calls_ms * 1e-3) / 1e6, 1)},
         "roofline": roofline, "cpu_baseline": cpu, "qualifying_point": qual, "matrix_serial": serial,
         "unrolled_training_step": unrolled,
         "batched_vs_plain": batched,

@@ -163,6 +163,24 @@ int mbp_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
                const void *llr, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
                uint8_t *ok_out, void *llr_out, void *stream);
 
+/* mbp_decode with the channel given as Bob's bits and each frame's error
+ * rate (Sec. 2 and Sec. 3B, eq. (5)) instead of LLR rows: the decoder forms
+ * lambda = (1 - 2y) ln((1-e)/e) itself, exactly as mbp_llr_from_bits would
+ * (ln((1-e)/e) in FP64, rounded once to p->dtype), so every output equals
+ * mbp_llr_from_bits followed by mbp_decode, bit for bit. The LLRs are never
+ * stored as rows: the kernels read 64-frame bit words and one magnitude per
+ * frame, which saves the first iteration's LLR gathers and the LLR reads of
+ * every variable pass.
+ *   y     device [nframes][n] bytes, 0 = bit 0, nonzero = bit 1
+ *   e     device [nframes] FP64 error rates, each in (0, 0.5]
+ * Every other argument, the output contract and the errors are those of
+ * mbp_decode (the workspace holds 8 g n bytes of bit words and 64 g
+ * magnitudes in place of the 64 g n LLRs). Error rates are not read on the
+ * host; a value outside (0, 0.5] gives non-finite or sign-flipped LLRs. */
+int mbp_decode_from_bits(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,
+                         const uint8_t *y, const double *e, const uint8_t *synd, uint8_t *bits_out,
+                         int32_t *iters_out, uint8_t *ok_out, void *llr_out, void *stream);
+
 /* Unrolled normalized min-sum with a hand-written adjoint (for training the
  * min-sum weights, or any gradient through the decoder). The forward runs K
  * flooding iterations of the min-sum check rule of mbp_decode with no

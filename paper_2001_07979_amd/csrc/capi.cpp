@@ -38,6 +38,33 @@ using mbp::hip_fail;
         if (_e != hipSuccess) return hip_fail(_e, #expr); \
     } while (0)
 
+namespace {
+
+// Checks shared by mbp_decode and mbp_decode_from_bits; `f` names the call.
+int check_decode(const char *f, mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes) {
+    const std::string fn(f);
+    if (!ctx || !code || !p) return fail(MBP_EINVAL, fn + ": null ctx, code or params");
+    if (code->ctx != ctx) return fail(MBP_EINVAL, fn + ": code belongs to another context");
+    if (p->algo != MBP_ALGO_SPA && p->algo != MBP_ALGO_NMS) return fail(MBP_EINVAL, fn + ": unknown algo");
+    if (p->dtype != MBP_F32 && p->dtype != MBP_F64) return fail(MBP_EINVAL, fn + ": unknown dtype");
+    if (p->max_iter < 1 || p->max_iter > 10000) return fail(MBP_EINVAL, fn + ": max_iter must be in [1, 10000]");
+    if (p->early_exit != 0 && p->early_exit != 1) return fail(MBP_EINVAL, fn + ": early_exit must be 0 or 1");
+    if (p->compact != 0 && p->compact != 1) return fail(MBP_EINVAL, fn + ": compact must be 0 or 1");
+    if (p->schedule != MBP_FLOODING && p->schedule != MBP_MATRIX_SERIAL)
+        return fail(MBP_EINVAL, fn + ": unknown schedule");
+    if (!std::isfinite(p->llr_clip) || p->llr_clip <= 0.0)
+        return fail(MBP_EINVAL, fn + ": llr_clip must be finite and > 0");
+    if (p->algo == MBP_ALGO_SPA && p->llr_clip > 30.0)
+        return fail(MBP_EINVAL, fn + ": llr_clip must be <= 30 for sum-product");
+    if (p->algo == MBP_ALGO_NMS && (!std::isfinite(p->alpha) || p->alpha <= 0.0))
+        return fail(MBP_EINVAL, fn + ": alpha must be finite and > 0");
+    if (nframes < 0) return fail(MBP_EINVAL, fn + ": nframes < 0");
+    if (nframes > 65535 * mbp::kLanes) return fail(MBP_EINVAL, fn + ": at most 65535 * 64 frames per call");
+    return MBP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *mbp_last_error(void) { return mbp::g_last_error.c_str(); }
@@ -231,31 +258,22 @@ int mbp_llr_from_bits(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y
 int mbp_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,
                const void *llr, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
                uint8_t *ok_out, void *llr_out, void *stream) {
-    if (!ctx || !code || !p) return fail(MBP_EINVAL, "mbp_decode: null ctx, code or params");
-    if (code->ctx != ctx) return fail(MBP_EINVAL, "mbp_decode: code belongs to another context");
-    if (p->algo != MBP_ALGO_SPA && p->algo != MBP_ALGO_NMS)
-        return fail(MBP_EINVAL, "mbp_decode: unknown algo");
-    if (p->dtype != MBP_F32 && p->dtype != MBP_F64) return fail(MBP_EINVAL, "mbp_decode: unknown dtype");
-    if (p->max_iter < 1 || p->max_iter > 10000)
-        return fail(MBP_EINVAL, "mbp_decode: max_iter must be in [1, 10000]");
-    if (p->early_exit != 0 && p->early_exit != 1)
-        return fail(MBP_EINVAL, "mbp_decode: early_exit must be 0 or 1");
-    if (p->compact != 0 && p->compact != 1) return fail(MBP_EINVAL, "mbp_decode: compact must be 0 or 1");
-    if (p->schedule != MBP_FLOODING && p->schedule != MBP_MATRIX_SERIAL)
-        return fail(MBP_EINVAL, "mbp_decode: unknown schedule");
-    if (!std::isfinite(p->llr_clip) || p->llr_clip <= 0.0)
-        return fail(MBP_EINVAL, "mbp_decode: llr_clip must be finite and > 0");
-    if (p->algo == MBP_ALGO_SPA && p->llr_clip > 30.0)
-        return fail(MBP_EINVAL, "mbp_decode: llr_clip must be <= 30 for sum-product");
-    if (p->algo == MBP_ALGO_NMS && (!std::isfinite(p->alpha) || p->alpha <= 0.0))
-        return fail(MBP_EINVAL, "mbp_decode: alpha must be finite and > 0");
-    if (nframes < 0) return fail(MBP_EINVAL, "mbp_decode: nframes < 0");
-    if (nframes > 65535 * mbp::kLanes)
-        return fail(MBP_EINVAL, "mbp_decode: at most 65535 * 64 frames per call");
-    if (nframes == 0) return MBP_OK;
+    int rc = check_decode("mbp_decode", ctx, code, p, nframes);
+    if (rc != MBP_OK || nframes == 0) return rc;
     if (!llr || !synd || !bits_out || !iters_out || !ok_out)
         return fail(MBP_EINVAL, "mbp_decode: null buffer");
-    return mbp::decode_impl(ctx, code, p, nframes, llr, synd, bits_out, iters_out, ok_out, llr_out,
+    return mbp::decode_impl(ctx, code, p, nframes, llr, nullptr, nullptr, synd, bits_out, iters_out, ok_out,
+                            llr_out, (hipStream_t)stream);
+}
+
+int mbp_decode_from_bits(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,
+                         const uint8_t *y, const double *e, const uint8_t *synd, uint8_t *bits_out,
+                         int32_t *iters_out, uint8_t *ok_out, void *llr_out, void *stream) {
+    int rc = check_decode("mbp_decode_from_bits", ctx, code, p, nframes);
+    if (rc != MBP_OK || nframes == 0) return rc;
+    if (!y || !e || !synd || !bits_out || !iters_out || !ok_out)
+        return fail(MBP_EINVAL, "mbp_decode_from_bits: null buffer");
+    return mbp::decode_impl(ctx, code, p, nframes, nullptr, y, e, synd, bits_out, iters_out, ok_out, llr_out,
                             (hipStream_t)stream);
 }
 

@@ -12,27 +12,50 @@ template <typename T>
 using CheckFn = void (*)(const int32_t *, const int32_t *, const int32_t *, const float *,
                          const uint64_t *, const uint64_t *, const T *, const T *, T *, Dims);
 
-template <typename T, int ALGO>
+template <typename T, int ALGO, bool BITS = false>
 CheckFn<T> check_kernel(int dmax) {
     switch (dmax) {
-        case 8: return &k_check<T, ALGO, 8>;
-        case 16: return &k_check<T, ALGO, 16>;
-        case 24: return &k_check<T, ALGO, 24>;
-        case 32: return &k_check<T, ALGO, 32>;
-        case 48: return &k_check<T, ALGO, 48>;
-        default: return &k_check<T, ALGO, 64>;
+        case 8: return &k_check<T, ALGO, 8, BITS>;
+        case 10: return &k_check<T, ALGO, 10, BITS>;
+        case 16: return &k_check<T, ALGO, 16, BITS>;
+        case 18: return &k_check<T, ALGO, 18, BITS>;
+        case 24: return &k_check<T, ALGO, 24, BITS>;
+        case 32: return &k_check<T, ALGO, 32, BITS>;
+        case 34: return &k_check<T, ALGO, 34, BITS>;
+        case 48: return &k_check<T, ALGO, 48, BITS>;
+        default: return &k_check<T, ALGO, 64, BITS>;
     }
 }
 
+template <typename T, bool BITS = false>
+CheckFn<T> check_kernel_for(int algo, int dmax) {
+    return algo == MBP_ALGO_NMS ? check_kernel<T, kNMS, BITS>(dmax) : check_kernel<T, kSPA, BITS>(dmax);
+}
+
+// The channel of a decode: LLR rows [F][n] of the decode's element type, or
+// Bob's bits y [F][n] (bytes, nonzero = 1) with the error rate e [F] of each
+// frame, from which lambda = (1 - 2y) ln((1 - e)/e) is formed inside the
+// kernels (eq. (5)).
+struct Channel {
+    const void *llr;
+    const uint8_t *y;
+    const double *e;
+};
+
+// The unrolled slot count of the check pass for a largest check degree d:
+// every slot past a check's degree still costs its running updates, so the
+// sizes sit just above common degrees of the codes in use (PEG rows of one
+// code differ in degree by at most one or two).
 int dmax_for(int d) {
-    for (int c : {8, 16, 24, 32, 48}) if (d <= c) return c;
+    for (int c : {8, 10, 16, 18, 24, 32, 34, 48}) if (d <= c) return c;
     return 64;
 }
 
 template <typename T>
 int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t F,
-               const void *llr, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
+               const Channel &ch, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
                uint8_t *ok_out, void *llr_out, hipStream_t stream) {
+    const bool from_bits = ch.y != nullptr;
     const int32_t n = code->n, M = code->M;
     const int64_t E = code->E;
     const int32_t ngroups = (F + G - 1) / G;
@@ -46,9 +69,11 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     const size_t sz_z = align_up(static_cast<size_t>(ntot) * M * sizeof(uint64_t));
     const size_t sz_d = align_up(static_cast<size_t>(ntot) * n * sizeof(uint64_t));
     const size_t sz_f = align_up(static_cast<size_t>(ntot) * G * sizeof(int32_t));
+    // lambda: rows like L, or Bob's bit words and one magnitude per slot
+    const size_t sz_lam = from_bits ? sz_d + align_up(static_cast<size_t>(ntot) * G * s) : sz_L;
     // status words, one 256-byte line per group, then the stopping-test counters
     const size_t sz_m = align_up(static_cast<size_t>(ntot) * kStride * sizeof(uint64_t)) + 256;
-    int rc = ensure_workspace(ctx, sz_c + 2 * sz_L + sz_z + sz_d + 2 * sz_f + sz_m);
+    int rc = ensure_workspace(ctx, sz_c + sz_L + sz_lam + sz_z + sz_d + 2 * sz_f + sz_m);
     if (rc != MBP_OK) return rc;
     if ((rc = ensure_status(ctx, ntot)) != MBP_OK) return rc;
     char *base = static_cast<char *>(ctx->ws);
@@ -60,7 +85,15 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     };
     T *c = reinterpret_cast<T *>(carve(sz_c));
     T *Lp = reinterpret_cast<T *>(carve(sz_L));
-    T *lam = reinterpret_cast<T *>(carve(sz_L));
+    T *lam = nullptr;
+    uint64_t *yb = nullptr;
+    T *ymag = nullptr;
+    if (from_bits) {
+        yb = reinterpret_cast<uint64_t *>(carve(sz_d));
+        ymag = reinterpret_cast<T *>(carve(sz_lam - sz_d));
+    } else {
+        lam = reinterpret_cast<T *>(carve(sz_L));
+    }
     uint64_t *zb = reinterpret_cast<uint64_t *>(carve(sz_z));
     uint64_t *D = reinterpret_cast<uint64_t *>(carve(sz_d));
     int32_t *fid = reinterpret_cast<int32_t *>(carve(sz_f));
@@ -78,19 +111,32 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
 
     LAUNCH_OR_FAIL(kStaging, k_init_running<<<(ntot * G + 255) / 256, 256, 0, stream>>>(
                                  words, ctx->status_dev, tail, fid, F, ngroups, nspare));
-    const dim3 tgrid((n + 63) / 64, ngroups);
-    // L^0 = lambda: the first check pass reads lam, so only lam is staged
-    LAUNCH_OR_FAIL(kStaging, k_stage_llr<T><<<tgrid, kBlock, 0, stream>>>(
-                                 static_cast<const T *>(llr), lam, nullptr, F, n));
+    if (from_bits) {
+        // Bob's bits as 64-frame words per variable, and |lambda| per slot
+        LAUNCH_OR_FAIL(kStaging, k_stage_synd<<<dim3((n + kBlock - 1) / kBlock, ngroups), kBlock, 0, stream>>>(
+                                     ch.y, yb, F, n));
+        LAUNCH_OR_FAIL(kStaging, k_stage_mag<T><<<(ntot * G + kBlock - 1) / kBlock, kBlock, 0, stream>>>(
+                                     ch.e, ymag, F, ntot * G));
+    } else {
+        // L^0 = lambda: the first check pass reads lam, so only lam is staged
+        const dim3 tgrid((n + 63) / 64, ngroups);
+        LAUNCH_OR_FAIL(kStaging, k_stage_llr<T><<<tgrid, kBlock, 0, stream>>>(
+                                     static_cast<const T *>(ch.llr), lam, nullptr, F, n));
+    }
     LAUNCH_OR_FAIL(kStaging, k_stage_synd<<<dim3((M + kBlock - 1) / kBlock, ngroups), kBlock, 0, stream>>>(
                                  synd, zb, F, M));
 
     const int dmax = dmax_for(code->max_check_deg);
-    const CheckFn<T> kc = p->algo == MBP_ALGO_NMS ? check_kernel<T, kNMS>(dmax) : check_kernel<T, kSPA>(dmax);
+    const CheckFn<T> kc = check_kernel_for<T>(p->algo, dmax);
+    // the first iteration's first check pass starts from lambda
+    const CheckFn<T> kc1 = from_bits ? check_kernel_for<T, true>(p->algo, dmax) : kc;
     Dims dc{E, n, M, ntot, (M + kRowsPerTile - 1) / kRowsPerTile, 0, 0, p->alpha, p->llr_clip};
     int vpt = 0;
-    const VarFn<T> kv = variable_kernel<T>(code->max_var_deg, &vpt);
+    const VarFn<T> kv = from_bits ? variable_kernel<T, true>(code->max_var_deg, &vpt)
+                                  : variable_kernel<T>(code->max_var_deg, &vpt);
     Dims dv{E, n, M, ntot, (n + vpt - 1) / vpt, 0, 0, p->alpha, p->llr_clip};
+    dc.ybits = dv.ybits = yb;
+    dc.ymag = dv.ymag = ymag;
     Dims ds{E, n, M, ntot, (M + kBlock - 1) / kBlock, 0, 0, p->alpha, p->llr_clip, p->max_iter, ngroups,
             nspare};
     const int grid_c = grid_for(ctx, reinterpret_cast<const void *>(kc),
@@ -144,8 +190,9 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
             Dims d = phases[ph].d;
             d.t = t;
             // L^0 = lambda until the first variable pass has run
-            const T *Lin = t == 1 && ph == 0 ? lam : Lp;
-            LAUNCH_OR_FAIL(kCheckNode, kc<<<phases[ph].grid, kBlock, 0, stream>>>(
+            const bool start = t == 1 && ph == 0;
+            const T *Lin = start ? lam : Lp;
+            LAUNCH_OR_FAIL(kCheckNode, (start ? kc1 : kc)<<<phases[ph].grid, kBlock, 0, stream>>>(
                                            code->d_row_ptr, code->d_col, code->d_row_mat, nullptr, zb, words, Lin,
                                            c, c, d));
             // decision words only after the iteration's last phase
@@ -163,7 +210,7 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
                                       iters_out, ok_out, fid, src, tail, ds));
         // fills the spare groups the stopping test's compaction planned
         if (nspare && t <= p->max_iter - 2)
-            LAUNCH_OR_FAIL(kSyndrome, k_move<T><<<grid_m, kBlock, 0, stream>>>(c, Lp, lam, zb, src, tail, E, n,
+            LAUNCH_OR_FAIL(kSyndrome, k_move<T><<<grid_m, kBlock, 0, stream>>>(c, Lp, lam, zb, yb, ymag, src, tail, E, n,
                                                                                 M));
         if (p->early_exit) {
             if ((err = hipEventRecord(ctx->poll_events[t & 1], stream)) != hipSuccess)
@@ -191,16 +238,15 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
 }  // namespace
 
 int decode_impl(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,
-                const void *llr, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
-                uint8_t *ok_out, void *llr_out, hipStream_t stream) {
+                const void *llr, const uint8_t *y, const double *e, const uint8_t *synd, uint8_t *bits_out,
+                int32_t *iters_out, uint8_t *ok_out, void *llr_out, hipStream_t stream) {
     (void)hipGetLastError();  // errors of earlier, unrelated calls are not ours
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipError_t err = hipSetDevice(ctx->device);
+    if (err != hipSuccess) return hip_fail(err, "hipSetDevice");
+    const Channel ch{llr, y, e};
     if (p->dtype == MBP_F32)
-        return run_decode<float>(ctx, code, p, nframes, llr, synd, bits_out, iters_out, ok_out, llr_out,
-                                 stream);
-    return run_decode<double>(ctx, code, p, nframes, llr, synd, bits_out, iters_out, ok_out, llr_out,
-                              stream);
+        return run_decode<float>(ctx, code, p, nframes, ch, synd, bits_out, iters_out, ok_out, llr_out, stream);
+    return run_decode<double>(ctx, code, p, nframes, ch, synd, bits_out, iters_out, ok_out, llr_out, stream);
 }
 
 int llr_impl(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y, const double *e,

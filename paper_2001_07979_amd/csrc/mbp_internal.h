@@ -79,10 +79,12 @@ struct mbp_code {
 
 namespace mbp {
 
-// Implemented in decode.hip; arguments are validated by capi.cpp.
+// Implemented in decode.hip; arguments are validated by capi.cpp. The
+// channel is either llr (y and e null) or Bob's bits y with error rates e
+// (llr null).
 int decode_impl(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,
-                const void *llr, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
-                uint8_t *ok_out, void *llr_out, hipStream_t stream);
+                const void *llr, const uint8_t *y, const double *e, const uint8_t *synd, uint8_t *bits_out,
+                int32_t *iters_out, uint8_t *ok_out, void *llr_out, hipStream_t stream);
 int llr_impl(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y, const double *e,
              int32_t dtype, void *llr_out, hipStream_t stream);
 

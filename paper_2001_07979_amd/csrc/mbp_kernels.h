@@ -54,20 +54,19 @@ __device__ __forceinline__ int wave_id() {
 }
 
 // 1 - tanh(a/2) = 2v / (1 + v) with v = e^-a, for a magnitude a >= 0 (at
-// most the clip, so v does not underflow). v comes from the hardware exp2
-// with -a log2(e) split into its rounded value and the residual, which keeps
-// its relative error near one rounding for every a; the complement itself is
-// accurate to a few roundings (relative), including where tanh is near 1.
+// most the clip, so v does not underflow). v is the hardware exp2 of the
+// rounded product -a log2(e): its relative error grows with a, to about 7e-7
+// at a = 20, which becomes an absolute error of that size in a message that
+// large (far inside the FP32 parity bound); the complement itself adds a few
+// roundings (relative), and stays accurate where tanh is near 1.
 __device__ __forceinline__ float tanh_complement(float a) {
-    constexpr float kL2E = 1.44269504088896340736f;
-    constexpr float kL2ELo = 1.925963033500011e-08f;  // log2(e) - kL2E
-    constexpr float kLn2 = 0.693147180559945309f;
-    const float y = -a * kL2E;
-    const float ylo = fmaf(-a, kL2E, -y) + (-a) * kL2ELo;
-    float v = __builtin_amdgcn_exp2f(y);
-    v = fmaf(v, ylo * kLn2, v);
+    constexpr float kNegL2E = -1.44269504088896340736f;
+    const float v = __builtin_amdgcn_exp2f(a * kNegL2E);
     return 2.0f * v * __builtin_amdgcn_rcpf(1.0f + v);
 }
+
+// IEEE sign bit of a float as a word (1u << 31 or 0).
+__device__ __forceinline__ uint32_t sign_word(float x) { return __float_as_uint(x) & 0x80000000u; }
 
 // 2 atanh(1 - E) = ln((2 - E) / E) for a complement E in (0, 1], with two
 // hardware log2: no quotient is rounded, and nothing cancels where E is small
@@ -108,7 +107,26 @@ struct Dims {
     int32_t row0 = 0;     // check pass: first stacked check of the pass
     int32_t row1 = -1;    // check pass: one past its last check (-1: M)
     int64_t emax = -1;    // variable pass: sum only edges below this (-1: all)
+    // Channel LLRs given as Bob's bits (the BITS kernel instances): lambda of
+    // slot k of group g at variable i is -mag or +mag, by bit k of
+    // ybits[g * n + i], with mag = ymag[64 g + k] (element type T).
+    const uint64_t *ybits = nullptr;
+    const void *ymag = nullptr;
 };
+
+// Bob's bit words: each lane reads the 32-bit half of word i that holds its
+// bit. The address is per lane, so the read is one vector load touching a
+// single 8-byte word for the whole wave (a uniform address would become a
+// chain of scalar loads, which measured slower than gathering 256-byte
+// rows). Callers issue every such load before converting any (lam_of_half),
+// so the loads stay in flight together.
+__device__ __forceinline__ uint32_t bit_half(const uint64_t *yg, int i, unsigned lane) {
+    return reinterpret_cast<const uint32_t *>(yg + i)[lane >> 5];
+}
+template <typename T>
+__device__ __forceinline__ T lam_of_half(uint32_t half, unsigned lane, T mag) {
+    return (half >> (lane & 31u)) & 1u ? -mag : mag;
+}
 
 // Counters after the plain decode's status words: the stopping test's
 // arrival count, the spare groups filled so far, and the compaction the
@@ -131,10 +149,12 @@ constexpr int kRun = 0, kUnmet = 1;
 //
 // c_in holds c^{t-1} (unused at t = 1) and c_out receives c^t; the plain
 // decode passes the same array for both (each edge is read before it is
-// written, by the same lane). alpha_l, if not null, gives the min-sum weight
+// written, by the same lane). The BITS instance runs the first iteration from
+// Bob's bits instead of Lp (q = lambda, c^0 = 0): its gathers touch one
+// 8-byte bit word per edge rather than a 256-byte row. alpha_l, if not null, gives the min-sum weight
 // of each matrix for this iteration (row_mat maps a check to its matrix);
 // otherwise a.alpha applies to every check.
-template <typename T, int ALGO, int DMAX>
+template <typename T, int ALGO, int DMAX, bool BITS = false>
 __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ row_ptr,
                                                   const int32_t *__restrict__ col,
                                                   const int32_t *__restrict__ row_mat,
@@ -158,6 +178,8 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
         // are a scalar base plus one per-lane offset
         const T *Lg = Lp + static_cast<size_t>(g) * a.n * G;
         const uint64_t *zg = zb + static_cast<size_t>(g) * a.M;
+        const uint64_t *yg = BITS ? a.ybits + static_cast<size_t>(g) * a.n : nullptr;
+        const T ym = BITS ? static_cast<const T *>(a.ymag)[static_cast<size_t>(g) * G + lane] : T(0);
         for (int k = 0; k < kRowsPerWave; ++k) {
             const int r = a.row0 + tile * kRowsPerTile + k * kWaves + wave;
             if (r >= (a.row1 < 0 ? a.M : a.row1)) break;
@@ -174,19 +196,61 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
             if (on) {
                 // issue every gather of the check before using any of them
                 T q[DMAX], co[DMAX];
+                uint32_t yh[DMAX];
 #pragma unroll
                 for (int j = 0; j < DMAX; ++j) {
                     if (j < d) {
-                        q[j] = (Lg + static_cast<size_t>(v[j]) * G)[lane];
-                        co[j] = first ? T(0) : (ci + j * G)[lane];
+                        if constexpr (BITS) {
+                            yh[j] = bit_half(yg, v[j], lane);
+                        } else {
+                            q[j] = (Lg + static_cast<size_t>(v[j]) * G)[lane];
+                            co[j] = first ? T(0) : (ci + j * G)[lane];
+                        }
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < DMAX; ++j)
-                    if (j < d) q[j] -= co[j];
+                for (int j = 0; j < DMAX; ++j) {
+                    if (j < d) {
+                        if constexpr (BITS)
+                            q[j] = lam_of_half(yh[j], lane, ym);
+                        else
+                            q[j] -= co[j];
+                    }
+                }
                 uint64_t neg = 0;
                 int sx = zbit;  // syndrome sign times every message sign
-                if constexpr (ALGO == kNMS) {
+                if constexpr (ALGO == kNMS && sizeof(T) == 4) {
+                    // FP32 min-sum. Each message's sign rides in its IEEE
+                    // sign bit (after q + 0 turns -0 into +0: sgn(0) = +1),
+                    // so the sign product is an XOR of words; slots past
+                    // the degree enter the running minima as +inf, which
+                    // leaves them unchanged. m2 = med3(m1, a, m2) is the
+                    // second minimum after taking a, as m1 <= m2 always.
+                    uint32_t sxb = static_cast<uint32_t>(zbit) << 31;
+                    float m1 = INFINITY, m2 = INFINITY;
+                    int i1 = 0;
+#pragma unroll
+                    for (int j = 0; j < DMAX; ++j) {
+                        float aj = INFINITY;
+                        if (j < d) {
+                            q[j] = q[j] + 0.0f;
+                            sxb ^= __float_as_uint(q[j]);
+                            aj = fminf(fabsf(q[j]), clip);
+                        }
+                        m2 = __builtin_amdgcn_fmed3f(m1, aj, m2);
+                        i1 = aj < m1 ? j : i1;
+                        m1 = fminf(m1, aj);
+                    }
+                    const float a1 = alpha * m1, a2 = alpha * m2;
+#pragma unroll
+                    for (int j = 0; j < DMAX; ++j) {
+                        if (j < d) {
+                            const float mag = j == i1 ? a2 : a1;  // >= 0
+                            (cg + j * G)[lane] = __uint_as_float(__float_as_uint(mag) |
+                                                                 sign_word(__uint_as_float(sxb ^ __float_as_uint(q[j]))));
+                        }
+                    }
+                } else if constexpr (ALGO == kNMS) {
                     T m1 = T(INFINITY), m2 = T(INFINITY);
                     int i1 = 0;
 #pragma unroll
@@ -220,36 +284,42 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                     // (a prefix and a suffix, merged per edge), so magnitudes
                     // near the clip, where tanh rounds to 1, keep their
                     // precision: 1 - (1 - x)(1 - y) = x + y - xy.
-                    T ep[DMAX];
+                    // Slots past the degree hold the complement 0 (tanh = 1),
+                    // for which both running updates below are exact no-ops,
+                    // so they run over every slot without a per-slot test.
+                    // Each complement carries its message's sign in its sign
+                    // bit (read through fabsf, which costs nothing), and the
+                    // sign product is an XOR of words, as in min-sum.
+                    uint32_t sxb = static_cast<uint32_t>(zbit) << 31;
+                    float ep[DMAX];
 #pragma unroll
                     for (int j = 0; j < DMAX; ++j) {
+                        ep[j] = 0.0f;
                         if (j < d) {
-                            const int s = q[j] < T(0) ? 1 : 0;
-                            sx ^= s;
-                            neg |= static_cast<uint64_t>(s) << j;
-                            T aj = fabs(q[j]);
-                            aj = aj < clip ? aj : clip;
-                            ep[j] = tanh_complement(aj);
+                            const float qj = q[j] + 0.0f;  // -0 -> +0: sgn(0) = +1
+                            sxb ^= __float_as_uint(qj);
+                            ep[j] = __uint_as_float(__float_as_uint(tanh_complement(fminf(fabsf(qj), clip))) |
+                                                    sign_word(qj));
                         }
                     }
-                    T run = T(0);
+                    float run = 0.0f;
 #pragma unroll
                     for (int j = 0; j < DMAX; ++j) {
-                        if (j < d) {
-                            q[j] = run;  // complement of the product before j
-                            run = fmaf(-run, ep[j], run + ep[j]);
-                        }
+                        const float e = fabsf(ep[j]);
+                        q[j] = run;  // complement of the product before j
+                        run = fmaf(-run, e, run + e);
                     }
-                    T suf = T(0);
+                    float suf = 0.0f;
 #pragma unroll
                     for (int j = DMAX - 1; j >= 0; --j) {
                         if (j < d) {
-                            const T E = fmaf(-q[j], suf, q[j] + suf);
-                            const T mag = atanh2_of_complement(E);
-                            suf = fmaf(-suf, ep[j], suf + ep[j]);
-                            const int s = sx ^ static_cast<int>((neg >> j) & 1);
-                            (cg + j * G)[lane] = s ? -mag : mag;
+                            const float E = fmaf(-q[j], suf, q[j] + suf);
+                            const float mag = atanh2_of_complement(E);
+                            const uint32_t sb = sign_word(__uint_as_float(sxb ^ __float_as_uint(ep[j])));
+                            (cg + j * G)[lane] = __uint_as_float((__float_as_uint(mag) & 0x7fffffffu) | sb);
                         }
+                        const float e = fabsf(ep[j]);
+                        suf = fmaf(-suf, e, suf + e);
                     }
                 } else {
                     // sum-product, FP64: tanh domain with prefix/suffix products
@@ -466,17 +536,21 @@ constexpr int kMovePerWave = kMoveRows / kWaves;
 
 // Fills the groups the last stopping test's compaction planned (none: the
 // kernel does nothing): rows of c (E), L and lambda (n each) and syndrome
-// words (M), each lane from its source slot src[]. Work items are runs of
+// words (M), each lane from its source slot src[]. With the channel given as
+// bits (lam null), Bob's bit words (n, after the syndrome words) and the
+// per-slot magnitudes move instead of the lambda rows. Work items are runs of
 // kMoveRows rows of one region of one group.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_move(T *c, T *Lp, T *lam, uint64_t *zb, const int32_t *src,
-                                                 const StopTail *tail, int64_t E, int32_t n, int32_t M) {
+__global__ __launch_bounds__(kBlock) void k_move(T *c, T *Lp, T *lam, uint64_t *zb, uint64_t *yb, T *ymag,
+                                                 const int32_t *src, const StopTail *tail, int64_t E, int32_t n,
+                                                 int32_t M) {
     const int count = tail->move_count, first = tail->move_first;
     if (count == 0) return;
     const unsigned lane = lane_id();
     const int wave = wave_id();
+    const int64_t nw = M + (yb ? n : 0);  // word rows: syndromes, then Bob's bits
     const int64_t ic = (E + kMoveRows - 1) / kMoveRows, il = (n + kMoveRows - 1) / kMoveRows,
-                  iz = (M + kMoveRows - 1) / kMoveRows, per_group = ic + il + iz;
+                  iz = (nw + kMoveRows - 1) / kMoveRows, per_group = ic + il + iz;
     for (int64_t w = blockIdx.x; w < count * per_group; w += gridDim.x) {
         const int64_t g = first + w / per_group;
         int64_t item = w % per_group;
@@ -494,19 +568,20 @@ __global__ __launch_bounds__(kBlock) void k_move(T *c, T *Lp, T *lam, uint64_t *
                 if (has && r0 + j < E) c[(g * E + r0 + j) * G + lane] = v[j];
         } else if ((item -= ic) < il) {
             const int64_t r0 = item * kMoveRows + wave * kMovePerWave;
+            if (ymag && item == 0 && wave == 0 && has) ymag[g * G + lane] = ymag[sg * G + sl];
             T v[kMovePerWave], u[kMovePerWave];
 #pragma unroll
             for (int j = 0; j < kMovePerWave; ++j) {
                 if (has && r0 + j < n) {
                     v[j] = Lp[(sg * n + r0 + j) * G + sl];
-                    u[j] = lam[(sg * n + r0 + j) * G + sl];
+                    if (lam) u[j] = lam[(sg * n + r0 + j) * G + sl];
                 }
             }
 #pragma unroll
             for (int j = 0; j < kMovePerWave; ++j) {
                 if (has && r0 + j < n) {
                     Lp[(g * n + r0 + j) * G + lane] = v[j];
-                    lam[(g * n + r0 + j) * G + lane] = u[j];
+                    if (lam) lam[(g * n + r0 + j) * G + lane] = u[j];
                 }
             }
         } else {
@@ -514,11 +589,20 @@ __global__ __launch_bounds__(kBlock) void k_move(T *c, T *Lp, T *lam, uint64_t *
             const int64_t r0 = item * kMoveRows + wave * kMovePerWave;
             uint64_t v[kMovePerWave];
 #pragma unroll
-            for (int j = 0; j < kMovePerWave; ++j) v[j] = has && r0 + j < M ? zb[sg * M + r0 + j] : 0;
+            for (int j = 0; j < kMovePerWave; ++j) {
+                const int64_t r = r0 + j;
+                v[j] = !has || r >= nw ? 0 : r < M ? zb[sg * M + r] : yb[sg * n + (r - M)];
+            }
 #pragma unroll
             for (int j = 0; j < kMovePerWave; ++j) {
+                const int64_t r = r0 + j;
                 const uint64_t bits = __ballot((v[j] >> sl) & 1);
-                if (lane == 0 && r0 + j < M) zb[g * M + r0 + j] = bits;
+                if (lane == 0 && r < nw) {
+                    if (r < M)
+                        zb[g * M + r] = bits;
+                    else
+                        yb[g * n + (r - M)] = bits;
+                }
             }
         }
     }
@@ -560,7 +644,7 @@ __global__ __launch_bounds__(kBlock) void k_output_slots(const T *Lp, const int3
 // gathers before summing any. D, if not null, receives the decision word of
 // each variable (bit k set when frame 64g+k decides 1, i.e. L < 0; frames
 // not running leave 0).
-template <typename T, int DV, int VPW>
+template <typename T, int DV, int VPW, bool BITS = false>
 __global__ __launch_bounds__(kBlock) void k_variable(
     const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_edge,
     const T *__restrict__ c, const T *__restrict__ lam, T *__restrict__ Lp,
@@ -576,6 +660,8 @@ __global__ __launch_bounds__(kBlock) void k_variable(
         const bool on = (run >> lane) & 1;
         const size_t gb = static_cast<size_t>(g) * a.n * G;
         const T *cg = c + static_cast<size_t>(g) * a.E * G;
+        const uint64_t *yg = BITS ? a.ybits + static_cast<size_t>(g) * a.n : nullptr;
+        const T ym = BITS ? static_cast<const T *>(a.ymag)[static_cast<size_t>(g) * G + lane] : T(0);
         int i[VPW], k0[VPW], deg[VPW];
         bool in[VPW];
 #pragma unroll
@@ -593,14 +679,22 @@ __global__ __launch_bounds__(kBlock) void k_variable(
             // iteration of the matrix-serial schedule
             const int64_t lim = a.emax < 0 ? INT64_MAX : a.emax;
             int ev[VPW][DV];
+            uint32_t yh[VPW];
 #pragma unroll
             for (int v = 0; v < VPW; ++v) {
 #pragma unroll
                 for (int j = 0; j < DV; ++j) ev[v][j] = var_edge[k0[v] + j];
-                s[v] = in[v] ? (lam + gb + static_cast<size_t>(i[v]) * G)[lane] : T(0);
+                if constexpr (BITS)
+                    yh[v] = in[v] ? bit_half(yg, i[v], lane) : 0u;
+                else
+                    s[v] = in[v] ? (lam + gb + static_cast<size_t>(i[v]) * G)[lane] : T(0);
 #pragma unroll
                 for (int j = 0; j < DV; ++j)
                     if (j < deg[v] && ev[v][j] < lim) x[v][j] = (cg + static_cast<size_t>(ev[v][j]) * G)[lane];
+            }
+            if constexpr (BITS) {
+#pragma unroll
+                for (int v = 0; v < VPW; ++v) s[v] = in[v] ? lam_of_half(yh[v], lane, ym) : T(0);
             }
 #pragma unroll
             for (int v = 0; v < VPW; ++v) {
@@ -626,13 +720,13 @@ template <typename T>
 using VarFn = void (*)(const int32_t *, const int32_t *, const T *, const T *, T *, const uint64_t *,
                        uint64_t *, Dims);
 
-template <typename T>
+template <typename T, bool BITS = false>
 VarFn<T> variable_kernel(int dmax, int *vars_per_tile) {
-    if (dmax <= 8) { *vars_per_tile = 4 * kWaves; return &k_variable<T, 8, 4>; }
-    if (dmax <= 16) { *vars_per_tile = 4 * kWaves; return &k_variable<T, 16, 4>; }
-    if (dmax <= 32) { *vars_per_tile = 2 * kWaves; return &k_variable<T, 32, 2>; }
+    if (dmax <= 8) { *vars_per_tile = 4 * kWaves; return &k_variable<T, 8, 4, BITS>; }
+    if (dmax <= 16) { *vars_per_tile = 4 * kWaves; return &k_variable<T, 16, 4, BITS>; }
+    if (dmax <= 32) { *vars_per_tile = 2 * kWaves; return &k_variable<T, 32, 2, BITS>; }
     *vars_per_tile = kWaves;
-    return &k_variable<T, 64, 1>;
+    return &k_variable<T, 64, 1, BITS>;
 }
 
 // Running set of the plain and unrolled decodes before the first iteration:
@@ -691,6 +785,21 @@ __global__ __launch_bounds__(kBlock) void k_stage_llr(const T *llr, T *lam, T *L
             if (Lp) Lp[o] = v;
         }
     }
+}
+
+// |lambda| = ln((1 - e)/e) of every slot, for frames given as Bob's bits
+// (eq. (5)); formed in FP64 and rounded once, as k_llr does. Slots past the
+// frames get 0.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_stage_mag(const double *e, T *mag, int32_t nframes, int32_t nslots) {
+    const int s = blockIdx.x * kBlock + static_cast<int>(threadIdx.x);
+    if (s >= nslots) return;
+    T m = T(0);
+    if (s < nframes) {
+        const double ef = e[s];
+        m = static_cast<T>(log((1.0 - ef) / ef));
+    }
+    mag[s] = m;
 }
 
 // [F][M] syndrome bytes -> [g][M] 64-bit lane masks. One thread per check

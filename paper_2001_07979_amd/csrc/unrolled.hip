@@ -267,6 +267,7 @@ using AdjPtr = void (*)(const int32_t *, const int32_t *, const int32_t *, const
 void pick(int dmax, FwdFn *f, AdjPtr *b) {
     switch (dmax) {
         case 8: *f = &k_check<float, MBP_ALGO_NMS, 8>; *b = &k_check_adjoint<8>; break;
+        case 10: *f = &k_check<float, MBP_ALGO_NMS, 10>; *b = &k_check_adjoint<10>; break;
         case 16: *f = &k_check<float, MBP_ALGO_NMS, 16>; *b = &k_check_adjoint<16>; break;
         case 24: *f = &k_check<float, MBP_ALGO_NMS, 24>; *b = &k_check_adjoint<24>; break;
         case 32: *f = &k_check<float, MBP_ALGO_NMS, 32>; *b = &k_check_adjoint<32>; break;
@@ -276,7 +277,7 @@ void pick(int dmax, FwdFn *f, AdjPtr *b) {
 }
 
 int dmax_of(int d) {
-    for (int c : {8, 16, 24, 32, 48}) if (d <= c) return c;
+    for (int c : {8, 10, 16, 24, 32, 48}) if (d <= c) return c;
     return 64;
 }
 

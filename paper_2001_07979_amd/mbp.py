@@ -20,6 +20,7 @@ MBP_OK = 0
 MBP_EINVAL, MBP_ENOMEM, MBP_EDEVICE, MBP_ESTATE, MBP_EUNSUPPORTED = -1, -2, -3, -4, -5
 MBP_ALGO_SPA, MBP_ALGO_NMS = 0, 1
 MBP_F32, MBP_F64 = 0, 1
+MBP_FLOODING, MBP_MATRIX_SERIAL = 0, 1
 KERNEL_IDS = {"check": 0, "variable": 1, "syndrome": 2, "staging": 3}
 
 _lib = None
@@ -72,6 +73,7 @@ def lib():
             "mbp_code_info": (ctypes.c_int, [vp] + [vp] * 6),
             "mbp_llr_from_bits": (ctypes.c_int, [vp, i32, i32, vp, vp, i32, vp, vp]),
             "mbp_decode": (ctypes.c_int, [vp, vp, ctypes.POINTER(mbp_params), i32] + [vp] * 7),
+            "mbp_decode_from_bits": (ctypes.c_int, [vp, vp, ctypes.POINTER(mbp_params), i32] + [vp] * 8),
             "mbp_unrolled_workspace_bytes": (ctypes.c_int, [vp, i32, i32, i32,
                                                              ctypes.POINTER(ctypes.c_uint64)]),
             "mbp_nms_unrolled_fwd": (ctypes.c_int, [vp, vp, i32, i32, i32, ctypes.c_double] + [vp] * 5
@@ -242,6 +244,20 @@ def llr_from_bits(ctx: Context, y, e, dtype="f32", out=None, stream=None):
     return out
 
 
+def _params(algo, dt, max_iter, early_exit, alpha, clip, compact, schedule):
+    return mbp_params(MBP_ALGO_SPA if algo == "spa" else MBP_ALGO_NMS, dt, int(max_iter),
+                      int(bool(early_exit)), float(alpha), float(clip), int(bool(compact)),
+                      {"flooding": MBP_FLOODING, "serial": MBP_MATRIX_SERIAL}[schedule])
+
+
+def _decode_outputs(F, n, dtype, dev, want_llr):
+    import torch
+    return dict(bits=torch.empty((F, n), dtype=torch.uint8, device=dev),
+                iters=torch.empty(F, dtype=torch.int32, device=dev),
+                ok=torch.empty(F, dtype=torch.uint8, device=dev),
+                llr=torch.empty((F, n), dtype=dtype, device=dev) if want_llr else None)
+
+
 def decode(ctx: Context, code: Code, llr, synd, algo: str = "spa", max_iter: int = 50,
            early_exit: bool = True, alpha: float = 0.75, clip: float = 20.0,
            want_llr: bool = True, out: Optional[dict] = None, stream=None,
@@ -259,19 +275,40 @@ def decode(ctx: Context, code: Code, llr, synd, algo: str = "spa", max_iter: int
         raise ValueError("llr and synd must be contiguous")
     if synd.dtype != torch.uint8:
         raise ValueError("synd must be uint8")
-    dev = llr.device
     if out is None:
-        out = dict(bits=torch.empty((F, code.n), dtype=torch.uint8, device=dev),
-                   iters=torch.empty(F, dtype=torch.int32, device=dev),
-                   ok=torch.empty(F, dtype=torch.uint8, device=dev),
-                   llr=torch.empty((F, code.n), dtype=llr.dtype, device=dev) if want_llr else None)
-    p = mbp_params(MBP_ALGO_SPA if algo == "spa" else MBP_ALGO_NMS, dt, int(max_iter),
-                   int(bool(early_exit)), float(alpha), float(clip), int(bool(compact)),
-                   {"flooding": 0, "serial": 1}[schedule])
+        out = _decode_outputs(F, code.n, llr.dtype, llr.device, want_llr)
+    p = _params(algo, dt, max_iter, early_exit, alpha, clip, compact, schedule)
     _check(lib().mbp_decode(ctx.handle, code.handle, ctypes.byref(p), F, _dev_ptr(llr),
                             _dev_ptr(synd), _dev_ptr(out["bits"]), _dev_ptr(out["iters"]),
                             _dev_ptr(out["ok"]), _dev_ptr(out.get("llr")), _stream_ptr(stream)),
            "mbp_decode")
+    return out
+
+
+def decode_from_bits(ctx: Context, code: Code, y, e, synd, dtype: str = "f32", algo: str = "spa",
+                     max_iter: int = 50, early_exit: bool = True, alpha: float = 0.75,
+                     clip: float = 20.0, want_llr: bool = True, out: Optional[dict] = None,
+                     stream=None, compact: bool = True, schedule: str = "flooding") -> dict:
+    """decode() with the channel given as Bob's bits y [F, n] (uint8, GPU) and
+    error rates e [F] (float64, GPU); the LLRs are formed inside the decoder.
+    Same outputs as llr_from_bits followed by decode, bit for bit."""
+    import torch
+    F = int(y.shape[0])
+    if y.dim() != 2 or y.shape[1] != code.n or tuple(e.shape) != (F,) or tuple(synd.shape) != (F, code.M):
+        raise ValueError("y must be [F, n], e [F] and synd [F, M]")
+    if not (y.is_contiguous() and e.is_contiguous() and synd.is_contiguous()):
+        raise ValueError("y, e and synd must be contiguous")
+    if y.dtype != torch.uint8 or synd.dtype != torch.uint8 or e.dtype != torch.float64:
+        raise ValueError("y and synd must be uint8, e float64")
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    if out is None:
+        out = _decode_outputs(F, code.n, tdt, y.device, want_llr)
+    p = _params(algo, _dtype_code(tdt), max_iter, early_exit, alpha, clip, compact, schedule)
+    _check(lib().mbp_decode_from_bits(ctx.handle, code.handle, ctypes.byref(p), F, _dev_ptr(y),
+                                      _dev_ptr(e), _dev_ptr(synd), _dev_ptr(out["bits"]),
+                                      _dev_ptr(out["iters"]), _dev_ptr(out["ok"]),
+                                      _dev_ptr(out.get("llr")), _stream_ptr(stream)),
+           "mbp_decode_from_bits")
     return out
 
 

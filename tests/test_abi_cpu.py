@@ -46,6 +46,8 @@ def test_version_and_error_paths_without_device():
     p = mbp.mbp_params(0, 0, 10, 1, 0.75, 20.0)
     assert L.mbp_decode(None, None, ctypes.byref(p), 1, *([None] * 7)) == mbp.MBP_EINVAL
     assert L.mbp_llr_from_bits(None, 1, 1, None, None, 0, None, None) == mbp.MBP_EINVAL
+    assert L.mbp_decode_from_bits(None, None, ctypes.byref(p), 1, *([None] * 8)) == mbp.MBP_EINVAL
+    assert "mbp_decode_from_bits" in mbp.last_error()
     n, ms = ctypes.c_int64(), ctypes.c_double()
     assert L.mbp_profile_get(None, 0, ctypes.byref(n), ctypes.byref(ms)) == mbp.MBP_EINVAL
     L.mbp_ctx_destroy(None)

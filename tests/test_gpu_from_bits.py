@@ -1,0 +1,153 @@
+"""GPU: decoding from Bob's bits and error rates (mbp_decode_from_bits, the
+LLRs of eq. (5) formed inside the decoder) gives the same outputs, bit for
+bit, as mbp_llr_from_bits followed by mbp_decode (itself held to the oracle
+by test_gpu_decode.py and test_gpu_serial.py), and sampled frames match the
+oracle directly."""
+import numpy as np
+import pytest
+
+from paper_2001_07979_amd.inputs import bsc_frames, peg_code
+from paper_2001_07979_amd.inputs import workloads as W
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2001_07979_amd import mbp
+    c = mbp.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def codes():
+    return {2: peg_code(1000, 260, 2, W.IRREGULAR_238, seed_base=7100, name="peg-n1000"),
+            3: peg_code(640, 200, 3, {2: 0.3, 3: 0.7}, seed_base=7300, name="peg-n640-u3")}
+
+
+def _dev(fr):
+    import torch
+    return (torch.from_numpy(fr.y).cuda(), torch.from_numpy(fr.p.astype(np.float64)).cuda(),
+            torch.from_numpy(fr.z).cuda())
+
+
+def _both(ctx, dc, fr, dtype="f32", **kw):
+    """(from bits, LLRs then decode) outputs as numpy dicts."""
+    import torch
+    from paper_2001_07979_amd import mbp
+    y, e, z = _dev(fr)
+    a = mbp.decode_from_bits(ctx, dc, y, e, z, dtype=dtype, **kw)
+    llr = mbp.llr_from_bits(ctx, y, e, dtype=dtype)
+    b = mbp.decode(ctx, dc, llr, z, **kw)
+    torch.cuda.synchronize()
+    return ({k: v.cpu().numpy() for k, v in a.items() if v is not None},
+            {k: v.cpu().numpy() for k, v in b.items() if v is not None})
+
+
+def _same(a, b):
+    for k in ("bits", "iters", "ok", "llr"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("u", [2, 3])
+@pytest.mark.parametrize("algo,dtype", [("nms", "f32"), ("spa", "f32"), ("spa", "f64"), ("nms", "f64")])
+@pytest.mark.parametrize("schedule", ["flooding", "serial"])
+@pytest.mark.parametrize("F", [1, 65, 130])
+def test_from_bits_equals_llr_path(ctx, codes, u, algo, dtype, schedule, F):
+    from paper_2001_07979_amd import mbp
+    code = codes[u]
+    fr = bsc_frames(code, F, np.linspace(0.01, 0.04, F), seed=500 + F + u)
+    dc = mbp.Code.from_inputs(ctx, code)
+    a, b = _both(ctx, dc, fr, dtype, algo=algo, max_iter=40, schedule=schedule)
+    _same(a, b)
+    assert a["ok"].sum() >= F // 2
+
+
+@pytest.mark.parametrize("algo,dtype", [("spa", "f32"), ("nms", "f32"), ("spa", "f64")])
+@pytest.mark.parametrize("schedule", ["flooding", "serial"])
+def test_from_bits_compaction(ctx, codes, algo, dtype, schedule):
+    """300 frames whose decodes stop anywhere from 2 to T iterations: the bit
+    words and magnitudes move with their frames when compaction regroups
+    them; outputs equal the decode without compaction and the LLR path."""
+    from paper_2001_07979_amd import mbp
+    code = codes[2]
+    p = np.random.default_rng(912).permutation(np.geomspace(0.02, 0.09, 300))
+    fr = bsc_frames(code, 300, p, seed=912)
+    dc = mbp.Code.from_inputs(ctx, code)
+    a, b = _both(ctx, dc, fr, dtype, algo=algo, max_iter=60, schedule=schedule)
+    c, _ = _both(ctx, dc, fr, dtype, algo=algo, max_iter=60, schedule=schedule, compact=False)
+    _same(a, b)
+    _same(a, c)
+    its = a["iters"]
+    assert (its == 60).sum() > 30 and (its <= 5).sum() > 40
+
+
+def test_from_bits_fixed_iterations_and_edges(ctx, codes):
+    """T = 1 and 2 without early exit; error-free frames; no frames."""
+    import torch
+    from paper_2001_07979_amd import mbp
+    code = codes[3]
+    dc = mbp.Code.from_inputs(ctx, code)
+    fr = bsc_frames(code, 70, 0.04, seed=41)
+    for T in (1, 2):
+        for algo in ("spa", "nms"):
+            a, b = _both(ctx, dc, fr, algo=algo, max_iter=T, early_exit=False)
+            _same(a, b)
+            assert np.all(a["iters"] == T)
+    clean = bsc_frames(code, 5, 0.0, seed=42)
+    clean.p[:] = 0.03
+    a, b = _both(ctx, dc, clean, algo="spa", max_iter=10)
+    _same(a, b)
+    assert np.all(a["iters"] == 1) and np.array_equal(a["bits"], clean.x)
+    y = torch.zeros((0, code.n), dtype=torch.uint8, device="cuda")
+    e = torch.zeros(0, dtype=torch.float64, device="cuda")
+    z = torch.zeros((0, code.M), dtype=torch.uint8, device="cuda")
+    o = mbp.decode_from_bits(ctx, dc, y, e, z)
+    assert o["bits"].shape == (0, code.n)
+
+
+def test_from_bits_rejects_bad_arguments(ctx, codes):
+    import ctypes
+    import torch
+    from paper_2001_07979_amd import mbp
+    code = codes[2]
+    dc = mbp.Code.from_inputs(ctx, code)
+    y = torch.zeros((2, code.n), dtype=torch.uint8, device="cuda")
+    z = torch.zeros((2, code.M), dtype=torch.uint8, device="cuda")
+    out = [torch.empty((2, code.n), dtype=torch.uint8, device="cuda"),
+           torch.empty(2, dtype=torch.int32, device="cuda"), torch.empty(2, dtype=torch.uint8, device="cuda")]
+    p = mbp.mbp_params(mbp.MBP_ALGO_SPA, mbp.MBP_F32, 10, 1, 0.75, 20.0, 1, 0)
+    rc = mbp.lib().mbp_decode_from_bits(ctx.handle, dc.handle, ctypes.byref(p), 2, y.data_ptr(), None,
+                                        z.data_ptr(), out[0].data_ptr(), out[1].data_ptr(),
+                                        out[2].data_ptr(), None, None)
+    assert rc == mbp.MBP_EINVAL and "null buffer" in mbp.last_error()
+    p.max_iter = 0
+    e = torch.full((2,), 0.05, dtype=torch.float64, device="cuda")
+    rc = mbp.lib().mbp_decode_from_bits(ctx.handle, dc.handle, ctypes.byref(p), 2, y.data_ptr(), e.data_ptr(),
+                                        z.data_ptr(), out[0].data_ptr(), out[1].data_ptr(),
+                                        out[2].data_ptr(), None, None)
+    assert rc == mbp.MBP_EINVAL
+
+
+@pytest.mark.parametrize("algo", ["spa", "nms"])
+def test_from_bits_n65536_full_batch(ctx, algo):
+    """The benchmarked workload: every output equals the LLR path; sampled
+    frames against the oracle under the parity protocol (min-sum bit for bit
+    against its binary32 decode)."""
+    from paper_2001_07979_amd import mbp
+    wl = W.qkd_n65536(algo=algo)
+    fr = wl.frames()
+    dc = mbp.Code.from_inputs(ctx, wl.code)
+    a, b = _both(ctx, dc, fr, algo=algo, max_iter=wl.max_iter, alpha=wl.alpha)
+    _same(a, b)
+    g = dict(bits=a["bits"], iters=a["iters"], ok=a["ok"], L=a["llr"].astype(np.float64))
+    idx = np.array([0, 5, 64, 130, 255])
+    o = parity.oracle_run(wl.code, fr, algo, "f32", wl.max_iter, alpha=wl.alpha, idx=idx)
+    parity.compare(g, o, wl.max_iter, 1e-4, idx=idx, atol=parity.ATOL32)
+    if algo == "nms":
+        parity.assert_bitwise(g, parity.oracle_f32_run(wl.code, fr, wl.max_iter, idx=idx), idx=idx)
+    assert a["ok"].mean() > 0.99
