@@ -104,7 +104,7 @@ int mbp_ctx_create(int32_t device, mbp_ctx **out);
 void mbp_ctx_destroy(mbp_ctx *ctx);
 
 /* Upload u parity-check matrices (Sec. 2: u PEG matrices, m_l x n each).
- *   n          key bits per frame, 1..2^30
+ *   n          key bits per frame, 1..2^23
  *   u          number of matrices, 1..64
  *   m          [u] host: checks per matrix, >= 1
  *   row_ptr    [u] host pointers to host CSR row offsets, m_l + 1 each,

@@ -107,7 +107,9 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
     if (!out) return fail(MBP_EINVAL, "mbp_code_create: out is NULL");
     *out = nullptr;
     if (!ctx) return fail(MBP_EINVAL, "mbp_code_create: ctx is NULL");
-    if (n < 1 || n > (1 << 30)) return fail(MBP_EINVAL, "mbp_code_create: n must be in [1, 2^30]");
+    // the FP32 check pass addresses a variable's 64-frame row (256 bytes)
+    // with a 32-bit signed byte offset
+    if (n < 1 || n > (1 << 23)) return fail(MBP_EINVAL, "mbp_code_create: n must be in [1, 2^23]");
     if (u < 1 || u > 64) return fail(MBP_EINVAL, "mbp_code_create: u must be in [1, 64]");
     if (!m || !row_ptr || !col_idx) return fail(MBP_EINVAL, "mbp_code_create: null array");
     int64_t M = 0, E = 0;

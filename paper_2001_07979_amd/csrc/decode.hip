@@ -137,6 +137,7 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     Dims dv{E, n, M, ntot, (n + vpt - 1) / vpt, 0, 0, p->alpha, p->llr_clip};
     dc.ybits = dv.ybits = yb;
     dc.ymag = dv.ymag = ymag;
+    dv.reverse = 1;
     Dims ds{E, n, M, ntot, (M + kBlock - 1) / kBlock, 0, 0, p->alpha, p->llr_clip, p->max_iter, ngroups,
             nspare};
     const int grid_c = grid_for(ctx, reinterpret_cast<const void *>(kc),

@@ -68,6 +68,23 @@ __device__ __forceinline__ float tanh_complement(float a) {
 // IEEE sign bit of a float as a word (1u << 31 or 0).
 __device__ __forceinline__ uint32_t sign_word(float x) { return __float_as_uint(x) & 0x80000000u; }
 
+// Raw buffer access for the FP32 check pass: a descriptor per base address,
+// a per-lane byte offset (the lane's slot in a 64-frame row) and a
+// wave-uniform byte offset (the row), so a gather of a row costs no vector
+// address arithmetic. Reads at or past num_records (measured from the
+// per-lane offset) return 0 without touching memory.
+using BufRsrc = __amdgpu_buffer_rsrc_t;
+constexpr uint32_t kBufAll = 0xFFFFFFFFu;
+__device__ __forceinline__ BufRsrc buf_rsrc(const void *base, uint32_t num_records) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, static_cast<int>(num_records), 0x00020000);
+}
+__device__ __forceinline__ uint32_t buf_load(BufRsrc r, int lane_off, int row_off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, row_off, 0);
+}
+__device__ __forceinline__ void buf_store(uint32_t x, BufRsrc r, int lane_off, int row_off) {
+    __builtin_amdgcn_raw_buffer_store_b32(x, r, lane_off, row_off, 0);
+}
+
 // 2 atanh(1 - E) = ln((2 - E) / E) for a complement E in (0, 1], with two
 // hardware log2: no quotient is rounded, and nothing cancels where E is small
 // (large messages). Where E is near 1 the result is small and carries an
@@ -112,6 +129,11 @@ struct Dims {
     // ybits[g * n + i], with mag = ymag[64 g + k] (element type T).
     const uint64_t *ybits = nullptr;
     const void *ymag = nullptr;
+    // variable pass: visit the groups last to first. The check pass visits
+    // them first to last, so the variable pass starts on the group whose
+    // messages were written last (the likeliest still in the last-level
+    // cache), and the next check pass on the group read last.
+    int32_t reverse = 0;
 };
 
 // Bob's bit words: each lane reads the 32-bit half of word i that holds its
@@ -141,19 +163,123 @@ struct StopTail {
 // frames with an unmet check in the stopping test under way.
 constexpr int kRun = 0, kUnmet = 1;
 
+// One check of the FP32 check pass, for the lanes of one wave (frames of
+// one group): v[] holds the check's variable indices (slots past the degree
+// d hold other valid indices), src the group's L rows (or, BITS, its bit
+// words), ci / cg the check's first c^{t-1} / c^t row. Every slot loads,
+// unconditionally (a slot past the degree reads row 0 and is neutralised
+// below), so the loads carry no branches and no vector address arithmetic;
+// only the stores test the degree.
+template <int ALGO, int DMAX, bool BITS>
+__device__ __forceinline__ void check_row_f32(const int (&v)[DMAX], int d, uint32_t zbit, float alpha,
+                                              float clip, bool first, BufRsrc src, const float *ci, float *cg,
+                                              unsigned lane, float ym) {
+    const int lo = static_cast<int>(lane) * 4;
+    // c^{t-1} of the check's edges, or zeros (no memory read) at t = 1
+    const BufRsrc rin = buf_rsrc(ci, first || BITS ? 0u : kBufAll);
+    const BufRsrc rout = buf_rsrc(cg, kBufAll);
+    float q[DMAX];
+    if constexpr (BITS) {
+        uint32_t yh[DMAX];
+        const int hl = static_cast<int>(lane >> 5) * 4;  // the 32-bit half holding the lane's bit
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) yh[j] = buf_load(src, hl, (j < d ? v[j] : 0) * 8);
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) q[j] = lam_of_half(yh[j], lane, ym);
+    } else {
+        float co[DMAX];
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            q[j] = __uint_as_float(buf_load(src, lo, (j < d ? v[j] : 0) * G * 4));
+            co[j] = __uint_as_float(buf_load(rin, lo, (j < d ? j : 0) * G * 4));
+        }
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) q[j] -= co[j];
+    }
+    // Signs ride in the IEEE sign bits (q + 0 turns -0 into +0: sgn(0) =
+    // +1), so the sign product is an XOR of words; slots past the degree
+    // contribute no sign.
+    uint32_t sxb = zbit << 31;
+    if constexpr (ALGO == kNMS) {
+        // slots past the degree enter the running minima as +inf, which
+        // leaves them unchanged; m2 = med3(m1, a, m2) is the second minimum
+        // after taking a, as m1 <= m2 always
+        float m1 = INFINITY, m2 = INFINITY;
+        int i1 = 0;
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            const bool real = j < d;
+            q[j] = q[j] + 0.0f;
+            sxb ^= real ? __float_as_uint(q[j]) : 0u;
+            const float aj = real ? fminf(fabsf(q[j]), clip) : INFINITY;
+            m2 = __builtin_amdgcn_fmed3f(m1, aj, m2);
+            i1 = aj < m1 ? j : i1;
+            m1 = fminf(m1, aj);
+        }
+        const float a1 = alpha * m1, a2 = alpha * m2;
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            if (j < d) {
+                const float mag = j == i1 ? a2 : a1;  // >= 0
+                buf_store(__float_as_uint(mag) | sign_word(__uint_as_float(sxb ^ __float_as_uint(q[j]))), rout,
+                          lo, j * G * 4);
+            }
+        }
+    } else {
+        // sum-product: the tanh product over the other edges, carried as
+        // complements E = 1 - prod tanh(a/2) (a prefix and a suffix, merged
+        // per edge), so magnitudes near the clip, where tanh rounds to 1,
+        // keep their precision: 1 - (1 - x)(1 - y) = x + y - xy. Slots past
+        // the degree hold the complement 0 (tanh = 1), for which both
+        // running updates are exact no-ops. Each complement carries its
+        // message's sign in its sign bit (read through fabsf, which costs
+        // nothing).
+        float ep[DMAX];
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            const bool real = j < d;
+            const float qj = q[j] + 0.0f;
+            sxb ^= real ? __float_as_uint(qj) : 0u;
+            const float e = __uint_as_float(__float_as_uint(tanh_complement(fminf(fabsf(qj), clip))) |
+                                            sign_word(qj));
+            ep[j] = real ? e : 0.0f;
+        }
+        float run = 0.0f;
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            const float e = fabsf(ep[j]);
+            q[j] = run;  // complement of the product before j
+            run = fmaf(-run, e, run + e);
+        }
+        float suf = 0.0f;
+#pragma unroll
+        for (int j = DMAX - 1; j >= 0; --j) {
+            if (j < d) {
+                const float E = fmaf(-q[j], suf, q[j] + suf);
+                const float mag = atanh2_of_complement(E);
+                const uint32_t sb = sign_word(__uint_as_float(sxb ^ __float_as_uint(ep[j])));
+                buf_store((__float_as_uint(mag) & 0x7fffffffu) | sb, rout, lo, j * G * 4);
+            }
+            const float e = fabsf(ep[j]);
+            suf = fmaf(-suf, e, suf + e);
+        }
+    }
+}
+
 // Check-node pass, iteration t. Each wave handles kRowsPerWave checks of one
 // group. The check's edge indices are read up front as scalars (the column
-// array is padded by 64 entries so a full DMAX block is always in bounds),
-// then all gathers of the check are issued before any is consumed; the
-// messages stay in registers (q[j]) between the gather and the write.
+// array is padded by kIndexPad entries so a full DMAX block is always in
+// bounds), then all gathers of the check are issued before any is consumed;
+// the messages stay in registers (q[j]) between the gather and the write.
+// FP32 checks run check_row_f32; the body below is the FP64 one.
 //
 // c_in holds c^{t-1} (unused at t = 1) and c_out receives c^t; the plain
 // decode passes the same array for both (each edge is read before it is
 // written, by the same lane). The BITS instance runs the first iteration from
 // Bob's bits instead of Lp (q = lambda, c^0 = 0): its gathers touch one
-// 8-byte bit word per edge rather than a 256-byte row. alpha_l, if not null, gives the min-sum weight
-// of each matrix for this iteration (row_mat maps a check to its matrix);
-// otherwise a.alpha applies to every check.
+// 8-byte bit word per edge rather than a 256-byte row. alpha_l, if not null,
+// gives the min-sum weight of each matrix for this iteration (row_mat maps a
+// check to its matrix); otherwise a.alpha applies to every check.
 template <typename T, int ALGO, int DMAX, bool BITS = false>
 __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ row_ptr,
                                                   const int32_t *__restrict__ col,
@@ -193,7 +319,12 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
             int v[DMAX];
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) v[j] = col[e0 + j];
-            if (on) {
+            if constexpr (sizeof(T) == 4) {
+                if (on)
+                    check_row_f32<ALGO, DMAX, BITS>(
+                        v, d, static_cast<uint32_t>(zbit), alpha, clip, first,
+                        BITS ? buf_rsrc(yg, kBufAll) : buf_rsrc(Lg, kBufAll), ci, cg, lane, ym);
+            } else if (on) {
                 // issue every gather of the check before using any of them
                 T q[DMAX], co[DMAX];
                 uint32_t yh[DMAX];
@@ -219,38 +350,8 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                 }
                 uint64_t neg = 0;
                 int sx = zbit;  // syndrome sign times every message sign
-                if constexpr (ALGO == kNMS && sizeof(T) == 4) {
-                    // FP32 min-sum. Each message's sign rides in its IEEE
-                    // sign bit (after q + 0 turns -0 into +0: sgn(0) = +1),
-                    // so the sign product is an XOR of words; slots past
-                    // the degree enter the running minima as +inf, which
-                    // leaves them unchanged. m2 = med3(m1, a, m2) is the
-                    // second minimum after taking a, as m1 <= m2 always.
-                    uint32_t sxb = static_cast<uint32_t>(zbit) << 31;
-                    float m1 = INFINITY, m2 = INFINITY;
-                    int i1 = 0;
-#pragma unroll
-                    for (int j = 0; j < DMAX; ++j) {
-                        float aj = INFINITY;
-                        if (j < d) {
-                            q[j] = q[j] + 0.0f;
-                            sxb ^= __float_as_uint(q[j]);
-                            aj = fminf(fabsf(q[j]), clip);
-                        }
-                        m2 = __builtin_amdgcn_fmed3f(m1, aj, m2);
-                        i1 = aj < m1 ? j : i1;
-                        m1 = fminf(m1, aj);
-                    }
-                    const float a1 = alpha * m1, a2 = alpha * m2;
-#pragma unroll
-                    for (int j = 0; j < DMAX; ++j) {
-                        if (j < d) {
-                            const float mag = j == i1 ? a2 : a1;  // >= 0
-                            (cg + j * G)[lane] = __uint_as_float(__float_as_uint(mag) |
-                                                                 sign_word(__uint_as_float(sxb ^ __float_as_uint(q[j]))));
-                        }
-                    }
-                } else if constexpr (ALGO == kNMS) {
+                // FP64 from here (FP32 takes check_row_f32)
+                if constexpr (ALGO == kNMS) {
                     T m1 = T(INFINITY), m2 = T(INFINITY);
                     int i1 = 0;
 #pragma unroll
@@ -277,49 +378,6 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                             const int s = sx ^ static_cast<int>((neg >> j) & 1);
                             (cg + j * G)[lane] = s ? -mag : mag;
                         }
-                    }
-                } else if constexpr (sizeof(T) == 4) {
-                    // sum-product, FP32: the tanh product over the other
-                    // edges, carried as complements E = 1 - prod tanh(a/2)
-                    // (a prefix and a suffix, merged per edge), so magnitudes
-                    // near the clip, where tanh rounds to 1, keep their
-                    // precision: 1 - (1 - x)(1 - y) = x + y - xy.
-                    // Slots past the degree hold the complement 0 (tanh = 1),
-                    // for which both running updates below are exact no-ops,
-                    // so they run over every slot without a per-slot test.
-                    // Each complement carries its message's sign in its sign
-                    // bit (read through fabsf, which costs nothing), and the
-                    // sign product is an XOR of words, as in min-sum.
-                    uint32_t sxb = static_cast<uint32_t>(zbit) << 31;
-                    float ep[DMAX];
-#pragma unroll
-                    for (int j = 0; j < DMAX; ++j) {
-                        ep[j] = 0.0f;
-                        if (j < d) {
-                            const float qj = q[j] + 0.0f;  // -0 -> +0: sgn(0) = +1
-                            sxb ^= __float_as_uint(qj);
-                            ep[j] = __uint_as_float(__float_as_uint(tanh_complement(fminf(fabsf(qj), clip))) |
-                                                    sign_word(qj));
-                        }
-                    }
-                    float run = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < DMAX; ++j) {
-                        const float e = fabsf(ep[j]);
-                        q[j] = run;  // complement of the product before j
-                        run = fmaf(-run, e, run + e);
-                    }
-                    float suf = 0.0f;
-#pragma unroll
-                    for (int j = DMAX - 1; j >= 0; --j) {
-                        if (j < d) {
-                            const float E = fmaf(-q[j], suf, q[j] + suf);
-                            const float mag = atanh2_of_complement(E);
-                            const uint32_t sb = sign_word(__uint_as_float(sxb ^ __float_as_uint(ep[j])));
-                            (cg + j * G)[lane] = __uint_as_float((__float_as_uint(mag) & 0x7fffffffu) | sb);
-                        }
-                        const float e = fabsf(ep[j]);
-                        suf = fmaf(-suf, e, suf + e);
                     }
                 } else {
                     // sum-product, FP64: tanh domain with prefix/suffix products
@@ -653,7 +711,8 @@ __global__ __launch_bounds__(kBlock) void k_variable(
     const int wave = wave_id();
     const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-        const int g = static_cast<int>(w / a.ntiles);
+        const int gw = static_cast<int>(w / a.ntiles);
+        const int g = a.reverse ? a.ngroups - 1 - gw : gw;
         const int tile = static_cast<int>(w % a.ntiles);
         const uint64_t run = act[kStride * g + kRun];
         if (run == 0) continue;
