@@ -56,6 +56,9 @@ def lib():
         L.oracle_mbp_decode_nms_f32.restype = ctypes.c_int32
         L.oracle_mbp_decode_nms_f32.argtypes = [ctypes.POINTER(_Code), ctypes.POINTER(_Params),
                                                 ctypes.c_int32] + [ctypes.c_void_p] * 6 + [ctypes.c_int32]
+        L.oracle_syndrome.restype = ctypes.c_int32
+        L.oracle_syndrome.argtypes = [ctypes.POINTER(_Code), ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_void_p]
         L.oracle_unsatisfied.restype = ctypes.c_int32
         L.oracle_unsatisfied.argtypes = [ctypes.POINTER(_Code), ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
@@ -158,6 +161,18 @@ def decode_nms_f32(code, llr: np.ndarray, synd: np.ndarray, max_iter: int = 50,
     if rc != 0:
         raise ValueError("oracle_mbp_decode_nms_f32 rejected its input")
     return dict(bits=bits, iters=iters, ok=ok, L=L)
+
+
+def syndrome(code, x: np.ndarray) -> np.ndarray:
+    """Eq. (1): the stacked syndromes [H_1 x; ...; H_u x] mod 2 of each frame."""
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.uint8)
+    cs, keep = _pack(code)
+    z = np.zeros((x.shape[0], int(sum(code.m))), dtype=np.uint8)
+    rc = lib().oracle_syndrome(ctypes.byref(cs), x.shape[0], x.ctypes.data, z.ctypes.data)
+    del keep
+    if rc != 0:
+        raise ValueError("oracle_syndrome rejected its input")
+    return z
 
 
 def unsatisfied(code, x: np.ndarray, synd: np.ndarray) -> np.ndarray:

@@ -496,6 +496,26 @@ int32_t oracle_mbp_decode_nms_f32(const oracle_code *code, const oracle_params *
     return run_decode(code, P, nframes, llr, synd, bits, iters, ok, Lout, NULL, nthreads, 1);
 }
 
+/* Alice's syndromes, eq. (1): z^l = H_l x over GF(2) for every matrix, the
+   u syndromes of a frame back to back in matrix order ([nframes][M] bytes,
+   0 / 1). Each check's parity is the XOR of x at its variables (x bytes:
+   0 = bit 0, nonzero = bit 1). */
+int32_t oracle_syndrome(const oracle_code *code, int32_t nframes, const uint8_t *x, uint8_t *z) {
+    graph g;
+    if (graph_build(code, &g)) return -1;
+    for (int32_t f = 0; f < nframes; ++f) {
+        const uint8_t *xf = x + (size_t)f * (size_t)g.n;
+        uint8_t *zf = z + (size_t)f * (size_t)g.M;
+        for (int32_t r = 0; r < g.M; ++r) {
+            int par = 0;
+            for (int32_t e = g.row_start[r]; e < g.row_start[r + 1]; ++e) par ^= xf[g.edge_var[e]] ? 1 : 0;
+            zf[r] = (uint8_t)par;
+        }
+    }
+    graph_free(&g);
+    return 0;
+}
+
 /* Residual syndrome weight of decided bits: per frame, the number of stacked
    checks whose parity over x differs from z. */
 int32_t oracle_unsatisfied(const oracle_code *code, int32_t nframes, const uint8_t *x,

@@ -557,3 +557,36 @@ def test_serial_needs_fewer_iterations():
     assert s["iters"][both].mean() < f["iters"][both].mean()
     okf = s["ok"] == 1
     assert np.array_equal(syndromes(code, s["bits"][okf]), fr.z[okf])
+
+
+# ------------------------------------------------------------- eq. (1) syndromes
+def test_syndrome_is_the_dense_product_over_gf2():
+    """z^l = H_l x mod 2 for every matrix, stacked in matrix order, against a
+    dense integer product (every check of degree >= 2, as decoding needs);
+    nonzero bytes count as 1."""
+    rng = np.random.default_rng(21)
+    Hs = []
+    for m, p in ((9, 0.25), (6, 0.4), (3, 0.5)):
+        H = (rng.random((m, 31)) < p).astype(np.uint8)
+        H[:, :2] = 1  # degree >= 2
+        Hs.append(H)
+    code = code_from_dense(Hs)
+    x = rng.integers(0, 2, (11, 31), dtype=np.uint8)
+    want = np.concatenate([(x.astype(np.int64) @ H.T.astype(np.int64)) % 2 for H in Hs], axis=1)
+    z = oracle.syndrome(code, x)
+    assert np.array_equal(z, want.astype(np.uint8))
+    assert 0 < z.mean() < 1
+    assert np.array_equal(oracle.syndrome(code, x * 7), z)  # nonzero = 1
+
+
+def test_syndrome_is_linear_and_agrees_with_the_residual_weight(small_peg):
+    """H(x ^ y) = Hx ^ Hy; the all-zero word has the zero syndrome; and the
+    number of checks where Hx differs from a syndrome is the oracle's residual
+    weight of x against it."""
+    rng = np.random.default_rng(22)
+    x = rng.integers(0, 2, (5, small_peg.n), dtype=np.uint8)
+    y = rng.integers(0, 2, (5, small_peg.n), dtype=np.uint8)
+    zx, zy = oracle.syndrome(small_peg, x), oracle.syndrome(small_peg, y)
+    assert np.array_equal(oracle.syndrome(small_peg, x ^ y), zx ^ zy)
+    assert not oracle.syndrome(small_peg, np.zeros_like(x)).any()
+    assert np.array_equal(oracle.unsatisfied(small_peg, x, zy), (zx != zy).sum(axis=1))
