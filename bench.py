@@ -320,6 +320,26 @@ def serial_schedule(ctx, wl, fr, dcode, y, e, z, steps: int):
             "max_iters": int(out["iters"].max().item())}
 
 
+def alice_syndromes(ctx, wl, fr, dcode, steps: int):
+    """Alice's side, eq. (1): the u syndromes of every frame of the main
+    workload from her key bits (resident in HBM), per step."""
+    import torch
+    from paper_2001_07979_amd import mbp
+
+    x = torch.from_numpy(fr.x).to("cuda")
+    z = torch.empty((fr.nframes, wl.code.M), dtype=torch.uint8, device="cuda")
+    mbp.syndrome(ctx, dcode, x, out=z)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        mbp.syndrome(ctx, dcode, x, out=z)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    assert np.array_equal(z.cpu().numpy(), fr.z)
+    return {"workload": wl.name, "frames": fr.nframes, "mbps": round(fr.nframes * wl.code.n / dt / 1e6, 1),
+            "ms_per_step": round(dt * 1e3, 4)}
+
+
 def unrolled_step(ctx, steps: int):
     """One training step of the differentiable decoder: K=20 unrolled min-sum
     iterations (weights per iteration and matrix) on 512 frames of the u=2
@@ -534,6 +554,9 @@ def main():
         log("bench: main workload, matrix-serial schedule")
         serial = serial_schedule(ctx, wl, fr, dcode, y, e, z, 5)
 
+    log("bench: Alice's syndromes")
+    alice = alice_syndromes(ctx, wl, fr, dcode, 10)
+
     unrolled = None
     if not args.no_unrolled:
         log("bench: unrolled K=20 training step")
@@ -557,7 +580,7 @@ def main():
         "f": round(m / (n * h), 4), "f_leak": round(code.u * m / (n * h), 4),
         "llr_rows_then_decode": {"ms_per_step": round(two_calls_ms, 4),
                                  "mbps": round(F * n / (two_calls_ms * 1e-3) / 1e6, 1)},
-        "roofline": roofline, "cpu_baseline": cpu, "qualifying_point": qual, "matrix_serial": serial,
+        "roofline": roofline, "cpu_baseline": cpu, "qualifying_point": qual, "matrix_serial": serial, "alice_syndromes": alice,
         "unrolled_training_step": unrolled,
         "batched_vs_plain": batched,
     }

@@ -141,6 +141,20 @@ int mbp_code_info(const mbp_code *code, int32_t *n, int32_t *u, int32_t *M, int6
 int mbp_llr_from_bits(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y,
                       const double *e, int32_t dtype, void *llr_out, void *stream);
 
+/* Alice's syndromes (Sec. 2, eq. (1)): z^l = H_l x over GF(2) for every
+ * matrix of the code, for nframes key frames.
+ *   x         device [nframes][n] key bits, bytes (0 = bit 0, nonzero = 1)
+ *   synd_out  device [nframes][M] syndrome bytes 0/1, the u syndromes of
+ *             each frame back to back in matrix order (the layout
+ *             mbp_decode reads)
+ * The call uses the context's workspace (8 bytes per variable per 64
+ * frames) and returns once the syndromes are written. nframes may be 0 and
+ * at most 65535 * 64.
+ * Errors: EINVAL (null pointers, sizes, a code of another context), ENOMEM,
+ * EDEVICE. */
+int mbp_syndrome(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, const uint8_t *x, uint8_t *synd_out,
+                 void *stream);
+
 /* Decode nframes frames of one code (Sec. 2; Algorithm 1).
  *   llr       device [nframes][n] channel LLRs of p->dtype, finite
  *   synd      device [nframes][M] syndrome bytes (0 / nonzero), the u

@@ -26,7 +26,8 @@ HIP_FLAGS = [
     "-I", os.path.join(ROOT, "include"),
 ]
 
-HIP_SOURCES = ["csrc/capi.cpp", "csrc/decode.hip", "csrc/unrolled.hip", "csrc/batched.hip"]
+HIP_SOURCES = ["csrc/capi.cpp", "csrc/decode.hip", "csrc/unrolled.hip", "csrc/batched.hip",
+               "csrc/syndrome.hip"]
 
 
 def _run(cmd, cwd=None):

@@ -257,6 +257,17 @@ int mbp_llr_from_bits(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y
     return mbp::llr_impl(ctx, nframes, n, y, e, dtype, llr_out, (hipStream_t)stream);
 }
 
+int mbp_syndrome(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, const uint8_t *x, uint8_t *synd_out,
+                 void *stream) {
+    if (!ctx || !code) return fail(MBP_EINVAL, "mbp_syndrome: null ctx or code");
+    if (code->ctx != ctx) return fail(MBP_EINVAL, "mbp_syndrome: code belongs to another context");
+    if (nframes < 0) return fail(MBP_EINVAL, "mbp_syndrome: nframes < 0");
+    if (nframes > 65535 * mbp::kLanes) return fail(MBP_EINVAL, "mbp_syndrome: at most 65535 * 64 frames per call");
+    if (nframes == 0) return MBP_OK;
+    if (!x || !synd_out) return fail(MBP_EINVAL, "mbp_syndrome: null buffer");
+    return mbp::syndrome_impl(ctx, code, nframes, x, synd_out, (hipStream_t)stream);
+}
+
 int mbp_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,
                const void *llr, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
                uint8_t *ok_out, void *llr_out, void *stream) {

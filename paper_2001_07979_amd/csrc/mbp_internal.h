@@ -85,6 +85,9 @@ namespace mbp {
 int decode_impl(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,
                 const void *llr, const uint8_t *y, const double *e, const uint8_t *synd, uint8_t *bits_out,
                 int32_t *iters_out, uint8_t *ok_out, void *llr_out, hipStream_t stream);
+// Implemented in syndrome.hip; arguments are validated by capi.cpp.
+int syndrome_impl(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, const uint8_t *x, uint8_t *z,
+                  hipStream_t stream);
 int llr_impl(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y, const double *e,
              int32_t dtype, void *llr_out, hipStream_t stream);
 

@@ -134,3 +134,44 @@ def queue_frames(queue, seed: int = 4):
         p = np.array([queue[i].p for i in idx])
         out[cell] = (code, idx, bsc_frames(code, len(idx), p, 1000 * seed + k))
     return out
+
+
+# ------------------------------------------------------------------- sweeps
+# The axes of the paper's experiments (Sec. 4, Figs. 2-3, Table 3): the number
+# of matrices u, the error rate e and the code rate R, on n = 65536 frames of
+# {2,3,10} PEG matrices. The codes for u = 1, 2, 3 at one rate share their
+# matrices (u takes the first u of three).
+SWEEP_N = 65536
+SWEEP_RATES = (0.5, 0.6, 0.7, 0.8)
+
+
+def sweep_code(rate: float, u: int):
+    n = SWEEP_N
+    m = int(round((1.0 - rate) * n))
+    return peg_code(n, m, u, IRREGULAR_2310, seed_base=6000 + 10 * int(round(rate * 10)),
+                    max_depth=peg_depth(n), name=f"peg-n{n}-r{rate}-u{u}-d2310")
+
+
+def binary_entropy(e: float) -> float:
+    return float(-e * np.log2(e) - (1 - e) * np.log2(1 - e))
+
+
+def e_for_efficiency(rate: float, f: float) -> float:
+    """The BSC error rate e <= 1/2 at which f = m / (n h(e)) (eq. (3), m of
+    one matrix) equals f for a code of rate R = 1 - m/n: h(e) = (1 - R)/f,
+    solved by bisection."""
+    target = (1.0 - rate) / f
+    lo, hi = 1e-12, 0.5
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if binary_entropy(mid) < target:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def sweep_workload(rate: float, u: int, e: float, nframes: int = 256, algo: str = "spa") -> Workload:
+    code = sweep_code(rate, u)
+    return Workload(f"mbp-{algo}-f32-n{SWEEP_N}-r{rate}-u{u}-p{e:.4f}", code, nframes, float(e),
+                    7000 + int(round(e * 1e4)), algo, "f32", 100, meta=dict(rate=rate, u=u))

@@ -61,6 +61,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        # torch first: the library then binds to the HIP runtime torch loaded,
+        # so the process holds one runtime (loaded the other way round, torch
+        # finds no GPU)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         sig = {
@@ -74,6 +78,7 @@ def lib():
             "mbp_llr_from_bits": (ctypes.c_int, [vp, i32, i32, vp, vp, i32, vp, vp]),
             "mbp_decode": (ctypes.c_int, [vp, vp, ctypes.POINTER(mbp_params), i32] + [vp] * 7),
             "mbp_decode_from_bits": (ctypes.c_int, [vp, vp, ctypes.POINTER(mbp_params), i32] + [vp] * 8),
+            "mbp_syndrome": (ctypes.c_int, [vp, vp, i32, vp, vp, vp]),
             "mbp_unrolled_workspace_bytes": (ctypes.c_int, [vp, i32, i32, i32,
                                                              ctypes.POINTER(ctypes.c_uint64)]),
             "mbp_nms_unrolled_fwd": (ctypes.c_int, [vp, vp, i32, i32, i32, ctypes.c_double] + [vp] * 5
@@ -256,6 +261,20 @@ def _decode_outputs(F, n, dtype, dev, want_llr):
                 iters=torch.empty(F, dtype=torch.int32, device=dev),
                 ok=torch.empty(F, dtype=torch.uint8, device=dev),
                 llr=torch.empty((F, n), dtype=dtype, device=dev) if want_llr else None)
+
+
+def syndrome(ctx: Context, code: Code, x, out=None, stream=None):
+    """Alice's syndromes, eq. (1): x [F, n] uint8 key bits (GPU) -> [F, M] uint8
+    (the u syndromes of each frame back to back), computed on the GPU."""
+    import torch
+    F = int(x.shape[0])
+    if x.dim() != 2 or x.shape[1] != code.n or x.dtype != torch.uint8 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous uint8 [F, n] tensor")
+    if out is None:
+        out = torch.empty((F, code.M), dtype=torch.uint8, device=x.device)
+    _check(lib().mbp_syndrome(ctx.handle, code.handle, F, _dev_ptr(x), _dev_ptr(out), _stream_ptr(stream)),
+           "mbp_syndrome")
+    return out
 
 
 def decode(ctx: Context, code: Code, llr, synd, algo: str = "spa", max_iter: int = 50,

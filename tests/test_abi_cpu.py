@@ -48,6 +48,7 @@ def test_version_and_error_paths_without_device():
     assert L.mbp_llr_from_bits(None, 1, 1, None, None, 0, None, None) == mbp.MBP_EINVAL
     assert L.mbp_decode_from_bits(None, None, ctypes.byref(p), 1, *([None] * 8)) == mbp.MBP_EINVAL
     assert "mbp_decode_from_bits" in mbp.last_error()
+    assert L.mbp_syndrome(None, None, 1, None, None, None) == mbp.MBP_EINVAL
     n, ms = ctypes.c_int64(), ctypes.c_double()
     assert L.mbp_profile_get(None, 0, ctypes.byref(n), ctypes.byref(ms)) == mbp.MBP_EINVAL
     L.mbp_ctx_destroy(None)

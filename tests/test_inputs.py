@@ -45,3 +45,16 @@ def test_mixed_queue_shape():
     assert abs(t[-1] - 2.048) < 0.3  # 2048 Poisson arrivals at 1000 per second
     # the arrival trace changes nothing else
     assert [f.cell for f in W.mixed_queue(2048, seed=4, rate_fps=1000.0)] == [f.cell for f in q]
+
+
+def test_error_rate_for_an_efficiency():
+    """e_for_efficiency inverts eq. (3) as the oracle computes it:
+    f = m / (n h(e)) at the returned e, for the rates and bins of the sweeps."""
+    import oracle
+    n = 65536
+    for rate in W.SWEEP_RATES:
+        m = int(round((1 - rate) * n))
+        for f in (1.1, 1.125, 1.3):
+            e = W.e_for_efficiency(rate, f)
+            assert 0 < e < 0.5
+            assert abs(oracle.efficiency(m, n, e) - f) < 1e-4
