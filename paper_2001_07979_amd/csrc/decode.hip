@@ -1,6 +1,7 @@
 // Host-side iteration driver of the plain multi-matrix syndrome BP decode
 // (mbp_decode) and the channel-LLR entry (mbp_llr_from_bits). The kernels are
 // in mbp_kernels.h.
+#include <type_traits>
 #include <vector>
 
 #include "mbp_kernels.h"
@@ -30,6 +31,20 @@ CheckFn<T> check_kernel(int dmax) {
 template <typename T, bool BITS = false>
 CheckFn<T> check_kernel_for(int algo, int dmax) {
     return algo == MBP_ALGO_NMS ? check_kernel<T, kNMS, BITS>(dmax) : check_kernel<T, kSPA, BITS>(dmax);
+}
+
+// FP32 min-sum instances with the compressed check state (null: the slot
+// count has none).
+template <bool BITS>
+CheckFn<float> check_kernel_state(int dmax) {
+    switch (dmax) {
+        case 8: return &k_check<float, kNMS, 8, BITS, true>;
+        case 10: return &k_check<float, kNMS, 10, BITS, true>;
+        case 16: return &k_check<float, kNMS, 16, BITS, true>;
+        case 18: return &k_check<float, kNMS, 18, BITS, true>;
+        case 24: return &k_check<float, kNMS, 24, BITS, true>;
+        default: return nullptr;
+    }
 }
 
 // The channel of a decode: LLR rows [F][n] of the decode's element type, or
@@ -69,11 +84,17 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     const size_t sz_z = align_up(static_cast<size_t>(ntot) * M * sizeof(uint64_t));
     const size_t sz_d = align_up(static_cast<size_t>(ntot) * n * sizeof(uint64_t));
     const size_t sz_f = align_up(static_cast<size_t>(ntot) * G * sizeof(int32_t));
+    const int dmax = dmax_for(code->max_check_deg);
+    // FP32 min-sum keeps a compressed check state in place of re-reading
+    // every old message (where the slot count allows one)
+    const bool with_state = std::is_same<T, float>::value && p->algo == MBP_ALGO_NMS && dmax <= kStateMaxDeg;
+    const size_t sz_cs = with_state ? align_up(static_cast<size_t>(ntot) * M * kStateRows * G * sizeof(uint32_t))
+                                    : 0;
     // lambda: rows like L, or Bob's bit words and one magnitude per slot
     const size_t sz_lam = from_bits ? sz_d + align_up(static_cast<size_t>(ntot) * G * s) : sz_L;
     // status words, one 256-byte line per group, then the stopping-test counters
     const size_t sz_m = align_up(static_cast<size_t>(ntot) * kStride * sizeof(uint64_t)) + 256;
-    int rc = ensure_workspace(ctx, sz_c + sz_L + sz_lam + sz_z + sz_d + 2 * sz_f + sz_m);
+    int rc = ensure_workspace(ctx, sz_c + sz_L + sz_lam + sz_z + sz_d + 2 * sz_f + sz_m + sz_cs);
     if (rc != MBP_OK) return rc;
     if ((rc = ensure_status(ctx, ntot)) != MBP_OK) return rc;
     char *base = static_cast<char *>(ctx->ws);
@@ -100,6 +121,7 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     int32_t *src = reinterpret_cast<int32_t *>(carve(sz_f));
     uint64_t *words = reinterpret_cast<uint64_t *>(carve(sz_m - 256));
     StopTail *tail = reinterpret_cast<StopTail *>(carve(256));
+    T *cs = with_state ? reinterpret_cast<T *>(carve(sz_cs)) : nullptr;
 
     Timer tm{ctx, stream, {}, 0};
     hipError_t err;
@@ -126,10 +148,15 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     LAUNCH_OR_FAIL(kStaging, k_stage_synd<<<dim3((M + kBlock - 1) / kBlock, ngroups), kBlock, 0, stream>>>(
                                  synd, zb, F, M));
 
-    const int dmax = dmax_for(code->max_check_deg);
-    const CheckFn<T> kc = check_kernel_for<T>(p->algo, dmax);
+    CheckFn<T> kc = check_kernel_for<T>(p->algo, dmax);
     // the first iteration's first check pass starts from lambda
-    const CheckFn<T> kc1 = from_bits ? check_kernel_for<T, true>(p->algo, dmax) : kc;
+    CheckFn<T> kc1 = from_bits ? check_kernel_for<T, true>(p->algo, dmax) : kc;
+    if constexpr (std::is_same<T, float>::value) {
+        if (with_state) {
+            kc = check_kernel_state<false>(dmax);
+            kc1 = from_bits ? check_kernel_state<true>(dmax) : kc;
+        }
+    }
     Dims dc{E, n, M, ntot, (M + kRowsPerTile - 1) / kRowsPerTile, 0, 0, p->alpha, p->llr_clip};
     int vpt = 0;
     const VarFn<T> kv = from_bits ? variable_kernel<T, true>(code->max_var_deg, &vpt)
@@ -137,6 +164,7 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     Dims dv{E, n, M, ntot, (n + vpt - 1) / vpt, 0, 0, p->alpha, p->llr_clip};
     dc.ybits = dv.ybits = yb;
     dc.ymag = dv.ymag = ymag;
+    dc.cstate = cs;
     dv.reverse = 1;
     Dims ds{E, n, M, ntot, (M + kBlock - 1) / kBlock, 0, 0, p->alpha, p->llr_clip, p->max_iter, ngroups,
             nspare};
@@ -211,7 +239,7 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
                                       iters_out, ok_out, fid, src, tail, ds));
         // fills the spare groups the stopping test's compaction planned
         if (nspare && t <= p->max_iter - 2)
-            LAUNCH_OR_FAIL(kSyndrome, k_move<T><<<grid_m, kBlock, 0, stream>>>(c, Lp, lam, zb, yb, ymag, src, tail, E, n,
+            LAUNCH_OR_FAIL(kSyndrome, k_move<T><<<grid_m, kBlock, 0, stream>>>(c, Lp, lam, zb, yb, ymag, cs, src, tail, E, n,
                                                                                 M));
         if (p->early_exit) {
             if ((err = hipEventRecord(ctx->poll_events[t & 1], stream)) != hipSuccess)

@@ -73,6 +73,13 @@ __device__ __forceinline__ uint32_t sign_word(float x) { return __float_as_uint(
 // wave-uniform byte offset (the row), so a gather of a row costs no vector
 // address arithmetic. Reads at or past num_records (measured from the
 // per-lane offset) return 0 without touching memory.
+// Compressed min-sum check state: rows per check, the largest degree it
+// holds (one sign bit per edge below the position field) and where the
+// position of the minimum sits in the third row.
+constexpr int kStateRows = 3;
+constexpr int kStateMaxDeg = 24;
+constexpr int kStateArgShift = 26;
+
 using BufRsrc = __amdgpu_buffer_rsrc_t;
 constexpr uint32_t kBufAll = 0xFFFFFFFFu;
 __device__ __forceinline__ BufRsrc buf_rsrc(const void *base, uint32_t num_records) {
@@ -129,6 +136,11 @@ struct Dims {
     // ybits[g * n + i], with mag = ymag[64 g + k] (element type T).
     const uint64_t *ybits = nullptr;
     const void *ymag = nullptr;
+    // FP32 min-sum check pass with a compressed check state (CST instances):
+    // per group and check, three 64-frame rows of words (kStateRows), read
+    // at t >= 2 in place of the check's old messages and written every
+    // iteration. Element type uint32_t.
+    void *cstate = nullptr;
     // variable pass: visit the groups last to first. The check pass visits
     // them first to last, so the variable pass starts on the group whose
     // messages were written last (the likeliest still in the last-level
@@ -170,16 +182,39 @@ constexpr int kRun = 0, kUnmet = 1;
 // unconditionally (a slot past the degree reads row 0 and is neutralised
 // below), so the loads carry no branches and no vector address arithmetic;
 // only the stores test the degree.
-template <int ALGO, int DMAX, bool BITS>
+//
+// With CST (min-sum only, DMAX <= kStateMaxDeg) the check's state `st`
+// replaces its old messages: row 0 holds alpha m1, row 1 alpha m2, row 2 the
+// sign of each outgoing message (bit j) and the position of the minimum
+// (bits 26-31). Every old message is rebuilt from them bit for bit, so the
+// pass reads 3 rows per check instead of one per edge; it still writes
+// every message (the variable pass reads them) and the new state.
+template <int ALGO, int DMAX, bool BITS, bool CST = false>
 __device__ __forceinline__ void check_row_f32(const int (&v)[DMAX], int d, uint32_t zbit, float alpha,
                                               float clip, bool first, BufRsrc src, const float *ci, float *cg,
-                                              unsigned lane, float ym) {
+                                              unsigned lane, float ym, uint32_t *st = nullptr) {
+    static_assert(!CST || (ALGO == kNMS && DMAX <= kStateMaxDeg), "compressed state: min-sum, small degree");
     const int lo = static_cast<int>(lane) * 4;
     // c^{t-1} of the check's edges, or zeros (no memory read) at t = 1
-    const BufRsrc rin = buf_rsrc(ci, first || BITS ? 0u : kBufAll);
+    const BufRsrc rin = buf_rsrc(ci, first || BITS || CST ? 0u : kBufAll);
     const BufRsrc rout = buf_rsrc(cg, kBufAll);
+    const BufRsrc rst = buf_rsrc(st, CST ? kBufAll : 0u);
     float q[DMAX];
-    if constexpr (BITS) {
+    if constexpr (CST && !BITS) {
+        // the old messages from the state (zeros at t = 1: nothing to read)
+        const BufRsrc rold = buf_rsrc(st, first ? 0u : kBufAll);
+        const float o1 = __uint_as_float(buf_load(rold, lo, 0));
+        const float o2 = __uint_as_float(buf_load(rold, lo, G * 4));
+        const uint32_t os = buf_load(rold, lo, 2 * G * 4);
+        const int oi = static_cast<int>(os >> kStateArgShift);
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) q[j] = __uint_as_float(buf_load(src, lo, (j < d ? v[j] : 0) * G * 4));
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            const float mag = j == oi ? o2 : o1;
+            q[j] -= __uint_as_float(__float_as_uint(mag) | (((os >> j) & 1u) << 31));
+        }
+    } else if constexpr (BITS) {
         uint32_t yh[DMAX];
         const int hl = static_cast<int>(lane >> 5) * 4;  // the 32-bit half holding the lane's bit
 #pragma unroll
@@ -217,13 +252,20 @@ __device__ __forceinline__ void check_row_f32(const int (&v)[DMAX], int d, uint3
             m1 = fminf(m1, aj);
         }
         const float a1 = alpha * m1, a2 = alpha * m2;
+        uint32_t signs = 0;
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) {
+            const uint32_t sw = sign_word(__uint_as_float(sxb ^ __float_as_uint(q[j])));
+            if constexpr (CST) signs |= (sw >> 31) << j;
             if (j < d) {
                 const float mag = j == i1 ? a2 : a1;  // >= 0
-                buf_store(__float_as_uint(mag) | sign_word(__uint_as_float(sxb ^ __float_as_uint(q[j]))), rout,
-                          lo, j * G * 4);
+                buf_store(__float_as_uint(mag) | sw, rout, lo, j * G * 4);
             }
+        }
+        if constexpr (CST) {
+            buf_store(__float_as_uint(a1), rst, lo, 0);
+            buf_store(__float_as_uint(a2), rst, lo, G * 4);
+            buf_store(signs | (static_cast<uint32_t>(i1) << kStateArgShift), rst, lo, 2 * G * 4);
         }
     } else {
         // sum-product: the tanh product over the other edges, carried as
@@ -280,7 +322,7 @@ __device__ __forceinline__ void check_row_f32(const int (&v)[DMAX], int d, uint3
 // 8-byte bit word per edge rather than a 256-byte row. alpha_l, if not null,
 // gives the min-sum weight of each matrix for this iteration (row_mat maps a
 // check to its matrix); otherwise a.alpha applies to every check.
-template <typename T, int ALGO, int DMAX, bool BITS = false>
+template <typename T, int ALGO, int DMAX, bool BITS = false, bool CST = false>
 __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ row_ptr,
                                                   const int32_t *__restrict__ col,
                                                   const int32_t *__restrict__ row_mat,
@@ -320,10 +362,13 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) v[j] = col[e0 + j];
             if constexpr (sizeof(T) == 4) {
+                uint32_t *st = CST ? static_cast<uint32_t *>(a.cstate) +
+                                         (static_cast<size_t>(g) * a.M + r) * kStateRows * G
+                                   : nullptr;
                 if (on)
-                    check_row_f32<ALGO, DMAX, BITS>(
+                    check_row_f32<ALGO, DMAX, BITS, CST>(
                         v, d, static_cast<uint32_t>(zbit), alpha, clip, first,
-                        BITS ? buf_rsrc(yg, kBufAll) : buf_rsrc(Lg, kBufAll), ci, cg, lane, ym);
+                        BITS ? buf_rsrc(yg, kBufAll) : buf_rsrc(Lg, kBufAll), ci, cg, lane, ym, st);
             } else if (on) {
                 // issue every gather of the check before using any of them
                 T q[DMAX], co[DMAX];
@@ -596,18 +641,22 @@ constexpr int kMovePerWave = kMoveRows / kWaves;
 // kernel does nothing): rows of c (E), L and lambda (n each) and syndrome
 // words (M), each lane from its source slot src[]. With the channel given as
 // bits (lam null), Bob's bit words (n, after the syndrome words) and the
-// per-slot magnitudes move instead of the lambda rows. Work items are runs of
+// per-slot magnitudes move instead of the lambda rows; a compressed check
+// state (cs, kStateRows rows per check) moves with the messages. Work items are runs of
 // kMoveRows rows of one region of one group.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_move(T *c, T *Lp, T *lam, uint64_t *zb, uint64_t *yb, T *ymag,
-                                                 const int32_t *src, const StopTail *tail, int64_t E, int32_t n,
-                                                 int32_t M) {
+                                                 T *cs, const int32_t *src, const StopTail *tail, int64_t E,
+                                                 int32_t n, int32_t M) {
     const int count = tail->move_count, first = tail->move_first;
     if (count == 0) return;
     const unsigned lane = lane_id();
     const int wave = wave_id();
     const int64_t nw = M + (yb ? n : 0);  // word rows: syndromes, then Bob's bits
-    const int64_t ic = (E + kMoveRows - 1) / kMoveRows, il = (n + kMoveRows - 1) / kMoveRows,
+    // rows of one value per lane: messages (E), then the compressed check
+    // state if there is one (kStateRows per check; 4-byte words moved as T)
+    const int64_t nc = E + (cs ? static_cast<int64_t>(kStateRows) * M : 0);
+    const int64_t ic = (nc + kMoveRows - 1) / kMoveRows, il = (n + kMoveRows - 1) / kMoveRows,
                   iz = (nw + kMoveRows - 1) / kMoveRows, per_group = ic + il + iz;
     for (int64_t w = blockIdx.x; w < count * per_group; w += gridDim.x) {
         const int64_t g = first + w / per_group;
@@ -617,13 +666,23 @@ __global__ __launch_bounds__(kBlock) void k_move(T *c, T *Lp, T *lam, uint64_t *
         const int64_t sg = has ? s / G : g, sl = has ? s % G : 0;
         if (item < ic) {
             const int64_t r0 = item * kMoveRows + wave * kMovePerWave;
+            const int64_t ns = nc - E;  // state rows per group
             T v[kMovePerWave];
 #pragma unroll
-            for (int j = 0; j < kMovePerWave; ++j)
-                if (has && r0 + j < E) v[j] = c[(sg * E + r0 + j) * G + sl];
+            for (int j = 0; j < kMovePerWave; ++j) {
+                const int64_t r = r0 + j;
+                if (has && r < nc) v[j] = r < E ? c[(sg * E + r) * G + sl] : cs[(sg * ns + r - E) * G + sl];
+            }
 #pragma unroll
-            for (int j = 0; j < kMovePerWave; ++j)
-                if (has && r0 + j < E) c[(g * E + r0 + j) * G + lane] = v[j];
+            for (int j = 0; j < kMovePerWave; ++j) {
+                const int64_t r = r0 + j;
+                if (has && r < nc) {
+                    if (r < E)
+                        c[(g * E + r) * G + lane] = v[j];
+                    else
+                        cs[(g * ns + r - E) * G + lane] = v[j];
+                }
+            }
         } else if ((item -= ic) < il) {
             const int64_t r0 = item * kMoveRows + wave * kMovePerWave;
             if (ymag && item == 0 && wave == 0 && has) ymag[g * G + lane] = ymag[sg * G + sl];
