@@ -276,14 +276,17 @@ __device__ __forceinline__ void check_row_f32(const int (&v)[DMAX], int d, uint3
         // running updates are exact no-ops. Each complement carries its
         // message's sign in its sign bit (read through fabsf, which costs
         // nothing).
+        // From Bob's bits every message of a frame has the magnitude ym, so
+        // its complement is formed once (the same value each slot would get).
+        const float e_bits = BITS ? tanh_complement(fminf(fabsf(ym), clip)) : 0.0f;
         float ep[DMAX];
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) {
             const bool real = j < d;
             const float qj = q[j] + 0.0f;
             sxb ^= real ? __float_as_uint(qj) : 0u;
-            const float e = __uint_as_float(__float_as_uint(tanh_complement(fminf(fabsf(qj), clip))) |
-                                            sign_word(qj));
+            const float mag = BITS ? e_bits : tanh_complement(fminf(fabsf(qj), clip));
+            const float e = __uint_as_float(__float_as_uint(mag) | sign_word(qj));
             ep[j] = real ? e : 0.0f;
         }
         float run = 0.0f;
