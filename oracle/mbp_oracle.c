@@ -94,6 +94,7 @@ typedef struct {
     int32_t *edge_var;    /* [E] variable of each edge */
     int32_t *var_start;   /* [n+1] */
     int32_t *var_edges;   /* [E] edges of each variable, ascending */
+    int32_t *edge_matrix; /* [E] which matrix the edge's check belongs to */
 } graph;
 
 static void graph_free(graph *g) {
@@ -102,6 +103,7 @@ static void graph_free(graph *g) {
     free(g->edge_var);
     free(g->var_start);
     free(g->var_edges);
+    free(g->edge_matrix);
 }
 
 static int graph_build(const oracle_code *c, graph *g) {
@@ -122,7 +124,9 @@ static int graph_build(const oracle_code *c, graph *g) {
     g->edge_var = malloc(sizeof(int32_t) * (size_t)(E > 0 ? E : 1));
     g->var_start = calloc((size_t)c->n + 1, sizeof(int32_t));
     g->var_edges = malloc(sizeof(int32_t) * (size_t)(E > 0 ? E : 1));
-    if (!g->row_start || !g->row_matrix || !g->edge_var || !g->var_start || !g->var_edges) {
+    g->edge_matrix = malloc(sizeof(int32_t) * (size_t)(E > 0 ? E : 1));
+    if (!g->row_start || !g->row_matrix || !g->edge_var || !g->var_start || !g->var_edges ||
+        !g->edge_matrix) {
         graph_free(g);
         return -1;
     }
@@ -137,6 +141,7 @@ static int graph_build(const oracle_code *c, graph *g) {
             for (int32_t k = rp[j]; k < rp[j + 1]; ++k) {
                 int32_t v = ci[k];
                 if (v < 0 || v >= c->n) { graph_free(g); return -1; }
+                g->edge_matrix[e] = l;
                 g->edge_var[e++] = v;
             }
             ++r;
@@ -158,6 +163,60 @@ static int graph_build(const oracle_code *c, graph *g) {
 static double sgn(double x) { return x < 0.0 ? -1.0 : 1.0; }
 
 static double clip_to(double x, double C) { return x > C ? C : (x < -C ? -C : x); }
+
+/* Eq. (2) with its nesting: L_i = lambda_i + sum over matrices l (in order)
+   of [sum over the checks j of H_l at variable i (in order) of c]. Each
+   matrix's messages are summed first, from 0, and that sum is added to the
+   running total; a matrix with no edge at the variable adds nothing. The
+   binary32 variant does the same additions in binary32. */
+static double vsum_d(const graph *g, int32_t i, double lam, const double *c) {
+    double L = lam, S = 0.0;
+    int32_t cur = -1;
+    for (int32_t k = g->var_start[i]; k < g->var_start[i + 1]; ++k) {
+        const int32_t e = g->var_edges[k];
+        if (g->edge_matrix[e] != cur) {
+            if (cur >= 0) L += S;
+            S = 0.0;
+            cur = g->edge_matrix[e];
+        }
+        S += c[e];
+    }
+    if (cur >= 0) L += S;
+    return L;
+}
+
+static float vsum_f(const graph *g, int32_t i, float lam, const float *c) {
+    float L = lam, S = 0.0f;
+    int32_t cur = -1;
+    for (int32_t k = g->var_start[i]; k < g->var_start[i + 1]; ++k) {
+        const int32_t e = g->var_edges[k];
+        if (g->edge_matrix[e] != cur) {
+            if (cur >= 0) L += S;
+            S = 0.0f;
+            cur = g->edge_matrix[e];
+        }
+        S += c[e];
+    }
+    if (cur >= 0) L += S;
+    return L;
+}
+
+/* the same over messages held as doubles of binary32 values */
+static float vsum_fd(const graph *g, int32_t i, float lam, const double *c) {
+    float L = lam, S = 0.0f;
+    int32_t cur = -1;
+    for (int32_t k = g->var_start[i]; k < g->var_start[i + 1]; ++k) {
+        const int32_t e = g->var_edges[k];
+        if (g->edge_matrix[e] != cur) {
+            if (cur >= 0) L += S;
+            S = 0.0f;
+            cur = g->edge_matrix[e];
+        }
+        S += (float)c[e];
+    }
+    if (cur >= 0) L += S;
+    return L;
+}
 
 /* Sec. 3B, eq. (6): check-to-variable messages of one check, sum-product.
    For each edge k: c_k = (-1)^z * 2 atanh( prod over the other edges k' of
@@ -288,13 +347,8 @@ static void decode_frame(const graph *g, const oracle_params *P, const double *l
                 for (int32_t k = 0; k < d; ++k) b->c[e0 + k] = b->tmp[k];
             }
             /* eq. (2): soft decision = channel LLR + every incoming check
-               message, summed over matrices in order, then checks in order */
-            for (int32_t i = 0; i < n; ++i) {
-                double s = lam[i];
-                for (int32_t k = g->var_start[i]; k < g->var_start[i + 1]; ++k)
-                    s += b->c[g->var_edges[k]];
-                b->L[i] = s;
-            }
+               message, a sum per matrix added in matrix order */
+            for (int32_t i = 0; i < n; ++i) b->L[i] = vsum_d(g, i, lam[i], b->c);
         }
         /* decision: bit 1 iff L < 0 */
         for (int32_t i = 0; i < n; ++i) b->xhat[i] = b->L[i] < 0.0 ? 1 : 0;
@@ -372,11 +426,7 @@ static void decode_frame_nms_f32(const graph *g, const oracle_params *P, const d
                 }
                 for (int32_t k = 0; k < d; ++k) c[e0 + k] = tmp[k];
             }
-            for (int32_t i = 0; i < n; ++i) {
-                float s = lam[i];
-                for (int32_t k = g->var_start[i]; k < g->var_start[i + 1]; ++k) s += c[g->var_edges[k]];
-                L[i] = s;
-            }
+            for (int32_t i = 0; i < n; ++i) L[i] = vsum_f(g, i, lam[i], c);
         }
         for (int32_t i = 0; i < n; ++i) b->xhat[i] = L[i] < 0.0f ? 1 : 0;
         if (P->early_exit && unsatisfied(g, b->xhat, z) == 0) {
@@ -563,11 +613,7 @@ static void nms_iteration_f32(const graph *g, const double *alpha, int32_t t, do
             c[e0 + k] = (double)(zs * a_tl * sg * mn);
         }
     }
-    for (int32_t i = 0; i < n; ++i) {
-        float s = (float)lam[i];
-        for (int32_t k = g->var_start[i]; k < g->var_start[i + 1]; ++k) s += (float)c[g->var_edges[k]];
-        L[i] = (double)s;
-    }
+    for (int32_t i = 0; i < n; ++i) L[i] = (double)vsum_fd(g, i, (float)lam[i], c);
 }
 
 static void nms_unrolled_frame(const graph *g, int32_t K, const double *alpha, double C,
@@ -593,11 +639,7 @@ static void nms_unrolled_frame(const graph *g, int32_t K, const double *alpha, d
             check_rule_nms(d, q + e0, z[r], alpha[(size_t)(t - 1) * u + g->row_matrix[r]], C,
                            c + e0);
         }
-        for (int32_t i = 0; i < n; ++i) {
-            double s = lam[i];
-            for (int32_t k = g->var_start[i]; k < g->var_start[i + 1]; ++k) s += c[g->var_edges[k]];
-            L[i] = s;
-        }
+        for (int32_t i = 0; i < n; ++i) L[i] = vsum_d(g, i, lam[i], c);
     }
     for (int32_t i = 0; i < n; ++i) Lout[i] = Ls[(size_t)K * n + i];
     if (!gL_in) return;

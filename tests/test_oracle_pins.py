@@ -487,7 +487,11 @@ def test_unrolled_binary32_gradient_matches_its_finite_differences():
         fp, f0, fm = J_of_lam(xp), J_of_lam(lam), J_of_lam(xm)
         right, left = (fp - f0) / eps, (f0 - fm) / eps
         if abs(right - left) <= 1e-3 * (1 + abs(right)):
-            assert glam.flat[i] == pytest.approx(0.5 * (right + left), rel=1e-3, abs=1e-3)
+            # each binary32 L (|L| up to ~30) carries about one ulp (2^-19)
+            # of rounding, so J over 96 entries with unit weights is noisy to
+            # ~2e-5, and the central difference over 2 eps = 0.02 to ~1.5e-3
+            # (more where the rounding of a step's two ends happens to differ)
+            assert glam.flat[i] == pytest.approx(0.5 * (right + left), rel=1e-3, abs=4e-3)
             checked += 1
     assert checked >= 15
 
