@@ -43,9 +43,10 @@ def source_hash() -> str:
     return h.hexdigest()[:12]
 
 
-def stored_traffic(algo: str):
+def stored_traffic(algo: str, schedule: str):
     """HBM bytes per check-node launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources."""
+    summary of the same algorithm and schedule, if it was taken on the
+    current kernel sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -56,7 +57,7 @@ def stored_traffic(algo: str):
     if vals.get("kernel_source_sha1") != source_hash():
         return None
     try:
-        return float(vals[f"hbm_bytes_per_launch_{algo}"])
+        return float(vals[f"hbm_bytes_per_launch_{algo}_{schedule}"])
     except (KeyError, ValueError):
         return None
 
@@ -254,7 +255,7 @@ def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_
     }
 
 
-def qualifying_point(ctx, steps: int, algo: str):
+def qualifying_point(ctx, steps: int, algo: str, schedule: str):
     """The operating point that meets f <= 1.1: u=3 {2,3,10} PEG matrices,
     n=2^18, rate 0.85, BSC 0.02 (f = 1.061), 64 frames, decoded like the main
     workload (decoded from Bob's bits and error rates per step, inputs resident)."""
@@ -273,7 +274,7 @@ def qualifying_point(ctx, steps: int, algo: str):
 
     def step():
         return mbp.decode_from_bits(ctx, dcode, y, e, z, dtype="f32", algo=wl.algo, max_iter=wl.max_iter,
-                                    alpha=wl.alpha, clip=wl.clip)
+                                    alpha=wl.alpha, clip=wl.clip, schedule=schedule)
 
     step()
     torch.cuda.synchronize()
@@ -285,17 +286,19 @@ def qualifying_point(ctx, steps: int, algo: str):
     bits = out["bits"].cpu().numpy()
     fer = float(np.any(bits != fr.x, axis=1).mean())
     m = code.m[0]
-    return {"workload": wl.name, "frames": fr.nframes, "mbps": round(fr.nframes * code.n / dt / 1e6, 1),
+    return {"workload": wl.name, "schedule": schedule, "frames": fr.nframes,
+            "mbps": round(fr.nframes * code.n / dt / 1e6, 1),
             "ms_per_step": round(dt * 1e3, 4), "fer": fer, "f": round(m / (code.n * float(h2(0.02))), 4),
             "f_leak": round(code.u * m / (code.n * float(h2(0.02))), 4),
             "avg_iters": float(out["iters"].float().mean().item()),
             "note": "FER from these frames only; 64 frames bound FER below about 4.7% (rule of three)"}
 
 
-def serial_schedule(ctx, wl, fr, dcode, y, e, z, steps: int):
-    """The main workload decoded with the matrix-serial schedule (Algorithm 1:
-    within an iteration each matrix's check pass is followed by a variable
-    pass): fewer iterations per frame, one more pair of passes per matrix."""
+def other_schedule(ctx, wl, fr, dcode, y, e, z, steps: int, schedule: str):
+    """The main workload decoded with the other schedule: flooding (every
+    matrix's checks from the previous iteration's messages, one variable pass
+    per iteration) beside the matrix-serial schedule of Algorithm 1 (each
+    matrix's check pass followed by a variable pass), or the reverse."""
     import torch
     from paper_2001_07979_amd import mbp
 
@@ -303,7 +306,7 @@ def serial_schedule(ctx, wl, fr, dcode, y, e, z, steps: int):
 
     def step():
         return mbp.decode_from_bits(ctx, dcode, y, e, z, dtype="f32", algo=wl.algo, max_iter=wl.max_iter,
-                                    alpha=wl.alpha, clip=wl.clip, schedule="serial")
+                                    alpha=wl.alpha, clip=wl.clip, schedule=schedule)
 
     step()
     torch.cuda.synchronize()
@@ -313,7 +316,7 @@ def serial_schedule(ctx, wl, fr, dcode, y, e, z, steps: int):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     bits = out["bits"].cpu().numpy()
-    return {"workload": wl.name, "schedule": "matrix-serial", "frames": fr.nframes,
+    return {"workload": wl.name, "schedule": schedule, "frames": fr.nframes,
             "mbps": round(fr.nframes * code.n / dt / 1e6, 1), "ms_per_step": round(dt * 1e3, 4),
             "fer": float(np.any(bits != fr.x, axis=1).mean()),
             "avg_iters": float(out["iters"].float().mean().item()),
@@ -407,8 +410,11 @@ def main():
     ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled training step")
     ap.add_argument("--no-two-call", action="store_true",
                     help="skip timing the same step as two calls (LLR rows stored, then decoded)")
-    ap.add_argument("--no-serial", action="store_true",
-                    help="skip the main workload under the matrix-serial schedule")
+    ap.add_argument("--schedule", choices=["serial", "flooding"], default="serial",
+                    help="schedule of the timed step (serial: Algorithm 1 as printed, each matrix's "
+                         "check pass followed by a variable pass)")
+    ap.add_argument("--no-other-schedule", action="store_true",
+                    help="skip timing the main workload under the other schedule")
     ap.add_argument("--no-qualifying", action="store_true",
                     help="skip the f <= 1.1 operating point (n=262144, rate 0.85)")
     ap.add_argument("--arrival-load", type=float, default=0.7,
@@ -449,13 +455,13 @@ def main():
         # the decoder (the same outputs as llr_from_bits then decode)
         mbp.decode_from_bits(ctx, dcode, y, e, z, dtype="f32", algo=wl.algo, max_iter=wl.max_iter,
                              early_exit=wl.early_exit, alpha=wl.alpha, clip=wl.clip, out=out,
-                             stream=stream)
+                             stream=stream, schedule=args.schedule)
 
     def step_two_calls():
         mbp.llr_from_bits(ctx, y, e, dtype="f32", out=llr, stream=stream)
         mbp.decode(ctx, dcode, llr, z, algo=wl.algo, max_iter=wl.max_iter,
                    early_exit=wl.early_exit, alpha=wl.alpha, clip=wl.clip, out=out,
-                   stream=stream)
+                   stream=stream, schedule=args.schedule)
 
     if args.copy_probe_mib:
         src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
@@ -509,19 +515,29 @@ def main():
     roofline = None
     if profile:
         n_c, ms_c = ctx.profile_get("check")
-        # algorithmic bytes of the check-node pass: for every iteration a
-        # frame runs, read c (E) and L (n) and write c (E); at t = 1 there
-        # is no c to read, and lambda comes as one bit per variable
+        # algorithmic bytes of the check-node passes, per frame and
+        # iteration it runs: every pass reads L (n; the first pass of the
+        # first iteration reads lambda as one bit per variable) and writes c
+        # (E over the passes); from t = 2 it reads the old c (E), which
+        # min-sum with a compressed check state replaces by reading and
+        # writing 3 words per check
         s = 4
+        phases = code.u if args.schedule == "serial" else 1
+        cst = wl.algo == "nms" and max(int(np.diff(rp).max()) for rp in code.row_ptr) <= 24
+        old = 2 * 3 * s * code.M if cst else s * E
         per_step = 0
         for t in range(1, int(iters.max()) + 1):
             full = int((iters >= t).sum())
-            per_step += full * (s * (2 * E + n) if t >= 2 else s * E + n / 8)
+            if t == 1:
+                per_frame = s * E + n / 8 + s * n * (phases - 1) + (3 * s * code.M if cst else 0)
+            else:
+                per_frame = s * E + old + s * n * phases
+            per_step += full * per_frame
         launches_per_step = n_c / args.steps
         bytes_per_launch = per_step / launches_per_step
         avg_ms = ms_c / n_c
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        traffic = stored_traffic(wl.algo)
+        traffic = stored_traffic(wl.algo, args.schedule)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": traffic, "kernel": "k_check (check-node pass)",
@@ -552,12 +568,13 @@ def main():
     qual = None
     if not args.no_qualifying:
         log("bench: qualifying point (n=262144, rate 0.85, f=1.061)")
-        qual = qualifying_point(ctx, 5, args.algo)
+        qual = qualifying_point(ctx, 5, args.algo, args.schedule)
 
-    serial = None
-    if not args.no_serial:
-        log("bench: main workload, matrix-serial schedule")
-        serial = serial_schedule(ctx, wl, fr, dcode, y, e, z, 5)
+    other = None
+    if not args.no_other_schedule:
+        sched = "flooding" if args.schedule == "serial" else "serial"
+        log(f"bench: main workload, {sched} schedule")
+        other = other_schedule(ctx, wl, fr, dcode, y, e, z, 5, sched)
 
     log("bench: Alice's syndromes")
     alice = alice_syndromes(ctx, wl, fr, dcode, 10)
@@ -579,12 +596,12 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "frames": F, "n": n, "u": code.u, "m": m, "E": E,
                    "rate": 1 - m / n, "p": p, "algo": wl.algo, "max_iter": wl.max_iter,
-                   "early_exit": wl.early_exit, "peg": code.name},
+                   "early_exit": wl.early_exit, "schedule": args.schedule, "peg": code.name},
         "fer": fer, "decoder_failures": int((ok == 0).sum()),
         "avg_iters": float(iters.mean()), "max_iters": int(iters.max()),
         "f": round(m / (n * h), 4), "f_leak": round(code.u * m / (n * h), 4),
         "llr_rows_then_decode": two_calls,
-        "roofline": roofline, "cpu_baseline": cpu, "qualifying_point": qual, "matrix_serial": serial, "alice_syndromes": alice,
+        "roofline": roofline, "cpu_baseline": cpu, "qualifying_point": qual, "other_schedule": other, "alice_syndromes": alice,
         "unrolled_training_step": unrolled,
         "batched_vs_plain": batched,
     }

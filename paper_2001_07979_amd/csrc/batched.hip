@@ -290,8 +290,12 @@ __device__ void vn_tile(const GroupDesc &G_, int tile, const PArgs &a, uint64_t 
         const bool two = k + 1 < a.vars_per_wave && i1 < G_.n;
         const int p0 = ldc(G_.var_ptr, i0), q0 = ldc(G_.var_ptr, i0 + 1);
         const int p1 = two ? ldc(G_.var_ptr, i1) : 0, q1 = two ? ldc(G_.var_ptr, i1 + 1) : 0;
+        // eq. (2) nested: each matrix's messages summed from 0 (a0, a1),
+        // each such sum added to L in matrix order; a flagged edge (bit 31)
+        // starts the next matrix's run
         float s0 = on ? ldg(G_.lam, static_cast<int64_t>(i0) * G + lane) : 0.0f;
         float s1 = on && two ? ldg(G_.lam, static_cast<int64_t>(i1) * G + lane) : 0.0f;
+        float a0 = 0.0f, a1 = 0.0f;
         const int dmax = q0 - p0 > q1 - p1 ? q0 - p0 : q1 - p1;
         for (int c0 = 0; c0 < dmax; c0 += VC) {
             int e0[VC], e1[VC];
@@ -304,16 +308,30 @@ __device__ void vn_tile(const GroupDesc &G_, int tile, const PArgs &a, uint64_t 
                 float x0[VC], x1[VC];
 #pragma unroll
                 for (int j = 0; j < VC; ++j) {
-                    if (p0 + c0 + j < q0) x0[j] = ldg(G_.c, static_cast<int64_t>(e0[j]) * G + lane);
-                    if (p1 + c0 + j < q1) x1[j] = ldg(G_.c, static_cast<int64_t>(e1[j]) * G + lane);
+                    if (p0 + c0 + j < q0) x0[j] = ldg(G_.c, static_cast<int64_t>(e0[j] & 0x7fffffff) * G + lane);
+                    if (p1 + c0 + j < q1) x1[j] = ldg(G_.c, static_cast<int64_t>(e1[j] & 0x7fffffff) * G + lane);
                 }
 #pragma unroll
                 for (int j = 0; j < VC; ++j) {
-                    if (p0 + c0 + j < q0) s0 += x0[j];
-                    if (p1 + c0 + j < q1) s1 += x1[j];
+                    if (p0 + c0 + j < q0) {
+                        if (e0[j] < 0) {
+                            s0 += a0;
+                            a0 = 0.0f;
+                        }
+                        a0 += x0[j];
+                    }
+                    if (p1 + c0 + j < q1) {
+                        if (e1[j] < 0) {
+                            s1 += a1;
+                            a1 = 0.0f;
+                        }
+                        a1 += x1[j];
+                    }
                 }
             }
         }
+        if (q0 > p0) s0 += a0;
+        if (q1 > p1) s1 += a1;
         vn_finish(G_, i0, s0, on, lane);
         if (two) vn_finish(G_, i1, s1, on, lane);
     }
@@ -672,7 +690,7 @@ Built lay_out(int32_t nb, const mbp_batch *b, const mbp_tuning &tu) {
             d.row_ptr = code->d_row_ptr;
             d.col = code->d_col;
             d.var_ptr = code->d_var_ptr;
-            d.var_edge = code->d_var_edge;
+            d.var_edge = code->d_var_edge_f;
             // state pointers are filled in once the workspace base is known
             d.c = reinterpret_cast<float *>(P.c + k * sc);
             d.Lp = reinterpret_cast<float *>(P.Lp + k * sl);

@@ -166,6 +166,27 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
     for (int32_t i = 0; i < n; ++i) var_cnt[i + 1] += var_cnt[i];
     std::vector<int32_t> h_var_edge(E), fill(var_cnt.begin(), var_cnt.end() - 1);
     for (int64_t k = 0; k < E; ++k) h_var_edge[fill[h_col[k]]++] = (int32_t)k;
+    // each variable's edges ascend, so its edges of one matrix are one run:
+    // mark where each run after the first starts, and where every matrix's
+    // run starts (empty runs included)
+    std::vector<int32_t> edge_mat(E);
+    for (int64_t rr = 0; rr < M; ++rr)
+        for (int32_t k = h_row_ptr[rr]; k < h_row_ptr[rr + 1]; ++k) edge_mat[k] = h_row_mat[rr];
+    std::vector<int32_t> h_var_edge_f(h_var_edge), h_var_mptr(static_cast<size_t>(u + 1) * n);
+    int32_t maxvdm = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t k = var_cnt[i];
+        for (int32_t l = 0; l < u; ++l) {
+            h_var_mptr[static_cast<size_t>(l) * n + i] = k;
+            const int32_t k0 = k;
+            while (k < var_cnt[i + 1] && edge_mat[h_var_edge[k]] == l) {
+                if (k == k0 && k > var_cnt[i]) h_var_edge_f[k] |= static_cast<int32_t>(0x80000000u);
+                ++k;
+            }
+            maxvdm = std::max(maxvdm, k - k0);
+        }
+        h_var_mptr[static_cast<size_t>(u) * n + i] = var_cnt[i + 1];
+    }
 
     mbp_code *code = new (std::nothrow) mbp_code();
     if (!code) return fail(MBP_ENOMEM, "mbp_code_create: out of host memory");
@@ -179,6 +200,7 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
     for (int32_t l = 0; l <= u; ++l) code->e_off[l] = h_row_ptr[h_mat_off[l]];
     code->max_check_deg = maxcd;
     code->max_var_deg = maxvd;
+    code->max_var_deg_matrix = maxvdm;
     auto cleanup = [&](int rc) {
         (void)hipFree(code->d_row_ptr);
         (void)hipFree(code->d_row_mat);
@@ -186,6 +208,8 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
         (void)hipFree(code->d_col);
         (void)hipFree(code->d_var_ptr);
         (void)hipFree(code->d_var_edge);
+        (void)hipFree(code->d_var_edge_f);
+        (void)hipFree(code->d_var_mptr);
         delete code;
         return rc;
     };
@@ -196,12 +220,15 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
         (he = hipMalloc(&code->d_mat_off, sizeof(int32_t) * (u + 1))) != hipSuccess ||
         (he = hipMalloc(&code->d_col, sizeof(int32_t) * (E + mbp::kIndexPad))) != hipSuccess ||
         (he = hipMalloc(&code->d_var_ptr, sizeof(int32_t) * (n + 1))) != hipSuccess ||
-        (he = hipMalloc(&code->d_var_edge, sizeof(int32_t) * (E + mbp::kIndexPad))) != hipSuccess)
+        (he = hipMalloc(&code->d_var_edge, sizeof(int32_t) * (E + mbp::kIndexPad))) != hipSuccess ||
+        (he = hipMalloc(&code->d_var_edge_f, sizeof(int32_t) * (E + mbp::kIndexPad))) != hipSuccess ||
+        (he = hipMalloc(&code->d_var_mptr, sizeof(int32_t) * (u + 1) * n)) != hipSuccess)
         return cleanup(hip_fail(he, "mbp_code_create: hipMalloc"));
     // the kernels read edge indices in fixed-size blocks that may run past the
     // last edge; the padding holds valid (zero) indices
     h_col.resize(E + mbp::kIndexPad, 0);
     h_var_edge.resize(E + mbp::kIndexPad, 0);
+    h_var_edge_f.resize(E + mbp::kIndexPad, 0);
     if ((he = hipMemcpy(code->d_row_ptr, h_row_ptr.data(), sizeof(int32_t) * (M + 1),
                         hipMemcpyHostToDevice)) != hipSuccess ||
         (he = hipMemcpy(code->d_row_mat, h_row_mat.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice)) !=
@@ -213,6 +240,10 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
         (he = hipMemcpy(code->d_var_ptr, var_cnt.data(), sizeof(int32_t) * (n + 1),
                         hipMemcpyHostToDevice)) != hipSuccess ||
         (he = hipMemcpy(code->d_var_edge, h_var_edge.data(), sizeof(int32_t) * (E + mbp::kIndexPad),
+                        hipMemcpyHostToDevice)) != hipSuccess ||
+        (he = hipMemcpy(code->d_var_edge_f, h_var_edge_f.data(), sizeof(int32_t) * (E + mbp::kIndexPad),
+                        hipMemcpyHostToDevice)) != hipSuccess ||
+        (he = hipMemcpy(code->d_var_mptr, h_var_mptr.data(), sizeof(int32_t) * (u + 1) * n,
                         hipMemcpyHostToDevice)) != hipSuccess)
         return cleanup(hip_fail(he, "mbp_code_create: hipMemcpy"));
     ctx->live_codes++;
@@ -230,6 +261,8 @@ void mbp_code_destroy(mbp_code *code) {
     (void)hipFree(code->d_col);
     (void)hipFree(code->d_var_ptr);
     (void)hipFree(code->d_var_edge);
+    (void)hipFree(code->d_var_edge_f);
+    (void)hipFree(code->d_var_mptr);
     code->ctx->live_codes--;
     delete code;
 }

@@ -90,11 +90,15 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     const bool with_state = std::is_same<T, float>::value && p->algo == MBP_ALGO_NMS && dmax <= kStateMaxDeg;
     const size_t sz_cs = with_state ? align_up(static_cast<size_t>(ntot) * M * kStateRows * G * sizeof(uint32_t))
                                     : 0;
+    // the matrix-serial variable passes keep each matrix's sum at every
+    // variable, so a pass reads only its own matrix's messages
+    const bool phase_sums = p->schedule == MBP_MATRIX_SERIAL && code->u > 1 && code->u <= kPhaseMaxU;
+    const size_t sz_ps = phase_sums ? align_up(static_cast<size_t>(ntot) * code->u * n * G * s) : 0;
     // lambda: rows like L, or Bob's bit words and one magnitude per slot
     const size_t sz_lam = from_bits ? sz_d + align_up(static_cast<size_t>(ntot) * G * s) : sz_L;
     // status words, one 256-byte line per group, then the stopping-test counters
     const size_t sz_m = align_up(static_cast<size_t>(ntot) * kStride * sizeof(uint64_t)) + 256;
-    int rc = ensure_workspace(ctx, sz_c + sz_L + sz_lam + sz_z + sz_d + 2 * sz_f + sz_m + sz_cs);
+    int rc = ensure_workspace(ctx, sz_c + sz_L + sz_lam + sz_z + sz_d + 2 * sz_f + sz_m + sz_cs + sz_ps);
     if (rc != MBP_OK) return rc;
     if ((rc = ensure_status(ctx, ntot)) != MBP_OK) return rc;
     char *base = static_cast<char *>(ctx->ws);
@@ -122,6 +126,7 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     uint64_t *words = reinterpret_cast<uint64_t *>(carve(sz_m - 256));
     StopTail *tail = reinterpret_cast<StopTail *>(carve(256));
     T *cs = with_state ? reinterpret_cast<T *>(carve(sz_cs)) : nullptr;
+    T *ps = phase_sums ? reinterpret_cast<T *>(carve(sz_ps)) : nullptr;
 
     Timer tm{ctx, stream, {}, 0};
     hipError_t err;
@@ -166,10 +171,20 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     dc.ymag = dv.ymag = ymag;
     dc.cstate = cs;
     dv.reverse = 1;
+    int vpt_p = 0;
+    const VarPhaseFn<T> kvp = from_bits ? variable_phase_kernel<T, true>(code->max_var_deg_matrix, &vpt_p)
+                                        : variable_phase_kernel<T>(code->max_var_deg_matrix, &vpt_p);
+    Dims dvs = dv;  // the matrix-serial phase passes
+    dvs.ntiles = (n + vpt_p - 1) / vpt_p;
+    dvs.u = code->u;
+    dvs.vmptr = code->d_var_mptr;
+    dvs.psum = ps;
     Dims ds{E, n, M, ntot, (M + kBlock - 1) / kBlock, 0, 0, p->alpha, p->llr_clip, p->max_iter, ngroups,
             nspare};
     const int grid_c = grid_for(ctx, reinterpret_cast<const void *>(kc),
                                 static_cast<int64_t>(ngroups) * dc.ntiles);
+    const int grid_vp = grid_for(ctx, reinterpret_cast<const void *>(kvp),
+                                 static_cast<int64_t>(ngroups) * dvs.ntiles);
     const int grid_v = grid_for(ctx, reinterpret_cast<const void *>(kv),
                                 static_cast<int64_t>(ngroups) * dv.ntiles);
     const int grid_s = grid_for(ctx, reinterpret_cast<const void *>(&k_stop_test),
@@ -228,10 +243,21 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
             uint64_t *Dout = ph + 1 == phases.size() ? D : nullptr;
             // in the first serial iteration only matrices 0..ph have sent
             // check messages; the others' are zero, so their edges are left out
-            Dims dvp = dv;
-            dvp.emax = t == 1 && phases.size() > 1 ? code->e_off[ph + 1] : -1;
-            LAUNCH_OR_FAIL(kVarNode, kv<<<grid_v, kBlock, 0, stream>>>(code->d_var_ptr, code->d_var_edge, c, lam,
-                                                                       Lp, words, Dout, dvp));
+            if (phase_sums) {
+                Dims dp = dvs;
+                dp.t = t;
+                dp.phase = static_cast<int32_t>(ph);
+                LAUNCH_OR_FAIL(kVarNode, kvp<<<grid_vp, kBlock, 0, stream>>>(
+                                             code->d_var_ptr, code->d_var_edge, c, lam, Lp, words, Dout, dp));
+            } else {
+                // flooding, or a serial schedule of more matrices than the
+                // stored sums cover: every message summed again; in the first
+                // serial iteration only the matrices visited so far count
+                Dims dvp = dv;
+                dvp.emax = t == 1 && phases.size() > 1 ? code->e_off[ph + 1] : -1;
+                LAUNCH_OR_FAIL(kVarNode, kv<<<grid_v, kBlock, 0, stream>>>(code->d_var_ptr, code->d_var_edge_f, c,
+                                                                           lam, Lp, words, Dout, dvp));
+            }
         }
         if (!p->early_exit && t < p->max_iter) continue;
         LAUNCH_OR_FAIL(kSyndrome, k_stop_test<<<grid_s, kBlock, 0, stream>>>(
@@ -239,7 +265,7 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
                                       iters_out, ok_out, fid, src, tail, ds));
         // fills the spare groups the stopping test's compaction planned
         if (nspare && t <= p->max_iter - 2)
-            LAUNCH_OR_FAIL(kSyndrome, k_move<T><<<grid_m, kBlock, 0, stream>>>(c, Lp, lam, zb, yb, ymag, cs, src, tail, E, n,
+            LAUNCH_OR_FAIL(kSyndrome, k_move<T><<<grid_m, kBlock, 0, stream>>>(c, Lp, lam, zb, yb, ymag, cs, ps, code->u, src, tail, E, n,
                                                                                 M));
         if (p->early_exit) {
             if ((err = hipEventRecord(ctx->poll_events[t & 1], stream)) != hipSuccess)

@@ -66,6 +66,7 @@ struct mbp_code {
     std::vector<int32_t> m;
     std::vector<int64_t> e_off;  // [u + 1] first stacked edge of each matrix
     int32_t max_check_deg = 0, max_var_deg = 0;
+    int32_t max_var_deg_matrix = 0;  // largest degree of a variable within one matrix
     // Device edge layouts of the stacked graph [H_1; ...; H_u]:
     // edges in check-major order (matrix, row, column); for each variable its
     // edges in the same order.
@@ -75,6 +76,12 @@ struct mbp_code {
     int32_t *d_col = nullptr;       // [E]
     int32_t *d_var_ptr = nullptr;   // [n + 1]
     int32_t *d_var_edge = nullptr;  // [E]
+    // var_edge again, with bit 31 set on an entry whose edge starts the next
+    // matrix's edges in its variable's list (not on a variable's first entry)
+    int32_t *d_var_edge_f = nullptr;  // [E]
+    // position in var_edge of the first edge of matrix l at variable i, at
+    // [l * n + i] for l = 0..u (row u: one past the variable's last edge)
+    int32_t *d_var_mptr = nullptr;  // [(u + 1) n]
 };
 
 namespace mbp {

@@ -141,6 +141,14 @@ struct Dims {
     // at t >= 2 in place of the check's old messages and written every
     // iteration. Element type uint32_t.
     void *cstate = nullptr;
+    // matrix-serial variable pass (k_variable_phase): the code's matrices,
+    // this pass's matrix, the per-matrix positions of every variable's edges
+    // ([l * n + i], l = 0..u) and the stored per-matrix sums
+    // ([group][l][n][64], element type T)
+    int32_t u = 1;
+    int32_t phase = 0;
+    const int32_t *vmptr = nullptr;
+    void *psum = nullptr;
     // variable pass: visit the groups last to first. The check pass visits
     // them first to last, so the variable pass starts on the group whose
     // messages were written last (the likeliest still in the last-level
@@ -645,20 +653,24 @@ constexpr int kMovePerWave = kMoveRows / kWaves;
 // words (M), each lane from its source slot src[]. With the channel given as
 // bits (lam null), Bob's bit words (n, after the syndrome words) and the
 // per-slot magnitudes move instead of the lambda rows; a compressed check
-// state (cs, kStateRows rows per check) moves with the messages. Work items are runs of
+// state (cs, kStateRows rows per check) and stored per-matrix sums (ps, u
+// rows per variable) move with the messages. Work items are runs of
 // kMoveRows rows of one region of one group.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_move(T *c, T *Lp, T *lam, uint64_t *zb, uint64_t *yb, T *ymag,
-                                                 T *cs, const int32_t *src, const StopTail *tail, int64_t E,
-                                                 int32_t n, int32_t M) {
+                                                 T *cs, T *ps, int32_t u, const int32_t *src,
+                                                 const StopTail *tail, int64_t E, int32_t n, int32_t M) {
     const int count = tail->move_count, first = tail->move_first;
     if (count == 0) return;
     const unsigned lane = lane_id();
     const int wave = wave_id();
     const int64_t nw = M + (yb ? n : 0);  // word rows: syndromes, then Bob's bits
     // rows of one value per lane: messages (E), then the compressed check
-    // state if there is one (kStateRows per check; 4-byte words moved as T)
-    const int64_t nc = E + (cs ? static_cast<int64_t>(kStateRows) * M : 0);
+    // state if there is one (kStateRows per check; 4-byte words moved as T),
+    // then the stored per-matrix sums if there are (u per variable)
+    const int64_t ns = cs ? static_cast<int64_t>(kStateRows) * M : 0;
+    const int64_t np = ps ? static_cast<int64_t>(u) * n : 0;
+    const int64_t nc = E + ns + np;
     const int64_t ic = (nc + kMoveRows - 1) / kMoveRows, il = (n + kMoveRows - 1) / kMoveRows,
                   iz = (nw + kMoveRows - 1) / kMoveRows, per_group = ic + il + iz;
     for (int64_t w = blockIdx.x; w < count * per_group; w += gridDim.x) {
@@ -669,22 +681,22 @@ __global__ __launch_bounds__(kBlock) void k_move(T *c, T *Lp, T *lam, uint64_t *
         const int64_t sg = has ? s / G : g, sl = has ? s % G : 0;
         if (item < ic) {
             const int64_t r0 = item * kMoveRows + wave * kMovePerWave;
-            const int64_t ns = nc - E;  // state rows per group
+            // row r of a group: its array, rows per group and row within
+            auto at = [&](int64_t grp, int64_t r) -> T * {
+                if (r < E) return c + (grp * E + r) * G;
+                if (r < E + ns) return cs + (grp * ns + r - E) * G;
+                return ps + (grp * np + r - E - ns) * G;
+            };
             T v[kMovePerWave];
 #pragma unroll
             for (int j = 0; j < kMovePerWave; ++j) {
                 const int64_t r = r0 + j;
-                if (has && r < nc) v[j] = r < E ? c[(sg * E + r) * G + sl] : cs[(sg * ns + r - E) * G + sl];
+                if (has && r < nc) v[j] = at(sg, r)[sl];
             }
 #pragma unroll
             for (int j = 0; j < kMovePerWave; ++j) {
                 const int64_t r = r0 + j;
-                if (has && r < nc) {
-                    if (r < E)
-                        c[(g * E + r) * G + lane] = v[j];
-                    else
-                        cs[(g * ns + r - E) * G + lane] = v[j];
-                }
+                if (has && r < nc) at(g, r)[lane] = v[j];
             }
         } else if ((item -= ic) < il) {
             const int64_t r0 = item * kMoveRows + wave * kMovePerWave;
@@ -758,10 +770,13 @@ __global__ __launch_bounds__(kBlock) void k_output_slots(const T *Lp, const int3
     }
 }
 
-// Variable-node pass, eq. (2): L = lambda + every incoming check message,
-// summed over the variable's edges in edge order (matrix, then check). Each
-// wave takes VPW variables of degree at most DV and issues all their
-// gathers before summing any. D, if not null, receives the decision word of
+// Variable-node pass, eq. (2) with its nesting: L = lambda + the sum, over
+// the matrices in order, of each matrix's check messages at the variable
+// (summed from 0 in check order). var_edge is the flagged list: an entry
+// with bit 31 set starts the next matrix's run of the variable's edges, where
+// the running matrix sum is added to L and restarted. Each wave takes VPW
+// variables of degree at most DV and issues all their gathers before summing
+// any. D, if not null, receives the decision word of
 // each variable (bit k set when frame 64g+k decides 1, i.e. L < 0; frames
 // not running leave 0).
 template <typename T, int DV, int VPW, bool BITS = false>
@@ -800,11 +815,16 @@ __global__ __launch_bounds__(kBlock) void k_variable(
             // iteration of the matrix-serial schedule
             const int64_t lim = a.emax < 0 ? INT64_MAX : a.emax;
             int ev[VPW][DV];
+            bool fl[VPW][DV];
             uint32_t yh[VPW];
 #pragma unroll
             for (int v = 0; v < VPW; ++v) {
 #pragma unroll
-                for (int j = 0; j < DV; ++j) ev[v][j] = var_edge[k0[v] + j];
+                for (int j = 0; j < DV; ++j) {
+                    const int raw = var_edge[k0[v] + j];
+                    fl[v][j] = raw < 0;
+                    ev[v][j] = raw & 0x7fffffff;
+                }
                 if constexpr (BITS)
                     yh[v] = in[v] ? bit_half(yg, i[v], lane) : 0u;
                 else
@@ -819,9 +839,20 @@ __global__ __launch_bounds__(kBlock) void k_variable(
             }
 #pragma unroll
             for (int v = 0; v < VPW; ++v) {
+                T acc = T(0);  // the running matrix's sum
+                bool any = false;
 #pragma unroll
-                for (int j = 0; j < DV; ++j)
-                    if (j < deg[v] && ev[v][j] < lim) s[v] += x[v][j];
+                for (int j = 0; j < DV; ++j) {
+                    if (j < deg[v] && ev[v][j] < lim) {
+                        if (fl[v][j]) {
+                            s[v] += acc;
+                            acc = T(0);
+                        }
+                        acc += x[v][j];
+                        any = true;
+                    }
+                }
+                if (any) s[v] += acc;
                 if (in[v]) (Lp + gb + static_cast<size_t>(i[v]) * G)[lane] = s[v];
             }
         }
@@ -833,6 +864,124 @@ __global__ __launch_bounds__(kBlock) void k_variable(
             }
         }
     }
+}
+
+// Variable pass of phase l of the matrix-serial schedule, for codes of at
+// most kPhaseMaxU matrices. Only matrix l's messages changed since the last
+// variable pass, so only they are read: their sum at each variable (from 0,
+// in check order) is formed and stored, and L = lambda + the per-matrix sums
+// of every matrix in order, the others read back from where earlier passes
+// stored them. This is eq. (2) with the nesting the full sum uses, so L is
+// the same, bit for bit, as summing every message again. A matrix with no
+// edge at the variable adds nothing, nor, in the first iteration, does a
+// matrix not visited yet (its messages are still zero).
+constexpr int kPhaseMaxU = 4;
+
+template <typename T, int DV, int VPW, bool BITS = false>
+__global__ __launch_bounds__(kBlock) void k_variable_phase(
+    const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_edge,
+    const T *__restrict__ c, const T *__restrict__ lam, T *__restrict__ Lp,
+    const uint64_t *__restrict__ act, uint64_t *__restrict__ D, const Dims a) {
+    (void)var_ptr;
+    const unsigned lane = lane_id();
+    const int wave = wave_id();
+    const int l = a.phase;
+    const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        const int gw = static_cast<int>(w / a.ntiles);
+        const int g = a.reverse ? a.ngroups - 1 - gw : gw;
+        const int tile = static_cast<int>(w % a.ntiles);
+        const uint64_t run = act[kStride * g + kRun];
+        if (run == 0) continue;
+        const bool on = (run >> lane) & 1;
+        const size_t gb = static_cast<size_t>(g) * a.n * G;
+        const T *cg = c + static_cast<size_t>(g) * a.E * G;
+        T *sg = static_cast<T *>(a.psum) + static_cast<size_t>(g) * a.u * a.n * G;
+        const uint64_t *yg = BITS ? a.ybits + static_cast<size_t>(g) * a.n : nullptr;
+        const T ym = BITS ? static_cast<const T *>(a.ymag)[static_cast<size_t>(g) * G + lane] : T(0);
+        int i[VPW], k0[VPW], deg[VPW];
+        bool in[VPW];
+        int cnt[VPW][kPhaseMaxU];
+#pragma unroll
+        for (int v = 0; v < VPW; ++v) {
+            i[v] = (tile * VPW + v) * kWaves + wave;
+            in[v] = i[v] < a.n;
+            const int ii = in[v] ? i[v] : a.n - 1;
+#pragma unroll
+            for (int m = 0; m < kPhaseMaxU; ++m)
+                cnt[v][m] = m < a.u && in[v] ? a.vmptr[(m + 1) * a.n + ii] - a.vmptr[m * a.n + ii] : 0;
+            k0[v] = a.vmptr[l * a.n + ii];
+            deg[v] = cnt[v][0];
+#pragma unroll
+            for (int m = 1; m < kPhaseMaxU; ++m) deg[v] = m == l ? cnt[v][m] : deg[v];
+        }
+        T x[VPW][DV], s[VPW], part[VPW][kPhaseMaxU];
+        if (on) {
+            int ev[VPW][DV];
+            uint32_t yh[VPW];
+#pragma unroll
+            for (int v = 0; v < VPW; ++v) {
+#pragma unroll
+                for (int j = 0; j < DV; ++j) ev[v][j] = var_edge[k0[v] + j];
+                if constexpr (BITS)
+                    yh[v] = in[v] ? bit_half(yg, i[v], lane) : 0u;
+                else
+                    s[v] = in[v] ? (lam + gb + static_cast<size_t>(i[v]) * G)[lane] : T(0);
+#pragma unroll
+                for (int j = 0; j < DV; ++j)
+                    if (j < deg[v]) x[v][j] = (cg + static_cast<size_t>(ev[v][j]) * G)[lane];
+                // the other matrices' sums, as earlier passes stored them
+#pragma unroll
+                for (int m = 0; m < kPhaseMaxU; ++m)
+                    if (m != l && cnt[v][m] > 0 && (a.t > 1 || m < l))
+                        part[v][m] = (sg + (static_cast<size_t>(m) * a.n + i[v]) * G)[lane];
+            }
+            if constexpr (BITS) {
+#pragma unroll
+                for (int v = 0; v < VPW; ++v) s[v] = in[v] ? lam_of_half(yh[v], lane, ym) : T(0);
+            }
+#pragma unroll
+            for (int v = 0; v < VPW; ++v) {
+                T acc = T(0);
+#pragma unroll
+                for (int j = 0; j < DV; ++j)
+                    if (j < deg[v]) acc += x[v][j];
+#pragma unroll
+                for (int m = 0; m < kPhaseMaxU; ++m) {
+                    if (m == l) {
+                        if (cnt[v][m] > 0) s[v] += acc;
+                    } else if (cnt[v][m] > 0 && (a.t > 1 || m < l)) {
+                        s[v] += part[v][m];
+                    }
+                }
+                if (in[v]) {
+                    if (deg[v] > 0) (sg + (static_cast<size_t>(l) * a.n + i[v]) * G)[lane] = acc;
+                    (Lp + gb + static_cast<size_t>(i[v]) * G)[lane] = s[v];
+                }
+            }
+        }
+        if (D) {
+#pragma unroll
+            for (int v = 0; v < VPW; ++v) {
+                const uint64_t bits = __ballot(on && in[v] && s[v] < T(0));
+                if (lane == 0 && in[v]) D[static_cast<size_t>(g) * a.n + i[v]] = bits;
+            }
+        }
+    }
+}
+
+template <typename T, bool BITS = false>
+using VarPhaseFn = void (*)(const int32_t *, const int32_t *, const T *, const T *, T *, const uint64_t *,
+                            uint64_t *, Dims);
+
+template <typename T, bool BITS = false>
+VarPhaseFn<T> variable_phase_kernel(int dmax, int *vars_per_tile) {
+    if (dmax <= 4) { *vars_per_tile = 4 * kWaves; return &k_variable_phase<T, 4, 4, BITS>; }
+    if (dmax <= 8) { *vars_per_tile = 4 * kWaves; return &k_variable_phase<T, 8, 4, BITS>; }
+    if (dmax <= 16) { *vars_per_tile = 2 * kWaves; return &k_variable_phase<T, 16, 2, BITS>; }
+    if (dmax <= 32) { *vars_per_tile = kWaves; return &k_variable_phase<T, 32, 1, BITS>; }
+    *vars_per_tile = kWaves;
+    return &k_variable_phase<T, 64, 1, BITS>;
 }
 
 // The variable-pass instance for a joint variable degree up to dmax, and the

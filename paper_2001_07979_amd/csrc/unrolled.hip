@@ -338,7 +338,7 @@ struct Run {
         fwd<<<grid_c, kBlock, 0, stream>>>(code->d_row_ptr, code->d_col, code->d_row_mat,
                                            alpha + static_cast<size_t>(t - 1) * code->u, zb, act,
                                            a.L, a.c ? a.c : b.c, b.c_mut, dc);
-        kv<<<grid_v, kBlock, 0, stream>>>(code->d_var_ptr, code->d_var_edge, b.c,
+        kv<<<grid_v, kBlock, 0, stream>>>(code->d_var_ptr, code->d_var_edge_f, b.c,
                                           reinterpret_cast<const float *>(ws + Ly.lam), b.L, act, nullptr, dv);
     }
 };

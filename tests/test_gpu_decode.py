@@ -246,8 +246,13 @@ def test_stack_equivalence_on_gpu(ctx, ragged_code):
     one = type(ragged_code)(n=ragged_code.n, row_ptr=[rp], col_idx=[ci])
     a = parity.gpu_run(ctx, upload(ctx, ragged_code), fr, "spa", "f32", 40)
     b = parity.gpu_run(ctx, upload(ctx, one), fr, "spa", "f32", 40)
-    for k in ("bits", "iters", "ok", "L"):
+    for k in ("bits", "iters", "ok"):
         assert np.array_equal(a[k], b[k])
+    # the same messages; eq. (2) adds them per matrix first, the single
+    # stacked matrix in one run, so FP32 rounding differs in the last bits,
+    # and over the longer decodes (up to 40 iterations here) the difference
+    # grows as any FP32 rounding does (the parity protocol's long-decode bound)
+    np.testing.assert_allclose(a["L"], b["L"], rtol=1e-2, atol=5e-2)
 
 
 def test_invalid_arguments_are_rejected(ctx, ragged_code):
