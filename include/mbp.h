@@ -70,12 +70,16 @@ typedef struct mbp_code mbp_code;
  *              groups); 0: never. Results are the same either way. The
  *              batched calls use mbp_tuning.compact instead.
  *   schedule   MBP_FLOODING: every check of every matrix from the previous
- *              iteration's messages, then every variable (the default);
+ *              iteration's messages, then every variable (value 0);
  *              MBP_MATRIX_SERIAL: Algorithm 1 taken literally, the matrices
  *              in turn within an iteration, each matrix's check update
  *              followed by the soft decisions (eq. (2)) before the next
  *              matrix; the stopping test follows the last matrix. mbp_decode
- *              only (the batched and unrolled calls are flooding). */
+ *              and mbp_decode_from_bits only (the batched and unrolled calls
+ *              are flooding).
+ * Soft decisions (eq. (2)) are summed with the equation's nesting: each
+ * matrix's check messages at a variable are summed first (in check order),
+ * and those sums are added to the channel LLR in matrix order. */
 #define MBP_FLOODING 0
 #define MBP_MATRIX_SERIAL 1
 typedef struct {
@@ -172,7 +176,10 @@ int mbp_syndrome(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, const uint
  * Errors: EINVAL (bad parameters, sizes or null pointers), ENOMEM (the
  * context's workspace, about 64 g (E + 2n) sizeof(dtype) + 8 g (M + n)
  * bytes for g = ceil(nframes/64) groups, plus a quarter more groups with
- * p->compact and early exit, could not be allocated), EDEVICE. */
+ * p->compact and early exit; with the matrix-serial schedule and u <= 4,
+ * another 64 g u n sizeof(dtype) for each matrix's sum at every variable;
+ * with FP32 min-sum and check degrees <= 24, another 768 g M bytes of
+ * compressed check state; could not be allocated), EDEVICE. */
 int mbp_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,
                const void *llr, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
                uint8_t *ok_out, void *llr_out, void *stream);
