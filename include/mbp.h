@@ -103,8 +103,10 @@ int32_t mbp_version(void);
  * Errors: EINVAL (null out, bad device), EDEVICE, ENOMEM. */
 int mbp_ctx_create(int32_t device, mbp_ctx **out);
 
-/* Destroy a context and its workspace. Codes created on it must be destroyed
- * first. NULL is ignored. */
+/* Destroy a context and its workspace. Codes and plans created on it may be
+ * destroyed before or after it (nothing else may use the context
+ * afterwards); the context's own record is freed with the last of them.
+ * NULL is ignored. */
 void mbp_ctx_destroy(mbp_ctx *ctx);
 
 /* Upload u parity-check matrices (Sec. 2: u PEG matrices, m_l x n each).

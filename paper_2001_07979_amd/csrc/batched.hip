@@ -218,8 +218,11 @@ __device__ void cn_tile(const GroupDesc &G_, int tile, int t, const PArgs &a, ui
         const int d = ldc(G_.row_ptr, r + 1) - e0;
         const int zbit = static_cast<int>((ld_fresh(G_.zb + r) >> lane) & 1);
         float *cg = G_.c + static_cast<size_t>(e0) * G;
+        // the plain pass's FP32 min-sum rule (same results, bit for bit):
+        // signs as IEEE sign bits (q + 0 turns -0 into +0: sgn(0) = +1),
+        // the second minimum as med3(m1, a, m2)
         uint64_t neg = 0;
-        int sx = zbit;
+        uint32_t sxb = static_cast<uint32_t>(zbit) << 31;
         float m1 = INFINITY, m2 = INFINITY;
         int i1 = 0;
         for (int j0 = 0; j0 < d; j0 += kChunk) {
@@ -238,29 +241,25 @@ __device__ void cn_tile(const GroupDesc &G_, int tile, int t, const PArgs &a, ui
 #pragma unroll
                 for (int j = 0; j < kChunk; ++j) {
                     if (j0 + j < d) {
-                        const float q = Lv[j] - cv[j];
-                        const int s = q < 0.0f ? 1 : 0;
-                        sx ^= s;
-                        neg |= static_cast<uint64_t>(s) << (j0 + j);
-                        float aj = fabsf(q);
-                        aj = aj < a.clip ? aj : a.clip;
-                        if (aj < m1) {
-                            m2 = m1;
-                            m1 = aj;
-                            i1 = j0 + j;
-                        } else if (aj < m2) {
-                            m2 = aj;
-                        }
+                        const float q = (Lv[j] - cv[j]) + 0.0f;
+                        const uint32_t qb = __float_as_uint(q);
+                        sxb ^= qb;
+                        neg |= static_cast<uint64_t>(qb >> 31) << (j0 + j);
+                        const float aj = fminf(fabsf(q), a.clip);
+                        m2 = __builtin_amdgcn_fmed3f(m1, aj, m2);
+                        i1 = aj < m1 ? j0 + j : i1;
+                        m1 = fminf(m1, aj);
                     }
                 }
             }
         }
         if (on) {
-            const float mag1 = a.alpha * m1, mag2 = a.alpha * m2;
+            const float mag1 = a.alpha * m1, mag2 = a.alpha * m2;  // >= 0
+            const uint32_t sx = sxb >> 31;
             for (int j = 0; j < d; ++j) {
                 const float mag = j == i1 ? mag2 : mag1;
-                const int s = sx ^ static_cast<int>((neg >> j) & 1);
-                stg(cg, static_cast<int64_t>(j) * G + lane, s ? -mag : mag);
+                const uint32_t sb = (sx ^ static_cast<uint32_t>((neg >> j) & 1)) << 31;
+                stg(cg, static_cast<int64_t>(j) * G + lane, __uint_as_float(__float_as_uint(mag) | sb));
             }
         }
     }

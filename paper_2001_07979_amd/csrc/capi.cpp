@@ -91,14 +91,26 @@ int mbp_ctx_create(int32_t device, mbp_ctx **out) {
 }
 
 void mbp_ctx_destroy(mbp_ctx *ctx) {
-    if (!ctx) return;
+    if (!ctx || ctx->closed) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->status_host) (void)hipHostFree(ctx->status_host);
     for (hipEvent_t e : ctx->poll_events) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->timing_events) (void)hipEventDestroy(e);
-    delete ctx;
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    ctx->status_host = nullptr;
+    ctx->status_dev = nullptr;
+    ctx->status_cap = 0;
+    ctx->poll_events.clear();
+    ctx->timing_events.clear();
+    // codes still alive keep the struct (their destroy reads its device and
+    // count); the last of them frees it
+    if (ctx->live_codes > 0)
+        ctx->closed = true;
+    else
+        delete ctx;
 }
 
 int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
@@ -263,8 +275,9 @@ void mbp_code_destroy(mbp_code *code) {
     (void)hipFree(code->d_var_edge);
     (void)hipFree(code->d_var_edge_f);
     (void)hipFree(code->d_var_mptr);
-    code->ctx->live_codes--;
+    mbp_ctx *ctx = code->ctx;
     delete code;
+    if (--ctx->live_codes == 0 && ctx->closed) delete ctx;
 }
 
 int mbp_code_info(const mbp_code *code, int32_t *n, int32_t *u, int32_t *M, int64_t *E,
@@ -447,6 +460,7 @@ int mbp_plan_create(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches, co
         delete plan;
         return rc;
     }
+    ctx->live_codes++;  // a plan, like a code, keeps the context record
     *out = plan;
     return MBP_OK;
 }
@@ -473,7 +487,9 @@ void mbp_plan_destroy(mbp_plan *plan) {
     (void)hipDeviceSynchronize();
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     (void)hipFree(plan->ws);
+    mbp_ctx *ctx = plan->ctx;
     delete plan;
+    if (--ctx->live_codes == 0 && ctx->closed) delete ctx;
 }
 
 // Text cache of autotuned settings: one line per batch mix,

@@ -49,7 +49,11 @@ struct mbp_ctx {
     int32_t profiling = 0;  // bit k: time launches of kernel id k
     mbp::KernelStat stats[mbp::kNumKernels];
     std::vector<hipEvent_t> timing_events;
-    int32_t live_codes = 0;
+    int32_t live_codes = 0;  // codes and plans of the context not yet destroyed
+    // set by mbp_ctx_destroy while codes or plans of the context are still
+    // alive: the GPU resources are gone and the last of their destroy calls
+    // frees the struct
+    bool closed = false;
 };
 
 struct mbp_plan {

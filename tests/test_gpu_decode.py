@@ -295,3 +295,22 @@ def test_profiling_counts_launches(ctx, ragged_code):
     assert ctx.profile_get("check")[0] == n_c and ctx.profile_get("variable")[0] == 0
     from paper_2001_07979_amd import mbp
     assert mbp.lib().mbp_profile_enable(ctx.handle, 16) == mbp.MBP_EINVAL
+
+
+def test_context_may_go_before_its_codes(ragged_code):
+    """Destroying a context while a code (and the binding's objects) of it are
+    alive leaves no HIP error behind: the code's destroy still works, and a
+    fresh context decodes normally."""
+    import torch
+    from paper_2001_07979_amd import mbp
+    c1 = mbp.Context(0)
+    dc = mbp.Code.from_inputs(c1, ragged_code)
+    c1.close()
+    dc.close()
+    torch.cuda.synchronize()
+    x = torch.empty(16, device="cuda")  # would raise if a HIP error were pending
+    c2 = mbp.Context(0)
+    fr = bsc_frames(ragged_code, 8, 0.02, seed=77)
+    g = parity.gpu_run(c2, mbp.Code.from_inputs(c2, ragged_code), fr, "spa", "f32", 20)
+    assert g["ok"].all() and x.numel() == 16
+    c2.close()
