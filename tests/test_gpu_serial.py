@@ -198,3 +198,29 @@ def test_schedule_is_validated(ctx, codes):
     rc = mbp.lib().mbp_decode_batched(ctx.handle, 1, mbp._batches(items, outs), ctypes.byref(p),
                                       None, None)
     assert rc == mbp.MBP_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("u", [4, 5])
+def test_serial_many_matrices(ctx, u):
+    """Four matrices (the most whose per-matrix sums the serial variable
+    passes keep) and five (every message summed again each phase): min-sum
+    bit for bit against the binary32 oracle, sum-product FP64 against the
+    oracle, both with compaction on a spread of stopping iterations."""
+    code = peg_code(512, 96, u, {2: 0.3, 3: 0.7}, seed_base=7600 + u, name=f"peg-n512-u{u}")
+    F = 140
+    p = np.random.default_rng(u).permutation(np.geomspace(0.01, 0.09, F))
+    fr = bsc_frames(code, F, p, seed=40 + u)
+    dc = _upload(ctx, code)
+    lam = parity.oracle_llr(fr, "f32")
+    g = parity.gpu_run(ctx, dc, fr, "nms", "f32", 50, schedule=S)
+    parity.assert_bitwise(g, parity.oracle_f32_run(code, fr, 50, lam=lam, schedule=S))
+    lam64 = parity.oracle_llr(fr, "f64")
+    g64 = parity.gpu_run(ctx, dc, fr, "spa", "f64", 50, llr=lam64, schedule=S)
+    o64 = parity.oracle_run(code, fr, "spa", "f64", 50, lam=lam64, schedule=S)
+    # FP64: 1e-9 within 8 iterations; these codes run frames to 35-50
+    # iterations, where the two FP64 check rules' last-bit differences
+    # (prefix/suffix products against the direct product) grow to ~1e-6
+    # absolute around small L
+    parity.compare(g64, o64, 50, RTOL64, long_rtol=1e-4, atol=1e-9)
+    its = g["iters"]
+    assert (its == 50).sum() > 20 and (its <= 4).sum() > 50  # the oracle: 39/34 and 75/77
