@@ -311,6 +311,35 @@ void mbp_plan_destroy(mbp_plan *plan);
 int mbp_autotune(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches, const mbp_params *p,
                  const char *cache_path, mbp_tuning *out);
 
+/* Serving queue over the batched decode, for callers that receive frames a
+ * few at a time (the batched decode's queue of heterogeneous frames).
+ *   mbp_queue_create   parameters as for mbp_decode_batched (min-sum, FP32,
+ *                      flooding); tuning may be NULL for the default. The
+ *                      queue keeps the context's record alive until it is
+ *                      destroyed.
+ *   mbp_queue_submit   append batches (descriptors are copied; the device
+ *                      buffers they name are borrowed until their flush has
+ *                      completed). Nothing runs yet.
+ *   mbp_queue_flush    decode every batch submitted since the last flush in
+ *                      one batched launch, enqueued on `stream` after the
+ *                      previous flush's launch (one runs at a time: its
+ *                      blocks must all be resident); allocates that launch's
+ *                      workspace; returns without waiting.
+ *   mbp_queue_poll     without blocking, retire the flushes that completed
+ *                      (oldest first) and report how many submitted frames
+ *                      have their outputs written.
+ *   mbp_queue_wait     block until every flush has completed.
+ *   mbp_queue_destroy  wait, then free. NULL is ignored.
+ * Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE (also if a flush's grid
+ * barrier timed out; its frames count as done, their outputs undefined). */
+typedef struct mbp_queue mbp_queue;
+int mbp_queue_create(mbp_ctx *ctx, const mbp_params *p, const mbp_tuning *tuning, mbp_queue **out);
+int mbp_queue_submit(mbp_queue *q, int32_t nbatches, const mbp_batch *batches);
+int mbp_queue_flush(mbp_queue *q, void *stream);
+int mbp_queue_poll(mbp_queue *q, int64_t *frames_done);
+int mbp_queue_wait(mbp_queue *q);
+void mbp_queue_destroy(mbp_queue *q);
+
 /* Kernel timing. Every plain decode brackets each launch of the kernels
  * selected by the mask with HIP events on the decode's stream and adds the
  * elapsed times to per-kernel totals. Kernel ids: 0 = check-node pass,

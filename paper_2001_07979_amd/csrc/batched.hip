@@ -848,6 +848,20 @@ int batched_decode(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_param
     return MBP_OK;
 }
 
+int batched_launch(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_params *p, const mbp_tuning &tu,
+                   void *ws, hipStream_t stream, int32_t **err_dev) {
+    (void)hipGetLastError();
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    Built B = lay_out(nb, b, tu);
+    char *base = static_cast<char *>(ws);
+    int rc = upload_descriptors(B, base);
+    if (rc != MBP_OK) return rc;
+    if ((rc = enqueue_kernels(nb, b, p, tu, B, base, ctx->num_cus, stream, true)) != MBP_OK) return rc;
+    *err_dev = reinterpret_cast<int32_t *>(base + B.off_err);
+    return MBP_OK;
+}
+
 int batched_plan_capture(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_params *p, const mbp_tuning &tu,
                          void *ws, hipGraphExec_t *exec, int32_t **err_dev) {
     (void)hipGetLastError();

@@ -492,6 +492,131 @@ void mbp_plan_destroy(mbp_plan *plan) {
     if (--ctx->live_codes == 0 && ctx->closed) delete ctx;
 }
 
+int mbp_queue_create(mbp_ctx *ctx, const mbp_params *p, const mbp_tuning *tuning, mbp_queue **out) {
+    if (!out) return fail(MBP_EINVAL, "mbp_queue_create: out is NULL");
+    *out = nullptr;
+    if (!ctx || !p) return fail(MBP_EINVAL, "mbp_queue_create: null ctx or params");
+    // the parameter checks of a batched decode (a stand-in batch carries no frames yet)
+    if (p->algo != MBP_ALGO_NMS || p->dtype != MBP_F32)
+        return fail(MBP_EUNSUPPORTED, "mbp_queue_create: the batched decode runs normalized min-sum in FP32 only");
+    if (p->schedule != MBP_FLOODING)
+        return fail(MBP_EUNSUPPORTED, "mbp_queue_create: the batched decode runs the flooding schedule only");
+    if (p->max_iter < 1 || p->max_iter > 10000 || (p->early_exit != 0 && p->early_exit != 1) ||
+        !std::isfinite(p->llr_clip) || p->llr_clip <= 0.0 || !std::isfinite(p->alpha) || p->alpha <= 0.0)
+        return fail(MBP_EINVAL, "mbp_queue_create: bad parameters");
+    const mbp_tuning tu = tuning ? *tuning : mbp::default_tuning();
+    if (int rc = mbp::check_tuning(tu); rc != MBP_OK) return rc;
+    mbp_queue *q = new (std::nothrow) mbp_queue();
+    if (!q) return fail(MBP_ENOMEM, "mbp_queue_create: out of host memory");
+    q->ctx = ctx;
+    q->params = *p;
+    q->tuning = tu;
+    ctx->live_codes++;  // a queue, like a code, keeps the context record
+    *out = q;
+    return MBP_OK;
+}
+
+int mbp_queue_submit(mbp_queue *q, int32_t nbatches, const mbp_batch *batches) {
+    if (!q) return fail(MBP_EINVAL, "mbp_queue_submit: queue is NULL");
+    int rc = check_batches("mbp_queue_submit", q->ctx, nbatches, batches, &q->params, nullptr);
+    if (rc != MBP_OK) return rc;
+    for (int32_t i = 0; i < nbatches; ++i) {
+        q->pending.push_back(batches[i]);
+        q->pending_frames += batches[i].nframes;
+    }
+    return MBP_OK;
+}
+
+int mbp_queue_flush(mbp_queue *q, void *stream) {
+    if (!q) return fail(MBP_EINVAL, "mbp_queue_flush: queue is NULL");
+    if (q->pending.empty()) return MBP_OK;
+    const int32_t nb = static_cast<int32_t>(q->pending.size());
+    int rc = check_batches("mbp_queue_flush", q->ctx, nb, q->pending.data(), &q->params, nullptr);
+    if (rc != MBP_OK) return rc;
+    hipError_t e = hipSetDevice(q->ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    // one batched launch at a time: its blocks must all be resident together
+    if (!q->flights.empty() && (e = hipStreamWaitEvent(s, q->flights.back().done, 0)) != hipSuccess)
+        return hip_fail(e, "hipStreamWaitEvent");
+    mbp_queue::Flight f;
+    f.frames = q->pending_frames;
+    if ((e = hipMalloc(&f.ws, mbp::batched_workspace_bytes(nb, q->pending.data(), q->tuning))) != hipSuccess)
+        return hip_fail(e, "mbp_queue_flush: workspace");
+    if ((e = hipEventCreateWithFlags(&f.done, hipEventDisableTiming)) != hipSuccess) {
+        (void)hipFree(f.ws);
+        return hip_fail(e, "hipEventCreate");
+    }
+    rc = mbp::batched_launch(q->ctx, nb, q->pending.data(), &q->params, q->tuning, f.ws, s, &f.err_dev);
+    if (rc == MBP_OK && (e = hipEventRecord(f.done, s)) != hipSuccess) rc = hip_fail(e, "hipEventRecord");
+    if (rc != MBP_OK) {
+        (void)hipStreamSynchronize(s);
+        (void)hipEventDestroy(f.done);
+        (void)hipFree(f.ws);
+        return rc;
+    }
+    q->flights.push_back(f);
+    q->pending.clear();
+    q->pending_frames = 0;
+    return MBP_OK;
+}
+
+// Retire the completed flushes, oldest first (all of them, waiting, if `block`).
+static int queue_retire(mbp_queue *q, bool block) {
+    hipError_t e = hipSetDevice(q->ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    int rc = MBP_OK;
+    size_t k = 0;
+    for (; k < q->flights.size(); ++k) {
+        mbp_queue::Flight &f = q->flights[k];
+        e = block ? hipEventSynchronize(f.done) : hipEventQuery(f.done);
+        if (e == hipErrorNotReady) break;
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "queue completion");
+            break;
+        }
+        int32_t flag = 0;
+        if ((e = hipMemcpy(&flag, f.err_dev, sizeof(flag), hipMemcpyDeviceToHost)) != hipSuccess)
+            rc = hip_fail(e, "queue error flag");
+        else if (flag)
+            rc = fail(MBP_EDEVICE, "queue flush: a grid barrier timed out");
+        (void)hipEventDestroy(f.done);
+        (void)hipFree(f.ws);
+        q->done_frames += f.frames;
+        if (rc != MBP_OK) {
+            ++k;
+            break;
+        }
+    }
+    q->flights.erase(q->flights.begin(), q->flights.begin() + static_cast<std::ptrdiff_t>(k));
+    return rc;
+}
+
+int mbp_queue_poll(mbp_queue *q, int64_t *frames_done) {
+    if (!q || !frames_done) return fail(MBP_EINVAL, "mbp_queue_poll: null queue or output");
+    const int rc = queue_retire(q, false);
+    *frames_done = q->done_frames;
+    return rc;
+}
+
+int mbp_queue_wait(mbp_queue *q) {
+    if (!q) return fail(MBP_EINVAL, "mbp_queue_wait: queue is NULL");
+    return queue_retire(q, true);
+}
+
+void mbp_queue_destroy(mbp_queue *q) {
+    if (!q) return;
+    (void)queue_retire(q, true);
+    for (mbp_queue::Flight &f : q->flights) {  // left by an error: wait, then free
+        (void)hipEventSynchronize(f.done);
+        (void)hipEventDestroy(f.done);
+        (void)hipFree(f.ws);
+    }
+    mbp_ctx *ctx = q->ctx;
+    delete q;
+    if (--ctx->live_codes == 0 && ctx->closed) delete ctx;
+}
+
 // Text cache of autotuned settings: one line per batch mix,
 // "<key> <rows_per_wave> <vars_per_wave> <blocks_per_cu> <schedule> <compact> <ms>".
 static std::string tune_key(int32_t nb, const mbp_batch *b, const mbp_params *p) {

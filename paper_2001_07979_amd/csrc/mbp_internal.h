@@ -49,11 +49,30 @@ struct mbp_ctx {
     int32_t profiling = 0;  // bit k: time launches of kernel id k
     mbp::KernelStat stats[mbp::kNumKernels];
     std::vector<hipEvent_t> timing_events;
-    int32_t live_codes = 0;  // codes and plans of the context not yet destroyed
+    int32_t live_codes = 0;  // codes, plans and queues of the context not yet destroyed
     // set by mbp_ctx_destroy while codes or plans of the context are still
     // alive: the GPU resources are gone and the last of their destroy calls
     // frees the struct
     bool closed = false;
+};
+
+// A serving queue: frames submitted as batches wait until a flush decodes
+// everything pending in one batched launch; each flush owns its workspace and
+// an event until poll or wait sees it complete.
+struct mbp_queue {
+    mbp_ctx *ctx = nullptr;
+    mbp_params params{};
+    mbp_tuning tuning{};
+    std::vector<mbp_batch> pending;
+    int64_t pending_frames = 0;
+    struct Flight {
+        void *ws = nullptr;
+        hipEvent_t done = nullptr;
+        int32_t *err_dev = nullptr;
+        int64_t frames = 0;
+    };
+    std::vector<Flight> flights;  // oldest first
+    int64_t done_frames = 0;
 };
 
 struct mbp_plan {
@@ -108,6 +127,11 @@ int check_tuning(const mbp_tuning &tu);
 uint64_t batched_workspace_bytes(int32_t nb, const mbp_batch *b, const mbp_tuning &tu);
 int batched_decode(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_params *p, const mbp_tuning &tu,
                    hipStream_t stream);
+// Uploads the descriptors into ws (a workspace of batched_workspace_bytes)
+// and enqueues the whole batched decode on stream, without waiting; *err_dev
+// receives the grid-barrier error flag's address in ws (nonzero: timed out).
+int batched_launch(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_params *p, const mbp_tuning &tu,
+                   void *ws, hipStream_t stream, int32_t **err_dev);
 int batched_plan_capture(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_params *p, const mbp_tuning &tu,
                          void *ws, hipGraphExec_t *exec, int32_t **err_dev);
 

@@ -95,6 +95,13 @@ def lib():
             "mbp_plan_launch": (ctypes.c_int, [vp, vp]),
             "mbp_plan_wait": (ctypes.c_int, [vp, vp]),
             "mbp_plan_destroy": (None, [vp]),
+            "mbp_queue_create": (ctypes.c_int, [vp, ctypes.POINTER(mbp_params), ctypes.POINTER(mbp_tuning),
+                                                ctypes.POINTER(vp)]),
+            "mbp_queue_submit": (ctypes.c_int, [vp, i32, ctypes.POINTER(mbp_batch)]),
+            "mbp_queue_flush": (ctypes.c_int, [vp, vp]),
+            "mbp_queue_poll": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
+            "mbp_queue_wait": (ctypes.c_int, [vp]),
+            "mbp_queue_destroy": (None, [vp]),
             "mbp_autotune": (ctypes.c_int, [vp, i32, ctypes.POINTER(mbp_batch),
                                             ctypes.POINTER(mbp_params), ctypes.c_char_p,
                                             ctypes.POINTER(mbp_tuning)]),
@@ -509,6 +516,62 @@ class Plan:
         if self.handle:
             lib().mbp_plan_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Queue:
+    """Serving queue over the batched decode (mbp_queue_*): submit batches of
+    frames as they arrive, flush to decode everything pending in one batched
+    launch, poll for the frames done. Submitted tensors must stay alive until
+    their flush completes; the queue keeps references to them until then."""
+
+    def __init__(self, ctx: Context, max_iter: int = 100, early_exit: bool = True, alpha: float = 0.75,
+                 clip: float = 20.0, tuning=None):
+        p = _nms_params(max_iter, early_exit, alpha, clip)
+        tu = _tuning(tuning)
+        h = ctypes.c_void_p()
+        _check(lib().mbp_queue_create(ctx.handle, ctypes.byref(p), ctypes.byref(tu) if tu is not None else None,
+                                      ctypes.byref(h)), "mbp_queue_create")
+        self.handle = h
+        self._pending, self._flights, self._done = [], [], 0
+
+    def submit(self, items, outs):
+        """items: [(Code, llr [F, n] f32, synd [F, M] u8)], outs: batch_outputs(...) per item."""
+        arr = _batches(items, outs)
+        _check(lib().mbp_queue_submit(self.handle, len(items), arr), "mbp_queue_submit")
+        self._pending.append((items, outs, sum(int(llr.shape[0]) for _, llr, _ in items)))
+
+    def flush(self, stream=None):
+        _check(lib().mbp_queue_flush(self.handle, _stream_ptr(stream)), "mbp_queue_flush")
+        if self._pending:
+            self._flights.append(self._pending)
+            self._pending = []
+
+    def _release(self, done: int):
+        # drop the references of flushes whose frames are all done
+        while self._flights and done - self._done >= sum(f for _, _, f in self._flights[0]):
+            self._done += sum(f for _, _, f in self._flights.pop(0))
+
+    def poll(self) -> int:
+        n = ctypes.c_int64()
+        _check(lib().mbp_queue_poll(self.handle, ctypes.byref(n)), "mbp_queue_poll")
+        self._release(int(n.value))
+        return int(n.value)
+
+    def wait(self):
+        _check(lib().mbp_queue_wait(self.handle), "mbp_queue_wait")
+        return self.poll()
+
+    def close(self):
+        if self.handle:
+            lib().mbp_queue_destroy(self.handle)
+            self.handle = None
+            self._flights = []
 
     def __del__(self):
         try:

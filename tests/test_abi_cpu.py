@@ -49,6 +49,10 @@ def test_version_and_error_paths_without_device():
     assert L.mbp_decode_from_bits(None, None, ctypes.byref(p), 1, *([None] * 8)) == mbp.MBP_EINVAL
     assert "mbp_decode_from_bits" in mbp.last_error()
     assert L.mbp_syndrome(None, None, 1, None, None, None) == mbp.MBP_EINVAL
+    qh = ctypes.c_void_p()
+    assert L.mbp_queue_create(None, ctypes.byref(p), None, ctypes.byref(qh)) == mbp.MBP_EINVAL
+    assert L.mbp_queue_submit(None, 1, None) == mbp.MBP_EINVAL
+    L.mbp_queue_destroy(None)
     n, ms = ctypes.c_int64(), ctypes.c_double()
     assert L.mbp_profile_get(None, 0, ctypes.byref(n), ctypes.byref(ms)) == mbp.MBP_EINVAL
     L.mbp_ctx_destroy(None)

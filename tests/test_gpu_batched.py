@@ -214,3 +214,31 @@ def test_batched_rejects_sum_product(ctx, mix):
     p = mbp.mbp_params(mbp.MBP_ALGO_SPA, mbp.MBP_F32, 10, 1, 0.75, 20.0)
     rc = mbp.lib().mbp_decode_batched(ctx.handle, len(items), arr, ctypes.byref(p), None, None)
     assert rc == mbp.MBP_EUNSUPPORTED
+
+
+def test_queue_matches_batched_decode(ctx, mix):
+    """Frames submitted to the serving queue in two submits and flushes (and
+    an empty flush) decode exactly as the batched call; poll reaches the
+    frame count, wait returns it."""
+    import time
+    from paper_2001_07979_amd import mbp
+    items, _ = mix
+    ref = [_np(o) for o in mbp.decode_batched(ctx, items, max_iter=60)]
+    q = mbp.Queue(ctx, max_iter=60)
+    assert q.poll() == 0
+    outs = [mbp.batch_outputs(dc, llr) for dc, llr, _ in items]
+    q.submit(items[:1], outs[:1])
+    q.flush()
+    q.submit(items[1:], outs[1:])
+    q.flush()
+    q.flush()  # nothing pending
+    total = sum(int(llr.shape[0]) for _, llr, _ in items)
+    t0 = time.time()
+    while q.poll() < total and time.time() - t0 < 60:
+        time.sleep(0.001)
+    assert q.wait() == total
+    for a, b in zip([_np(o) for o in outs], ref):
+        _same(a, b)
+    q.close()
+    with pytest.raises(mbp.MbpError):
+        mbp.Queue(ctx, max_iter=0)
