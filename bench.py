@@ -43,10 +43,10 @@ def source_hash() -> str:
     return h.hexdigest()[:12]
 
 
-def stored_traffic(algo: str, schedule: str):
-    """HBM bytes per check-node launch from the committed rocprofv3 counter
-    summary of the same algorithm and schedule, if it was taken on the
-    current kernel sources."""
+def stored_traffic(algo: str, schedule: str, kernel: str = "check"):
+    """HBM bytes per launch of the check-node (or variable-node) pass from the
+    committed rocprofv3 counter summary of the same algorithm and schedule,
+    if it was taken on the current kernel sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -57,7 +57,9 @@ def stored_traffic(algo: str, schedule: str):
     if vals.get("kernel_source_sha1") != source_hash():
         return None
     try:
-        return float(vals[f"hbm_bytes_per_launch_{algo}_{schedule}"])
+        key = f"hbm_bytes_per_launch_{algo}_{schedule}" if kernel == "check" else \
+            f"hbm_bytes_per_{kernel}_launch_{algo}_{schedule}"
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
 
@@ -479,12 +481,23 @@ def main():
         del src, dst
 
     log(f"bench: warmup {args.warmup}")
-    for _ in range(args.warmup):
+    profile = not args.no_profile
+    # the last warmup step times both iteration kernels, to find the one with
+    # the larger share of the step (the dominant kernel)
+    dominant = "check"
+    for w in range(args.warmup):
+        if profile and w == args.warmup - 1:
+            ctx.profile_reset()
+            ctx.profile_enable(True, kernels=["check", "variable"])
         step()
     torch.cuda.synchronize()
-    profile = not args.no_profile
+    if profile and args.warmup:
+        ctx.profile_enable(False)
+        dominant = "check" if ctx.profile_get("check")[1] >= ctx.profile_get("variable")[1] else "variable"
+    other_kernel = "variable" if dominant == "check" else "check"
     ctx.profile_reset()
-    ctx.profile_enable(profile, kernels=["check"])  # events around the dominant kernel only
+    # events around the dominant kernel only, to disturb the timed region least
+    ctx.profile_enable(profile, kernels=[dominant])
     log(f"bench: timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -495,6 +508,13 @@ def main():
     ctx.profile_enable(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     mbps = F * n / ((t1 - t0) / args.steps) / 1e6
+    if profile:
+        # the other iteration kernel, timed over the same number of steps after the timed region
+        ctx.profile_enable(True, kernels=[other_kernel])
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ctx.profile_enable(False)
 
     iters = out["iters"].cpu().numpy()
     ok = out["ok"].cpu().numpy()
@@ -519,37 +539,52 @@ def main():
     h = -p * log2(p) - (1 - p) * log2(1 - p)
     m = code.m[0]
 
-    roofline = None
+    roofline = roofline_other = None
     if profile:
-        n_c, ms_c = ctx.profile_get("check")
-        # algorithmic bytes of the check-node passes, per frame and
-        # iteration it runs: every pass reads L (n; the first pass of the
-        # first iteration reads lambda as one bit per variable) and writes c
-        # (E over the passes); from t = 2 it reads the old c (E), which
-        # min-sum with a compressed check state replaces by reading and
-        # writing 3 words per check
         s = 4
-        phases = code.u if args.schedule == "serial" else 1
+        u = code.u
+        serial = args.schedule == "serial"
+        phases = u if serial else 1
         cst = wl.algo == "nms" and max(int(np.diff(rp).max()) for rp in code.row_ptr) <= 24
         old = 2 * 3 * s * code.M if cst else s * E
-        per_step = 0
+        stored = serial and 1 < u <= 4  # serial passes keep each matrix's sum per variable
+        chk = vn = 0
         for t in range(1, int(iters.max()) + 1):
             full = int((iters >= t).sum())
+            # check-node passes, per frame: every pass reads L (n; the first
+            # pass of the first iteration reads lambda as one bit per
+            # variable) and writes c (E over the passes); from t = 2 they
+            # read the old c (E), which min-sum with a compressed check
+            # state replaces by reading and writing 3 words per check
             if t == 1:
-                per_frame = s * E + n / 8 + s * n * (phases - 1) + (3 * s * code.M if cst else 0)
+                chk += full * (s * E + n / 8 + s * n * (phases - 1) + (3 * s * code.M if cst else 0))
             else:
-                per_frame = s * E + old + s * n * phases
-            per_step += full * per_frame
-        launches_per_step = n_c / args.steps
-        bytes_per_launch = per_step / launches_per_step
-        avg_ms = ms_c / n_c
-        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        traffic = stored_traffic(wl.algo, args.schedule)
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": traffic, "kernel": "k_check (check-node pass)",
-                    "avg_launch_ms": round(avg_ms, 5), "launches": n_c,
-                    "algorithmic_bytes_per_launch": int(bytes_per_launch)}
+                chk += full * (s * E + old + s * n * phases)
+            # variable-node passes, per frame: read the messages (E over the
+            # passes) and lambda's bit words, write L and the decision words;
+            # serial passes with stored sums also write their matrix's sum
+            # and read the others' (only the matrices visited so far at t = 1)
+            if stored:
+                others = sum(l if t == 1 else u - 1 for l in range(u))
+                vn += full * (s * E + u * n / 8 + s * n * (2 * u + others) + n / 8)
+            else:
+                vn += full * (phases * (s * E + n / 8 + s * n) + n / 8)
+
+        def line(which, per_step, kernel):
+            n_k, ms_k = ctx.profile_get(which)
+            per_launch = per_step / (n_k / args.steps)
+            avg_ms = ms_k / n_k
+            achieved = per_launch / (avg_ms * 1e-3) / 1e9
+            return ms_k, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                          "traffic": stored_traffic(wl.algo, args.schedule, which), "kernel": kernel,
+                          "avg_launch_ms": round(avg_ms, 5), "launches": n_k,
+                          "algorithmic_bytes_per_launch": int(per_launch)}
+
+        _, r_chk = line("check", chk, "k_check (check-node pass)")
+        _, r_vn = line("variable", vn, "k_variable_phase (variable-node pass)" if stored
+                       else "k_variable (variable-node pass)")
+        roofline, roofline_other = (r_chk, r_vn) if dominant == "check" else (r_vn, r_chk)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -608,7 +643,7 @@ def main():
         "avg_iters": float(iters.mean()), "max_iters": int(iters.max()),
         "f": round(m / (n * h), 4), "f_leak": round(code.u * m / (n * h), 4),
         "llr_rows_then_decode": two_calls,
-        "roofline": roofline, "cpu_baseline": cpu, "qualifying_point": qual, "other_schedule": other, "alice_syndromes": alice,
+        "roofline": roofline, "roofline_other_kernel": roofline_other, "cpu_baseline": cpu, "qualifying_point": qual, "other_schedule": other, "alice_syndromes": alice,
         "unrolled_training_step": unrolled,
         "batched_vs_plain": batched,
     }
