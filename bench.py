@@ -2,13 +2,15 @@
 
 One step is one pass of the whole hot path over one batch of frames whose
 inputs (Bob's bits, the per-frame error rates, Alice's syndromes) are already
-resident in HBM: channel LLRs (eq. (5)), staging, the flooding iterations
-with the per-frame stopping test, and the decided bits, iteration counts,
-success flags and soft decisions written back to HBM.
+resident in HBM: channel LLRs (eq. (5), formed inside the decoder), staging,
+the iterations of Algorithm 1 (matrix-serial by default, flooding with
+--schedule flooding) with the per-frame stopping test, and the decided bits,
+iteration counts, success flags and soft decisions written back to HBM.
 
 Prints one JSON line: reconciled Mbps (frames x n bits per second), the
-roofline of the dominant kernel (the check-node pass) from HIP events on the
-decode stream, and the FP64 CPU oracle timed on the host cores.
+roofline of the step's dominant kernel and of the other iteration kernel
+from HIP events on the decode stream, and the FP64 CPU oracle timed on the
+host cores.
 """
 from __future__ import annotations
 

@@ -133,21 +133,27 @@ def test_from_bits_rejects_bad_arguments(ctx, codes):
     assert rc == mbp.MBP_EINVAL
 
 
+@pytest.mark.parametrize("schedule", ["serial", "flooding"])
 @pytest.mark.parametrize("algo", ["spa", "nms"])
-def test_from_bits_n65536_full_batch(ctx, algo):
-    """The benchmarked workload: every output equals the LLR path; sampled
+def test_from_bits_n65536_full_batch(ctx, algo, schedule):
+    """The benchmarked workload and step (from Bob's bits; the bench times
+    the matrix-serial schedule): every output equals the LLR path; sampled
     frames against the oracle under the parity protocol (min-sum bit for bit
     against its binary32 decode)."""
     from paper_2001_07979_amd import mbp
     wl = W.qkd_n65536(algo=algo)
     fr = wl.frames()
     dc = mbp.Code.from_inputs(ctx, wl.code)
-    a, b = _both(ctx, dc, fr, algo=algo, max_iter=wl.max_iter, alpha=wl.alpha)
+    a, b = _both(ctx, dc, fr, algo=algo, max_iter=wl.max_iter, alpha=wl.alpha, schedule=schedule)
     _same(a, b)
     g = dict(bits=a["bits"], iters=a["iters"], ok=a["ok"], L=a["llr"].astype(np.float64))
     idx = np.array([0, 5, 64, 130, 255])
-    o = parity.oracle_run(wl.code, fr, algo, "f32", wl.max_iter, alpha=wl.alpha, idx=idx)
-    parity.compare(g, o, wl.max_iter, 1e-4, idx=idx, atol=parity.ATOL32)
     if algo == "nms":
-        parity.assert_bitwise(g, parity.oracle_f32_run(wl.code, fr, wl.max_iter, idx=idx), idx=idx)
-    assert a["ok"].mean() > 0.99
+        parity.assert_bitwise(g, parity.oracle_f32_run(wl.code, fr, wl.max_iter, idx=idx, schedule=schedule),
+                              idx=idx)
+    o = parity.oracle_run(wl.code, fr, algo, "f32", wl.max_iter, alpha=wl.alpha, idx=idx, schedule=schedule)
+    parity.compare(g, o, wl.max_iter, 1e-4, idx=idx, atol=parity.ATOL32,
+                   long_rtol=None if algo == "nms" else 1e-2,
+                   long_after=parity.LONG_AFTER // (wl.code.u if schedule == "serial" else 1))
+    okf = a["ok"] == 1
+    assert okf.mean() > 0.99 and np.array_equal(a["bits"][okf], fr.x[okf])
