@@ -187,8 +187,10 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
                                  static_cast<int64_t>(ngroups) * dvs.ntiles);
     const int grid_v = grid_for(ctx, reinterpret_cast<const void *>(kv),
                                 static_cast<int64_t>(ngroups) * dv.ntiles);
-    const int grid_s = grid_for(ctx, reinterpret_cast<const void *>(&k_stop_test),
-                                static_cast<int64_t>(ntot) * ds.ntiles);
+    // one block per CU at most: the test is short, and every block meets the
+    // others at the last-block counter (a fence and an atomic on one word)
+    const int grid_s = std::min(ctx->num_cus, grid_for(ctx, reinterpret_cast<const void *>(&k_stop_test),
+                                                       static_cast<int64_t>(ntot) * ds.ntiles));
     const int grid_m = grid_for(ctx, reinterpret_cast<const void *>(&k_move<T>),
                                 static_cast<int64_t>(std::max(nspare, 1)) * (E + 2 * n + M) / kMoveRows);
 
