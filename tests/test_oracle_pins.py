@@ -463,8 +463,17 @@ def test_unrolled_binary32_gradient_single_check_closed_form():
 
 
 def test_unrolled_binary32_gradient_matches_its_finite_differences():
-    """Central differences of the binary32 forward itself (step 1e-2, where
-    float rounding of J is far below the step's change) on smooth coordinates."""
+    """The FP64 reverse sweep of the binary32 trajectory against central
+    differences (step 1e-2) on coordinates where the map is linear across the
+    step (R15: the minima, signs and caps are those of the float messages).
+
+    On these tie-free inputs the binary32 and FP64 trajectories take the same
+    minima and signs, so the gradient must equal the central difference of the
+    FP64 forward to FP64 rounding (1e-7 relative). Against the binary32
+    forward's own central difference the deviation is bounded by the rounding
+    of J at the two ends: FD32 - FD64 = ((J32 - J64)(x + eps) - (J32 - J64)(x - eps)) / (2 eps),
+    so |g - FD32| <= |g - FD64| + (|n+| + |n-|) / (2 eps) with n = J32 - J64
+    measured at each end (about 2e-5 here, i.e. ~2e-3 after the division)."""
     code = peg_code(48, 24, 2, {3: 1.0}, seed_base=9100)
     fr = bsc_frames(code, 2, 0.08, seed=41)
     lam = oracle.llr_from_bits(fr.y, fr.p)
@@ -474,8 +483,8 @@ def test_unrolled_binary32_gradient_matches_its_finite_differences():
     lam = lam * rng.uniform(0.7, 1.3, size=lam.shape)
     w = rng.normal(size=lam.shape)
 
-    def J_of_lam(l):
-        return float((oracle.nms_unrolled(code, K, alpha, l, fr.z, binary32=True) * w).sum())
+    def J(l, b32):
+        return float((oracle.nms_unrolled(code, K, alpha, l, fr.z, binary32=b32) * w).sum())
 
     _, glam, _ = oracle.nms_unrolled(code, K, alpha, lam, fr.z, gL=w, binary32=True)
     eps = 1e-2
@@ -484,15 +493,18 @@ def test_unrolled_binary32_gradient_matches_its_finite_differences():
         xp, xm = lam.copy(), lam.copy()
         xp.flat[i] += eps
         xm.flat[i] -= eps
-        fp, f0, fm = J_of_lam(xp), J_of_lam(lam), J_of_lam(xm)
-        right, left = (fp - f0) / eps, (f0 - fm) / eps
-        if abs(right - left) <= 1e-3 * (1 + abs(right)):
-            # each binary32 L (|L| up to ~30) carries about one ulp (2^-19)
-            # of rounding, so J over 96 entries with unit weights is noisy to
-            # ~2e-5, and the central difference over 2 eps = 0.02 to ~1.5e-3
-            # (more where the rounding of a step's two ends happens to differ)
-            assert glam.flat[i] == pytest.approx(0.5 * (right + left), rel=1e-3, abs=4e-3)
-            checked += 1
+        fp, f0, fm = J(xp, True), J(lam, True), J(xm, True)
+        gp, g0, gm = J(xp, False), J(lam, False), J(xm, False)
+        r64, l64 = (gp - g0) / eps, (g0 - gm) / eps
+        if abs(r64 - l64) > 1e-9 * (1 + abs(r64)):
+            continue  # a minimum, sign or cap changes within the step
+        g = glam.flat[i]
+        fd64 = 0.5 * (r64 + l64)
+        assert g == pytest.approx(fd64, rel=1e-7, abs=1e-9)
+        fd32 = (fp - fm) / (2 * eps)
+        bound = abs(g - fd64) + (abs(fp - gp) + abs(fm - gm)) / (2 * eps)
+        assert abs(g - fd32) <= bound * (1 + 1e-9) + 1e-12
+        checked += 1
     assert checked >= 15
 
 
@@ -594,3 +606,140 @@ def test_syndrome_is_linear_and_agrees_with_the_residual_weight(small_peg):
     assert np.array_equal(oracle.syndrome(small_peg, x ^ y), zx ^ zy)
     assert not oracle.syndrome(small_peg, np.zeros_like(x)).any()
     assert np.array_equal(oracle.unsatisfied(small_peg, x, zy), (zx != zy).sum(axis=1))
+
+
+# --------------------------------------- binary32 rounding order (R16, R12)
+def _nms_f32_by_hand(Hs, lam, z, alpha, T, C=20.0, nested=True, alpha_in_double=False):
+    """T flooding min-sum iterations written out in numpy float32 for a tiny
+    code: q = L - c; |q| capped at C; c = (-1)^z * alpha * prod sgn * min over
+    the other edges; eq. (2) either with its nesting (each matrix's messages
+    summed from 0 in check order, those sums added to lambda in matrix order)
+    or flattened (every message added to lambda in turn). alpha_in_double
+    forms alpha * min from the FP64 weight and rounds once, the mistake of
+    not rounding the weight to binary32 first."""
+    f32 = np.float32
+    rows = [(l, np.nonzero(h)[0]) for l, H in enumerate(Hs) for h in H]
+    lam = lam.astype(f32)
+    c = [np.zeros(len(r), f32) for _, r in rows]
+    L = lam.copy()
+    for _ in range(T):
+        q = [L[r] - c[k] for k, (_, r) in enumerate(rows)]
+        new = []
+        for k, (_, r) in enumerate(rows):
+            out = np.zeros(len(r), f32)
+            for j in range(len(r)):
+                others = [q[k][jj] for jj in range(len(r)) if jj != j]
+                sg = f32(np.prod([f32(-1) if x < 0 else f32(1) for x in others]))
+                mn = min(min(abs(x), f32(C)) for x in others)
+                zs = f32(-1) if z[k] else f32(1)
+                out[j] = f32(float(zs) * alpha * float(sg) * float(mn)) if alpha_in_double else \
+                    zs * f32(alpha) * sg * mn
+            new.append(out)
+        c = new
+        L = np.zeros_like(lam)
+        for i in range(lam.size):
+            msgs = [(l, c[k][j]) for k, (l, r) in enumerate(rows) for j, v in enumerate(r) if v == i]
+            s = lam[i]
+            if nested:
+                for l in range(len(Hs)):
+                    part = [x for m, x in msgs if m == l]
+                    if part:
+                        S = f32(0)
+                        for x in part:
+                            S = f32(S + x)
+                        s = f32(s + S)
+            else:
+                for _, x in msgs:
+                    s = f32(s + x)
+            L[i] = s
+    return L
+
+
+def test_nms_f32_nesting_and_weight_rounding():
+    """Non-dyadic binary32 min-sum on a u = 2 code where variable 0 has two
+    messages from H_1 and one from H_2 (unequal per-matrix counts), alpha =
+    0.7 (not a binary32 value). The oracle must give, bit for bit, the values
+    of eq. (2) with its nesting and alpha rounded to binary32 (R12, R16) at
+    T = 1, 2, 3; the inputs are chosen so that summing the messages flattened,
+    or forming alpha * min from the FP64 weight, gives different bits."""
+    Hs = [np.array([[1, 1, 0, 0], [1, 0, 1, 0]]), np.array([[1, 0, 1, 1]])]
+    code = code_from_dense(Hs)
+    lam = np.array([-1.7725950479507446, -1.961043357849121, -0.43938955664634705, 0.036386072635650635])
+    z = np.array([1, 1, 1], np.uint8)
+    for T in (1, 2, 3):
+        want = _nms_f32_by_hand(Hs, lam, z, 0.7, T)
+        got = oracle.decode_nms_f32(code, lam[None], z[None], max_iter=T, early_exit=False, alpha=0.7)["L"][0]
+        assert got.tolist() == want.astype(np.float64).tolist(), T
+        if T <= 2:  # the example discriminates both mistakes
+            assert not np.array_equal(want, _nms_f32_by_hand(Hs, lam, z, 0.7, T, nested=False))
+            assert not np.array_equal(want, _nms_f32_by_hand(Hs, lam, z, 0.7, T, alpha_in_double=True))
+    # the binary32 unrolled forward rounds the same way
+    L = oracle.nms_unrolled(code, 2, np.full((2, 2), 0.7), lam[None], z[None], binary32=True)[0]
+    assert L.tolist() == _nms_f32_by_hand(Hs, lam, z, 0.7, 2).astype(np.float64).tolist()
+
+
+# ------------------------------------------------------------ near-tie flag
+def test_tie_flag_hand_cases():
+    """The near-tie flag on hand-worked frames (golden file): condition 1 (a
+    soft decision within delta of 0 when the frame stops), condition 2 (an
+    earlier iteration whose small soft decisions touch at least as many checks
+    as are unmet), and two frames that must not be flagged."""
+    G = json.load(open(GOLDEN))
+    t = G["tie_flag_final"]
+    code = code_from_dense([np.array(h) for h in t["H"]])
+    z = np.array([t["z"]], np.uint8)
+    kw = dict(algo=oracle.NMS, alpha=1.0, max_iter=5, clip=1e3)
+    r = _dec(code, np.array([t["lambda"]]), z, **kw)
+    assert (r["ok"][0], r["iters"][0], r["flag"][0]) == (t["ok"], t["iters"], t["flag"])
+    np.testing.assert_allclose(r["L"][0], t["L2"], atol=1e-12)
+    r = _dec(code, np.array([t["lambda_unflagged"]]), z, **kw)
+    assert (r["ok"][0], r["iters"][0], r["flag"][0]) == (1, 2, 0)
+    r = _dec(code, np.array([t["lambda_final"]]), z, **kw)
+    assert (r["ok"][0], r["iters"][0], r["flag"][0]) == (t["ok_final"], t["iters_final"], t["flag_final"])
+    np.testing.assert_allclose(r["L"][0], t["L_final"], atol=1e-12)
+    n = G["tie_flag_too_many_unmet"]
+    code = code_from_dense([np.array(h) for h in n["H"]])
+    r = _dec(code, np.array([n["lambda"]]), np.array([n["z"]], np.uint8), **kw)
+    assert (r["ok"][0], r["iters"][0], r["flag"][0]) == (n["ok"], n["iters"], n["flag"])
+    r1 = _dec(code, np.array([n["lambda"]]), np.array([n["z"]], np.uint8), algo=oracle.NMS, alpha=1.0,
+              max_iter=1, early_exit=False, clip=1e3)
+    np.testing.assert_allclose(r1["L"][0], n["L1"], atol=1e-12)
+
+
+@pytest.mark.parametrize("algo", [oracle.SPA, oracle.NMS])
+def test_tie_flag_follows_its_definition(algo):
+    """The flag recomputed from its definition with a dense H and the
+    trajectory L^1, L^2, ... (the decoder is deterministic, so a run with
+    T = t and no early exit gives L^t): flag = (some |L^{t*}_i| < delta at the
+    last iteration) or (for an iteration t before the stop, or any t of a
+    failed frame, S_t = {i : |L^t_i| < delta} is not empty and the residual
+    syndrome weight is at most the summed degree of S_t). A large delta makes
+    every kind of frame occur: flagged by either condition alone or both,
+    not flagged, and not flagged although S_t was non-empty (too many unmet
+    checks)."""
+    code = peg_code(96, 48, 2, {2: 0.25, 3: 0.45, 8: 0.30}, seed_base=9300, name="flagpins")
+    H = code.dense().astype(np.int64)
+    deg = H.sum(0)
+    fr = bsc_frames(code, 40, 0.1, seed=5)
+    lam = oracle.llr_from_bits(fr.y, fr.p)
+    T, delta = 12, 0.5
+    full = oracle.decode(code, lam, fr.z, algo=algo, max_iter=T, margin=delta)
+    traj = [oracle.decode(code, lam, fr.z, algo=algo, max_iter=t, early_exit=False)["L"] for t in range(1, T + 1)]
+    kinds = set()
+    for f in range(lam.shape[0]):
+        ok, last = int(full["ok"][f]), int(full["iters"][f])
+        c1 = c2 = c2_rejected = False
+        for t in range(1, last + 1):
+            Lt = traj[t - 1][f]
+            S = np.abs(Lt) < delta
+            w = int((((H @ (Lt < 0).astype(np.int64)) % 2) != fr.z[f]).sum())
+            if t == last:
+                c1 = bool(S.any())
+            if (t < last or not ok) and w > 0 and S.any():
+                if w <= deg[S].sum():
+                    c2 = True
+                else:
+                    c2_rejected = True
+        assert int(full["flag"][f]) == int(c1 or c2), f
+        kinds.add((c1, c2, c2_rejected and not (c1 or c2)))
+    assert {(True, False, False), (False, True, False), (False, False, False)} <= kinds, kinds
