@@ -1,16 +1,22 @@
 """Benchmark of the multi-matrix syndrome BP decoder on one MI355X.
 
-One step is one pass of the whole hot path over one batch of frames whose
-inputs (Bob's bits, the per-frame error rates, Alice's syndromes) are already
-resident in HBM: channel LLRs (eq. (5), formed inside the decoder), staging,
-the iterations of Algorithm 1 (matrix-serial by default, flooding with
---schedule flooding) with the per-frame stopping test, and the decided bits,
-iteration counts, success flags and soft decisions written back to HBM.
+The timed workload is the operating point that meets efficiency f <= 1.1
+(Sec. 2, eqs. (3)-(4)): u = 3 PEG matrices with variable degrees {2, 3, 10},
+n = 2^18, rate 0.85 (m = 39322 per matrix), BSC 0.02 (f = 1.061), 1024 frames,
+FP32 sum-product with the flooding schedule, T = 100, early exit.
 
-Prints one JSON line: reconciled Mbps (frames x n bits per second), the
-roofline of the step's dominant kernel and of the other iteration kernel
-from HIP events on the decode stream, and the FP64 CPU oracle timed on the
-host cores.
+One step is one pass of the whole hot path over the batch, with its inputs
+(Bob's bits, the per-frame error rates, Alice's syndromes) already resident in
+HBM: channel LLRs (eq. (5), formed inside the decoder), staging, the
+iterations of Algorithm 1 with the per-frame stopping test, and the decided
+bits, iteration counts, success flags and soft decisions written back to HBM.
+
+Prints one JSON line: reconciled Mbps (frames x n bits per second) with the
+batch's frame-error rate, the roofline of the step's dominant kernel and of
+the other iteration kernel from HIP events on the decode stream, the FP64 CPU
+oracle timed on a bounded sample of the same frames, and further
+measurements (the other schedule, the n = 65536 workload, Alice's syndromes,
+the unrolled training step, batched against plain decoding of a mixed queue).
 """
 from __future__ import annotations
 
@@ -129,6 +135,8 @@ def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_
     res_b = [{k: v.cpu() for k, v in o.items()} for o in outs_b]
     if batched_only:
         plan.close()
+        for P in pool.values():
+            P["dc"].close()
         return {"frames": nframes, "bits": total_bits, "tuning": tune,
                 "batched_mbps": round(total_bits / t_batched / 1e6, 1)}
 
@@ -235,6 +243,8 @@ def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_
     log("bench: online plain per-frame")
     lat_p = serve_plain()
     plan.close()
+    for P in pool.values():
+        P["dc"].close()
 
     def pct(a):
         return {"p50_ms": round(float(np.percentile(a, 50)) * 1e3, 3),
@@ -259,57 +269,46 @@ def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_
     }
 
 
-def qualifying_point(ctx, steps: int, algo: str, schedule: str):
-    """The operating point that meets f <= 1.1: u=3 {2,3,10} PEG matrices,
-    n=2^18, rate 0.85, BSC 0.02 (f = 1.061), 64 frames, decoded like the main
-    workload (decoded from Bob's bits and error rates per step, inputs resident)."""
+def n65536_point(ctx, steps: int, algo: str):
+    """The u=2 n=65536 rate-3/4 workload (256 frames, BSC 0.02, f = 1.77) under
+    both schedules, decoded from Bob's bits like the headline step."""
     import torch
     from paper_2001_07979_amd import mbp
     from paper_2001_07979_amd.inputs import workloads as W
 
-    wl = W.qkd_n262144(0.85, nframes=64, algo=algo)
+    wl = W.qkd_n65536(nframes=256, algo=algo)
     fr = wl.frames()
     code = wl.code
-    dev = torch.device("cuda", 0)
-    dcode = mbp.Code.from_inputs(ctx, code)
-    y = torch.from_numpy(fr.y).to(dev)
-    e = torch.from_numpy(fr.p).to(dev)
-    z = torch.from_numpy(fr.z).to(dev)
-
-    def step(sched):
-        return mbp.decode_from_bits(ctx, dcode, y, e, z, dtype="f32", algo=wl.algo, max_iter=wl.max_iter,
-                                    alpha=wl.alpha, clip=wl.clip, schedule=sched)
-
-    def timed(sched):
-        step(sched)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            o = step(sched)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps, o
-
-    other = "flooding" if schedule == "serial" else "serial"
-    dt_other, out_other = timed(other)
-    dt, out = timed(schedule)
-    bits = out["bits"].cpu().numpy()
-    fer = float(np.any(bits != fr.x, axis=1).mean())
-    m = code.m[0]
-    return {"workload": wl.name, "schedule": schedule, "frames": fr.nframes,
-            "mbps": round(fr.nframes * code.n / dt / 1e6, 1),
-            "ms_per_step": round(dt * 1e3, 4), "fer": fer, "f": round(m / (code.n * float(h2(0.02))), 4),
-            "f_leak": round(code.u * m / (code.n * float(h2(0.02))), 4),
-            "avg_iters": float(out["iters"].float().mean().item()),
-            "other_schedule": {"schedule": other, "mbps": round(fr.nframes * code.n / dt_other / 1e6, 1),
-                               "avg_iters": float(out_other["iters"].float().mean().item())},
-            "note": "FER from these frames only; 64 frames bound FER below about 4.7% (rule of three)"}
+    dev = torch.device("cuda", ctx.device)
+    res = {"workload": wl.name, "frames": fr.nframes,
+           "f": round(code.m[0] / (code.n * float(h2(0.02))), 4)}
+    with mbp.Code.from_inputs(ctx, code) as dcode:
+        y = torch.from_numpy(fr.y).to(dev)
+        e = torch.from_numpy(fr.p).to(dev)
+        z = torch.from_numpy(fr.z).to(dev)
+        for sched in ("serial", "flooding"):
+            def step():
+                return mbp.decode_from_bits(ctx, dcode, y, e, z, dtype="f32", algo=wl.algo,
+                                            max_iter=wl.max_iter, alpha=wl.alpha, clip=wl.clip,
+                                            schedule=sched)
+            step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                out = step()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            bits = out["bits"].cpu().numpy()
+            res[sched] = {"mbps": round(fr.nframes * code.n / dt / 1e6, 1), "ms_per_step": round(dt * 1e3, 4),
+                          "fer": float(np.any(bits != fr.x, axis=1).mean()),
+                          "avg_iters": float(out["iters"].float().mean().item())}
+    return res
 
 
 def other_schedule(ctx, wl, fr, dcode, y, e, z, steps: int, schedule: str):
-    """The main workload decoded with the other schedule: flooding (every
-    matrix's checks from the previous iteration's messages, one variable pass
-    per iteration) beside the matrix-serial schedule of Algorithm 1 (each
-    matrix's check pass followed by a variable pass), or the reverse."""
+    """The headline workload decoded with the other schedule: the
+    matrix-serial schedule of Algorithm 1 (each matrix's check pass followed
+    by a variable pass) beside flooding, or the reverse."""
     import torch
     from paper_2001_07979_amd import mbp
 
@@ -357,31 +356,42 @@ def alice_syndromes(ctx, wl, fr, dcode, steps: int):
 def unrolled_step(ctx, steps: int):
     """One training step of the differentiable decoder: K=20 unrolled min-sum
     iterations (weights per iteration and matrix) on 512 frames of the u=2
-    n=16384 rate-1/2 code, mean BCE of sigma(-L^K) against Alice's bits, and
-    the backward through the hand-written adjoint (checkpoints every 5)."""
+    n=16384 rate-1/2 code at BSC p ~ U[0.04, 0.08], mean BCE of sigma(-L^K)
+    against Alice's bits, and the backward through the hand-written adjoint
+    (checkpoints every 5). Every such frame decodes well inside K, so its
+    loss is vanishingly small; the same step is therefore also run as 10 Adam
+    updates of the weights on 512 frames just above min-sum's threshold on
+    this code (p ~ U[0.08, 0.09], where about half the frames fail), whose
+    loss carries signal. Both steps cost the same (no early exit)."""
     import torch
     from paper_2001_07979_amd import mbp
+    from paper_2001_07979_amd.inputs import bsc_frames
     from paper_2001_07979_amd.inputs import workloads as W
 
     wl = W.unrolled_n16384(nframes=512)
-    fr = wl.frames()
     code = wl.code
     K = wl.max_iter
     dev = torch.device("cuda", 0)
     dcode = mbp.Code.from_inputs(ctx, code)
-    y = torch.from_numpy(fr.y).to(dev)
-    e = torch.from_numpy(fr.p).to(dev)
-    z = torch.from_numpy(fr.z).to(dev)
-    x = torch.from_numpy(fr.x.astype(np.float32)).to(dev)
+
+    def frames_on_device(fr):
+        return (torch.from_numpy(fr.y).to(dev), torch.from_numpy(fr.p).to(dev), torch.from_numpy(fr.z).to(dev),
+                torch.from_numpy(fr.x.astype(np.float32)).to(dev))
+
+    def make_step(fr, alpha):
+        y, e, z, x = frames_on_device(fr)
+
+        def step():
+            llr = mbp.llr_from_bits(ctx, y, e).requires_grad_(True)
+            L = mbp.unrolled_nms(ctx, dcode, llr, z, alpha, ckpt_every=5)
+            loss = torch.nn.functional.binary_cross_entropy_with_logits(-L, x)
+            loss.backward()
+            return loss
+        return step
+
+    fr = wl.frames()
     alpha = torch.full((K, code.u), 0.75, device=dev, requires_grad=True)
-
-    def step():
-        llr = mbp.llr_from_bits(ctx, y, e).requires_grad_(True)
-        L = mbp.unrolled_nms(ctx, dcode, llr, z, alpha, ckpt_every=5)
-        loss = torch.nn.functional.binary_cross_entropy_with_logits(-L, x)
-        loss.backward()
-        return loss
-
+    step = make_step(fr, alpha)
     step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -396,9 +406,82 @@ def unrolled_step(ctx, steps: int):
     fwd_iter = 4 * (3 * E + 3 * n)
     adj_iter = 4 * (4 * E + 3 * n)
     bytes_step = fr.nframes * (K * fwd_iter + (K - K // 5) * fwd_iter + K * adj_iter)
+
+    # near the threshold: 10 Adam steps on the weights
+    p_hard = np.random.default_rng(55).uniform(0.08, 0.09, 512)
+    hard = bsc_frames(code, 512, p_hard, 55)
+    alpha_t = torch.full((K, code.u), 0.75, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([alpha_t], lr=0.02)
+    hard_step = make_step(hard, alpha_t)
+    losses = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(10):
+        opt.zero_grad()
+        losses.append(float(hard_step().item()))
+        opt.step()
+    torch.cuda.synchronize()
+    dt_hard = (time.perf_counter() - t1) / 10
+    dcode.close()
     return {"workload": wl.name, "frames": fr.nframes, "K": K, "ckpt_every": 5,
             "ms_per_step": round(dt * 1e3, 3), "frames_per_s": round(fr.nframes / dt, 1),
-            "loss": float(loss.item()), "approx_GBps": round(bytes_step / dt / 1e9, 1)}
+            "loss": float(loss.item()), "approx_GBps": round(bytes_step / dt / 1e9, 1),
+            "near_threshold": {"p": [0.08, 0.09], "frames": 512, "adam_lr": 0.02,
+                               "ms_per_step": round(dt_hard * 1e3, 3),
+                               "loss_by_step": [round(v, 5) for v in losses],
+                               "alpha_mean_after": round(float(alpha_t.detach().mean().item()), 4)}}
+
+
+def host_info() -> dict:
+    """CPU model and core counts of the host (for the CPU baseline)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": aff}
+
+
+def algorithmic_bytes(code, iters, algo: str, schedule: str):
+    """Algorithmic HBM bytes of all check passes and of all variable passes of
+    one step (FP32), summed over the frames each iteration advanced.
+
+    Per frame and iteration (flooding): the check pass reads c^{t-1} (4E), the
+    soft decisions L^{t-1} once (4n) and writes c^t (4E); in the first
+    iteration, decoded from Bob's bits, it reads one bit per variable (n/8)
+    and writes c (4E). Min-sum with a compressed check state replaces the
+    read of c^{t-1} by 3 words per check, read and written (2 * 12 M). The
+    variable pass reads c^t (4E) and Bob's bits (n/8) and writes L^t (4n) and
+    the decision bits (n/8). Under the matrix-serial schedule each phase's
+    check pass reads L (4n) and its matrix's c; its variable pass reads its
+    matrix's messages and the other matrices' stored sums and writes L and
+    its matrix's sum."""
+    s, n, E, M, u = 4, code.n, code.E, code.M, code.u
+    serial = schedule == "serial"
+    phases = u if serial else 1
+    cst = algo == "nms" and max(int(np.diff(rp).max()) for rp in code.row_ptr) <= 24
+    old = 2 * 3 * s * M if cst else s * E
+    stored = serial and 1 < u <= 4
+    chk = vn = 0.0
+    for t in range(1, int(iters.max()) + 1):
+        full = int((iters >= t).sum())
+        if t == 1:
+            chk += full * (s * E + n / 8 + s * n * (phases - 1) + (3 * s * M if cst else 0))
+        else:
+            chk += full * (s * E + old + s * n * phases)
+        if stored:
+            others = sum(l if t == 1 else u - 1 for l in range(u))
+            vn += full * (s * E + u * n / 8 + s * n * (2 * u + others) + n / 8)
+        else:
+            vn += full * (phases * (s * E + n / 8 + s * n) + n / 8)
+    return chk, vn
 
 
 def main():
@@ -407,10 +490,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--algo", choices=["spa", "nms"], default="spa")
-    ap.add_argument("--frames", type=int, default=256)
+    ap.add_argument("--frames", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="minimum wall time of the FP64 oracle baseline")
+    ap.add_argument("--cpu-frames", type=int, default=32,
+                    help="frames of the headline workload in the oracle's bounded sample")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-launch HIP events (no roofline)")
     ap.add_argument("--queue-frames", type=int, default=2048,
@@ -421,13 +506,16 @@ def main():
     ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled training step")
     ap.add_argument("--no-two-call", action="store_true",
                     help="skip timing the same step as two calls (LLR rows stored, then decoded)")
-    ap.add_argument("--schedule", choices=["serial", "flooding"], default="serial",
-                    help="schedule of the timed step (serial: Algorithm 1 as printed, each matrix's "
-                         "check pass followed by a variable pass)")
+    ap.add_argument("--schedule", choices=["serial", "flooding"], default="flooding",
+                    help="schedule of the timed step (flooding: every matrix's checks from the previous "
+                         "iteration's messages; serial: Algorithm 1's per-matrix loop)")
     ap.add_argument("--no-other-schedule", action="store_true",
-                    help="skip timing the main workload under the other schedule")
-    ap.add_argument("--no-qualifying", action="store_true",
-                    help="skip the f <= 1.1 operating point (n=262144, rate 0.85)")
+                    help="skip timing the headline workload under the other schedule")
+    ap.add_argument("--no-n65536", action="store_true",
+                    help="skip the u=2 n=65536 workload (both schedules)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time only the headline step (for profiling): no other schedule, n=65536 point, "
+                         "syndromes, unrolled step, queue or two-call leg")
     ap.add_argument("--arrival-load", type=float, default=0.7,
                     help="Poisson arrival rate as a fraction of the batched offline frame rate")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -438,23 +526,41 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); frames are independent, "
               "so more GPUs would each decode their own share with no exchange", file=sys.stderr)
         sys.exit(2)
+    if args.no_extras:
+        args.no_other_schedule = args.no_n65536 = args.no_unrolled = args.no_two_call = True
+        args.queue_frames = 0
 
     import torch
     from paper_2001_07979_amd import mbp
     from paper_2001_07979_amd.inputs import workloads as W
 
     log("bench: building inputs")
-    wl = W.qkd_n65536(nframes=args.frames, algo=args.algo)
+    wl = W.qkd_n262144(0.85, nframes=args.frames, algo=args.algo)
     fr = wl.frames()
     code = wl.code
     n, E, F = code.n, code.E, fr.nframes
     dev = torch.device("cuda", 0)
     ctx = mbp.Context(0)
     dcode = mbp.Code.from_inputs(ctx, code)
+    try:
+        rec = run(args, ctx, dcode, wl, fr, dev)
+    finally:
+        # every library object is released here, before the interpreter and
+        # the HIP runtime shut down
+        dcode.close()
+        ctx.close()
+    print(json.dumps(rec), flush=True)
+
+
+def run(args, ctx, dcode, wl, fr, dev):
+    import torch
+    from paper_2001_07979_amd import mbp
+
+    code = wl.code
+    n, E, F = code.n, code.E, fr.nframes
     y = torch.from_numpy(fr.y).to(dev)
     e = torch.from_numpy(fr.p).to(dev)
     z = torch.from_numpy(fr.z).to(dev)
-    llr = torch.empty((F, n), dtype=torch.float32, device=dev)
     out = dict(bits=torch.empty((F, n), dtype=torch.uint8, device=dev),
                iters=torch.empty(F, dtype=torch.int32, device=dev),
                ok=torch.empty(F, dtype=torch.uint8, device=dev),
@@ -467,12 +573,6 @@ def main():
         mbp.decode_from_bits(ctx, dcode, y, e, z, dtype="f32", algo=wl.algo, max_iter=wl.max_iter,
                              early_exit=wl.early_exit, alpha=wl.alpha, clip=wl.clip, out=out,
                              stream=stream, schedule=args.schedule)
-
-    def step_two_calls():
-        mbp.llr_from_bits(ctx, y, e, dtype="f32", out=llr, stream=stream)
-        mbp.decode(ctx, dcode, llr, z, algo=wl.algo, max_iter=wl.max_iter,
-                   early_exit=wl.early_exit, alpha=wl.alpha, clip=wl.clip, out=out,
-                   stream=stream, schedule=args.schedule)
 
     if args.copy_probe_mib:
         src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
@@ -525,6 +625,14 @@ def main():
     # the same step as two calls (LLR rows stored, then decoded)
     two_calls = None
     if not args.no_two_call:
+        llr = torch.empty((F, n), dtype=torch.float32, device=dev)
+
+        def step_two_calls():
+            mbp.llr_from_bits(ctx, y, e, dtype="f32", out=llr, stream=stream)
+            mbp.decode(ctx, dcode, llr, z, algo=wl.algo, max_iter=wl.max_iter,
+                       early_exit=wl.early_exit, alpha=wl.alpha, clip=wl.clip, out=out,
+                       stream=stream, schedule=args.schedule)
+
         step_two_calls()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
@@ -534,94 +642,76 @@ def main():
         two_calls_ms = (time.perf_counter() - t2) * 1e3 / args.steps
         assert np.array_equal(out["bits"].cpu().numpy(), bits)
         two_calls = {"ms_per_step": round(two_calls_ms, 4), "mbps": round(F * n / (two_calls_ms * 1e-3) / 1e6, 1)}
+        del llr
     frame_err = np.any(bits != fr.x, axis=1)
     fer = float(frame_err.mean())
     p = float(np.mean(fr.p))
-    from math import log2
-    h = -p * log2(p) - (1 - p) * log2(1 - p)
+    h = float(h2(p))
     m = code.m[0]
 
     roofline = roofline_other = None
     if profile:
-        s = 4
-        u = code.u
-        serial = args.schedule == "serial"
-        phases = u if serial else 1
-        cst = wl.algo == "nms" and max(int(np.diff(rp).max()) for rp in code.row_ptr) <= 24
-        old = 2 * 3 * s * code.M if cst else s * E
-        stored = serial and 1 < u <= 4  # serial passes keep each matrix's sum per variable
-        chk = vn = 0
-        for t in range(1, int(iters.max()) + 1):
-            full = int((iters >= t).sum())
-            # check-node passes, per frame: every pass reads L (n; the first
-            # pass of the first iteration reads lambda as one bit per
-            # variable) and writes c (E over the passes); from t = 2 they
-            # read the old c (E), which min-sum with a compressed check
-            # state replaces by reading and writing 3 words per check
-            if t == 1:
-                chk += full * (s * E + n / 8 + s * n * (phases - 1) + (3 * s * code.M if cst else 0))
-            else:
-                chk += full * (s * E + old + s * n * phases)
-            # variable-node passes, per frame: read the messages (E over the
-            # passes) and lambda's bit words, write L and the decision words;
-            # serial passes with stored sums also write their matrix's sum
-            # and read the others' (only the matrices visited so far at t = 1)
-            if stored:
-                others = sum(l if t == 1 else u - 1 for l in range(u))
-                vn += full * (s * E + u * n / 8 + s * n * (2 * u + others) + n / 8)
-            else:
-                vn += full * (phases * (s * E + n / 8 + s * n) + n / 8)
+        chk, vn = algorithmic_bytes(code, iters, wl.algo, args.schedule)
+        stored = args.schedule == "serial" and 1 < code.u <= 4
 
         def line(which, per_step, kernel):
             n_k, ms_k = ctx.profile_get(which)
             per_launch = per_step / (n_k / args.steps)
             avg_ms = ms_k / n_k
             achieved = per_launch / (avg_ms * 1e-3) / 1e9
-            return ms_k, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                          "traffic": stored_traffic(wl.algo, args.schedule, which), "kernel": kernel,
-                          "avg_launch_ms": round(avg_ms, 5), "launches": n_k,
-                          "algorithmic_bytes_per_launch": int(per_launch)}
+            return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": stored_traffic(wl.algo, args.schedule, which), "kernel": kernel,
+                    "avg_launch_ms": round(avg_ms, 5), "launches": n_k,
+                    "algorithmic_bytes_per_launch": int(per_launch)}
 
-        _, r_chk = line("check", chk, "k_check (check-node pass)")
-        _, r_vn = line("variable", vn, "k_variable_phase (variable-node pass)" if stored
-                       else "k_variable (variable-node pass)")
+        r_chk = line("check", chk, "k_check (check-node pass)")
+        r_vn = line("variable", vn, "k_variable_phase (variable-node pass)" if stored
+                    else "k_variable (variable-node pass)")
         roofline, roofline_other = (r_chk, r_vn) if dominant == "check" else (r_vn, r_chk)
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
         threads = host_threads()
-        lam = oracle.llr_from_bits(fr.y, fr.p).astype(np.float32).astype(np.float64)
-        # the whole batch, decoded again until at least args.cpu_seconds of work
-        log(f"bench: oracle on the {F} frames with {threads} threads, >= {args.cpu_seconds} s")
+        k = min(F, max(args.cpu_frames, threads))
+        lam = oracle.llr_from_bits(fr.y[:k], fr.p[:k]).astype(np.float32).astype(np.float64)
+        # a bounded sample: the first k frames, decoded again until at least
+        # args.cpu_seconds of work
+        log(f"bench: oracle on {k} of the {F} frames with {threads} threads, >= {args.cpu_seconds} s")
         c0 = time.perf_counter()
         passes = 0
         while True:
-            oracle.decode(code, lam, fr.z, algo=oracle.SPA if wl.algo == "spa" else oracle.NMS,
-                          max_iter=wl.max_iter, alpha=wl.alpha, clip=wl.clip, nthreads=threads)
+            ref = oracle.decode(code, lam, fr.z[:k], algo=oracle.SPA if wl.algo == "spa" else oracle.NMS,
+                                max_iter=wl.max_iter, alpha=wl.alpha, clip=wl.clip, nthreads=threads,
+                                schedule=oracle.SERIAL if args.schedule == "serial" else oracle.FLOODING)
             passes += 1
             if time.perf_counter() - c0 >= args.cpu_seconds:
                 break
         c1 = time.perf_counter()
-        cpu = {"value": round(passes * F * n / (c1 - c0) / 1e6, 3), "unit": "Mbps", "cores": threads,
+        cpu = {"value": round(passes * k * n / (c1 - c0) / 1e6, 3), "unit": "Mbps", "cores": threads,
                "kind": "oracle",
-               "sample": f"the {F} frames of the workload decoded {passes} times, FP64 {wl.algo}, "
-                         f"{threads} threads, {c1 - c0:.1f} s"}
-
-    qual = None
-    if not args.no_qualifying:
-        log("bench: qualifying point (n=262144, rate 0.85, f=1.061)")
-        qual = qualifying_point(ctx, 5, args.algo, args.schedule)
+               "sample": f"the first {k} of the {F} frames of the workload decoded {passes} times "
+                         f"(FP64 {wl.algo}, {args.schedule}, {threads} threads, {c1 - c0:.1f} s); the "
+                         f"oracle's iteration counts equal the GPU's on {int((ref['iters'] == iters[:k]).sum())} "
+                         f"of them",
+               **host_info()}
 
     other = None
     if not args.no_other_schedule:
         sched = "flooding" if args.schedule == "serial" else "serial"
-        log(f"bench: main workload, {sched} schedule")
+        log(f"bench: headline workload, {sched} schedule")
         other = other_schedule(ctx, wl, fr, dcode, y, e, z, 5, sched)
 
-    log("bench: Alice's syndromes")
-    alice = alice_syndromes(ctx, wl, fr, dcode, 10)
+    c2 = None
+    if not args.no_n65536:
+        log("bench: n=65536 workload, both schedules")
+        c2 = n65536_point(ctx, 10, args.algo)
+
+    alice = None
+    if not args.no_extras:
+        log("bench: Alice's syndromes")
+        alice = alice_syndromes(ctx, wl, fr, dcode, 10)
 
     unrolled = None
     if not args.no_unrolled:
@@ -633,7 +723,7 @@ def main():
         batched = batched_vs_plain(ctx, args.queue_frames, args.queue_reps, args.arrival_load,
                                    batched_only=args.queue_batched_only)
 
-    rec = {
+    return {
         "metric": "reconciled Mbps at FER<=1e-2, f<=1.1; % HBM peak; batched vs plain",
         "value": round(mbps, 1), "unit": "Mbps", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
@@ -641,15 +731,16 @@ def main():
         "config": {"workload": wl.name, "frames": F, "n": n, "u": code.u, "m": m, "E": E,
                    "rate": 1 - m / n, "p": p, "algo": wl.algo, "max_iter": wl.max_iter,
                    "early_exit": wl.early_exit, "schedule": args.schedule, "peg": code.name},
-        "fer": fer, "decoder_failures": int((ok == 0).sum()),
+        "fer": fer, "frame_errors": int(frame_err.sum()), "decoder_failures": int((ok == 0).sum()),
+        "fer_bound_95": round(3.0 / F, 5) if not frame_err.any() else None,
         "avg_iters": float(iters.mean()), "max_iters": int(iters.max()),
         "f": round(m / (n * h), 4), "f_leak": round(code.u * m / (n * h), 4),
         "llr_rows_then_decode": two_calls,
-        "roofline": roofline, "roofline_other_kernel": roofline_other, "cpu_baseline": cpu, "qualifying_point": qual, "other_schedule": other, "alice_syndromes": alice,
+        "roofline": roofline, "roofline_other_kernel": roofline_other, "cpu_baseline": cpu,
+        "other_schedule": other, "n65536": c2, "alice_syndromes": alice,
         "unrolled_training_step": unrolled,
         "batched_vs_plain": batched,
     }
-    print(json.dumps(rec), flush=True)
 
 
 if __name__ == "__main__":

@@ -251,8 +251,11 @@ int mbp_nms_unrolled_bwd(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, in
  * barrier between the check and variable passes, early exit when every frame
  * has stopped), so the whole decode is one launch plus staging and output
  * kernels, and can be captured into a hipGraph (mbp_plan_*). The results equal
- * mbp_decode's bit for bit for the same parameters. Normalized min-sum in FP32
- * only (p->algo = MBP_ALGO_NMS, p->dtype = MBP_F32; EUNSUPPORTED otherwise).
+ * mbp_decode's bit for bit for the same parameters. FP32 with the flooding
+ * schedule (p->dtype = MBP_F32, p->schedule = MBP_FLOODING; EUNSUPPORTED
+ * otherwise), with either check rule: normalized min-sum (MBP_ALGO_NMS) for
+ * any code, or sum-product (MBP_ALGO_SPA, Sec. 3B eq. (6)) for codes whose
+ * largest check degree is at most 34 (EUNSUPPORTED above that).
  *
  * mbp_tuning: work-item shape and schedule of the persistent kernel.
  *   rows_per_wave, vars_per_wave  checks / variables per wave per work item
@@ -267,7 +270,8 @@ int mbp_nms_unrolled_bwd(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, in
  *                                 same either way)
  * mbp_autotune times a set of tunings on the given batches (their outputs are
  * overwritten) and returns the fastest; with cache_path it first looks the
- * batch mix up in that text file and appends new results to it. */
+ * batch mix (with the check rule and iteration limit) up in that text file
+ * and appends new results to it. */
 typedef struct {
     const mbp_code *code;
     int32_t nframes;     /* 1 .. 65535 * 64 */
@@ -300,8 +304,11 @@ int mbp_decode_batched(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches,
 
 /* A captured hipGraph of the same decode for fixed batches: the plan owns its
  * workspace; each launch re-reads the batches' input buffers and rewrites
- * their outputs. mbp_plan_launch only enqueues; mbp_plan_wait synchronizes
- * the stream and reports a barrier timeout of the last launch as EDEVICE. */
+ * their outputs. The persistent kernel's node carries the cooperative launch
+ * attribute, so each launch has all its blocks resident at once;
+ * mbp_plan_create fails (EDEVICE) if the runtime refuses that attribute.
+ * mbp_plan_launch only enqueues; mbp_plan_wait synchronizes the stream and
+ * reports a barrier timeout of the last launch as EDEVICE. */
 int mbp_plan_create(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches, const mbp_params *p,
                     const mbp_tuning *tuning, mbp_plan **out);
 int mbp_plan_launch(mbp_plan *plan, void *stream);
@@ -313,8 +320,8 @@ int mbp_autotune(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches, const
 
 /* Serving queue over the batched decode, for callers that receive frames a
  * few at a time (the batched decode's queue of heterogeneous frames).
- *   mbp_queue_create   parameters as for mbp_decode_batched (min-sum, FP32,
- *                      flooding); tuning may be NULL for the default. The
+ *   mbp_queue_create   parameters as for mbp_decode_batched (FP32, flooding,
+ *                      either check rule); tuning may be NULL for the default. The
  *                      queue keeps the context's record alive until it is
  *                      destroyed.
  *   mbp_queue_submit   append batches (descriptors are copied; the device

@@ -12,6 +12,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -20,11 +21,12 @@ ARCH = "gfx950"
 
 # Packed-FP32 instructions are kept out of every HIP build.
 HIP_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Wall", "-Wno-unused-function",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]
+OBJ_DIR = os.path.join(PKG, "_build")
 
 HIP_SOURCES = ["csrc/capi.cpp", "csrc/decode.hip", "csrc/unrolled.hip", "csrc/batched.hip",
                "csrc/syndrome.hip"]
@@ -62,7 +64,15 @@ def build_mbp():
         return
     out = os.path.join(PKG, "libmbp.so")
     tmp = _atomic_out(out)
-    _run([HIPCC] + HIP_FLAGS + ["-o", tmp] + srcs)
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    objs = [os.path.join(OBJ_DIR, os.path.basename(s) + f".{os.getpid()}.o") for s in srcs]
+    # each source compiles on its own (the template-heavy ones dominate), then one link
+    jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as pool:
+        list(pool.map(lambda so: _run([HIPCC] + HIP_FLAGS + ["-c", so[0], "-o", so[1]]), zip(srcs, objs)))
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
+    for o in objs:
+        os.remove(o)
     os.replace(tmp, out)
 
 

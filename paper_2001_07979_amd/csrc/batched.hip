@@ -22,10 +22,15 @@
 // interleaved (item = block + k * grid) or in contiguous runs, as the tuning
 // says; retired and unused groups cost one load.
 //
-// The check rule is normalized min-sum in FP32, evaluated in chunks of the
-// check's edges so any check degree up to 64 shares one kernel: the first
-// pass keeps only the two smallest magnitudes, the position of the smallest
-// and the sign bits; the second pass writes every message from those.
+// The check rule is normalized min-sum or sum-product in FP32. Min-sum is
+// evaluated in chunks of the check's edges so any check degree up to 64
+// shares one code path: the first pass keeps only the two smallest
+// magnitudes, the position of the smallest and the sign bits; the second
+// pass writes every message from those. Sum-product takes the plain check
+// pass's row rule (complements of the tanh product, prefix and suffix over
+// the check's slots) with the slot count of each group's code, up to
+// kBatchedSpaMaxDeg edges per check, so its messages equal the plain
+// decode's bit for bit too.
 //
 // The barrier spins with a bounded wait: a block that waits longer than two
 // seconds, or sees another block give up, sets an error flag and leaves, so
@@ -74,6 +79,8 @@ struct GroupDesc {
     int32_t n, M;
     int32_t item;  // batch of the group
     int32_t cn_tiles, vn_tiles, st_tiles;
+    int32_t dslots;  // sum-product: unrolled slots of the check rule (dmax_for of the code)
+    int32_t pad_;
 };
 
 static_assert(sizeof(GroupDesc) % 8 == 0, "descriptors are copied as 64-bit words");
@@ -122,6 +129,7 @@ struct PArgs {
     int32_t ngroups, nitems, T, early_exit;
     int32_t rows_per_wave, vars_per_wave, schedule, compact;
     float alpha, clip;
+    int32_t algo;  // kNMS or kSPA
 };
 
 // A barrier wait gives up after this long on the 100 MHz real-time clock
@@ -261,6 +269,49 @@ __device__ void cn_tile(const GroupDesc &G_, int tile, int t, const PArgs &a, ui
                 const uint32_t sb = (sx ^ static_cast<uint32_t>((neg >> j) & 1)) << 31;
                 stg(cg, static_cast<int64_t>(j) * G + lane, __uint_as_float(__float_as_uint(mag) | sb));
             }
+        }
+    }
+}
+
+// Sum-product check rule of one check (row r of the group), through the
+// plain pass's check_row_f32 with DMAX slots: all gathers of the check in
+// flight, the complement prefix and suffix products in registers. The
+// column array is padded past E, so a full block of DMAX indices is always
+// in bounds.
+template <int DMAX>
+__device__ __forceinline__ void spa_row(const GroupDesc &G_, int r, bool first, const PArgs &a, unsigned lane,
+                                        bool on) {
+    const int e0 = ldc(G_.row_ptr, r);
+    const int d = ldc(G_.row_ptr, r + 1) - e0;
+    const uint32_t zbit = static_cast<uint32_t>((ld_fresh(G_.zb + r) >> lane) & 1);
+    int v[DMAX];
+#pragma unroll
+    for (int j = 0; j < DMAX; ++j) v[j] = ldc(G_.col, e0 + j);
+    float *cg = G_.c + static_cast<size_t>(e0) * G;
+    if (on)
+        check_row_f32<kSPA, DMAX, false>(v, d, zbit, a.alpha, a.clip, first, buf_rsrc(G_.Lp, kBufAll), cg, cg,
+                                         lane, 0.0f);
+}
+
+// Sum-product check pass over one tile of a group (rows_per_wave rows per
+// wave); the slot count is uniform over the group.
+__device__ void cn_tile_spa(const GroupDesc &G_, int tile, int t, const PArgs &a, uint64_t run) {
+    const unsigned lane = lane_id();
+    const int wave = wave_id();
+    const bool on = (run >> lane) & 1;
+    const bool first = t == 1;
+    const int rpt = a.rows_per_wave * kWaves;
+    for (int k = 0; k < a.rows_per_wave; ++k) {
+        const int r = tile * rpt + k * kWaves + wave;
+        if (r >= G_.M) break;
+        switch (G_.dslots) {
+            case 8: spa_row<8>(G_, r, first, a, lane, on); break;
+            case 10: spa_row<10>(G_, r, first, a, lane, on); break;
+            case 16: spa_row<16>(G_, r, first, a, lane, on); break;
+            case 18: spa_row<18>(G_, r, first, a, lane, on); break;
+            case 24: spa_row<24>(G_, r, first, a, lane, on); break;
+            case 32: spa_row<32>(G_, r, first, a, lane, on); break;
+            default: spa_row<kBatchedSpaMaxDeg>(G_, r, first, a, lane, on); break;
         }
     }
 }
@@ -543,6 +594,10 @@ __device__ void move_piece(const PArgs &a, int g, int p) {
     }
 }
 
+// One instance per check rule, so the min-sum decode keeps the register
+// budget (and resident blocks) of its chunked rule, and sum-product pays for
+// its unrolled slots alone.
+template <int ALGO>
 __global__ __launch_bounds__(kBlock) void k_persistent(PArgs a) {
     __shared__ uint32_t sh_or[2 * kWaves];
     for (int t = 1; t <= a.T; ++t) {
@@ -559,7 +614,12 @@ __global__ __launch_bounds__(kBlock) void k_persistent(PArgs a) {
             }
         }
         for_live_tiles(a, [](const GroupDesc *gd, int g) { return ldc(&gd[g].cn_tiles, 0); },
-                       [&](int, const GroupDesc &G_, uint64_t run, int tile) { cn_tile(G_, tile, t, a, run); });
+                       [&](int, const GroupDesc &G_, uint64_t run, int tile) {
+                           if constexpr (ALGO == kSPA)
+                               cn_tile_spa(G_, tile, t, a, run);
+                           else
+                               cn_tile(G_, tile, t, a, run);
+                       });
         if (!grid_sync(a.bar)) return;
         for_live_tiles(a, [](const GroupDesc *gd, int g) { return ldc(&gd[g].vn_tiles, 0); },
                        [&](int, const GroupDesc &G_, uint64_t run, int tile) { vn_tile(G_, tile, a, run); });
@@ -698,6 +758,7 @@ Built lay_out(int32_t nb, const mbp_batch *b, const mbp_tuning &tu) {
             d.D = reinterpret_cast<uint64_t *>(P.D + k * sd);
             d.E = code->E;
             d.n = code->n;
+            d.dslots = dmax_for(code->max_check_deg);
             d.M = code->M;
             d.item = i;
             d.cn_tiles = (code->M + rpt - 1) / rpt;
@@ -721,19 +782,9 @@ void rebase(Built &B, char *base) {
     }
 }
 
-int persistent_blocks_per_cu() {
-    static int cached = 0;
-    if (!cached) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_persistent),
-                                                         kBlock, 0) != hipSuccess ||
-            nb < 1) {
-            (void)hipGetLastError();
-            nb = 1;
-        }
-        cached = nb;
-    }
-    return cached;
+const void *persistent_kernel(int algo) {
+    return algo == kSPA ? reinterpret_cast<const void *>(&k_persistent<kSPA>)
+                        : reinterpret_cast<const void *>(&k_persistent<kNMS>);
 }
 
 // Upload the group and batch descriptors (synchronous) after pointing them
@@ -786,16 +837,16 @@ int enqueue_kernels(int32_t nb, const mbp_batch *b, const mbp_params *p, const m
             tu.schedule,
             tu.compact,
             static_cast<float>(p->alpha),
-            static_cast<float>(p->llr_clip)};
-    const int bpc = std::max(1, std::min({tu.blocks_per_cu, persistent_blocks_per_cu(), kMaxBlocksPerCu}));
+            static_cast<float>(p->llr_clip),
+            p->algo == MBP_ALGO_SPA ? kSPA : kNMS};
+    const void *kp = persistent_kernel(a.algo);
+    const int bpc = std::max(1, std::min({tu.blocks_per_cu, blocks_per_cu(kp), kMaxBlocksPerCu}));
     const int grid = num_cus * bpc;
     void *args[] = {&a};
     if (cooperative)
-        err = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_persistent), dim3(grid), dim3(kBlock),
-                                         args, 0, stream);
+        err = hipLaunchCooperativeKernel(kp, dim3(grid), dim3(kBlock), args, 0, stream);
     else
-        err = hipLaunchKernel(reinterpret_cast<const void *>(&k_persistent), dim3(grid), dim3(kBlock), args, 0,
-                              stream);
+        err = hipLaunchKernel(kp, dim3(grid), dim3(kBlock), args, 0, stream);
     if (err != hipSuccess) return hip_fail(err, "persistent decode launch");
     for (int32_t i = 0; i < nb; ++i) {
         const BatchPlace &P = B.place[i];
@@ -862,6 +913,34 @@ int batched_launch(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_param
     return MBP_OK;
 }
 
+// Sets the cooperative launch attribute on every node of `graph` that
+// launches a k_persistent instance (exactly one is expected).
+static int mark_persistent_cooperative(hipGraph_t graph) {
+    size_t count = 0;
+    hipError_t e = hipGraphGetNodes(graph, nullptr, &count);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphGetNodes");
+    std::vector<hipGraphNode_t> nodes(count);
+    if (count && (e = hipGraphGetNodes(graph, nodes.data(), &count)) != hipSuccess)
+        return hip_fail(e, "hipGraphGetNodes");
+    int marked = 0;
+    for (hipGraphNode_t node : nodes) {
+        hipGraphNodeType type;
+        if ((e = hipGraphNodeGetType(node, &type)) != hipSuccess) return hip_fail(e, "hipGraphNodeGetType");
+        if (type != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp{};
+        if ((e = hipGraphKernelNodeGetParams(node, &kp)) != hipSuccess)
+            return hip_fail(e, "hipGraphKernelNodeGetParams");
+        if (kp.func != persistent_kernel(kSPA) && kp.func != persistent_kernel(kNMS)) continue;
+        hipKernelNodeAttrValue v{};
+        v.cooperative = 1;
+        if ((e = hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &v)) != hipSuccess)
+            return hip_fail(e, "hipGraphKernelNodeSetAttribute(cooperative)");
+        ++marked;
+    }
+    if (marked != 1) return fail(MBP_EDEVICE, "plan capture: persistent kernel node not found");
+    return MBP_OK;
+}
+
 int batched_plan_capture(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_params *p, const mbp_tuning &tu,
                          void *ws, hipGraphExec_t *exec, int32_t **err_dev) {
     (void)hipGetLastError();
@@ -887,6 +966,16 @@ int batched_plan_capture(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp
         return rc;
     }
     if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    // Stream capture records the persistent kernel as a plain kernel node.
+    // Its grid barrier needs every block resident at once, which only a
+    // cooperative launch guarantees, so that node is marked cooperative
+    // before the graph is instantiated; a runtime that refuses the attribute
+    // fails the plan rather than leaving a launch that could wait on blocks
+    // that never start.
+    if ((rc = mark_persistent_cooperative(graph)) != MBP_OK) {
+        (void)hipGraphDestroy(graph);
+        return rc;
+    }
     e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");

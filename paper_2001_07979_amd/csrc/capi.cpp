@@ -401,24 +401,37 @@ int mbp_tuning_default(mbp_tuning *out) {
     return MBP_OK;
 }
 
-static int check_batches(const char *fn, mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_params *p,
-                         const mbp_tuning *tu) {
+// Parameters of a batched decode (FP32, flooding; min-sum or sum-product).
+static int check_batched_params(const char *fn, const mbp_params *p) {
     const std::string f(fn);
-    if (!ctx || !p) return fail(MBP_EINVAL, f + ": null ctx or params");
-    if (nb < 1 || !b) return fail(MBP_EINVAL, f + ": need at least one batch");
-    if (p->algo != MBP_ALGO_NMS || p->dtype != MBP_F32)
-        return fail(MBP_EUNSUPPORTED, f + ": the batched decode runs normalized min-sum in FP32 only");
+    if (p->algo != MBP_ALGO_NMS && p->algo != MBP_ALGO_SPA) return fail(MBP_EINVAL, f + ": unknown algo");
+    if (p->dtype != MBP_F32) return fail(MBP_EUNSUPPORTED, f + ": the batched decode runs in FP32 only");
     if (p->schedule != MBP_FLOODING)
         return fail(MBP_EUNSUPPORTED, f + ": the batched decode runs the flooding schedule only");
     if (p->max_iter < 1 || p->max_iter > 10000) return fail(MBP_EINVAL, f + ": max_iter must be in [1, 10000]");
     if (p->early_exit != 0 && p->early_exit != 1) return fail(MBP_EINVAL, f + ": early_exit must be 0 or 1");
     if (!std::isfinite(p->llr_clip) || p->llr_clip <= 0.0)
         return fail(MBP_EINVAL, f + ": llr_clip must be finite and > 0");
-    if (!std::isfinite(p->alpha) || p->alpha <= 0.0) return fail(MBP_EINVAL, f + ": alpha must be finite and > 0");
+    if (p->algo == MBP_ALGO_SPA && p->llr_clip > 30.0)
+        return fail(MBP_EINVAL, f + ": llr_clip must be <= 30 for sum-product");
+    if (p->algo == MBP_ALGO_NMS && (!std::isfinite(p->alpha) || p->alpha <= 0.0))
+        return fail(MBP_EINVAL, f + ": alpha must be finite and > 0");
+    return MBP_OK;
+}
+
+static int check_batches(const char *fn, mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_params *p,
+                         const mbp_tuning *tu) {
+    const std::string f(fn);
+    if (!ctx || !p) return fail(MBP_EINVAL, f + ": null ctx or params");
+    if (nb < 1 || !b) return fail(MBP_EINVAL, f + ": need at least one batch");
+    if (int rc = check_batched_params(fn, p); rc != MBP_OK) return rc;
     int64_t groups = 0;
     for (int32_t i = 0; i < nb; ++i) {
         const mbp_batch &x = b[i];
         if (!x.code || x.code->ctx != ctx) return fail(MBP_EINVAL, f + ": batch code missing or of another context");
+        if (p->algo == MBP_ALGO_SPA && x.code->max_check_deg > mbp::kBatchedSpaMaxDeg)
+            return fail(MBP_EUNSUPPORTED, f + ": the batched sum-product rule takes check degrees up to " +
+                                              std::to_string(mbp::kBatchedSpaMaxDeg));
         if (x.nframes < 1 || x.nframes > 65535 * mbp::kLanes)
             return fail(MBP_EINVAL, f + ": batch nframes must be in [1, 65535 * 64]");
         if (!x.llr || !x.synd || !x.bits_out || !x.iters_out || !x.ok_out)
@@ -496,14 +509,8 @@ int mbp_queue_create(mbp_ctx *ctx, const mbp_params *p, const mbp_tuning *tuning
     if (!out) return fail(MBP_EINVAL, "mbp_queue_create: out is NULL");
     *out = nullptr;
     if (!ctx || !p) return fail(MBP_EINVAL, "mbp_queue_create: null ctx or params");
-    // the parameter checks of a batched decode (a stand-in batch carries no frames yet)
-    if (p->algo != MBP_ALGO_NMS || p->dtype != MBP_F32)
-        return fail(MBP_EUNSUPPORTED, "mbp_queue_create: the batched decode runs normalized min-sum in FP32 only");
-    if (p->schedule != MBP_FLOODING)
-        return fail(MBP_EUNSUPPORTED, "mbp_queue_create: the batched decode runs the flooding schedule only");
-    if (p->max_iter < 1 || p->max_iter > 10000 || (p->early_exit != 0 && p->early_exit != 1) ||
-        !std::isfinite(p->llr_clip) || p->llr_clip <= 0.0 || !std::isfinite(p->alpha) || p->alpha <= 0.0)
-        return fail(MBP_EINVAL, "mbp_queue_create: bad parameters");
+    // the parameter checks of a batched decode (the codes come with the batches)
+    if (int rc = check_batched_params("mbp_queue_create", p); rc != MBP_OK) return rc;
     const mbp_tuning tu = tuning ? *tuning : mbp::default_tuning();
     if (int rc = mbp::check_tuning(tu); rc != MBP_OK) return rc;
     mbp_queue *q = new (std::nothrow) mbp_queue();
@@ -621,7 +628,7 @@ void mbp_queue_destroy(mbp_queue *q) {
 // "<key> <rows_per_wave> <vars_per_wave> <blocks_per_cu> <schedule> <compact> <ms>".
 static std::string tune_key(int32_t nb, const mbp_batch *b, const mbp_params *p) {
     std::ostringstream k;
-    k << "T" << p->max_iter << "e" << p->early_exit;
+    k << "a" << p->algo << "T" << p->max_iter << "e" << p->early_exit;
     for (int32_t i = 0; i < nb; ++i)
         k << "|n" << b[i].code->n << "M" << b[i].code->M << "E" << b[i].code->E << "u" << b[i].code->u << "f"
           << b[i].nframes;

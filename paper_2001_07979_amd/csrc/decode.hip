@@ -57,15 +57,6 @@ struct Channel {
     const double *e;
 };
 
-// The unrolled slot count of the check pass for a largest check degree d:
-// every slot past a check's degree still costs its running updates, so the
-// sizes sit just above common degrees of the codes in use (PEG rows of one
-// code differ in degree by at most one or two).
-int dmax_for(int d) {
-    for (int c : {8, 10, 16, 18, 24, 32, 34, 48}) if (d <= c) return c;
-    return 64;
-}
-
 template <typename T>
 int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t F,
                const Channel &ch, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,

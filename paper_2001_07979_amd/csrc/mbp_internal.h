@@ -15,6 +15,11 @@ namespace mbp {
 // Frames per interleaved group: one frame per lane of a 64-wide wavefront.
 constexpr int kLanes = 64;
 
+// Largest check degree the batched decode's sum-product rule handles (its
+// unrolled slot count: 34 slots keep the sum-product persistent kernel at 2
+// waves per SIMD; 64 would need all 256 registers, 1 wave).
+constexpr int kBatchedSpaMaxDeg = 34;
+
 // Extra zero entries after the device edge-index arrays, so kernels can read
 // indices in fixed blocks (up to 64 + 32 entries) past the end.
 constexpr int kIndexPad = 128;

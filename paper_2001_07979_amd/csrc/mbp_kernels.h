@@ -473,6 +473,15 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
     }
 }
 
+// The unrolled slot count of the check pass for a largest check degree d:
+// every slot past a check's degree still costs its running updates, so the
+// sizes sit just above common degrees of the codes in use (PEG rows of one
+// code differ in degree by at most one or two).
+inline int dmax_for(int d) {
+    for (int c : {8, 10, 16, 18, 24, 32, 34, 48}) if (d <= c) return c;
+    return 64;
+}
+
 // Edges of a check whose decision words the stopping test gathers at once.
 constexpr int kStopChunk = 24;
 

@@ -133,8 +133,51 @@ def _stream_ptr(stream) -> Optional[int]:
     return s.cuda_stream
 
 
-def _dev_ptr(t) -> Optional[int]:
-    return None if t is None else t.data_ptr()
+def _dev(t, name: str, device: int, dtypes=None, shape=None, optional: bool = False) -> Optional[int]:
+    """Device address of a tensor the library will read or write, after
+    checking that it is a contiguous torch tensor on GPU `device` with one of
+    `dtypes` and, if given, exactly `shape`. A host tensor, a tensor of
+    another device or a strided view would hand the kernels an address they
+    cannot use, so every such case is rejected here, before any launch."""
+    import torch
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor, not {type(t).__name__}")
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{name} must be on cuda:{device} (it is on {t.device})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtypes is not None and t.dtype not in dtypes:
+        raise ValueError(f"{name} must be {' or '.join(str(d) for d in dtypes)} (it is {t.dtype})")
+    if shape is not None and tuple(t.shape) != tuple(int(x) for x in shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (it has {tuple(t.shape)})")
+    return t.data_ptr()
+
+
+def _u8():
+    import torch
+    return (torch.uint8,)
+
+
+def _f32():
+    import torch
+    return (torch.float32,)
+
+
+def _f64():
+    import torch
+    return (torch.float64,)
+
+
+def _out_ptrs(out: dict, device: int, F: int, n: int, llr_dtype) -> tuple:
+    import torch
+    return (_dev(out.get("bits"), "out['bits']", device, _u8(), (F, n)),
+            _dev(out.get("iters"), "out['iters']", device, (torch.int32,), (F,)),
+            _dev(out.get("ok"), "out['ok']", device, _u8(), (F,)),
+            _dev(out.get("llr"), "out['llr']", device, (llr_dtype,), (F, n), optional=True))
 
 
 class Context:
@@ -150,6 +193,12 @@ class Context:
         if self.handle:
             lib().mbp_ctx_destroy(self.handle)
             self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:
@@ -198,6 +247,7 @@ class Code:
                                      ctypes.cast(ci_arr, ctypes.c_void_p), ctypes.byref(h)),
                "mbp_code_create")
         self.ctx = ctx
+        self.device = ctx.device
         self.handle = h
         self.n, self.u, self.m = int(n), u, m.tolist()
         self.M = int(m.sum())
@@ -221,6 +271,12 @@ class Code:
         if self.handle:
             lib().mbp_code_destroy(self.handle)
             self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:
@@ -248,11 +304,15 @@ def llr_from_bits(ctx: Context, y, e, dtype="f32", out=None, stream=None):
     per-frame error rates e [F] (float64, GPU)."""
     import torch
     dt = _dtype_code(dtype)
-    F, n = y.shape
+    if y.dim() != 2:
+        raise ValueError("y must be [F, n]")
+    F, n = (int(x) for x in y.shape)
+    py = _dev(y, "y", ctx.device, _u8())
+    pe = _dev(e, "e", ctx.device, _f64(), (F,))
     if out is None:
         out = torch.empty((F, n), dtype=_torch_dtype(dt), device=y.device)
-    _check(lib().mbp_llr_from_bits(ctx.handle, F, n, _dev_ptr(y), _dev_ptr(e), dt, _dev_ptr(out),
-                                   _stream_ptr(stream)), "mbp_llr_from_bits")
+    po = _dev(out, "out", ctx.device, (_torch_dtype(dt),), (F, n))
+    _check(lib().mbp_llr_from_bits(ctx.handle, F, n, py, pe, dt, po, _stream_ptr(stream)), "mbp_llr_from_bits")
     return out
 
 
@@ -274,13 +334,14 @@ def syndrome(ctx: Context, code: Code, x, out=None, stream=None):
     """Alice's syndromes, eq. (1): x [F, n] uint8 key bits (GPU) -> [F, M] uint8
     (the u syndromes of each frame back to back), computed on the GPU."""
     import torch
+    if x.dim() != 2:
+        raise ValueError("x must be [F, n]")
     F = int(x.shape[0])
-    if x.dim() != 2 or x.shape[1] != code.n or x.dtype != torch.uint8 or not x.is_contiguous():
-        raise ValueError("x must be a contiguous uint8 [F, n] tensor")
+    px = _dev(x, "x", ctx.device, _u8(), (F, code.n))
     if out is None:
         out = torch.empty((F, code.M), dtype=torch.uint8, device=x.device)
-    _check(lib().mbp_syndrome(ctx.handle, code.handle, F, _dev_ptr(x), _dev_ptr(out), _stream_ptr(stream)),
-           "mbp_syndrome")
+    po = _dev(out, "out", ctx.device, _u8(), (F, code.M))
+    _check(lib().mbp_syndrome(ctx.handle, code.handle, F, px, po, _stream_ptr(stream)), "mbp_syndrome")
     return out
 
 
@@ -294,20 +355,17 @@ def decode(ctx: Context, code: Code, llr, synd, algo: str = "spa", max_iter: int
     """
     import torch
     dt = _dtype_code(llr.dtype)
+    if llr.dim() != 2:
+        raise ValueError("llr must be [F, n]")
     F = int(llr.shape[0])
-    if llr.shape[1] != code.n or tuple(synd.shape) != (F, code.M):
-        raise ValueError("llr must be [F, n] and synd [F, M]")
-    if not (llr.is_contiguous() and synd.is_contiguous()):
-        raise ValueError("llr and synd must be contiguous")
-    if synd.dtype != torch.uint8:
-        raise ValueError("synd must be uint8")
+    pl = _dev(llr, "llr", ctx.device, (torch.float32, torch.float64), (F, code.n))
+    pz = _dev(synd, "synd", ctx.device, _u8(), (F, code.M))
     if out is None:
         out = _decode_outputs(F, code.n, llr.dtype, llr.device, want_llr)
+    pb, pi, pk, plo = _out_ptrs(out, ctx.device, F, code.n, llr.dtype)
     p = _params(algo, dt, max_iter, early_exit, alpha, clip, compact, schedule)
-    _check(lib().mbp_decode(ctx.handle, code.handle, ctypes.byref(p), F, _dev_ptr(llr),
-                            _dev_ptr(synd), _dev_ptr(out["bits"]), _dev_ptr(out["iters"]),
-                            _dev_ptr(out["ok"]), _dev_ptr(out.get("llr")), _stream_ptr(stream)),
-           "mbp_decode")
+    _check(lib().mbp_decode(ctx.handle, code.handle, ctypes.byref(p), F, pl, pz, pb, pi, pk, plo,
+                            _stream_ptr(stream)), "mbp_decode")
     return out
 
 
@@ -319,22 +377,19 @@ def decode_from_bits(ctx: Context, code: Code, y, e, synd, dtype: str = "f32", a
     error rates e [F] (float64, GPU); the LLRs are formed inside the decoder.
     Same outputs as llr_from_bits followed by decode, bit for bit."""
     import torch
+    if y.dim() != 2:
+        raise ValueError("y must be [F, n]")
     F = int(y.shape[0])
-    if y.dim() != 2 or y.shape[1] != code.n or tuple(e.shape) != (F,) or tuple(synd.shape) != (F, code.M):
-        raise ValueError("y must be [F, n], e [F] and synd [F, M]")
-    if not (y.is_contiguous() and e.is_contiguous() and synd.is_contiguous()):
-        raise ValueError("y, e and synd must be contiguous")
-    if y.dtype != torch.uint8 or synd.dtype != torch.uint8 or e.dtype != torch.float64:
-        raise ValueError("y and synd must be uint8, e float64")
-    tdt = torch.float32 if dtype == "f32" else torch.float64
+    py = _dev(y, "y", ctx.device, _u8(), (F, code.n))
+    pe = _dev(e, "e", ctx.device, _f64(), (F,))
+    pz = _dev(synd, "synd", ctx.device, _u8(), (F, code.M))
+    tdt = _torch_dtype(_dtype_code(dtype))
     if out is None:
         out = _decode_outputs(F, code.n, tdt, y.device, want_llr)
+    pb, pi, pk, plo = _out_ptrs(out, ctx.device, F, code.n, tdt)
     p = _params(algo, _dtype_code(tdt), max_iter, early_exit, alpha, clip, compact, schedule)
-    _check(lib().mbp_decode_from_bits(ctx.handle, code.handle, ctypes.byref(p), F, _dev_ptr(y),
-                                      _dev_ptr(e), _dev_ptr(synd), _dev_ptr(out["bits"]),
-                                      _dev_ptr(out["iters"]), _dev_ptr(out["ok"]),
-                                      _dev_ptr(out.get("llr")), _stream_ptr(stream)),
-           "mbp_decode_from_bits")
+    _check(lib().mbp_decode_from_bits(ctx.handle, code.handle, ctypes.byref(p), F, py, pe, pz, pb, pi, pk,
+                                      plo, _stream_ptr(stream)), "mbp_decode_from_bits")
     return out
 
 
@@ -350,14 +405,20 @@ def nms_unrolled_fwd(ctx: Context, code: Code, llr, synd, alpha, ckpt_every: int
                      workspace, out=None, stream=None):
     """L^K of K = alpha.shape[0] unrolled min-sum iterations (FP32, GPU tensors)."""
     import torch
+    if llr.dim() != 2 or alpha.dim() != 2:
+        raise ValueError("llr must be [F, n] and alpha [K, u]")
     F = int(llr.shape[0])
     K = int(alpha.shape[0])
+    pl = _dev(llr, "llr", ctx.device, _f32(), (F, code.n))
+    pz = _dev(synd, "synd", ctx.device, _u8(), (F, code.M))
+    pa = _dev(alpha, "alpha", ctx.device, _f32(), (K, code.u))
+    pw = _dev(workspace, "workspace", ctx.device, _u8())
     if out is None:
         out = torch.empty_like(llr)
+    po = _dev(out, "out", ctx.device, _f32(), (F, code.n))
     _check(lib().mbp_nms_unrolled_fwd(ctx.handle, code.handle, F, K, int(ckpt_every), float(clip),
-                                      _dev_ptr(llr), _dev_ptr(synd), _dev_ptr(alpha), _dev_ptr(out),
-                                      _dev_ptr(workspace), int(workspace.numel()),
-                                      _stream_ptr(stream)), "mbp_nms_unrolled_fwd")
+                                      pl, pz, pa, po, pw, int(workspace.numel()), _stream_ptr(stream)),
+           "mbp_nms_unrolled_fwd")
     return out
 
 
@@ -365,15 +426,20 @@ def nms_unrolled_bwd(ctx: Context, code: Code, llr, synd, alpha, grad_out, ckpt_
                      clip: float, workspace, stream=None):
     """(dJ/dllr, dJ/dalpha) of the unrolled forward for dJ/dL^K = grad_out."""
     import torch
+    if llr.dim() != 2 or alpha.dim() != 2:
+        raise ValueError("llr must be [F, n] and alpha [K, u]")
     F = int(llr.shape[0])
     K = int(alpha.shape[0])
+    pl = _dev(llr, "llr", ctx.device, _f32(), (F, code.n))
+    pz = _dev(synd, "synd", ctx.device, _u8(), (F, code.M))
+    pa = _dev(alpha, "alpha", ctx.device, _f32(), (K, code.u))
+    pg = _dev(grad_out, "grad_out", ctx.device, _f32(), (F, code.n))
+    pw = _dev(workspace, "workspace", ctx.device, _u8())
     grad_llr = torch.empty_like(llr)
     grad_alpha = torch.empty_like(alpha)
     _check(lib().mbp_nms_unrolled_bwd(ctx.handle, code.handle, F, K, int(ckpt_every), float(clip),
-                                      _dev_ptr(llr), _dev_ptr(synd), _dev_ptr(alpha),
-                                      _dev_ptr(grad_out), _dev_ptr(grad_llr), _dev_ptr(grad_alpha),
-                                      _dev_ptr(workspace), int(workspace.numel()),
-                                      _stream_ptr(stream)), "mbp_nms_unrolled_bwd")
+                                      pl, pz, pa, pg, grad_llr.data_ptr(), grad_alpha.data_ptr(), pw,
+                                      int(workspace.numel()), _stream_ptr(stream)), "mbp_nms_unrolled_bwd")
     return grad_llr, grad_alpha
 
 
@@ -418,9 +484,11 @@ def unrolled_nms(ctx: Context, code: Code, llr, synd, alpha, ckpt_every: int = 5
 
 
 # ----------------------------------------------------------- batched decode
-def _nms_params(max_iter, early_exit, alpha, clip):
-    return mbp_params(MBP_ALGO_NMS, MBP_F32, int(max_iter), int(bool(early_exit)), float(alpha),
-                      float(clip))
+def _batched_params(algo, max_iter, early_exit, alpha, clip):
+    if algo not in ("spa", "nms"):
+        raise ValueError(f"unknown algo {algo!r}")
+    return mbp_params(MBP_ALGO_SPA if algo == "spa" else MBP_ALGO_NMS, MBP_F32, int(max_iter),
+                      int(bool(early_exit)), float(alpha), float(clip))
 
 
 def batch_outputs(code: Code, llr, want_llr: bool = True) -> dict:
@@ -434,15 +502,17 @@ def batch_outputs(code: Code, llr, want_llr: bool = True) -> dict:
 
 
 def _batches(items, outs):
+    if len(items) != len(outs):
+        raise ValueError("one output dict per batch")
     arr = (mbp_batch * len(items))()
     for k, ((code, llr, synd), o) in enumerate(zip(items, outs)):
-        if llr.dtype.is_floating_point and llr.element_size() != 4:
-            raise ValueError("the batched decode takes float32 LLRs")
-        if tuple(llr.shape) != (llr.shape[0], code.n) or tuple(synd.shape) != (llr.shape[0], code.M):
-            raise ValueError("llr must be [F, n] and synd [F, M]")
-        arr[k] = mbp_batch(code.handle.value, int(llr.shape[0]), _dev_ptr(llr), _dev_ptr(synd),
-                           _dev_ptr(o["bits"]), _dev_ptr(o["iters"]), _dev_ptr(o["ok"]),
-                           _dev_ptr(o.get("llr")))
+        if llr.dim() != 2:
+            raise ValueError(f"batch {k}: llr must be [F, n]")
+        F, dev = int(llr.shape[0]), code.device
+        pl = _dev(llr, f"batch {k} llr", dev, _f32(), (F, code.n))
+        pz = _dev(synd, f"batch {k} synd", dev, _u8(), (F, code.M))
+        pb, pi, pk, plo = _out_ptrs(o, dev, F, code.n, llr.dtype)
+        arr[k] = mbp_batch(code.handle.value, F, pl, pz, pb, pi, pk, plo)
     return arr
 
 
@@ -463,13 +533,13 @@ def default_tuning() -> dict:
 
 def decode_batched(ctx: Context, items, max_iter: int = 100, early_exit: bool = True,
                    alpha: float = 0.75, clip: float = 20.0, tuning=None, outs=None,
-                   want_llr: bool = True, stream=None):
+                   want_llr: bool = True, stream=None, algo: str = "nms"):
     """Decode [(Code, llr [F, n] f32, synd [F, M] u8), ...] in one persistent launch
-    (normalized min-sum, FP32). Returns one output dict per item."""
+    (FP32, min-sum or sum-product). Returns one output dict per item."""
     if outs is None:
         outs = [batch_outputs(c, l, want_llr) for c, l, _ in items]
     arr = _batches(items, outs)
-    p = _nms_params(max_iter, early_exit, alpha, clip)
+    p = _batched_params(algo, max_iter, early_exit, alpha, clip)
     tu = _tuning(tuning)
     _check(lib().mbp_decode_batched(ctx.handle, len(items), arr, ctypes.byref(p),
                                     ctypes.byref(tu) if tu is not None else None,
@@ -479,11 +549,11 @@ def decode_batched(ctx: Context, items, max_iter: int = 100, early_exit: bool = 
 
 def autotune(ctx: Context, items, max_iter: int = 100, early_exit: bool = True,
              alpha: float = 0.75, clip: float = 20.0, cache_path: Optional[str] = None,
-             outs=None) -> dict:
+             outs=None, algo: str = "nms") -> dict:
     if outs is None:
         outs = [batch_outputs(c, l) for c, l, _ in items]
     arr = _batches(items, outs)
-    p = _nms_params(max_iter, early_exit, alpha, clip)
+    p = _batched_params(algo, max_iter, early_exit, alpha, clip)
     t = mbp_tuning()
     _check(lib().mbp_autotune(ctx.handle, len(items), arr, ctypes.byref(p),
                               cache_path.encode() if cache_path else None, ctypes.byref(t)),
@@ -495,16 +565,16 @@ class Plan:
     """A captured hipGraph of a batched decode over fixed buffers."""
 
     def __init__(self, ctx: Context, items, outs, max_iter: int = 100, early_exit: bool = True,
-                 alpha: float = 0.75, clip: float = 20.0, tuning=None):
+                 alpha: float = 0.75, clip: float = 20.0, tuning=None, algo: str = "nms"):
         arr = _batches(items, outs)
-        p = _nms_params(max_iter, early_exit, alpha, clip)
+        p = _batched_params(algo, max_iter, early_exit, alpha, clip)
         tu = _tuning(tuning)
         h = ctypes.c_void_p()
         _check(lib().mbp_plan_create(ctx.handle, len(items), arr, ctypes.byref(p),
                                      ctypes.byref(tu) if tu is not None else None, ctypes.byref(h)),
                "mbp_plan_create")
         self.handle = h
-        self.items, self.outs = items, outs
+        self.ctx, self.items, self.outs = ctx, items, outs
 
     def launch(self, stream=None):
         _check(lib().mbp_plan_launch(self.handle, _stream_ptr(stream)), "mbp_plan_launch")
@@ -516,6 +586,12 @@ class Plan:
         if self.handle:
             lib().mbp_plan_destroy(self.handle)
             self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:
@@ -531,13 +607,14 @@ class Queue:
     their flush completes; the queue keeps references to them until then."""
 
     def __init__(self, ctx: Context, max_iter: int = 100, early_exit: bool = True, alpha: float = 0.75,
-                 clip: float = 20.0, tuning=None):
-        p = _nms_params(max_iter, early_exit, alpha, clip)
+                 clip: float = 20.0, tuning=None, algo: str = "nms"):
+        p = _batched_params(algo, max_iter, early_exit, alpha, clip)
         tu = _tuning(tuning)
         h = ctypes.c_void_p()
         _check(lib().mbp_queue_create(ctx.handle, ctypes.byref(p), ctypes.byref(tu) if tu is not None else None,
                                       ctypes.byref(h)), "mbp_queue_create")
         self.handle = h
+        self.ctx = ctx
         self._pending, self._flights, self._done = [], [], 0
 
     def submit(self, items, outs):
@@ -572,6 +649,12 @@ class Queue:
             lib().mbp_queue_destroy(self.handle)
             self.handle = None
             self._flights = []
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:

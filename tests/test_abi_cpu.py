@@ -65,3 +65,71 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(mbp, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         mbp.lib()
+
+
+def test_binding_rejects_host_and_misshaped_tensors(monkeypatch):
+    """Every device buffer is checked in the binding before the library is
+    called: a host tensor (a GPU page fault if its address reached a kernel),
+    a strided view, a wrong dtype or shape, and an alpha that is not [K, u]
+    are all refused with ValueError, and no library call happens."""
+    import types
+
+    import torch
+    from paper_2001_07979_amd import mbp
+
+    def no_call():
+        raise AssertionError("the library was called")
+
+    monkeypatch.setattr(mbp, "lib", no_call)
+    ctx = types.SimpleNamespace(device=0, handle=None)
+    code = types.SimpleNamespace(n=8, M=4, u=2, device=0, handle=types.SimpleNamespace(value=None))
+    F = 3
+    y = torch.zeros((F, 8), dtype=torch.uint8)
+    e = torch.full((F,), 0.05, dtype=torch.float64)
+    z = torch.zeros((F, 4), dtype=torch.uint8)
+    lam = torch.zeros((F, 8), dtype=torch.float32)
+    with pytest.raises(ValueError, match="cuda:0"):
+        mbp.llr_from_bits(ctx, y, e)
+    with pytest.raises(ValueError, match="cuda:0"):
+        mbp.decode(ctx, code, lam, z)
+    with pytest.raises(ValueError, match="cuda:0"):
+        mbp.decode_from_bits(ctx, code, y, e, z)
+    with pytest.raises(ValueError, match="cuda:0"):
+        mbp.syndrome(ctx, code, y)
+    with pytest.raises(ValueError, match="cuda:0"):
+        mbp.nms_unrolled_fwd(ctx, code, lam, z, torch.zeros((5, 2)), 1, 20.0, torch.zeros(4, dtype=torch.uint8))
+    with pytest.raises(ValueError, match="cuda:0"):
+        mbp.decode_batched(ctx, [(code, lam, z)], outs=[{}])
+
+
+def test_device_check_order_on_fake_cuda_tensors(monkeypatch):
+    """The device check itself, with the CUDA test answered by a stand-in so
+    it runs without a GPU: strided views, wrong dtypes and shapes, and an
+    alpha of the wrong [K, u] shape are rejected."""
+    import torch
+    from paper_2001_07979_amd import mbp
+
+    class FakeCuda(torch.Tensor):
+        @property
+        def is_cuda(self):
+            return True
+
+        @property
+        def device(self):
+            return torch.device("cuda", 0)
+
+    def fake(t):
+        return t.as_subclass(FakeCuda)
+
+    a = fake(torch.zeros((4, 6), dtype=torch.float32))
+    assert mbp._dev(a, "a", 0, (torch.float32,), (4, 6)) == a.data_ptr()
+    with pytest.raises(ValueError, match="cuda:1"):
+        mbp._dev(a, "a", 1)
+    with pytest.raises(ValueError, match="contiguous"):
+        mbp._dev(fake(torch.zeros((6, 4)).t()), "a", 0)
+    with pytest.raises(ValueError, match="torch.float64"):
+        mbp._dev(a, "a", 0, (torch.float64,))
+    with pytest.raises(ValueError, match="shape"):
+        mbp._dev(a, "alpha", 0, (torch.float32,), (5, 2))
+    with pytest.raises(TypeError):
+        mbp._dev([1, 2], "a", 0)

@@ -218,3 +218,84 @@ def test_autograd_bce_training_step(ctx):
                                atol=1e-4 * np.abs(galpha32).max() + 1e-30)
     L64 = oracle.nms_unrolled(wl.code, K, a64, lam.astype(np.float64), fr.z)
     np.testing.assert_allclose(Lg, L64, rtol=1e-4, atol=1e-3)
+
+
+def test_config_scale_gradients(ctx):
+    """The configured training workload: the u=2 n=16384 rate-1/2 code, K=20,
+    checkpoints every 5, 512 frames at BSC p ~ U[0.04, 0.08], weights alpha
+    [20, 2] drawn in [0.65, 0.85], objective J = sum w * L^K with random w.
+
+    * Forward and backward on all 512 frames; on 8 sampled frames L^K bit
+      for bit against the oracle's binary32 forward and dJ/dllr against its
+      FP64 reverse sweep of that trajectory; dJ/dalpha over all frames equal
+      to the sum over 8 launches of 64 frames each (a different reduction
+      grouping: FP32 rounding only) and, for the 8-frame launch, to the oracle.
+    * Central differences (eps = 1e-3) of the GPU forward on 2 tie-free
+      frames: 64 llr coordinates (32 where w is nonzero, 32 anywhere) and all
+      40 weights, on coordinates where both one-sided slopes agree (the map
+      is piecewise linear)."""
+    import torch
+    from paper_2001_07979_amd import mbp
+    wl = W.unrolled_n16384(nframes=512)
+    fr = wl.frames()
+    code, K, F = wl.code, wl.max_iter, 512
+    rng = np.random.default_rng(20)
+    alpha = rng.uniform(0.65, 0.85, (K, 2)).astype(np.float32).astype(np.float64)
+    with mbp.Code.from_inputs(ctx, code) as dc:
+        llr, z, a, lam = _tensors(fr, alpha)
+        w = rng.normal(size=lam.shape)
+        wt = torch.from_numpy(w.astype(np.float32)).cuda()
+        L, g_llr, g_alpha = _run(ctx, dc, llr, z, a, gL=wt)
+        idx = np.array([0, 63, 64, 200, 317, 384, 450, 511])
+        L32, glam32, galpha32 = oracle.nms_unrolled(code, K, alpha, lam[idx], fr.z[idx], gL=w[idx], binary32=True)
+        assert np.array_equal(L[idx], L32)
+        close = _grad_close(g_llr[idx], glam32, 1e-4, 1e-5)
+        assert close.all(), f"{(~close).sum()} of {close.size} coordinates differ"
+        assert np.abs(g_alpha).max() > 1.0  # a gradient that carries signal
+        parts = np.zeros_like(g_alpha)
+        for c0 in range(0, F, 64):
+            parts += _run(ctx, dc, llr[c0:c0 + 64].contiguous(), z[c0:c0 + 64].contiguous(), a,
+                          gL=wt[c0:c0 + 64].contiguous())[2]
+        np.testing.assert_allclose(g_alpha, parts, rtol=1e-5, atol=1e-6 * np.abs(parts).max())
+        sub = _run(ctx, dc, llr[idx].contiguous(), z[idx].contiguous(), a, gL=wt[idx].contiguous())
+        np.testing.assert_allclose(sub[2], galpha32, rtol=1e-4, atol=1e-5 * np.abs(galpha32).max())
+
+        # central differences on two tie-free frames with a sparse objective
+        two = [np.argmax(fr.p), np.argsort(fr.p)[-2]]  # the two noisiest frames
+        lam2 = (lam[two] * rng.uniform(0.7, 1.3, (2, code.n))).astype(np.float32).astype(np.float64)
+        z2 = z[torch.tensor(two, device="cuda")].contiguous()
+        w2 = np.zeros_like(lam2)
+        sup = rng.choice(lam2.size, 256, replace=False)
+        w2.flat[sup] = rng.normal(size=256)
+        x2 = torch.from_numpy(lam2.astype(np.float32)).cuda()
+        _, g2, ga2 = _run(ctx, dc, x2, z2, a, gL=torch.from_numpy(w2.astype(np.float32)).cuda())
+
+        def J(l, al):
+            return float((_run(ctx, dc, torch.from_numpy(l.astype(np.float32)).cuda(), z2,
+                               torch.from_numpy(al.astype(np.float32)).cuda()) * w2).sum())
+
+        eps = 1e-3
+        j0 = J(lam2, alpha)
+        coords = np.concatenate([sup[:32], rng.choice(lam2.size, 32, replace=False)])
+        checked = 0
+        for i in coords:
+            xp, xm = lam2.copy(), lam2.copy()
+            xp.flat[i] += eps
+            xm.flat[i] -= eps
+            right, left = (J(xp, alpha) - j0) / eps, (j0 - J(xm, alpha)) / eps
+            if abs(right - left) <= 2e-2 * (1 + abs(right)):
+                fd = 0.5 * (right + left)
+                assert abs(g2.flat[i] - fd) <= 1e-2 * (1 + abs(fd)), (i, g2.flat[i], fd)
+                checked += 1
+        assert checked >= 48
+        checked = 0
+        for k in range(alpha.size):
+            ap, am = alpha.copy(), alpha.copy()
+            ap.flat[k] += eps
+            am.flat[k] -= eps
+            right, left = (J(lam2, ap) - j0) / eps, (j0 - J(lam2, am)) / eps
+            if abs(right - left) <= 2e-2 * (1 + abs(right)):
+                fd = 0.5 * (right + left)
+                assert abs(ga2.flat[k] - fd) <= 1e-3 * (1 + abs(fd)), (k, ga2.flat[k], fd)
+                checked += 1
+        assert checked >= 30
