@@ -32,9 +32,11 @@ class _Params(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("early_exit", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("clip", ctypes.c_double), ("alpha_tl", ctypes.c_void_p),
-                ("margin", ctypes.c_double), ("schedule", ctypes.c_int32)]
+                ("margin", ctypes.c_double), ("schedule", ctypes.c_int32),
+                ("coupling", ctypes.c_int32)]
 
 FLOODING, SERIAL = 0, 1  # schedules: flooding, matrix-serial
+JOINT, INDEPENDENT = 0, 1  # how the u matrices combine: one stacked graph, or u decoders joined by eq. (2)
 
 
 def lib():
@@ -107,7 +109,7 @@ def llr_from_bits(y: np.ndarray, e) -> np.ndarray:
 def decode(code, llr: np.ndarray, synd: np.ndarray, algo: int = SPA, max_iter: int = 50,
            early_exit: bool = True, alpha: float = 0.75, clip: float = 20.0,
            alpha_tl: Optional[np.ndarray] = None, margin: float = 1e-3,
-           nthreads: int = 0, schedule: int = FLOODING) -> dict:
+           nthreads: int = 0, schedule: int = FLOODING, coupling: int = JOINT) -> dict:
     """FP64 MBP decode of every frame; returns bits, iters, ok, L, flag."""
     llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float64)
     synd = np.ascontiguousarray(np.atleast_2d(synd), dtype=np.uint8)
@@ -119,7 +121,7 @@ def decode(code, llr: np.ndarray, synd: np.ndarray, algo: int = SPA, max_iter: i
         atl = np.ascontiguousarray(alpha_tl, dtype=np.float64)
         assert atl.shape == (max_iter, len(code.row_ptr))
     P = _Params(int(algo), int(max_iter), int(bool(early_exit)), float(alpha), float(clip),
-                atl.ctypes.data if atl is not None else None, float(margin), int(schedule))
+                atl.ctypes.data if atl is not None else None, float(margin), int(schedule), int(coupling))
     bits = np.zeros((F, n), dtype=np.uint8)
     iters = np.zeros(F, dtype=np.int32)
     ok = np.zeros(F, dtype=np.uint8)
@@ -137,7 +139,7 @@ def decode(code, llr: np.ndarray, synd: np.ndarray, algo: int = SPA, max_iter: i
 def decode_nms_f32(code, llr: np.ndarray, synd: np.ndarray, max_iter: int = 50,
                    early_exit: bool = True, alpha: float = 0.75, clip: float = 20.0,
                    alpha_tl: Optional[np.ndarray] = None, nthreads: int = 0,
-                   schedule: int = FLOODING) -> dict:
+                   schedule: int = FLOODING, coupling: int = JOINT) -> dict:
     """Normalized min-sum decode with every operation in binary32 (see the C source)."""
     llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float64)
     synd = np.ascontiguousarray(np.atleast_2d(synd), dtype=np.uint8)
@@ -149,7 +151,7 @@ def decode_nms_f32(code, llr: np.ndarray, synd: np.ndarray, max_iter: int = 50,
         atl = np.ascontiguousarray(alpha_tl, dtype=np.float64)
         assert atl.shape == (max_iter, len(code.row_ptr))
     P = _Params(NMS, int(max_iter), int(bool(early_exit)), float(alpha), float(clip),
-                atl.ctypes.data if atl is not None else None, 1e-3, int(schedule))
+                atl.ctypes.data if atl is not None else None, 1e-3, int(schedule), int(coupling))
     bits = np.zeros((F, n), dtype=np.uint8)
     iters = np.zeros(F, dtype=np.int32)
     ok = np.zeros(F, dtype=np.uint8)

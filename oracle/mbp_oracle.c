@@ -30,6 +30,15 @@
  *   - the normalized min-sum rule (not in the paper) replaces the tanh rule by
  *     alpha times the product of signs times the smallest other magnitude.
  *
+ * A second reading of how the u matrices combine (coupling = 1): Sec. 2
+ * forms the LLRs and variable-to-check messages "for all u matrices
+ * respectively", so each matrix may run its own decoder: matrix l's
+ * variable-to-check message on an edge is the channel LLR plus the other
+ * check messages of matrix l alone at that variable (its own posterior
+ * lambda + S^l minus the edge's message), and only the soft decision of
+ * eq. (2), lambda + sum over l of S^l, joins the matrices. S^l is matrix
+ * l's messages at the variable summed from 0 in check order.
+ *
  * Everything is FP64, one frame at a time, with every exclusion ("all other
  * edges of the check") evaluated directly as its definition states.
  * Frames are spread over POSIX threads; each frame's arithmetic is serial.
@@ -58,6 +67,7 @@ typedef struct {
     const double *alpha_tl;  /* optional [T][u] per-iteration, per-matrix weights (min-sum) */
     double margin;           /* delta for the near-tie flag */
     int32_t schedule;        /* 0 = flooding; 1 = matrix-serial (see phase_rows) */
+    int32_t coupling;        /* 0 = one stacked graph; 1 = u independent decoders (see below) */
 } oracle_params;
 
 /* ---------------------------------------------------------------------- */
@@ -218,6 +228,31 @@ static float vsum_fd(const graph *g, int32_t i, float lam, const double *c) {
     return L;
 }
 
+/* Independent decoders: matrix l's posterior at variable i, lambda + S^l
+   (S^l: matrix l's messages at i summed from 0 in check order), for every
+   matrix; lambda alone where matrix l has no edge at i. */
+static void matrix_posteriors_d(const graph *g, int32_t i, double lam, const double *c, double *Lm) {
+    for (int32_t l = 0; l < g->u; ++l) {
+        double S = 0.0;
+        for (int32_t k = g->var_start[i]; k < g->var_start[i + 1]; ++k) {
+            const int32_t e = g->var_edges[k];
+            if (g->edge_matrix[e] == l) S += c[e];
+        }
+        Lm[(size_t)l * (size_t)g->n + (size_t)i] = lam + S;
+    }
+}
+
+static void matrix_posteriors_f(const graph *g, int32_t i, float lam, const float *c, float *Lm) {
+    for (int32_t l = 0; l < g->u; ++l) {
+        float S = 0.0f;
+        for (int32_t k = g->var_start[i]; k < g->var_start[i + 1]; ++k) {
+            const int32_t e = g->var_edges[k];
+            if (g->edge_matrix[e] == l) S += c[e];
+        }
+        Lm[(size_t)l * (size_t)g->n + (size_t)i] = lam + S;
+    }
+}
+
 /* Sec. 3B, eq. (6): check-to-variable messages of one check, sum-product.
    For each edge k: c_k = (-1)^z * 2 atanh( prod over the other edges k' of
    tanh(q_k' / 2) ), with q clipped to [-C, C] first. */
@@ -269,6 +304,7 @@ static double weight_of(const oracle_params *P, int32_t t, int32_t l, int32_t u)
 
 typedef struct {
     double *c, *q, *L, *th, *tmp;
+    double *Lm; /* [u][n] per-matrix posteriors lambda + S^l (independent decoders) */
     uint8_t *xhat;
 } frame_buf;
 
@@ -279,7 +315,8 @@ static int buf_alloc(frame_buf *b, const graph *g, int32_t maxdeg) {
     b->th = malloc(sizeof(double) * (size_t)(maxdeg > g->n ? maxdeg : (g->n > 0 ? g->n : 1)));
     b->tmp = malloc(sizeof(double) * (size_t)(maxdeg > 0 ? maxdeg : 1));
     b->xhat = malloc((size_t)(g->n > 0 ? g->n : 1));
-    return (b->c && b->q && b->L && b->th && b->tmp && b->xhat) ? 0 : -1;
+    b->Lm = malloc(sizeof(double) * (size_t)(g->n > 0 ? g->n : 1) * (size_t)g->u);
+    return (b->c && b->q && b->L && b->th && b->tmp && b->xhat && b->Lm) ? 0 : -1;
 }
 
 static void buf_free(frame_buf *b) {
@@ -289,6 +326,7 @@ static void buf_free(frame_buf *b) {
     free(b->th);
     free(b->tmp);
     free(b->xhat);
+    free(b->Lm);
 }
 
 /* Rows (stacked checks) updated in phase ph of an iteration. Flooding: one
@@ -325,6 +363,8 @@ static void decode_frame(const graph *g, const oracle_params *P, const double *l
        channel LLR; equivalently no check message yet (c = 0) and L = lambda. */
     for (int32_t e = 0; e < E; ++e) b->c[e] = 0.0;
     for (int32_t i = 0; i < n; ++i) b->L[i] = lam[i];
+    for (int32_t l = 0; l < g->u; ++l)
+        for (int32_t i = 0; i < n; ++i) b->Lm[(size_t)l * (size_t)n + (size_t)i] = lam[i];
     int32_t t_stop = P->max_iter;
     int stopped = 0;
     uint8_t fl = 0;
@@ -333,9 +373,11 @@ static void decode_frame(const graph *g, const oracle_params *P, const double *l
             int32_t r0, r1;
             phase_rows(g, P, ph, &r0, &r1);
             /* variable-to-check messages from the current soft decisions:
-               the soft decision minus the message that came in on this edge */
+               the soft decision minus the message that came in on this edge
+               (independent decoders: the posterior of the edge's own matrix) */
             for (int32_t e = g->row_start[r0]; e < g->row_start[r1]; ++e)
-                b->q[e] = b->L[g->edge_var[e]] - b->c[e];
+                b->q[e] = (P->coupling ? b->Lm[(size_t)g->edge_matrix[e] * (size_t)n + (size_t)g->edge_var[e]]
+                                       : b->L[g->edge_var[e]]) - b->c[e];
             /* check-to-variable messages of the phase's checks */
             for (int32_t r = r0; r < r1; ++r) {
                 int32_t e0 = g->row_start[r], d = g->row_start[r + 1] - e0;
@@ -349,6 +391,8 @@ static void decode_frame(const graph *g, const oracle_params *P, const double *l
             /* eq. (2): soft decision = channel LLR + every incoming check
                message, a sum per matrix added in matrix order */
             for (int32_t i = 0; i < n; ++i) b->L[i] = vsum_d(g, i, lam[i], b->c);
+            if (P->coupling)
+                for (int32_t i = 0; i < n; ++i) matrix_posteriors_d(g, i, lam[i], b->c, b->Lm);
         }
         /* decision: bit 1 iff L < 0 */
         for (int32_t i = 0; i < n; ++i) b->xhat[i] = b->L[i] < 0.0 ? 1 : 0;
@@ -398,16 +442,21 @@ static void decode_frame_nms_f32(const graph *g, const oracle_params *P, const d
     const int32_t n = g->n, E = g->E;
     float *c = (float *)b->c, *q = (float *)b->q, *L = (float *)b->L, *lam = (float *)b->th;
     const float C = (float)P->clip;
+    float *Lm = (float *)b->Lm;
     for (int32_t i = 0; i < n; ++i) lam[i] = (float)lam64[i];
     for (int32_t e = 0; e < E; ++e) c[e] = 0.0f;
     for (int32_t i = 0; i < n; ++i) L[i] = lam[i];
+    for (int32_t l = 0; l < g->u; ++l)
+        for (int32_t i = 0; i < n; ++i) Lm[(size_t)l * (size_t)n + (size_t)i] = lam[i];
     int32_t t_stop = P->max_iter;
     int stopped = 0;
     for (int32_t t = 1; t <= P->max_iter; ++t) {
         for (int32_t ph = 0; ph < phase_count(g, P); ++ph) {
             int32_t r0, r1;
             phase_rows(g, P, ph, &r0, &r1);
-            for (int32_t e = g->row_start[r0]; e < g->row_start[r1]; ++e) q[e] = L[g->edge_var[e]] - c[e];
+            for (int32_t e = g->row_start[r0]; e < g->row_start[r1]; ++e)
+                q[e] = (P->coupling ? Lm[(size_t)g->edge_matrix[e] * (size_t)n + (size_t)g->edge_var[e]]
+                                    : L[g->edge_var[e]]) - c[e];
             for (int32_t r = r0; r < r1; ++r) {
                 int32_t e0 = g->row_start[r], d = g->row_start[r + 1] - e0;
                 float zs = z[r] ? -1.0f : 1.0f;
@@ -427,6 +476,8 @@ static void decode_frame_nms_f32(const graph *g, const oracle_params *P, const d
                 for (int32_t k = 0; k < d; ++k) c[e0 + k] = tmp[k];
             }
             for (int32_t i = 0; i < n; ++i) L[i] = vsum_f(g, i, lam[i], c);
+            if (P->coupling)
+                for (int32_t i = 0; i < n; ++i) matrix_posteriors_f(g, i, lam[i], c, Lm);
         }
         for (int32_t i = 0; i < n; ++i) b->xhat[i] = L[i] < 0.0f ? 1 : 0;
         if (P->early_exit && unsatisfied(g, b->xhat, z) == 0) {

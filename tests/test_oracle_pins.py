@@ -609,7 +609,7 @@ def test_syndrome_is_linear_and_agrees_with_the_residual_weight(small_peg):
 
 
 # --------------------------------------- binary32 rounding order (R16, R12)
-def _nms_f32_by_hand(Hs, lam, z, alpha, T, C=20.0, nested=True, alpha_in_double=False):
+def _nms_f32_by_hand(Hs, lam, z, alpha, T, C=20.0, nested=True, alpha_in_double=False, independent=False):
     """T flooding min-sum iterations written out in numpy float32 for a tiny
     code: q = L - c; |q| capped at C; c = (-1)^z * alpha * prod sgn * min over
     the other edges; eq. (2) either with its nesting (each matrix's messages
@@ -622,8 +622,9 @@ def _nms_f32_by_hand(Hs, lam, z, alpha, T, C=20.0, nested=True, alpha_in_double=
     lam = lam.astype(f32)
     c = [np.zeros(len(r), f32) for _, r in rows]
     L = lam.copy()
+    P = [lam.copy() for _ in Hs]  # each matrix's own posterior lambda + S^l (independent decoders)
     for _ in range(T):
-        q = [L[r] - c[k] for k, (_, r) in enumerate(rows)]
+        q = [(P[l] if independent else L)[r] - c[k] for k, (l, r) in enumerate(rows)]
         new = []
         for k, (_, r) in enumerate(rows):
             out = np.zeros(len(r), f32)
@@ -652,6 +653,12 @@ def _nms_f32_by_hand(Hs, lam, z, alpha, T, C=20.0, nested=True, alpha_in_double=
                 for _, x in msgs:
                     s = f32(s + x)
             L[i] = s
+            for l in range(len(Hs)):
+                S = f32(0)
+                for m, x in msgs:
+                    if m == l:
+                        S = f32(S + x)
+                P[l][i] = f32(lam[i] + S)
     return L
 
 
@@ -743,3 +750,102 @@ def test_tie_flag_follows_its_definition(algo):
         assert int(full["flag"][f]) == int(c1 or c2), f
         kinds.add((c1, c2, c2_rejected and not (c1 or c2)))
     assert {(True, False, False), (False, True, False), (False, False, False)} <= kinds, kinds
+
+
+# --------------------------- the u matrices as independent decoders (Sec. 2)
+def test_worked_path_example_independent():
+    g = json.load(open(GOLDEN))["path_u2_independent"]
+    code = code_from_dense([np.array(h) for h in g["H"]])
+    lam = np.array([g["lambda"]])
+    z = np.array([g["z"]], dtype=np.uint8)
+    kw = dict(algo=oracle.SPA, early_exit=False, clip=1e3, coupling=oracle.INDEPENDENT)
+    np.testing.assert_allclose(_dec(code, lam, z, max_iter=1, **kw)["L"][0], g["L_t1"], rtol=1e-14)
+    np.testing.assert_allclose(_dec(code, lam, z, max_iter=2, **kw)["L"][0], g["L_t2"], rtol=1e-14)
+    r = _dec(code, lam, z, algo=oracle.SPA, max_iter=6, clip=1e3, coupling=oracle.INDEPENDENT)
+    assert r["ok"][0] == g["ok"] and r["iters"][0] == 6 and r["bits"][0].tolist() == g["bits"]
+    # the stacked graph decodes the same frame (path_u2): the readings differ
+    assert _dec(code, lam, z, algo=oracle.SPA, max_iter=6, clip=1e3)["ok"][0] == 1
+
+
+def _forest_stack(rng, n, u):
+    """u matrices, each alone a spanning tree on the n bits (their stack has cycles)."""
+    return [brute.random_tree_code(rng, n, u=1)[0] for _ in range(u)]
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_independent_decoders_on_per_matrix_trees(seed):
+    """Each matrix alone a tree: each independent decoder converges to the
+    exact MAP LLRs of its own matrix (sum-product) or max-marginals (min-sum,
+    alpha = 1), so eq. (2) gives lambda + sum over l of (MAP_l - lambda),
+    computed here by enumeration of each matrix separately."""
+    rng = np.random.default_rng(700 + seed)
+    n = int(rng.integers(8, 13))
+    u = 2 + seed % 2
+    Hs = _forest_stack(rng, n, u)
+    code = code_from_dense(Hs)
+    x = rng.integers(0, 2, n).astype(np.uint8)
+    z = syndromes(code, x[None])[0]
+    zs = np.split(z, np.cumsum([h.shape[0] for h in Hs])[:-1])
+    lam = rng.normal(0, 2.5, size=n)
+    r = _dec(code, lam[None], z[None], algo=oracle.SPA, max_iter=n, early_exit=False, clip=1e3,
+             coupling=oracle.INDEPENDENT)
+    want = lam + sum(brute.map_llr(H, zl, lam) - lam for H, zl in zip(Hs, zs))
+    np.testing.assert_allclose(r["L"][0], want, rtol=1e-10, atol=1e-10)
+    r = _dec(code, lam[None], z[None], algo=oracle.NMS, alpha=1.0, max_iter=n, early_exit=False, clip=1e6,
+             coupling=oracle.INDEPENDENT)
+    want = lam + sum(brute.max_marginal(H, zl, lam) - lam for H, zl in zip(Hs, zs))
+    np.testing.assert_allclose(r["L"][0], want, rtol=1e-12, atol=1e-12)
+    # the joint reading on the same (cyclic) stack is a different decoder
+    j = _dec(code, lam[None], z[None], algo=oracle.SPA, max_iter=n, early_exit=False, clip=1e3)
+    assert not np.allclose(j["L"][0], r["L"][0])
+
+
+@pytest.mark.parametrize("algo", [oracle.SPA, oracle.NMS])
+def test_independent_is_single_matrix_decoders_joined_by_eq2(small_peg, algo):
+    """On codes with cycles, the independent reading's soft decisions after T
+    iterations are lambda + the sum over l of (L_l - lambda), L_l being a
+    u = 1 decode of H_l alone for T iterations; with one matrix the two
+    readings are the same decoder, bit for bit."""
+    from paper_2001_07979_amd.inputs import Code
+    fr = bsc_frames(small_peg, 6, 0.05, seed=71)
+    lam = oracle.llr_from_bits(fr.y, fr.p)
+    T = 6
+    r = _dec(small_peg, lam, fr.z, algo=algo, max_iter=T, early_exit=False, coupling=oracle.INDEPENDENT)
+    m = np.cumsum([0] + list(small_peg.m))
+    want = lam.copy()
+    for l in range(small_peg.u):
+        one = Code(n=small_peg.n, row_ptr=[small_peg.row_ptr[l]], col_idx=[small_peg.col_idx[l]], name="one")
+        L_l = _dec(one, lam, fr.z[:, m[l]:m[l + 1]], algo=algo, max_iter=T, early_exit=False)["L"]
+        want += L_l - lam
+        same = _dec(one, lam, fr.z[:, m[l]:m[l + 1]], algo=algo, max_iter=T, early_exit=False,
+                    coupling=oracle.INDEPENDENT)
+        assert np.array_equal(same["L"], L_l)
+    np.testing.assert_allclose(r["L"], want, rtol=1e-12, atol=1e-12)
+
+
+def test_independent_declared_success_meets_every_syndrome(small_peg):
+    fr = bsc_frames(small_peg, 24, np.linspace(0.01, 0.08, 24), seed=72)
+    lam = oracle.llr_from_bits(fr.y, fr.p)
+    for algo in (oracle.SPA, oracle.NMS):
+        r = _dec(small_peg, lam, fr.z, algo=algo, max_iter=40, coupling=oracle.INDEPENDENT)
+        ok = r["ok"] == 1
+        assert 0 < ok.sum()
+        assert np.array_equal(syndromes(small_peg, r["bits"][ok]), fr.z[ok])
+        assert np.all(r["iters"][~ok] == 40)
+
+
+def test_independent_binary32_by_hand():
+    """The binary32 min-sum decoder under the independent reading, written out
+    in numpy float32 (each matrix's messages from its own posterior), bit for
+    bit at T = 1, 2, 3; from T = 2 on it differs from the stacked reading."""
+    Hs = [np.array([[1, 1, 0, 0], [1, 0, 1, 0]]), np.array([[1, 0, 1, 1]])]
+    code = code_from_dense(Hs)
+    lam = np.array([-1.7725950479507446, -1.961043357849121, -0.43938955664634705, 0.036386072635650635])
+    z = np.array([1, 1, 1], np.uint8)
+    for T in (1, 2, 3):
+        want = _nms_f32_by_hand(Hs, lam, z, 0.7, T, independent=True)
+        got = oracle.decode_nms_f32(code, lam[None], z[None], max_iter=T, early_exit=False, alpha=0.7,
+                                    coupling=oracle.INDEPENDENT)["L"][0]
+        assert got.tolist() == want.astype(np.float64).tolist(), T
+        if T >= 2:
+            assert not np.array_equal(want, _nms_f32_by_hand(Hs, lam, z, 0.7, T))
