@@ -86,7 +86,8 @@ def h2(p):
     return -p * np.log2(p) - (1 - p) * np.log2(1 - p)
 
 
-def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_only: bool = False):
+def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_only: bool = False,
+                     algo: str = "spa"):
     """The heterogeneous queue (n, rate, u and p per frame) decoded three ways
     on the same device-resident inputs: the captured persistent batched
     decode, one plain decode call per frame in arrival order, and one plain
@@ -119,9 +120,9 @@ def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_
     T = 100
 
     log("bench: autotuning the batched decode")
-    tune = mbp.autotune(ctx, items, max_iter=T)
+    tune = mbp.autotune(ctx, items, max_iter=T, algo=algo)
     outs_b = [mbp.batch_outputs(dc, lam) for dc, lam, _ in items]
-    plan = mbp.Plan(ctx, items, outs_b, max_iter=T, tuning=tune)
+    plan = mbp.Plan(ctx, items, outs_b, max_iter=T, tuning=tune, algo=algo)
     plan.launch()
     plan.wait()
     torch.cuda.synchronize()
@@ -143,11 +144,11 @@ def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_
     # plain, one call per code (frames of a code grouped 64 to a wave)
     outs_g = [mbp.batch_outputs(dc, lam) for dc, lam, _ in items]
     for (dc, lam, z), o in zip(items, outs_g):  # warm
-        mbp.decode(ctx, dc, lam, z, algo="nms", max_iter=T, out=o)
+        mbp.decode(ctx, dc, lam, z, algo=algo, max_iter=T, out=o)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for (dc, lam, z), o in zip(items, outs_g):
-        mbp.decode(ctx, dc, lam, z, algo="nms", max_iter=T, out=o)
+        mbp.decode(ctx, dc, lam, z, algo=algo, max_iter=T, out=o)
     torch.cuda.synchronize()
     t_grouped = time.perf_counter() - t0
 
@@ -162,7 +163,7 @@ def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_
         k, j = where[i]
         dc, lam, z = items[k]
         o = {key: v[j:j + 1] for key, v in outs_p[k].items()}
-        mbp.decode(ctx, dc, lam[j:j + 1], z[j:j + 1], algo="nms", max_iter=T, out=o)
+        mbp.decode(ctx, dc, lam[j:j + 1], z[j:j + 1], algo=algo, max_iter=T, out=o)
 
     log("bench: plain per-frame offline")
     plain_one(0)
@@ -221,7 +222,7 @@ def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_
                 dc, lam, z = items[k]
                 its.append((dc, lam[j0:j1], z[j0:j1]))
                 outs.append({key: v[j0:j1] for key, v in outs_b[k].items()})
-            mbp.decode_batched(ctx, its, max_iter=T, tuning=tune, outs=outs)
+            mbp.decode_batched(ctx, its, max_iter=T, tuning=tune, outs=outs, algo=algo)
             torch.cuda.synchronize()
             done[nxt:hi] = time.perf_counter() - start
             nxt = hi
@@ -252,8 +253,9 @@ def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_
 
     return {
         "workload": f"mixed queue, {nframes} frames: n in {list(W.MIXED_N)}, rate in "
-                    f"{list(W.MIXED_RATES)}, u in [2, 3], p log-uniform [0.01, 0.08]; NMS FP32 "
-                    f"alpha 0.75, T={T}, early exit",
+                    f"{list(W.MIXED_RATES)}, u in [2, 3], p log-uniform [0.01, 0.08]; "
+                    + ("FP32 sum-product" if algo == "spa" else "FP32 min-sum alpha 0.75")
+                    + f", T={T}, early exit",
         "frames": nframes, "bits": total_bits, "tuning": tune,
         "batched_mbps": round(total_bits / t_batched / 1e6, 1),
         "plain_per_frame_mbps": round(total_bits / t_plain / 1e6, 1),
@@ -721,7 +723,7 @@ def run(args, ctx, dcode, wl, fr, dev):
     batched = None
     if args.queue_frames:
         batched = batched_vs_plain(ctx, args.queue_frames, args.queue_reps, args.arrival_load,
-                                   batched_only=args.queue_batched_only)
+                                   batched_only=args.queue_batched_only, algo=args.algo)
 
     return {
         "metric": "reconciled Mbps at FER<=1e-2, f<=1.1; % HBM peak; batched vs plain",

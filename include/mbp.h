@@ -77,11 +77,26 @@ typedef struct mbp_code mbp_code;
  *              matrix; the stopping test follows the last matrix. mbp_decode
  *              and mbp_decode_from_bits only (the batched and unrolled calls
  *              are flooding).
+ *   coupling   how the u matrices combine (Sec. 2 and eq. (2)).
+ *              MBP_JOINT (value 0): one Tanner graph of the stacked
+ *              matrices; a variable-to-check message is the soft decision
+ *              of eq. (2) minus the message on its own edge.
+ *              MBP_INDEPENDENT: each matrix runs its own decoder, as Sec. 2
+ *              forms the LLRs and messages of every matrix respectively:
+ *              matrix l's variable-to-check message is lambda plus matrix
+ *              l's other check messages at the variable, and only the soft
+ *              decision of eq. (2) (and so the decided bits and the stopping
+ *              test) joins the matrices. mbp_decode and mbp_decode_from_bits
+ *              only, codes of at most 4 matrices (else EUNSUPPORTED); the
+ *              workspace holds another 64 g u n sizeof(dtype) bytes for each
+ *              matrix's posterior at every variable.
  * Soft decisions (eq. (2)) are summed with the equation's nesting: each
  * matrix's check messages at a variable are summed first (in check order),
  * and those sums are added to the channel LLR in matrix order. */
 #define MBP_FLOODING 0
 #define MBP_MATRIX_SERIAL 1
+#define MBP_JOINT 0
+#define MBP_INDEPENDENT 1
 typedef struct {
     int32_t algo;
     int32_t dtype;
@@ -91,12 +106,13 @@ typedef struct {
     double llr_clip;
     int32_t compact;
     int32_t schedule;
+    int32_t coupling;
 } mbp_params;
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *mbp_last_error(void);
 
-/* ABI version of this library (currently 1). */
+/* ABI version of this library (currently 2: mbp_params has a coupling field). */
 int32_t mbp_version(void);
 
 /* Create a context on HIP device `device`; *out receives it.

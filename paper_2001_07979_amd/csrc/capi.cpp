@@ -52,6 +52,11 @@ int check_decode(const char *f, mbp_ctx *ctx, const mbp_code *code, const mbp_pa
     if (p->compact != 0 && p->compact != 1) return fail(MBP_EINVAL, fn + ": compact must be 0 or 1");
     if (p->schedule != MBP_FLOODING && p->schedule != MBP_MATRIX_SERIAL)
         return fail(MBP_EINVAL, fn + ": unknown schedule");
+    if (p->coupling != MBP_JOINT && p->coupling != MBP_INDEPENDENT)
+        return fail(MBP_EINVAL, fn + ": unknown coupling");
+    if (p->coupling == MBP_INDEPENDENT && code->u > mbp::kIndepMaxU)
+        return fail(MBP_EUNSUPPORTED, fn + ": independent decoders take codes of at most " +
+                                          std::to_string(mbp::kIndepMaxU) + " matrices");
     if (!std::isfinite(p->llr_clip) || p->llr_clip <= 0.0)
         return fail(MBP_EINVAL, fn + ": llr_clip must be finite and > 0");
     if (p->algo == MBP_ALGO_SPA && p->llr_clip > 30.0)
@@ -69,7 +74,7 @@ extern "C" {
 
 const char *mbp_last_error(void) { return mbp::g_last_error.c_str(); }
 
-int32_t mbp_version(void) { return 1; }
+int32_t mbp_version(void) { return 2; }
 
 int mbp_ctx_create(int32_t device, mbp_ctx **out) {
     if (!out) return fail(MBP_EINVAL, "mbp_ctx_create: out is NULL");
@@ -408,6 +413,8 @@ static int check_batched_params(const char *fn, const mbp_params *p) {
     if (p->dtype != MBP_F32) return fail(MBP_EUNSUPPORTED, f + ": the batched decode runs in FP32 only");
     if (p->schedule != MBP_FLOODING)
         return fail(MBP_EUNSUPPORTED, f + ": the batched decode runs the flooding schedule only");
+    if (p->coupling != MBP_JOINT)
+        return fail(MBP_EUNSUPPORTED, f + ": the batched decode runs the joint (stacked) graph only");
     if (p->max_iter < 1 || p->max_iter > 10000) return fail(MBP_EINVAL, f + ": max_iter must be in [1, 10000]");
     if (p->early_exit != 0 && p->early_exit != 1) return fail(MBP_EINVAL, f + ": early_exit must be 0 or 1");
     if (!std::isfinite(p->llr_clip) || p->llr_clip <= 0.0)

@@ -84,7 +84,12 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     // the matrix-serial variable passes keep each matrix's sum at every
     // variable, so a pass reads only its own matrix's messages
     const bool phase_sums = p->schedule == MBP_MATRIX_SERIAL && code->u > 1 && code->u <= kPhaseMaxU;
-    const size_t sz_ps = phase_sums ? align_up(static_cast<size_t>(ntot) * code->u * n * G * s) : 0;
+    // independent decoders: every matrix's posterior at every variable,
+    // after the stored sums in the same per-group block of rows
+    const bool indep = p->coupling == MBP_INDEPENDENT;
+    const int32_t lm0 = phase_sums ? code->u : 0;
+    const int32_t prows = lm0 + (indep ? code->u : 0);
+    const size_t sz_ps = prows ? align_up(static_cast<size_t>(ntot) * prows * n * G * s) : 0;
     // lambda: rows like L, or Bob's bit words and one magnitude per slot
     const size_t sz_lam = from_bits ? sz_d + align_up(static_cast<size_t>(ntot) * G * s) : sz_L;
     // status words, one 256-byte line per group, then the stopping-test counters
@@ -117,7 +122,8 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     uint64_t *words = reinterpret_cast<uint64_t *>(carve(sz_m - 256));
     StopTail *tail = reinterpret_cast<StopTail *>(carve(256));
     T *cs = with_state ? reinterpret_cast<T *>(carve(sz_cs)) : nullptr;
-    T *ps = phase_sums ? reinterpret_cast<T *>(carve(sz_ps)) : nullptr;
+    T *ps = prows ? reinterpret_cast<T *>(carve(sz_ps)) : nullptr;
+    T *lm = indep ? ps + static_cast<size_t>(lm0) * n * G : nullptr;
 
     Timer tm{ctx, stream, {}, 0};
     hipError_t err;
@@ -158,10 +164,14 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     const VarFn<T> kv = from_bits ? variable_kernel<T, true>(code->max_var_deg, &vpt)
                                   : variable_kernel<T>(code->max_var_deg, &vpt);
     Dims dv{E, n, M, ntot, (n + vpt - 1) / vpt, 0, 0, p->alpha, p->llr_clip};
+    dc.live = dv.live = &tail->live;
     dc.ybits = dv.ybits = yb;
     dc.ymag = dv.ymag = ymag;
     dc.cstate = cs;
     dv.reverse = 1;
+    dv.lm = lm;
+    dv.prows = prows;
+    for (int32_t l = 1; l < code->u && l <= 3; ++l) dv.emat[l - 1] = static_cast<int32_t>(code->e_off[l]);
     int vpt_p = 0;
     const VarPhaseFn<T> kvp = from_bits ? variable_phase_kernel<T, true>(code->max_var_deg_matrix, &vpt_p)
                                         : variable_phase_kernel<T>(code->max_var_deg_matrix, &vpt_p);
@@ -172,6 +182,7 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     dvs.psum = ps;
     Dims ds{E, n, M, ntot, (M + kBlock - 1) / kBlock, 0, 0, p->alpha, p->llr_clip, p->max_iter, ngroups,
             nspare};
+    ds.live = &tail->live;
     const int grid_c = grid_for(ctx, reinterpret_cast<const void *>(kc),
                                 static_cast<int64_t>(ngroups) * dc.ntiles);
     const int grid_vp = grid_for(ctx, reinterpret_cast<const void *>(kvp),
@@ -226,9 +237,14 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
         for (size_t ph = 0; ph < phases.size(); ++ph) {
             Dims d = phases[ph].d;
             d.t = t;
-            // L^0 = lambda until the first variable pass has run
-            const bool start = t == 1 && ph == 0;
-            const T *Lin = start ? lam : Lp;
+            // L^0 = lambda until the first variable pass has run; each
+            // independent decoder starts from lambda in its first check pass
+            const bool start = t == 1 && (ph == 0 || indep);
+            const T *Lin = start ? lam : indep ? lm : Lp;
+            if (indep && !start) {
+                d.lstride = static_cast<int64_t>(prows) * n * G;
+                d.mstride = static_cast<int64_t>(n) * G;
+            }
             LAUNCH_OR_FAIL(kCheckNode, (start ? kc1 : kc)<<<phases[ph].grid, kBlock, 0, stream>>>(
                                            code->d_row_ptr, code->d_col, code->d_row_mat, nullptr, zb, words, Lin,
                                            c, c, d));
@@ -258,8 +274,8 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
                                       iters_out, ok_out, fid, src, tail, ds));
         // fills the spare groups the stopping test's compaction planned
         if (nspare && t <= p->max_iter - 2)
-            LAUNCH_OR_FAIL(kSyndrome, k_move<T><<<grid_m, kBlock, 0, stream>>>(c, Lp, lam, zb, yb, ymag, cs, ps, code->u, src, tail, E, n,
-                                                                                M));
+            LAUNCH_OR_FAIL(kSyndrome, k_move<T><<<grid_m, kBlock, 0, stream>>>(c, Lp, lam, zb, yb, ymag, cs, ps, prows, src, tail, E,
+                                                                                n, M));
         if (p->early_exit) {
             if ((err = hipEventRecord(ctx->poll_events[t & 1], stream)) != hipSuccess)
                 return hip_fail(err, "hipEventRecord");

@@ -20,6 +20,10 @@ constexpr int kLanes = 64;
 // waves per SIMD; 64 would need all 256 registers, 1 wave).
 constexpr int kBatchedSpaMaxDeg = 34;
 
+// Largest number of matrices the independent-decoder coupling handles: the
+// flooding variable pass finds an edge's matrix from three boundaries.
+constexpr int kIndepMaxU = 4;
+
 // Extra zero entries after the device edge-index arrays, so kernels can read
 // indices in fixed blocks (up to 64 + 32 entries) past the end.
 constexpr int kIndexPad = 128;

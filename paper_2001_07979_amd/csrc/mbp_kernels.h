@@ -149,6 +149,26 @@ struct Dims {
     int32_t phase = 0;
     const int32_t *vmptr = nullptr;
     void *psum = nullptr;
+    // Independent decoders (coupling MBP_INDEPENDENT). The check pass reads
+    // the posterior of each check's own matrix: its L input of group g is
+    // at g * lstride (-1: n * 64, one L row per variable), plus
+    // row_mat[r] * mstride for check r (0: the same L for every matrix).
+    // The variable passes also write, per matrix l with an edge at the
+    // variable, lambda + matrix l's messages summed (from 0, in check order)
+    // to lm + g * prows * n * 64 + l * n * 64 (null: not written). emat
+    // holds the first stacked edge of matrices 1, 2 and 3 (INT32_MAX past
+    // the code's matrices), so an edge's matrix is the count it reaches.
+    int64_t lstride = -1;
+    int64_t mstride = 0;
+    void *lm = nullptr;
+    int32_t emat[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
+    // Frames still running (StopTail::live), or null. Once the stopping
+    // test has retired every frame, the iteration kernels the host launched
+    // ahead of its poll return at once.
+    const uint32_t *live = nullptr;
+    // rows of n * 64 values per group in the array holding the stored
+    // per-matrix sums (psum, rows 0..u-1) and the posteriors (lm)
+    int32_t prows = 0;
     // variable pass: visit the groups last to first. The check pass visits
     // them first to last, so the variable pass starts on the group whose
     // messages were written last (the likeliest still in the last-level
@@ -176,6 +196,7 @@ __device__ __forceinline__ T lam_of_half(uint32_t half, unsigned lane, T mag) {
 struct StopTail {
     uint32_t done, spare_used;
     int32_t move_first, move_count;
+    uint32_t live;  // frames still running after the last settle
 };
 
 // Per-group status words for the plain and unrolled decodes: word kRun of
@@ -342,6 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                                                   const uint64_t *__restrict__ act,
                                                   const T *__restrict__ Lp, const T *c_in, T *c_out,
                                                   const Dims a) {
+    if (a.live && *a.live == 0) return;  // every frame retired
     const unsigned lane = lane_id();
     const int wave = wave_id();
     const T clip = static_cast<T>(a.clip);
@@ -355,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
         const bool on = (gact >> lane) & 1;
         // wave-uniform bases; every access below is base[lane], so addresses
         // are a scalar base plus one per-lane offset
-        const T *Lg = Lp + static_cast<size_t>(g) * a.n * G;
+        const T *Lg = Lp + static_cast<size_t>(g) * (a.lstride < 0 ? static_cast<int64_t>(a.n) * G : a.lstride);
         const uint64_t *zg = zb + static_cast<size_t>(g) * a.M;
         const uint64_t *yg = BITS ? a.ybits + static_cast<size_t>(g) * a.n : nullptr;
         const T ym = BITS ? static_cast<const T *>(a.ymag)[static_cast<size_t>(g) * G + lane] : T(0);
@@ -369,6 +391,8 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
             const size_t cb = (static_cast<size_t>(g) * a.E + e0) * G;
             const T *ci = c_in + cb;
             T *cg = c_out + cb;
+            // independent decoders: the posterior of the check's own matrix
+            const T *Lr = a.mstride ? Lg + row_mat[r] * a.mstride : Lg;
             int v[DMAX];
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) v[j] = col[e0 + j];
@@ -379,7 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                 if (on)
                     check_row_f32<ALGO, DMAX, BITS, CST>(
                         v, d, static_cast<uint32_t>(zbit), alpha, clip, first,
-                        BITS ? buf_rsrc(yg, kBufAll) : buf_rsrc(Lg, kBufAll), ci, cg, lane, ym, st);
+                        BITS ? buf_rsrc(yg, kBufAll) : buf_rsrc(Lr, kBufAll), ci, cg, lane, ym, st);
             } else if (on) {
                 // issue every gather of the check before using any of them
                 T q[DMAX], co[DMAX];
@@ -390,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                         if constexpr (BITS) {
                             yh[j] = bit_half(yg, v[j], lane);
                         } else {
-                            q[j] = (Lg + static_cast<size_t>(v[j]) * G)[lane];
+                            q[j] = (Lr + static_cast<size_t>(v[j]) * G)[lane];
                             co[j] = first ? T(0) : (ci + j * G)[lane];
                         }
                     }
@@ -508,6 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_stop_test(const int32_t *__restrict_
                                                       uint64_t *status, int32_t *iters_out,
                                                       uint8_t *ok_out, int32_t *fid, int32_t *src,
                                                       StopTail *tail, const Dims a) {
+    if (a.live && *a.live == 0) return;  // every frame retired
     __shared__ uint32_t sh_or[2 * kWaves];
     __shared__ uint32_t scan[kBlock];
     __shared__ uint32_t sh_base, sh_R, sh_L;
@@ -648,6 +673,7 @@ __global__ __launch_bounds__(kBlock) void k_stop_test(const int32_t *__restrict_
         tail->move_first = first_new;
         tail->move_count = compact ? static_cast<int32_t>(K) : 0;
         if (compact) tail->spare_used = used + K;
+        tail->live = R;
         tail->done = 0;
     }
 }
@@ -667,7 +693,7 @@ constexpr int kMovePerWave = kMoveRows / kWaves;
 // kMoveRows rows of one region of one group.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_move(T *c, T *Lp, T *lam, uint64_t *zb, uint64_t *yb, T *ymag,
-                                                 T *cs, T *ps, int32_t u, const int32_t *src,
+                                                 T *cs, T *ps, int32_t prows, const int32_t *src,
                                                  const StopTail *tail, int64_t E, int32_t n, int32_t M) {
     const int count = tail->move_count, first = tail->move_first;
     if (count == 0) return;
@@ -676,9 +702,10 @@ __global__ __launch_bounds__(kBlock) void k_move(T *c, T *Lp, T *lam, uint64_t *
     const int64_t nw = M + (yb ? n : 0);  // word rows: syndromes, then Bob's bits
     // rows of one value per lane: messages (E), then the compressed check
     // state if there is one (kStateRows per check; 4-byte words moved as T),
-    // then the stored per-matrix sums if there are (u per variable)
+    // then the stored per-matrix sums and posteriors if there are (prows
+    // per variable)
     const int64_t ns = cs ? static_cast<int64_t>(kStateRows) * M : 0;
-    const int64_t np = ps ? static_cast<int64_t>(u) * n : 0;
+    const int64_t np = ps ? static_cast<int64_t>(prows) * n : 0;
     const int64_t nc = E + ns + np;
     const int64_t ic = (nc + kMoveRows - 1) / kMoveRows, il = (n + kMoveRows - 1) / kMoveRows,
                   iz = (nw + kMoveRows - 1) / kMoveRows, per_group = ic + il + iz;
@@ -793,6 +820,7 @@ __global__ __launch_bounds__(kBlock) void k_variable(
     const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_edge,
     const T *__restrict__ c, const T *__restrict__ lam, T *__restrict__ Lp,
     const uint64_t *__restrict__ act, uint64_t *__restrict__ D, const Dims a) {
+    if (a.live && *a.live == 0) return;  // every frame retired
     const unsigned lane = lane_id();
     const int wave = wave_id();
     const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
@@ -846,22 +874,34 @@ __global__ __launch_bounds__(kBlock) void k_variable(
 #pragma unroll
                 for (int v = 0; v < VPW; ++v) s[v] = in[v] ? lam_of_half(yh[v], lane, ym) : T(0);
             }
+            // independent decoders: each matrix's posterior lambda + its sum
+            T *lmg = static_cast<T *>(a.lm);
+            if (lmg) lmg += static_cast<size_t>(g) * a.prows * a.n * G;
 #pragma unroll
             for (int v = 0; v < VPW; ++v) {
                 T acc = T(0);  // the running matrix's sum
+                const T lam_v = s[v];
+                int mrun = 0;  // the running matrix
                 bool any = false;
 #pragma unroll
                 for (int j = 0; j < DV; ++j) {
                     if (j < deg[v] && ev[v][j] < lim) {
                         if (fl[v][j]) {
                             s[v] += acc;
+                            if (lmg && in[v])
+                                (lmg + (static_cast<size_t>(mrun) * a.n + i[v]) * G)[lane] = lam_v + acc;
                             acc = T(0);
                         }
+                        if (lmg && (fl[v][j] || !any))
+                            mrun = (ev[v][j] >= a.emat[0]) + (ev[v][j] >= a.emat[1]) + (ev[v][j] >= a.emat[2]);
                         acc += x[v][j];
                         any = true;
                     }
                 }
-                if (any) s[v] += acc;
+                if (any) {
+                    s[v] += acc;
+                    if (lmg && in[v]) (lmg + (static_cast<size_t>(mrun) * a.n + i[v]) * G)[lane] = lam_v + acc;
+                }
                 if (in[v]) (Lp + gb + static_cast<size_t>(i[v]) * G)[lane] = s[v];
             }
         }
@@ -891,6 +931,7 @@ __global__ __launch_bounds__(kBlock) void k_variable_phase(
     const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_edge,
     const T *__restrict__ c, const T *__restrict__ lam, T *__restrict__ Lp,
     const uint64_t *__restrict__ act, uint64_t *__restrict__ D, const Dims a) {
+    if (a.live && *a.live == 0) return;  // every frame retired
     (void)var_ptr;
     const unsigned lane = lane_id();
     const int wave = wave_id();
@@ -905,7 +946,9 @@ __global__ __launch_bounds__(kBlock) void k_variable_phase(
         const bool on = (run >> lane) & 1;
         const size_t gb = static_cast<size_t>(g) * a.n * G;
         const T *cg = c + static_cast<size_t>(g) * a.E * G;
-        T *sg = static_cast<T *>(a.psum) + static_cast<size_t>(g) * a.u * a.n * G;
+        T *sg = static_cast<T *>(a.psum) + static_cast<size_t>(g) * a.prows * a.n * G;
+        T *lmg = static_cast<T *>(a.lm);
+        if (lmg) lmg += static_cast<size_t>(g) * a.prows * a.n * G;
         const uint64_t *yg = BITS ? a.ybits + static_cast<size_t>(g) * a.n : nullptr;
         const T ym = BITS ? static_cast<const T *>(a.ymag)[static_cast<size_t>(g) * G + lane] : T(0);
         int i[VPW], k0[VPW], deg[VPW];
@@ -952,9 +995,13 @@ __global__ __launch_bounds__(kBlock) void k_variable_phase(
 #pragma unroll
             for (int v = 0; v < VPW; ++v) {
                 T acc = T(0);
+                const T lam_v = s[v];
 #pragma unroll
                 for (int j = 0; j < DV; ++j)
                     if (j < deg[v]) acc += x[v][j];
+                // independent decoders: matrix l's posterior
+                if (lmg && in[v] && deg[v] > 0)
+                    (lmg + (static_cast<size_t>(l) * a.n + i[v]) * G)[lane] = lam_v + acc;
 #pragma unroll
                 for (int m = 0; m < kPhaseMaxU; ++m) {
                     if (m == l) {
@@ -1015,7 +1062,7 @@ VarFn<T> variable_kernel(int dmax, int *vars_per_tile) {
 __global__ void k_init_running(uint64_t *words, uint64_t *status, StopTail *tail, int32_t *fid,
                                int32_t nframes, int32_t ngroups, int32_t nspare) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s == 0 && tail) *tail = StopTail{0, 0, 0, 0};
+    if (s == 0 && tail) *tail = StopTail{0, 0, 0, 0, static_cast<uint32_t>(nframes > 0 ? nframes : 0)};
     if (s >= (ngroups + nspare) * G) return;
     const int g = s / G, k = s % G;
     if (fid) fid[s] = g < ngroups && s < nframes ? s : -1;

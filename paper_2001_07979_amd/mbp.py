@@ -21,6 +21,9 @@ MBP_EINVAL, MBP_ENOMEM, MBP_EDEVICE, MBP_ESTATE, MBP_EUNSUPPORTED = -1, -2, -3, 
 MBP_ALGO_SPA, MBP_ALGO_NMS = 0, 1
 MBP_F32, MBP_F64 = 0, 1
 MBP_FLOODING, MBP_MATRIX_SERIAL = 0, 1
+MBP_JOINT, MBP_INDEPENDENT = 0, 1
+ABI_VERSION = 2  # mbp_version() of the library this binding marshals for
+_COUPLINGS = {"joint": MBP_JOINT, "independent": MBP_INDEPENDENT}
 KERNEL_IDS = {"check": 0, "variable": 1, "syndrome": 2, "staging": 3}
 
 _lib = None
@@ -52,7 +55,8 @@ class mbp_params(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("early_exit", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("llr_clip", ctypes.c_double),
-                ("compact", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+                ("compact", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("coupling", ctypes.c_int32)]
 
 
 def lib():
@@ -114,6 +118,9 @@ def lib():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        if L.mbp_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI version {L.mbp_version()}, this binding expects "
+                               f"{ABI_VERSION}: rebuild it with __graft_entry__.build()")
         _lib = L
     return _lib
 
@@ -316,10 +323,13 @@ def llr_from_bits(ctx: Context, y, e, dtype="f32", out=None, stream=None):
     return out
 
 
-def _params(algo, dt, max_iter, early_exit, alpha, clip, compact, schedule):
+def _params(algo, dt, max_iter, early_exit, alpha, clip, compact, schedule, coupling="joint"):
+    if coupling not in _COUPLINGS:
+        raise ValueError(f"unknown coupling {coupling!r}")
     return mbp_params(MBP_ALGO_SPA if algo == "spa" else MBP_ALGO_NMS, dt, int(max_iter),
                       int(bool(early_exit)), float(alpha), float(clip), int(bool(compact)),
-                      {"flooding": MBP_FLOODING, "serial": MBP_MATRIX_SERIAL}[schedule])
+                      {"flooding": MBP_FLOODING, "serial": MBP_MATRIX_SERIAL}[schedule],
+                      _COUPLINGS[coupling])
 
 
 def _decode_outputs(F, n, dtype, dev, want_llr):
@@ -348,9 +358,12 @@ def syndrome(ctx: Context, code: Code, x, out=None, stream=None):
 def decode(ctx: Context, code: Code, llr, synd, algo: str = "spa", max_iter: int = 50,
            early_exit: bool = True, alpha: float = 0.75, clip: float = 20.0,
            want_llr: bool = True, out: Optional[dict] = None, stream=None,
-           compact: bool = True, schedule: str = "flooding") -> dict:
+           compact: bool = True, schedule: str = "flooding", coupling: str = "joint") -> dict:
     """Decode every frame: llr [F, n] (float32/float64, GPU), synd [F, M] (uint8, GPU).
 
+    schedule: "flooding" or "serial" (Algorithm 1's per-matrix loop);
+    coupling: "joint" (one stacked graph) or "independent" (one decoder per
+    matrix, joined by eq. (2)).
     Returns dict(bits [F, n] uint8, iters [F] int32, ok [F] uint8, llr [F, n] or None).
     """
     import torch
@@ -363,7 +376,7 @@ def decode(ctx: Context, code: Code, llr, synd, algo: str = "spa", max_iter: int
     if out is None:
         out = _decode_outputs(F, code.n, llr.dtype, llr.device, want_llr)
     pb, pi, pk, plo = _out_ptrs(out, ctx.device, F, code.n, llr.dtype)
-    p = _params(algo, dt, max_iter, early_exit, alpha, clip, compact, schedule)
+    p = _params(algo, dt, max_iter, early_exit, alpha, clip, compact, schedule, coupling)
     _check(lib().mbp_decode(ctx.handle, code.handle, ctypes.byref(p), F, pl, pz, pb, pi, pk, plo,
                             _stream_ptr(stream)), "mbp_decode")
     return out
@@ -372,7 +385,8 @@ def decode(ctx: Context, code: Code, llr, synd, algo: str = "spa", max_iter: int
 def decode_from_bits(ctx: Context, code: Code, y, e, synd, dtype: str = "f32", algo: str = "spa",
                      max_iter: int = 50, early_exit: bool = True, alpha: float = 0.75,
                      clip: float = 20.0, want_llr: bool = True, out: Optional[dict] = None,
-                     stream=None, compact: bool = True, schedule: str = "flooding") -> dict:
+                     stream=None, compact: bool = True, schedule: str = "flooding",
+                     coupling: str = "joint") -> dict:
     """decode() with the channel given as Bob's bits y [F, n] (uint8, GPU) and
     error rates e [F] (float64, GPU); the LLRs are formed inside the decoder.
     Same outputs as llr_from_bits followed by decode, bit for bit."""
@@ -387,7 +401,7 @@ def decode_from_bits(ctx: Context, code: Code, y, e, synd, dtype: str = "f32", a
     if out is None:
         out = _decode_outputs(F, code.n, tdt, y.device, want_llr)
     pb, pi, pk, plo = _out_ptrs(out, ctx.device, F, code.n, tdt)
-    p = _params(algo, _dtype_code(tdt), max_iter, early_exit, alpha, clip, compact, schedule)
+    p = _params(algo, _dtype_code(tdt), max_iter, early_exit, alpha, clip, compact, schedule, coupling)
     _check(lib().mbp_decode_from_bits(ctx.handle, code.handle, ctypes.byref(p), F, py, pe, pz, pb, pi, pk,
                                       plo, _stream_ptr(stream)), "mbp_decode_from_bits")
     return out
@@ -488,7 +502,7 @@ def _batched_params(algo, max_iter, early_exit, alpha, clip):
     if algo not in ("spa", "nms"):
         raise ValueError(f"unknown algo {algo!r}")
     return mbp_params(MBP_ALGO_SPA if algo == "spa" else MBP_ALGO_NMS, MBP_F32, int(max_iter),
-                      int(bool(early_exit)), float(alpha), float(clip))
+                      int(bool(early_exit)), float(alpha), float(clip), 0, MBP_FLOODING, MBP_JOINT)
 
 
 def batch_outputs(code: Code, llr, want_llr: bool = True) -> dict:

@@ -32,10 +32,11 @@ LONG_AFTER = 8
 # |L| its FP32 value is good to about 1e-5 absolute, not 1e-4 relative.
 ATOL32 = 1e-5
 _SCHEDULES = {"flooding": oracle.FLOODING, "serial": oracle.SERIAL}
+_COUPLINGS = {"joint": oracle.JOINT, "independent": oracle.INDEPENDENT}
 
 
 def gpu_run(ctx, dcode, frames, algo, dtype, max_iter, early_exit=True, alpha=0.75,
-            clip=20.0, llr=None, schedule="flooding"):
+            clip=20.0, llr=None, schedule="flooding", coupling="joint", compact=True):
     import torch
     from paper_2001_07979_amd import mbp
     dev = torch.device("cuda", ctx.device)
@@ -47,7 +48,7 @@ def gpu_run(ctx, dcode, frames, algo, dtype, max_iter, early_exit=True, alpha=0.
         llr = torch.from_numpy(llr).to(dev)
     z = torch.from_numpy(frames.z).to(dev)
     out = mbp.decode(ctx, dcode, llr, z, algo=algo, max_iter=max_iter, early_exit=early_exit,
-                     alpha=alpha, clip=clip, schedule=schedule)
+                     alpha=alpha, clip=clip, schedule=schedule, coupling=coupling, compact=compact)
     torch.cuda.synchronize()
     return dict(llr_in=llr.cpu().numpy(), bits=out["bits"].cpu().numpy(),
                 iters=out["iters"].cpu().numpy(), ok=out["ok"].cpu().numpy(),
@@ -62,7 +63,7 @@ def oracle_llr(frames, dtype):
 
 
 def oracle_run(code, frames, algo, dtype, max_iter, early_exit=True, alpha=0.75, clip=20.0,
-               idx=None, lam=None, schedule="flooding"):
+               idx=None, lam=None, schedule="flooding", coupling="joint"):
     if lam is None:
         lam = oracle_llr(frames, dtype)
     z = frames.z
@@ -70,7 +71,7 @@ def oracle_run(code, frames, algo, dtype, max_iter, early_exit=True, alpha=0.75,
         lam, z = lam[idx], z[idx]
     r = oracle.decode(code, lam, z, algo=oracle.SPA if algo == "spa" else oracle.NMS,
                       max_iter=max_iter, early_exit=early_exit, alpha=alpha, clip=clip,
-                      schedule=_SCHEDULES[schedule])
+                      schedule=_SCHEDULES[schedule], coupling=_COUPLINGS[coupling])
     r["llr_in"] = lam
     return r
 
@@ -130,14 +131,15 @@ def compare(gpu, orc, max_iter, rtol, idx=None, exact_all=False, long_rtol=1e-2,
 
 
 def oracle_f32_run(code, frames, max_iter, early_exit=True, alpha=0.75, clip=20.0, idx=None,
-                   lam=None, schedule="flooding"):
+                   lam=None, schedule="flooding", coupling="joint"):
     if lam is None:
         lam = oracle_llr(frames, "f32")
     z = frames.z
     if idx is not None:
         lam, z = lam[idx], z[idx]
     return oracle.decode_nms_f32(code, lam, z, max_iter=max_iter, early_exit=early_exit,
-                                 alpha=alpha, clip=clip, schedule=_SCHEDULES[schedule])
+                                 alpha=alpha, clip=clip, schedule=_SCHEDULES[schedule],
+                                 coupling=_COUPLINGS[coupling])
 
 
 def assert_bitwise(gpu, ref, idx=None):
