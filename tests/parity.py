@@ -6,14 +6,16 @@ Protocol (GPU against the FP64 oracle):
   exactly in success, iteration count and every decided bit;
 * its final soft decisions must agree to `rtol` (1e-4 for FP32) relative,
   plus ATOL32 = 1e-5 absolute for FP32 (the representation limit of the
-  summed messages where they cancel), wherever |L| >= 1e-3, for frames that stop within LONG_AFTER = 8
-  iterations (the paper reports 3.71 to 6.67 iterations on average,
-  Tables 2 and 3). A longer FP32 trajectory drifts from FP64 by more than
-  that (measured: up to ~2e-3 for sum-product at 27 iterations, and far more
-  for min-sum, whose rounding errors grow by about alpha (d_v - 1) per
-  iteration, enough to move a long decode's stopping iteration); there
-  `long_rtol` applies to sum-product, while min-sum FP32 frames are held bit
-  for bit to the oracle's binary32 min-sum and only counted against FP64;
+  summed messages where they cancel), wherever |L| >= 1e-3, whatever the
+  frame's iteration count. A test may name a longer-decode bound instead
+  (`long_after`, `long_rtol`) where its inputs include decodes long enough
+  for FP32 to drift from FP64 by more than that; each such bound is a
+  measured one, recorded with its evidence beside the test;
+* FP32 min-sum frames that stop after `long_after` iterations with
+  `long_rtol=None` are held bit for bit to the oracle's binary32 min-sum by
+  their test, and against FP64 only counted: at most `long_budget` of the
+  frames may disagree (min-sum's rounding grows by about alpha (d_v - 1) per
+  iteration, enough to move a long decode's stopping iteration or outcome);
 * a frame the oracle fails must fail on the GPU too with iters = T;
 * flagged frames (a soft decision within 1e-3 of zero at a point where FP32
   rounding could change the outcome) are compared and counted; together with
@@ -26,7 +28,26 @@ import numpy as np
 import oracle
 
 SMALL = 1e-3
-LONG_AFTER = 8
+# Longer-decode bounds, measured (GPU against the FP64 oracle on the tests'
+# own inputs; the largest relative difference of L beyond ATOL32):
+# * FP32 sum-product stays within 1e-4 for frames that stop within
+#   SPA_LONG_AFTER = 16 iterations (largest 9.6e-5, at 13 iterations, among
+#   300 stragglers up to BSC 0.09); beyond, single frames near a code's
+#   threshold drift further (1.5e-4 to 0.10 between 18 and 47 iterations)
+#   with every decision the same, so those tests name their own bound.
+# * FP32 min-sum amplifies rounding by about alpha (d_v - 1) per iteration:
+#   within 1e-4 up to 7 flooding iterations (largest 2.1e-5) and 5 serial
+#   iterations of u = 2 (3.5e-5), 1.3e-4 already at 6. Later frames are held
+#   bit for bit to the binary32 oracle and only counted against FP64.
+SPA_LONG_AFTER = 16
+NMS_LONG_AFTER = 7
+
+
+def nms_long_after(schedule: str = "flooding", u: int = 1) -> int:
+    """Iterations within which FP32 min-sum is held to 1e-4 against FP64."""
+    if schedule == "flooding" or u <= 1:
+        return NMS_LONG_AFTER
+    return 5 if u == 2 else 3
 # FP32 holds a check message of size up to C = 20 only to 20 * 2^-24 = 1.2e-6;
 # a soft decision adds up to ~16 of them, so where they cancel to a small
 # |L| its FP32 value is good to about 1e-5 absolute, not 1e-4 relative.
@@ -76,29 +97,34 @@ def oracle_run(code, frames, algo, dtype, max_iter, early_exit=True, alpha=0.75,
     return r
 
 
-def compare(gpu, orc, max_iter, rtol, idx=None, exact_all=False, long_rtol=1e-2, atol=0.0,
-            long_after=LONG_AFTER):
+def compare(gpu, orc, max_iter, rtol, idx=None, exact_all=False, atol=0.0, long_after=None,
+            long_rtol=None, long_budget=0.05):
     """Apply the protocol; returns a summary dict, raising AssertionError on a bug.
 
-    long_rtol=None marks a run whose frames beyond `long_after` iterations are
-    held bit for bit to the binary32 oracle instead (FP32 min-sum): against
-    FP64 they are only counted. The matrix-serial schedule passes messages u
-    times per iteration, so its FP32 drift after t iterations is that of
-    flooding after about u t: its tests pass long_after = LONG_AFTER // u.
+    long_after=None: every strict frame is held to rtol. long_after=t with a
+    long_rtol: strict frames that stop after t iterations are held to
+    long_rtol instead. long_after=t with long_rtol=None: those frames are
+    counted against FP64 (long_mismatch, at most long_budget of the frames),
+    for FP32 min-sum runs whose tests hold them bit for bit to the binary32
+    oracle.
     """
     sel = (lambda a: a[idx]) if idx is not None else (lambda a: a)
     g = {k: sel(v) for k, v in gpu.items() if k != "llr_in"}
     F = len(orc["ok"])
     summary = dict(frames=F, oracle_ok=int(orc["ok"].sum()), flagged=int(orc["flag"].sum()),
                    flagged_mismatch=0, failed_mismatch=0, long_mismatch=0, max_rel=0.0,
-                   hamming_failed=[])
+                   max_rel_long=0.0, hamming_failed=[])
     for f in range(F):
         o_ok, o_it = int(orc["ok"][f]), int(orc["iters"][f])
         g_ok, g_it = int(g["ok"][f]), int(g["iters"][f])
         same_bits = np.array_equal(orc["bits"][f], g["bits"][f])
         same = g_ok == o_ok and g_it == o_it and same_bits
-        if long_rtol is None and o_it > long_after and not exact_all:
-            summary["long_mismatch"] += int(not same)
+        long = long_after is not None and o_it > long_after and not exact_all
+        if long and long_rtol is None:
+            # FP32 min-sum past long_after: a disagreement with FP64 (a decode
+            # the oracle completes that differs, or one it fails that the GPU
+            # completes or stops early) is counted
+            summary["long_mismatch"] += int(not same if o_ok else (g_ok or g_it != max_iter))
             continue
         strict = exact_all or (o_ok and not orc["flag"][f])
         if strict:
@@ -106,12 +132,13 @@ def compare(gpu, orc, max_iter, rtol, idx=None, exact_all=False, long_rtol=1e-2,
                 f"frame {f}: gpu ok={g_ok} iters={g_it}, oracle ok={o_ok} iters={o_it}")
             assert same_bits, f"frame {f}: {int((orc['bits'][f] != g['bits'][f]).sum())} bits differ"
             Lo, Lg = orc["L"][f], g["L"][f]
-            tol = rtol if o_it <= long_after else long_rtol
+            tol = long_rtol if long else rtol
             mask = np.abs(Lo) >= SMALL
             err = np.abs(Lg[mask] - Lo[mask])
             rel = err / np.abs(Lo[mask])
             if rel.size:
-                summary["max_rel"] = max(summary["max_rel"], float(rel.max()))
+                key = "max_rel_long" if long else "max_rel"
+                summary[key] = max(summary[key], float(rel.max()))
                 k = int(np.argmax(err - tol * np.abs(Lo[mask])))
                 Lo_k, Lg_k = Lo[mask][k], Lg[mask][k]
                 assert np.all(err <= tol * np.abs(Lo[mask]) + atol), (
@@ -127,6 +154,8 @@ def compare(gpu, orc, max_iter, rtol, idx=None, exact_all=False, long_rtol=1e-2,
             summary["flagged_mismatch"] += int(not same)
     bad = summary["flagged_mismatch"] + summary["failed_mismatch"]
     assert bad <= 0.01 * F, f"{bad} of {F} frames disagree: {summary}"
+    assert summary["long_mismatch"] <= long_budget * F, (
+        f"{summary['long_mismatch']} of {F} long min-sum decodes disagree with FP64: {summary}")
     return summary
 
 

@@ -268,11 +268,13 @@ def test_batched_sum_product_equals_plain_and_oracle(ctx, spa_mix):
             got = [_np(o) for o in mbp.decode_batched(ctx, items, max_iter=T, algo="spa", tuning=tuning)]
             for g, p in zip(got, plain):
                 _same(g, p)
+        # every frame against the oracle; the stragglers up to BSC 0.09 run to
+        # T = 60, where L drifts to 2.9e-3 (measured, a frame at 41
+        # iterations) with every decision the same
         for g, (code, fr, lam) in zip(got, frames):
-            idx = np.random.default_rng(6).choice(fr.nframes, min(fr.nframes, 16), replace=False)
-            o = parity.oracle_run(code, fr, "spa", "f32", T, idx=idx, lam=lam.astype(np.float64))
+            o = parity.oracle_run(code, fr, "spa", "f32", T, lam=lam.astype(np.float64))
             parity.compare(dict(bits=g["bits"], iters=g["iters"], ok=g["ok"], L=g["llr"]), o, T, 1e-4,
-                           idx=idx, atol=parity.ATOL32)
+                           atol=parity.ATOL32, long_after=parity.SPA_LONG_AFTER, long_rtol=1e-2)
 
 
 def test_graph_plan_sum_product(ctx, spa_mix):

@@ -78,9 +78,12 @@ def test_ragged_parity(ctx, ragged_code, algo, dtype, F):
         # test_llr_kernel_matches_oracle); both decoders start from one input
         g = parity.gpu_run(ctx, dc, fr, algo, dtype, 40, llr=lam)
     o = parity.oracle_run(ragged_code, fr, algo, dtype, 40, lam=lam)
-    long_rtol = {("spa", "f32"): 1e-2, ("nms", "f32"): None}.get((algo, dtype), 1e-6)
-    s = parity.compare(g, o, 40, RTOL32 if dtype == "f32" else RTOL64, long_rtol=long_rtol,
-                       atol=parity.ATOL32 if dtype == "f32" else 0.0)
+    # every frame at 1e-4 (FP32) / 1e-9 (FP64) whatever its iteration count
+    # (sum-product stops within 13 here); FP32 min-sum past 7 iterations is
+    # held bit for bit to the binary32 oracle below and counted against FP64
+    long = dict(long_after=parity.nms_long_after()) if (algo, dtype) == ("nms", "f32") else {}
+    s = parity.compare(g, o, 40, RTOL32 if dtype == "f32" else RTOL64,
+                       atol=parity.ATOL32 if dtype == "f32" else 0.0, **long)
     assert s["oracle_ok"] >= F // 2
     if (algo, dtype) == ("nms", "f32"):
         parity.assert_bitwise(g, parity.oracle_f32_run(ragged_code, fr, 40, lam=lam))
@@ -115,19 +118,19 @@ def test_fp64_n4096_every_frame_exact(ctx):
 
 
 @pytest.mark.parametrize("algo", ["spa", "nms"])
-def test_n65536_full_batch_sampled(ctx, algo):
-    """The benchmarked workload: 256 frames decoded together; the oracle
-    decodes a sample of frames one by one; every frame is checked for the
-    properties that hold at any size."""
+def test_n65536_full_batch_every_frame(ctx, algo):
+    """The u=2 n=65536 workload: 256 frames decoded together, every frame
+    against the oracle (min-sum also bit for bit with the binary32 oracle),
+    and the properties that hold at any size."""
     wl = W.qkd_n65536(algo=algo)
     fr = wl.frames()
     dc = upload(ctx, wl.code)
     g = parity.gpu_run(ctx, dc, fr, algo, "f32", wl.max_iter, alpha=wl.alpha)
-    idx = np.array([0, 1, 63, 64, 127, 128, 200, 255])
-    o = parity.oracle_run(wl.code, fr, algo, "f32", wl.max_iter, alpha=wl.alpha, idx=idx)
-    parity.compare(g, o, wl.max_iter, RTOL32, idx=idx, atol=parity.ATOL32)
+    o = parity.oracle_run(wl.code, fr, algo, "f32", wl.max_iter, alpha=wl.alpha)
+    s = parity.compare(g, o, wl.max_iter, RTOL32, atol=parity.ATOL32)
+    assert s["oracle_ok"] == 256 and s["flagged"] <= 2
     if algo == "nms":
-        parity.assert_bitwise(g, parity.oracle_f32_run(wl.code, fr, wl.max_iter, idx=idx), idx=idx)
+        parity.assert_bitwise(g, parity.oracle_f32_run(wl.code, fr, wl.max_iter))
     # every declared success meets all u syndromes (recomputed here)
     okf = g["ok"] == 1
     assert np.array_equal(syndromes(wl.code, g["bits"][okf]), fr.z[okf])
@@ -136,17 +139,23 @@ def test_n65536_full_batch_sampled(ctx, algo):
 
 
 @pytest.mark.parametrize("rate,algo", [(0.5, "spa"), (0.7, "spa"), (0.85, "spa"), (0.85, "nms")])
-def test_n262144_u3_sampled(ctx, rate, algo):
+def test_n262144_u3_every_frame(ctx, rate, algo):
     """QKD-scale frames: u=3 {2,3,10} PEG matrices, n=2^18, 64 frames at one
-    of the (rate, p) points, decoded in one call; sampled frames against the
-    oracle, properties on all."""
+    of the (rate, p) points, decoded in one call; every frame against the
+    oracle (min-sum also bit for bit with the binary32 oracle), properties
+    on all."""
     wl = W.qkd_n262144(rate, algo=algo)
     fr = wl.frames()
     dc = upload(ctx, wl.code)
     g = parity.gpu_run(ctx, dc, fr, algo, "f32", wl.max_iter, alpha=wl.alpha)
-    idx = np.array([0, 1, 31, 32, 63])
+    # min-sum with alpha = 0.75 fails every frame at rate 0.85 (the oracle
+    # too), so each runs all T = 100 iterations: the oracle takes a sample of
+    # 8 frames there (one in each half-group), sum-product every frame
+    idx = np.arange(0, 64, 8) if algo == "nms" else None
     o = parity.oracle_run(wl.code, fr, algo, "f32", wl.max_iter, alpha=wl.alpha, idx=idx)
-    parity.compare(g, o, wl.max_iter, RTOL32, idx=idx, atol=parity.ATOL32)
+    s = parity.compare(g, o, wl.max_iter, RTOL32, atol=parity.ATOL32, idx=idx,
+                       **(dict(long_after=parity.nms_long_after()) if algo == "nms" else {}))
+    assert s["oracle_ok"] == (64 if algo == "spa" else 0)
     if algo == "nms":
         parity.assert_bitwise(g, parity.oracle_f32_run(wl.code, fr, wl.max_iter, idx=idx), idx=idx)
     okf = g["ok"] == 1
@@ -178,17 +187,19 @@ def test_compaction_keeps_results(ctx, ragged_code, algo, dtype):
     its = a["iters"]
     assert (its == T).sum() > 50 and (its <= 5).sum() > 40
     g = dict(bits=a["bits"], iters=a["iters"], ok=a["ok"], L=a["llr"].astype(np.float64))
-    rng = np.random.default_rng(3)
+    # every frame against the oracle, failed or not
     if algo == "nms":
-        # every frame, failed or not, bit for bit against binary32 min-sum
-        idx = rng.choice(300, 16, replace=False)
-        parity.assert_bitwise(g, parity.oracle_f32_run(ragged_code, fr, T, idx=idx, lam=lam), idx=idx)
-    else:
-        # short decodes, where the protocol holds every frame to the oracle
-        idx = rng.choice(np.nonzero(its <= parity.LONG_AFTER)[0], 16, replace=False)
-        o = parity.oracle_run(ragged_code, fr, algo, dtype, T, idx=idx, lam=lam)
-        parity.compare(g, o, T, RTOL32 if dtype == "f32" else RTOL64, idx=idx,
-                       atol=parity.ATOL32 if dtype == "f32" else 0.0)
+        parity.assert_bitwise(g, parity.oracle_f32_run(ragged_code, fr, T, lam=lam))
+    o = parity.oracle_run(ragged_code, fr, algo, dtype, T, lam=lam)
+    # these stragglers run up to T = 60 near the code's threshold; measured
+    # beyond 16 iterations: FP32 sum-product L within 0.103 (one frame at 47
+    # iterations; 1.3e-3 up to 41), FP64 exact; FP32 min-sum against FP64:
+    # 10 of 300 long decodes differ
+    long = {("spa", "f32"): dict(long_after=parity.SPA_LONG_AFTER, long_rtol=0.25),
+            ("spa", "f64"): dict(long_after=parity.SPA_LONG_AFTER, long_rtol=1e-4),
+            ("nms", "f32"): dict(long_after=parity.nms_long_after(), long_budget=0.1)}[(algo, dtype)]
+    parity.compare(g, o, T, RTOL32 if dtype == "f32" else RTOL64,
+                   atol=parity.ATOL32 if dtype == "f32" else 0.0, **long)
 
 
 def test_edge_cases(ctx, ragged_code):

@@ -59,10 +59,12 @@ def test_serial_parity(ctx, codes, u, algo, dtype, F):
         parity.assert_bitwise(g, parity.oracle_f32_run(code, fr, 40, lam=lam, schedule=S))
     if (algo, dtype) == ("nms", "f64"):
         parity.assert_bitwise(g, o)
-    long_rtol = {("spa", "f32"): 1e-2, ("nms", "f32"): None}.get((algo, dtype), 1e-6)
-    s = parity.compare(g, o, 40, RTOL32 if dtype == "f32" else RTOL64, long_rtol=long_rtol,
-                       atol=parity.ATOL32 if dtype == "f32" else 0.0,
-                       long_after=parity.LONG_AFTER // u)
+    # every frame at 1e-4 / 1e-9 whatever its iteration count (sum-product
+    # stops within 6 here); FP32 min-sum past nms_long_after iterations is held
+    # bit for bit to the binary32 oracle above and counted against FP64
+    long = dict(long_after=parity.nms_long_after(S, u)) if (algo, dtype) == ("nms", "f32") else {}
+    s = parity.compare(g, o, 40, RTOL32 if dtype == "f32" else RTOL64,
+                       atol=parity.ATOL32 if dtype == "f32" else 0.0, **long)
     assert s["oracle_ok"] >= F // 2
 
 
@@ -118,36 +120,36 @@ def test_serial_compaction_keeps_results(ctx, codes, algo, dtype):
     its = a["iters"]
     assert (its == T).sum() > 30 and (its <= 5).sum() > 40
     g = dict(bits=a["bits"], iters=a["iters"], ok=a["ok"], L=a["llr"].astype(np.float64))
-    rng = np.random.default_rng(4)
+    # every frame against the oracle, failed or not
     if algo == "nms":
-        idx = rng.choice(300, 16, replace=False)
-        parity.assert_bitwise(g, parity.oracle_f32_run(code, fr, T, idx=idx, lam=lam, schedule=S),
-                              idx=idx)
-    else:
-        idx = rng.choice(np.nonzero(its <= parity.LONG_AFTER // 2)[0], 16, replace=False)
-        o = parity.oracle_run(code, fr, algo, dtype, T, idx=idx, lam=lam, schedule=S)
-        parity.compare(g, o, T, RTOL32 if dtype == "f32" else RTOL64, idx=idx,
-                       atol=parity.ATOL32 if dtype == "f32" else 0.0,
-                       long_after=parity.LONG_AFTER // 2)
+        parity.assert_bitwise(g, parity.oracle_f32_run(code, fr, T, lam=lam, schedule=S))
+    o = parity.oracle_run(code, fr, algo, dtype, T, lam=lam, schedule=S)
+    # stragglers up to T = 60 near the code's threshold; measured beyond 16
+    # iterations: FP32 sum-product L within 5.6e-3 (a frame at 29
+    # iterations), FP64 within 2.1e-5 (a frame at 56); FP32 min-sum against
+    # FP64: 23 of 300 long decodes differ
+    long = {("spa", "f32"): dict(long_after=parity.SPA_LONG_AFTER, long_rtol=2e-2),
+            ("spa", "f64"): dict(long_after=parity.SPA_LONG_AFTER, long_rtol=1e-4),
+            ("nms", "f32"): dict(long_after=parity.nms_long_after(S, 2), long_budget=0.1)}[(algo, dtype)]
+    parity.compare(g, o, T, RTOL32 if dtype == "f32" else RTOL64,
+                   atol=parity.ATOL32 if dtype == "f32" else 0.0, **long)
 
 
 @pytest.mark.parametrize("algo", ["spa", "nms"])
-def test_serial_n65536_sampled(ctx, algo):
-    """The benchmarked n = 65536, 256-frame workload under the serial
-    schedule: sampled frames against the oracle, properties on all, and fewer
-    iterations on average than flooding."""
+def test_serial_n65536_every_frame(ctx, algo):
+    """The u = 2 n = 65536, 256-frame workload under the serial schedule:
+    every frame against the oracle (min-sum also bit for bit with the
+    binary32 oracle), properties on all, and fewer iterations on average
+    than flooding."""
     wl = W.qkd_n65536(algo=algo)
     fr = wl.frames()
     dc = _upload(ctx, wl.code)
     g = parity.gpu_run(ctx, dc, fr, algo, "f32", wl.max_iter, alpha=wl.alpha, schedule=S)
-    idx = np.array([0, 1, 63, 64, 127, 128, 200, 255])
-    o = parity.oracle_run(wl.code, fr, algo, "f32", wl.max_iter, alpha=wl.alpha, idx=idx,
-                          schedule=S)
+    o = parity.oracle_run(wl.code, fr, algo, "f32", wl.max_iter, alpha=wl.alpha, schedule=S)
     if algo == "nms":
-        parity.assert_bitwise(g, parity.oracle_f32_run(wl.code, fr, wl.max_iter, idx=idx,
-                                                       schedule=S), idx=idx)
-    parity.compare(g, o, wl.max_iter, RTOL32, idx=idx, atol=parity.ATOL32,
-                   long_rtol=None if algo == "nms" else 1e-2, long_after=parity.LONG_AFTER // 2)
+        parity.assert_bitwise(g, parity.oracle_f32_run(wl.code, fr, wl.max_iter, schedule=S))
+    s = parity.compare(g, o, wl.max_iter, RTOL32, atol=parity.ATOL32)
+    assert s["oracle_ok"] == 256
     okf = g["ok"] == 1
     assert np.array_equal(syndromes(wl.code, g["bits"][okf]), fr.z[okf])
     assert np.all(g["iters"][~okf] == wl.max_iter)
@@ -156,17 +158,17 @@ def test_serial_n65536_sampled(ctx, algo):
     assert g["iters"].mean() < flood["iters"].mean()
 
 
-def test_serial_u3_n262144_sampled(ctx):
-    """Three matrices at QKD scale (n = 2^18, rate 0.85), sum-product."""
-    wl = W.qkd_n262144(0.85, algo="spa")
+@pytest.mark.parametrize("rate", [0.5, 0.7, 0.85])
+def test_serial_u3_n262144_every_frame(ctx, rate):
+    """Three matrices at QKD scale (n = 2^18, the three (rate, p) points),
+    sum-product: all 64 frames against the oracle."""
+    wl = W.qkd_n262144(rate, algo="spa")
     fr = wl.frames()
     dc = _upload(ctx, wl.code)
     g = parity.gpu_run(ctx, dc, fr, "spa", "f32", wl.max_iter, alpha=wl.alpha, schedule=S)
-    idx = np.array([0, 31, 63])
-    o = parity.oracle_run(wl.code, fr, "spa", "f32", wl.max_iter, alpha=wl.alpha, idx=idx,
-                          schedule=S)
-    parity.compare(g, o, wl.max_iter, RTOL32, idx=idx, atol=parity.ATOL32,
-                   long_after=parity.LONG_AFTER // 3)
+    o = parity.oracle_run(wl.code, fr, "spa", "f32", wl.max_iter, alpha=wl.alpha, schedule=S)
+    s = parity.compare(g, o, wl.max_iter, RTOL32, atol=parity.ATOL32)
+    assert s["oracle_ok"] == 64
     okf = g["ok"] == 1
     assert np.array_equal(syndromes(wl.code, g["bits"][okf]), fr.z[okf])
     assert np.all(g["iters"][~okf] == wl.max_iter)
@@ -221,6 +223,6 @@ def test_serial_many_matrices(ctx, u):
     # iterations, where the two FP64 check rules' last-bit differences
     # (prefix/suffix products against the direct product) grow to ~1e-6
     # absolute around small L
-    parity.compare(g64, o64, 50, RTOL64, long_rtol=1e-4, atol=1e-9)
+    parity.compare(g64, o64, 50, RTOL64, long_after=8, long_rtol=1e-4, atol=1e-9)
     its = g["iters"]
     assert (its == 50).sum() > 20 and (its <= 4).sum() > 50  # the oracle: 39/34 and 75/77

@@ -39,9 +39,12 @@ def test_sweep_points_match_oracle(ctx, rate, u, e):
         e = W.e_for_efficiency(rate, 1.125)
     wl = W.sweep_workload(rate, u, e)
     fr, g = _run(ctx, wl)
-    idx = np.array([0, 77, 200])
-    o = parity.oracle_run(wl.code, fr, "spa", "f32", wl.max_iter, idx=idx)
-    parity.compare(g, o, wl.max_iter, 1e-4, idx=idx, atol=parity.ATOL32)
+    # every frame against the oracle (256 frames of n = 65536); the u = 1
+    # point runs 17 to 35 iterations, where L drifts to 1.5e-4 (measured, a
+    # frame at 25 iterations) with every decision the same
+    o = parity.oracle_run(wl.code, fr, "spa", "f32", wl.max_iter)
+    parity.compare(g, o, wl.max_iter, 1e-4, atol=parity.ATOL32, long_after=parity.SPA_LONG_AFTER,
+                   long_rtol=1e-3)
     okf = g["ok"] == 1
     assert np.array_equal(syndromes(wl.code, g["bits"][okf]), fr.z[okf])
     assert np.all(g["iters"][~okf] == wl.max_iter)
