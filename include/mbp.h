@@ -177,6 +177,22 @@ int mbp_llr_from_bits(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y
 int mbp_syndrome(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, const uint8_t *x, uint8_t *synd_out,
                  void *stream);
 
+/* mbp_syndrome for callers that cannot allocate (work under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * outputs, bit for bit, with no allocation and no wait. The 64-frame key-bit
+ * words go to a fixed device array of 2^21 words (16 MiB per GPU, held until
+ * the process ends) instead of the context's workspace, so
+ * ceil(nframes / 64) * n must be at most 2^21 (else EINVAL, nothing
+ * enqueued); e.g. up to 512 frames at n = 2^18 or 2048 at n = 65536.
+ * The call only enqueues two kernels on `stream` and returns: x must stay
+ * valid, and synd_out is written, when the stream reaches them. Every call
+ * on one GPU shares that GPU's array: calls on one stream are ordered, but
+ * calls that overlap on one GPU (other streams, other threads) race, and
+ * the caller must order them. Arguments and other errors as mbp_syndrome;
+ * ESTATE if the array's address was not found when the context was created. */
+int mbp_syndrome_noalloc(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, const uint8_t *x,
+                         uint8_t *synd_out, void *stream);
+
 /* Decode nframes frames of one code (Sec. 2; Algorithm 1).
  *   llr       device [nframes][n] channel LLRs of p->dtype, finite
  *   synd      device [nframes][M] syndrome bytes (0 / nonzero), the u

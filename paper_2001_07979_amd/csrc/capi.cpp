@@ -87,6 +87,8 @@ int mbp_ctx_create(int32_t device, mbp_ctx **out) {
     HIP_OR_RETURN(hipSetDevice(device));
     hipDeviceProp_t prop;
     HIP_OR_RETURN(hipGetDeviceProperties(&prop, device));
+    // the allocation-free calls' fixed scratch: its address on this device
+    if (int rc = mbp::scratch_setup(device); rc != MBP_OK) return rc;
     mbp_ctx *ctx = new (std::nothrow) mbp_ctx();
     if (!ctx) return fail(MBP_ENOMEM, "mbp_ctx_create: out of host memory");
     ctx->device = device;
@@ -317,6 +319,18 @@ int mbp_syndrome(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, const uint
     if (nframes == 0) return MBP_OK;
     if (!x || !synd_out) return fail(MBP_EINVAL, "mbp_syndrome: null buffer");
     return mbp::syndrome_impl(ctx, code, nframes, x, synd_out, (hipStream_t)stream);
+}
+
+int mbp_syndrome_noalloc(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, const uint8_t *x,
+                         uint8_t *synd_out, void *stream) {
+    if (!ctx || !code) return fail(MBP_EINVAL, "mbp_syndrome_noalloc: null ctx or code");
+    if (code->ctx != ctx) return fail(MBP_EINVAL, "mbp_syndrome_noalloc: code belongs to another context");
+    if (nframes < 0) return fail(MBP_EINVAL, "mbp_syndrome_noalloc: nframes < 0");
+    if (nframes > 65535 * mbp::kLanes)
+        return fail(MBP_EINVAL, "mbp_syndrome_noalloc: at most 65535 * 64 frames per call");
+    if (nframes == 0) return MBP_OK;
+    if (!x || !synd_out) return fail(MBP_EINVAL, "mbp_syndrome_noalloc: null buffer");
+    return mbp::syndrome_noalloc_impl(ctx, code, nframes, x, synd_out, (hipStream_t)stream);
 }
 
 int mbp_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,

@@ -127,6 +127,13 @@ int decode_impl(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t
 // Implemented in syndrome.hip; arguments are validated by capi.cpp.
 int syndrome_impl(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, const uint8_t *x, uint8_t *z,
                   hipStream_t stream);
+// The allocation-free variant (syndrome.hip): its bit words live in a fixed
+// device array of kNoallocWords words, whose address scratch_setup looks up
+// once per device (with that device current).
+constexpr size_t kNoallocWords = size_t(1) << 21;  // 16 MiB
+int scratch_setup(int device);
+int syndrome_noalloc_impl(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, const uint8_t *x, uint8_t *z,
+                          hipStream_t stream);
 int llr_impl(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y, const double *e,
              int32_t dtype, void *llr_out, hipStream_t stream);
 

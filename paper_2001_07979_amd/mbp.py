@@ -83,6 +83,7 @@ def lib():
             "mbp_decode": (ctypes.c_int, [vp, vp, ctypes.POINTER(mbp_params), i32] + [vp] * 7),
             "mbp_decode_from_bits": (ctypes.c_int, [vp, vp, ctypes.POINTER(mbp_params), i32] + [vp] * 8),
             "mbp_syndrome": (ctypes.c_int, [vp, vp, i32, vp, vp, vp]),
+            "mbp_syndrome_noalloc": (ctypes.c_int, [vp, vp, i32, vp, vp, vp]),
             "mbp_unrolled_workspace_bytes": (ctypes.c_int, [vp, i32, i32, i32,
                                                              ctypes.POINTER(ctypes.c_uint64)]),
             "mbp_nms_unrolled_fwd": (ctypes.c_int, [vp, vp, i32, i32, i32, ctypes.c_double] + [vp] * 5
@@ -352,6 +353,19 @@ def syndrome(ctx: Context, code: Code, x, out=None, stream=None):
         out = torch.empty((F, code.M), dtype=torch.uint8, device=x.device)
     po = _dev(out, "out", ctx.device, _u8(), (F, code.M))
     _check(lib().mbp_syndrome(ctx.handle, code.handle, F, px, po, _stream_ptr(stream)), "mbp_syndrome")
+    return out
+
+
+def syndrome_noalloc(ctx: Context, code: Code, x, out, stream=None):
+    """syndrome() with no allocation and no wait (mbp_syndrome_noalloc): the
+    caller passes the output [F, M] uint8; at most 2^21 / n groups of 64 frames."""
+    if x.dim() != 2:
+        raise ValueError("x must be [F, n]")
+    F = int(x.shape[0])
+    px = _dev(x, "x", ctx.device, _u8(), (F, code.n))
+    po = _dev(out, "out", ctx.device, _u8(), (F, code.M))
+    _check(lib().mbp_syndrome_noalloc(ctx.handle, code.handle, F, px, po, _stream_ptr(stream)),
+           "mbp_syndrome_noalloc")
     return out
 
 
