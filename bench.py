@@ -271,6 +271,89 @@ def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_
     }
 
 
+def qualifying_queue(ctx, frames_per_cell: int, reps: int, algo: str = "spa"):
+    """A serving queue at the efficiency the metric asks for: rate 0.85 (the
+    rate at which f <= 1.1 holds over a band of error rates), n in {16384,
+    65536, 2^18}, u in {2, 3}, frames_per_cell frames per (n, u) cell with
+    BSC p log-uniform in [0.0191, 0.03] (f from 1.10 down to 0.79 of the
+    single-matrix syndrome; Sec. 2, eqs. (3)-(4)), in random arrival order.
+    Decoded by the captured persistent batched decode and by one plain
+    decode per cell (identical outputs); FER per cell over its frames, and
+    the qualifying Mbps: the bits of the cells whose FER is <= 1e-2, per
+    second of the batched decode."""
+    import torch
+    from paper_2001_07979_amd import mbp
+    from paper_2001_07979_amd.inputs import bsc_frames
+    from paper_2001_07979_amd.inputs import workloads as W
+
+    dev = torch.device("cuda", 0)
+    T = 100
+    cells = [(n, 0.85, u) for n in W.MIXED_N for u in (2, 3)]
+    rng = np.random.default_rng(85)
+    items, pool = [], []
+    for k, (n, rate, u) in enumerate(cells):
+        code = W.mixed_code(n, rate, u)
+        p = np.exp(rng.uniform(np.log(0.0191), np.log(0.03), frames_per_cell))
+        fr = bsc_frames(code, frames_per_cell, p, seed=8500 + k)
+        dc = mbp.Code.from_inputs(ctx, code)
+        lam = mbp.llr_from_bits(ctx, torch.from_numpy(fr.y).to(dev), torch.from_numpy(fr.p).to(dev))
+        items.append((dc, lam, torch.from_numpy(fr.z).to(dev)))
+        pool.append((code, fr))
+    torch.cuda.synchronize()
+    bits_total = sum(code.n * fr.nframes for code, fr in pool)
+    log("bench: qualifying queue, autotuning")
+    tune = mbp.autotune(ctx, items, max_iter=T, algo=algo)
+    outs_b = [mbp.batch_outputs(dc, lam) for dc, lam, _ in items]
+    plan = mbp.Plan(ctx, items, outs_b, max_iter=T, tuning=tune, algo=algo)
+    plan.launch()
+    plan.wait()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.launch()
+    plan.wait()
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / reps
+    outs_g = [mbp.batch_outputs(dc, lam) for dc, lam, _ in items]
+    for (dc, lam, z), o in zip(items, outs_g):
+        mbp.decode(ctx, dc, lam, z, algo=algo, max_iter=T, out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for (dc, lam, z), o in zip(items, outs_g):
+            mbp.decode(ctx, dc, lam, z, algo=algo, max_iter=T, out=o)
+    torch.cuda.synchronize()
+    t_g = (time.perf_counter() - t0) / reps
+    identical = all(torch.equal(ob[k], og[k]) for ob, og in zip(outs_b, outs_g)
+                    for k in ("bits", "iters", "ok", "llr"))
+    per_cell, qual_bits = {}, 0
+    for (code, fr), o, (n, rate, u) in zip(pool, outs_b, cells):
+        bits = o["bits"].cpu().numpy()
+        wrong = np.any(bits != fr.x, axis=1)
+        f = code.m[0] / (code.n * h2(fr.p))
+        fer = float(wrong.mean())
+        per_cell[f"n{n}-r{rate}-u{u}"] = {
+            "frames": fr.nframes, "fer": fer, "frame_errors": int(wrong.sum()),
+            "f_max": round(float(f.max()), 4), "f_min": round(float(f.min()), 4),
+            "avg_iters": round(float(o["iters"].float().mean().item()), 3)}
+        if fer <= 1e-2:
+            qual_bits += code.n * fr.nframes
+    plan.close()
+    for dc, _, _ in items:
+        dc.close()
+    return {"workload": f"rate 0.85, n in {list(W.MIXED_N)}, u in [2, 3], {frames_per_cell} frames per "
+                        f"(n, u) cell, BSC p log-uniform [0.0191, 0.03] (f <= 1.1); "
+                        + ("FP32 sum-product" if algo == "spa" else "FP32 min-sum alpha 0.75")
+                        + f", T={T}, early exit",
+            "frames": frames_per_cell * len(cells), "tuning": tune,
+            "batched_mbps": round(bits_total / t_b / 1e6, 1),
+            "plain_per_code_mbps": round(bits_total / t_g / 1e6, 1),
+            "speedup_vs_plain_per_code": round(t_g / t_b, 2),
+            "identical_outputs": identical,
+            "qualifying_mbps": round(qual_bits / t_b / 1e6, 1),
+            "cells": per_cell}
+
+
 def n65536_point(ctx, steps: int, algo: str):
     """The u=2 n=65536 rate-3/4 workload (256 frames, BSC 0.02, f = 1.77) under
     both schedules, decoded from Bob's bits like the headline step."""
@@ -503,6 +586,8 @@ def main():
     ap.add_argument("--queue-frames", type=int, default=2048,
                     help="frames of the heterogeneous queue for batched vs plain (0 skips it)")
     ap.add_argument("--queue-reps", type=int, default=5)
+    ap.add_argument("--qualifying-frames", type=int, default=320,
+                    help="frames per (n, u) cell of the rate-0.85, f <= 1.1 serving queue (0 skips it)")
     ap.add_argument("--queue-batched-only", action="store_true",
                     help="run only the batched offline leg of the queue (for profiling)")
     ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled training step")
@@ -531,6 +616,7 @@ def main():
     if args.no_extras:
         args.no_other_schedule = args.no_n65536 = args.no_unrolled = args.no_two_call = True
         args.queue_frames = 0
+        args.qualifying_frames = 0
 
     import torch
     from paper_2001_07979_amd import mbp
@@ -720,6 +806,10 @@ def run(args, ctx, dcode, wl, fr, dev):
         log("bench: unrolled K=20 training step")
         unrolled = unrolled_step(ctx, 5)
 
+    qualifying = None
+    if args.qualifying_frames:
+        qualifying = qualifying_queue(ctx, args.qualifying_frames, args.queue_reps, algo=args.algo)
+
     batched = None
     if args.queue_frames:
         batched = batched_vs_plain(ctx, args.queue_frames, args.queue_reps, args.arrival_load,
@@ -742,6 +832,7 @@ def run(args, ctx, dcode, wl, fr, dev):
         "other_schedule": other, "n65536": c2, "alice_syndromes": alice,
         "unrolled_training_step": unrolled,
         "batched_vs_plain": batched,
+        "qualifying_queue": qualifying,
     }
 
 

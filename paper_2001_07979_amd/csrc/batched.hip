@@ -289,7 +289,8 @@ __device__ __forceinline__ void spa_row(const GroupDesc &G_, int r, bool first, 
     for (int j = 0; j < DMAX; ++j) v[j] = ldc(G_.col, e0 + j);
     float *cg = G_.c + static_cast<size_t>(e0) * G;
     if (on)
-        check_row_f32<kSPA, DMAX, false>(v, d, zbit, a.alpha, a.clip, first, buf_rsrc(G_.Lp, kBufAll), cg, cg,
+        check_row_f32<kSPA, DMAX, false>([&v](int j) { return v[j]; }, d, zbit, a.alpha, a.clip, first,
+                                         buf_rsrc(G_.Lp, kBufAll), cg, cg,
                                          lane, 0.0f);
 }
 

@@ -183,6 +183,9 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     Dims ds{E, n, M, ntot, (M + kBlock - 1) / kBlock, 0, 0, p->alpha, p->llr_clip, p->max_iter, ngroups,
             nspare};
     ds.live = &tail->live;
+    // the iteration kernels index their (group, tile) work items in 32 bits
+    if (static_cast<int64_t>(ntot) * std::max({dc.ntiles, dv.ntiles, dvs.ntiles}) >= INT32_MAX)
+        return fail(MBP_EUNSUPPORTED, "decode: too many frame groups times tiles for one call");
     const int grid_c = grid_for(ctx, reinterpret_cast<const void *>(kc),
                                 static_cast<int64_t>(ngroups) * dc.ntiles);
     const int grid_vp = grid_for(ctx, reinterpret_cast<const void *>(kvp),

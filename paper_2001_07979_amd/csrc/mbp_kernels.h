@@ -205,12 +205,18 @@ struct StopTail {
 constexpr int kRun = 0, kUnmet = 1;
 
 // One check of the FP32 check pass, for the lanes of one wave (frames of
-// one group): v[] holds the check's variable indices (slots past the degree
-// d hold other valid indices), src the group's L rows (or, BITS, its bit
+// one group): v(j) gives the check's j-th variable index, wave-uniform (it is
+// read right where slot j's gather is issued; slots past the degree d read
+// row 0), src the group's L rows (or, BITS, its bit
 // words), ci / cg the check's first c^{t-1} / c^t row. Every slot loads,
 // unconditionally (a slot past the degree reads row 0 and is neutralised
 // below), so the loads carry no branches and no vector address arithmetic;
 // only the stores test the degree.
+//
+// `prefetch` runs once the check's loads are issued (the caller's loads for
+// its next check go out while these are in flight). Every lane loads and
+// computes (so the caller's prefetched values stay wave-uniform); only lanes
+// with `on` (frames still running) store.
 //
 // With CST (min-sum only, DMAX <= kStateMaxDeg) the check's state `st`
 // replaces its old messages: row 0 holds alpha m1, row 1 alpha m2, row 2 the
@@ -218,26 +224,37 @@ constexpr int kRun = 0, kUnmet = 1;
 // (bits 26-31). Every old message is rebuilt from them bit for bit, so the
 // pass reads 3 rows per check instead of one per edge; it still writes
 // every message (the variable pass reads them) and the new state.
-template <int ALGO, int DMAX, bool BITS, bool CST = false>
-__device__ __forceinline__ void check_row_f32(const int (&v)[DMAX], int d, uint32_t zbit, float alpha,
+struct NoPrefetch {
+    __device__ void operator()() const {}
+};
+
+template <int ALGO, int DMAX, bool BITS, bool CST = false, typename Cols, typename Prefetch = NoPrefetch>
+__device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbit, float alpha,
                                               float clip, bool first, BufRsrc src, const float *ci, float *cg,
-                                              unsigned lane, float ym, uint32_t *st = nullptr) {
+                                              unsigned lane, float ym, uint32_t *st = nullptr,
+                                              Prefetch prefetch = Prefetch(), bool on = true) {
     static_assert(!CST || (ALGO == kNMS && DMAX <= kStateMaxDeg), "compressed state: min-sum, small degree");
     const int lo = static_cast<int>(lane) * 4;
-    // c^{t-1} of the check's edges, or zeros (no memory read) at t = 1
-    const BufRsrc rin = buf_rsrc(ci, first || BITS || CST ? 0u : kBufAll);
+    // c^{t-1} of the check's edges (read only after the first iteration:
+    // c^0 = 0). The descriptors' record counts are constants: a count chosen
+    // at run time by a select can be formed in a vector register, and a
+    // descriptor held in vector registers costs a loop around every access.
+    const BufRsrc rin = buf_rsrc(ci, kBufAll);
     const BufRsrc rout = buf_rsrc(cg, kBufAll);
-    const BufRsrc rst = buf_rsrc(st, CST ? kBufAll : 0u);
+    const BufRsrc rst = buf_rsrc(st, kBufAll);
     float q[DMAX];
     if constexpr (CST && !BITS) {
         // the old messages from the state (zeros at t = 1: nothing to read)
-        const BufRsrc rold = buf_rsrc(st, first ? 0u : kBufAll);
-        const float o1 = __uint_as_float(buf_load(rold, lo, 0));
-        const float o2 = __uint_as_float(buf_load(rold, lo, G * 4));
-        const uint32_t os = buf_load(rold, lo, 2 * G * 4);
+        float o1 = 0.0f, o2 = 0.0f;
+        uint32_t os = 0;
+        if (!first) {
+            o1 = __uint_as_float(buf_load(rst, lo, 0));
+            o2 = __uint_as_float(buf_load(rst, lo, G * 4));
+            os = buf_load(rst, lo, 2 * G * 4);
+        }
         const int oi = static_cast<int>(os >> kStateArgShift);
 #pragma unroll
-        for (int j = 0; j < DMAX; ++j) q[j] = __uint_as_float(buf_load(src, lo, (j < d ? v[j] : 0) * G * 4));
+        for (int j = 0; j < DMAX; ++j) q[j] = __uint_as_float(buf_load(src, lo, (j < d ? v(j) : 0) * G * 4));
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) {
             const float mag = j == oi ? o2 : o1;
@@ -247,19 +264,26 @@ __device__ __forceinline__ void check_row_f32(const int (&v)[DMAX], int d, uint3
         uint32_t yh[DMAX];
         const int hl = static_cast<int>(lane >> 5) * 4;  // the 32-bit half holding the lane's bit
 #pragma unroll
-        for (int j = 0; j < DMAX; ++j) yh[j] = buf_load(src, hl, (j < d ? v[j] : 0) * 8);
+        for (int j = 0; j < DMAX; ++j) yh[j] = buf_load(src, hl, (j < d ? v(j) : 0) * 8);
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) q[j] = lam_of_half(yh[j], lane, ym);
     } else {
-        float co[DMAX];
+        if (first) {
 #pragma unroll
-        for (int j = 0; j < DMAX; ++j) {
-            q[j] = __uint_as_float(buf_load(src, lo, (j < d ? v[j] : 0) * G * 4));
-            co[j] = __uint_as_float(buf_load(rin, lo, (j < d ? j : 0) * G * 4));
+            for (int j = 0; j < DMAX; ++j) q[j] = __uint_as_float(buf_load(src, lo, (j < d ? v(j) : 0) * G * 4));
+        } else {
+            float co[DMAX];
+#pragma unroll
+            for (int j = 0; j < DMAX; ++j) {
+                q[j] = __uint_as_float(buf_load(src, lo, (j < d ? v(j) : 0) * G * 4));
+                co[j] = __uint_as_float(buf_load(rin, lo, (j < d ? j : 0) * G * 4));
+            }
+#pragma unroll
+            for (int j = 0; j < DMAX; ++j) q[j] -= co[j];
         }
-#pragma unroll
-        for (int j = 0; j < DMAX; ++j) q[j] -= co[j];
     }
+    // the caller's next loads go out while this check's are in flight
+    prefetch();
     // Signs ride in the IEEE sign bits (q + 0 turns -0 into +0: sgn(0) =
     // +1), so the sign product is an XOR of words; slots past the degree
     // contribute no sign.
@@ -286,15 +310,17 @@ __device__ __forceinline__ void check_row_f32(const int (&v)[DMAX], int d, uint3
         for (int j = 0; j < DMAX; ++j) {
             const uint32_t sw = sign_word(__uint_as_float(sxb ^ __float_as_uint(q[j])));
             if constexpr (CST) signs |= (sw >> 31) << j;
-            if (j < d) {
+            if (j < d && on) {
                 const float mag = j == i1 ? a2 : a1;  // >= 0
                 buf_store(__float_as_uint(mag) | sw, rout, lo, j * G * 4);
             }
         }
         if constexpr (CST) {
-            buf_store(__float_as_uint(a1), rst, lo, 0);
-            buf_store(__float_as_uint(a2), rst, lo, G * 4);
-            buf_store(signs | (static_cast<uint32_t>(i1) << kStateArgShift), rst, lo, 2 * G * 4);
+            if (on) {
+                buf_store(__float_as_uint(a1), rst, lo, 0);
+                buf_store(__float_as_uint(a2), rst, lo, G * 4);
+                buf_store(signs | (static_cast<uint32_t>(i1) << kStateArgShift), rst, lo, 2 * G * 4);
+            }
         }
     } else {
         // sum-product: the tanh product over the other edges, carried as
@@ -328,7 +354,7 @@ __device__ __forceinline__ void check_row_f32(const int (&v)[DMAX], int d, uint3
         float suf = 0.0f;
 #pragma unroll
         for (int j = DMAX - 1; j >= 0; --j) {
-            if (j < d) {
+            if (j < d && on) {
                 const float E = fmaf(-q[j], suf, q[j] + suf);
                 const float mag = atanh2_of_complement(E);
                 const uint32_t sb = sign_word(__uint_as_float(sxb ^ __float_as_uint(ep[j])));
@@ -369,6 +395,88 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
     const T clip = static_cast<T>(a.clip);
     const bool first = a.t == 1;
     const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
+    const int rend = a.row1 < 0 ? a.M : a.row1;
+    if constexpr (sizeof(T) == 4) {
+        // FP32: the wave's checks (kRowsPerWave per work item, items a grid
+        // stride apart) as one software-pipelined stream. While a check's
+        // gathers are in flight the wave loads the next check's column
+        // indices (one vector load: lane j holds column j) and the offsets,
+        // syndrome word and weight of the check after it, so no check waits
+        // on its own chain of index loads.
+        // A check's scalars travel in one register (lane 0: row_ptr[r],
+        // 1: row_ptr[r + 1], 2-3: the group's running set, 4-5: the check's
+        // syndrome word, 6: the group, 7: the check; r >= rend: none), read
+        // with one per-lane gather, so three checks in flight hold few
+        // scalar registers; its column indices in another (lane j < DMAX:
+        // col[row_ptr[r] + j], the array padded past E).
+        struct Row {
+            int32_t info, cols;
+        };
+        const int64_t nrows = ((total - blockIdx.x + gridDim.x - 1) / gridDim.x) * kRowsPerWave;
+        auto meta = [&](int64_t q, Row &R) {
+            // total < 2^31 (the host checks): 32-bit division
+            const uint32_t w = blockIdx.x + static_cast<uint32_t>(q / kRowsPerWave) * gridDim.x;
+            const int g = static_cast<int>(w / static_cast<uint32_t>(a.ntiles));
+            const int tile = static_cast<int>(w % static_cast<uint32_t>(a.ntiles));
+            const int r = a.row0 + tile * kRowsPerTile + static_cast<int>(q % kRowsPerWave) * kWaves + wave;
+            const int rr = r < rend ? r : rend - 1;
+            const int l = static_cast<int>(lane);
+            const int32_t *src = l < 2 ? row_ptr + rr + l
+                               : l < 4 ? reinterpret_cast<const int32_t *>(act + kStride * g + kRun) + (l - 2)
+                               : l < 6 ? reinterpret_cast<const int32_t *>(zb + static_cast<size_t>(g) * a.M + rr) + (l - 4)
+                                       : row_ptr + rr;
+            const int32_t got = *src;
+            R.info = l == 6 ? g : l == 7 ? r : got;
+        };
+        auto cols = [&](Row &R) {
+            R.cols = static_cast<int>(lane) < DMAX ? col[__builtin_amdgcn_readlane(R.info, 0) + static_cast<int>(lane)]
+                                                   : 0;
+        };
+        if (nrows <= 0) return;
+        Row cur, nxt, nn;
+        meta(0, cur);
+        cols(cur);
+        if (nrows > 1) meta(1, nxt);
+        for (int64_t q = 0; q < nrows; ++q) {
+            const bool more = q + 1 < nrows, more2 = q + 2 < nrows;
+            auto prefetch = [&]() {
+                if (more) cols(nxt);
+                if (more2) meta(q + 2, nn);
+            };
+            const int r = __builtin_amdgcn_readlane(cur.info, 7);
+            const uint64_t run = static_cast<uint32_t>(__builtin_amdgcn_readlane(cur.info, 2)) |
+                                 (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readlane(cur.info, 3))) << 32);
+            if (r < rend && run != 0) {
+                const int g = __builtin_amdgcn_readlane(cur.info, 6);
+                const bool on = (run >> lane) & 1;
+                const int e0 = __builtin_amdgcn_readlane(cur.info, 0);
+                const int d = __builtin_amdgcn_readlane(cur.info, 1) - e0;
+                const uint32_t zlo = static_cast<uint32_t>(__builtin_amdgcn_readlane(cur.info, 4));
+                const uint32_t zhi = static_cast<uint32_t>(__builtin_amdgcn_readlane(cur.info, 5));
+                const uint32_t zbit = ((lane < 32 ? zlo : zhi) >> (lane & 31u)) & 1u;
+                const float alpha = alpha_l ? alpha_l[row_mat[r]] : static_cast<float>(a.alpha);
+                const size_t cb = (static_cast<size_t>(g) * a.E + e0) * G;
+                const T *Lg = Lp + static_cast<size_t>(g) * (a.lstride < 0 ? static_cast<int64_t>(a.n) * G : a.lstride);
+                // independent decoders: the posterior of the check's own matrix
+                const T *Lr = a.mstride ? Lg + row_mat[r] * a.mstride : Lg;
+                const uint64_t *yg = BITS ? a.ybits + static_cast<size_t>(g) * a.n : nullptr;
+                const float ym = BITS ? static_cast<const float *>(a.ymag)[static_cast<size_t>(g) * G + lane] : 0.0f;
+                uint32_t *st = CST ? static_cast<uint32_t *>(a.cstate) + (static_cast<size_t>(g) * a.M + r) * kStateRows * G
+                                   : nullptr;
+                const int32_t cs = cur.cols;
+                auto v = [cs](int j) { return __builtin_amdgcn_readlane(cs, j); };
+                check_row_f32<ALGO, DMAX, BITS, CST>(v, d, zbit, alpha, clip, first,
+                                                     BITS ? buf_rsrc(yg, kBufAll) : buf_rsrc(Lr, kBufAll),
+                                                     c_in + cb, c_out + cb, lane, ym, st, prefetch, on);
+            } else {
+                prefetch();
+            }
+            cur = nxt;
+            nxt = nn;
+        }
+        return;
+    } else {
+    // FP64: one check after another
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
         const int g = static_cast<int>(w / a.ntiles);
         const int tile = static_cast<int>(w % a.ntiles);
@@ -396,15 +504,7 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
             int v[DMAX];
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) v[j] = col[e0 + j];
-            if constexpr (sizeof(T) == 4) {
-                uint32_t *st = CST ? static_cast<uint32_t *>(a.cstate) +
-                                         (static_cast<size_t>(g) * a.M + r) * kStateRows * G
-                                   : nullptr;
-                if (on)
-                    check_row_f32<ALGO, DMAX, BITS, CST>(
-                        v, d, static_cast<uint32_t>(zbit), alpha, clip, first,
-                        BITS ? buf_rsrc(yg, kBufAll) : buf_rsrc(Lr, kBufAll), ci, cg, lane, ym, st);
-            } else if (on) {
+            if (on) {
                 // issue every gather of the check before using any of them
                 T q[DMAX], co[DMAX];
                 uint32_t yh[DMAX];
@@ -494,6 +594,7 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                 }
             }
         }
+    }
     }
 }
 
@@ -811,107 +912,154 @@ __global__ __launch_bounds__(kBlock) void k_output_slots(const T *Lp, const int3
 // (summed from 0 in check order). var_edge is the flagged list: an entry
 // with bit 31 set starts the next matrix's run of the variable's edges, where
 // the running matrix sum is added to L and restarted. Each wave takes VPW
-// variables of degree at most DV and issues all their gathers before summing
-// any. D, if not null, receives the decision word of
-// each variable (bit k set when frame 64g+k decides 1, i.e. L < 0; frames
-// not running leave 0).
+// consecutive variables of degree at most DV and issues all their gathers
+// before summing any. D, if not null, receives the decision word of each
+// variable (bit k set when frame 64g+k decides 1, i.e. L < 0; frames not
+// running leave 0).
+//
+// The work items a wave visits are software-pipelined. A wave's VPW
+// variables have consecutive offsets and, together, at most 64 consecutive
+// edge-list entries, so each comes in one vector load (lane l holds offset
+// l, resp. entry l, and a wave-uniform copy is read from its lane where
+// needed). While one item's message gathers are in flight, the wave loads
+// the next item's edge lists and the offsets of the item after it, so no item
+// waits on its own chain of index loads (offsets, then edge lists, then
+// messages).
 template <typename T, int DV, int VPW, bool BITS = false>
 __global__ __launch_bounds__(kBlock) void k_variable(
     const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_edge,
     const T *__restrict__ c, const T *__restrict__ lam, T *__restrict__ Lp,
     const uint64_t *__restrict__ act, uint64_t *__restrict__ D, const Dims a) {
+    static_assert(DV * VPW <= 64, "a wave's edge lists fit its lanes");
     if (a.live && *a.live == 0) return;  // every frame retired
     const unsigned lane = lane_id();
     const int wave = wave_id();
     const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
-    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-        const int gw = static_cast<int>(w / a.ntiles);
-        const int g = a.reverse ? a.ngroups - 1 - gw : gw;
-        const int tile = static_cast<int>(w % a.ntiles);
-        const uint64_t run = act[kStride * g + kRun];
-        if (run == 0) continue;
-        const bool on = (run >> lane) & 1;
+    // emax >= 0 restricts the sum to stacked edges below it: the matrices
+    // whose check messages exist so far in the first iteration of the
+    // matrix-serial schedule
+    const int64_t lim = a.emax < 0 ? INT64_MAX : a.emax;
+    struct Item {
+        int g, i0;      // group; first variable of the wave
+        uint64_t run;   // frames of the group still running
+        int32_t off;    // lane l <= VPW: var_ptr[min(i0 + l, n)]
+        int32_t edges;  // lane l: var_edge[var_ptr[i0] + l] (the list is padded past E)
+    };
+    auto meta = [&](int64_t w, Item &it) {
+        // total < 2^31 (the host checks): 32-bit division
+        const uint32_t w32 = static_cast<uint32_t>(w);
+        const int gw = static_cast<int>(w32 / static_cast<uint32_t>(a.ntiles));
+        it.g = a.reverse ? a.ngroups - 1 - gw : gw;
+        const int tile = static_cast<int>(w32 % static_cast<uint32_t>(a.ntiles));
+        it.i0 = (tile * kWaves + wave) * VPW;
+        it.run = act[kStride * it.g + kRun];
+        it.off = var_ptr[min(it.i0 + min(static_cast<int>(lane), VPW), a.n)];
+    };
+    auto edges = [&](Item &it) {
+        it.edges = var_edge[__builtin_amdgcn_readlane(it.off, 0) + static_cast<int>(lane)];
+    };
+    int64_t w = blockIdx.x;
+    if (w >= total) return;
+    Item cur, nxt, nn;
+    meta(w, cur);
+    edges(cur);
+    bool more = w + gridDim.x < total;
+    if (more) meta(w + gridDim.x, nxt);
+    for (;;) {
+        const bool on = (cur.run >> lane) & 1;
+        const int g = cur.g;
         const size_t gb = static_cast<size_t>(g) * a.n * G;
         const T *cg = c + static_cast<size_t>(g) * a.E * G;
-        const uint64_t *yg = BITS ? a.ybits + static_cast<size_t>(g) * a.n : nullptr;
-        const T ym = BITS ? static_cast<const T *>(a.ymag)[static_cast<size_t>(g) * G + lane] : T(0);
-        int i[VPW], k0[VPW], deg[VPW];
+        // per variable: its index, first list position (relative to the
+        // wave's first) and degree; past n the offsets repeat E, degree 0
+        const int k0 = __builtin_amdgcn_readlane(cur.off, 0);
+        int i[VPW], p0[VPW], deg[VPW];
         bool in[VPW];
 #pragma unroll
         for (int v = 0; v < VPW; ++v) {
-            i[v] = (tile * VPW + v) * kWaves + wave;
+            i[v] = cur.i0 + v;
             in[v] = i[v] < a.n;
-            const int ii = in[v] ? i[v] : a.n - 1;
-            k0[v] = var_ptr[ii];
-            deg[v] = in[v] ? var_ptr[ii + 1] - k0[v] : 0;
+            p0[v] = __builtin_amdgcn_readlane(cur.off, v) - k0;
+            deg[v] = __builtin_amdgcn_readlane(cur.off, v + 1) - k0 - p0[v];
         }
+        // entry j of variable v (wave-uniform), read where it is used
+        auto entry = [&](int v, int j) { return __builtin_amdgcn_readlane(cur.edges, min(p0[v] + j, 63)); };
         T x[VPW][DV], s[VPW];
-        if (on) {
-            // emax >= 0 restricts the sum to stacked edges below it: the
-            // matrices whose check messages exist so far in the first
-            // iteration of the matrix-serial schedule
-            const int64_t lim = a.emax < 0 ? INT64_MAX : a.emax;
-            int ev[VPW][DV];
-            bool fl[VPW][DV];
-            uint32_t yh[VPW];
+        uint32_t yh[VPW];
+        if (cur.run != 0 && on) {
+            const uint64_t *yg = BITS ? a.ybits + static_cast<size_t>(g) * a.n : nullptr;
 #pragma unroll
             for (int v = 0; v < VPW; ++v) {
-#pragma unroll
-                for (int j = 0; j < DV; ++j) {
-                    const int raw = var_edge[k0[v] + j];
-                    fl[v][j] = raw < 0;
-                    ev[v][j] = raw & 0x7fffffff;
-                }
                 if constexpr (BITS)
                     yh[v] = in[v] ? bit_half(yg, i[v], lane) : 0u;
                 else
                     s[v] = in[v] ? (lam + gb + static_cast<size_t>(i[v]) * G)[lane] : T(0);
 #pragma unroll
-                for (int j = 0; j < DV; ++j)
-                    if (j < deg[v] && ev[v][j] < lim) x[v][j] = (cg + static_cast<size_t>(ev[v][j]) * G)[lane];
-            }
-            if constexpr (BITS) {
-#pragma unroll
-                for (int v = 0; v < VPW; ++v) s[v] = in[v] ? lam_of_half(yh[v], lane, ym) : T(0);
-            }
-            // independent decoders: each matrix's posterior lambda + its sum
-            T *lmg = static_cast<T *>(a.lm);
-            if (lmg) lmg += static_cast<size_t>(g) * a.prows * a.n * G;
-#pragma unroll
-            for (int v = 0; v < VPW; ++v) {
-                T acc = T(0);  // the running matrix's sum
-                const T lam_v = s[v];
-                int mrun = 0;  // the running matrix
-                bool any = false;
-#pragma unroll
                 for (int j = 0; j < DV; ++j) {
-                    if (j < deg[v] && ev[v][j] < lim) {
-                        if (fl[v][j]) {
-                            s[v] += acc;
-                            if (lmg && in[v])
-                                (lmg + (static_cast<size_t>(mrun) * a.n + i[v]) * G)[lane] = lam_v + acc;
-                            acc = T(0);
-                        }
-                        if (lmg && (fl[v][j] || !any))
-                            mrun = (ev[v][j] >= a.emat[0]) + (ev[v][j] >= a.emat[1]) + (ev[v][j] >= a.emat[2]);
-                        acc += x[v][j];
-                        any = true;
-                    }
+                    const int e = entry(v, j) & 0x7fffffff;
+                    if (j < deg[v] && e < lim) x[v][j] = (cg + static_cast<size_t>(e) * G)[lane];
                 }
-                if (any) {
-                    s[v] += acc;
-                    if (lmg && in[v]) (lmg + (static_cast<size_t>(mrun) * a.n + i[v]) * G)[lane] = lam_v + acc;
-                }
-                if (in[v]) (Lp + gb + static_cast<size_t>(i[v]) * G)[lane] = s[v];
             }
         }
-        if (D) {
+        // the next item's edge lists and the offsets of the one after, in
+        // flight with this item's gathers
+        const bool more2 = more && w + 2 * static_cast<int64_t>(gridDim.x) < total;
+        if (more) edges(nxt);
+        if (more2) meta(w + 2 * static_cast<int64_t>(gridDim.x), nn);
+        if (cur.run != 0) {
+            if (on) {
+                if constexpr (BITS) {
+                    const T ym = static_cast<const T *>(a.ymag)[static_cast<size_t>(g) * G + lane];
 #pragma unroll
-            for (int v = 0; v < VPW; ++v) {
-                const uint64_t bits = __ballot(on && in[v] && s[v] < T(0));
-                if (lane == 0 && in[v]) D[static_cast<size_t>(g) * a.n + i[v]] = bits;
+                    for (int v = 0; v < VPW; ++v) s[v] = in[v] ? lam_of_half(yh[v], lane, ym) : T(0);
+                }
+                // independent decoders: each matrix's posterior lambda + its sum
+                T *lmg = static_cast<T *>(a.lm);
+                if (lmg) lmg += static_cast<size_t>(g) * a.prows * a.n * G;
+#pragma unroll
+                for (int v = 0; v < VPW; ++v) {
+                    T acc = T(0);  // the running matrix's sum
+                    const T lam_v = s[v];
+                    int mrun = 0;  // the running matrix
+                    bool any = false;
+#pragma unroll
+                    for (int j = 0; j < DV; ++j) {
+                        const int raw = entry(v, j);
+                        const bool fl = raw < 0;
+                        const int e = raw & 0x7fffffff;
+                        if (j < deg[v] && e < lim) {
+                            if (fl) {
+                                s[v] += acc;
+                                if (lmg && in[v])
+                                    (lmg + (static_cast<size_t>(mrun) * a.n + i[v]) * G)[lane] = lam_v + acc;
+                                acc = T(0);
+                            }
+                            if (lmg && (fl || !any))
+                                mrun = (e >= a.emat[0]) + (e >= a.emat[1]) + (e >= a.emat[2]);
+                            acc += x[v][j];
+                            any = true;
+                        }
+                    }
+                    if (any) {
+                        s[v] += acc;
+                        if (lmg && in[v]) (lmg + (static_cast<size_t>(mrun) * a.n + i[v]) * G)[lane] = lam_v + acc;
+                    }
+                    if (in[v]) (Lp + gb + static_cast<size_t>(i[v]) * G)[lane] = s[v];
+                }
+            }
+            if (D) {
+#pragma unroll
+                for (int v = 0; v < VPW; ++v) {
+                    const uint64_t bits = __ballot(on && in[v] && s[v] < T(0));
+                    if (lane == 0 && in[v]) D[static_cast<size_t>(g) * a.n + i[v]] = bits;
+                }
             }
         }
+        if (!more) break;
+        cur = nxt;
+        nxt = nn;
+        more = more2;
+        w += gridDim.x;
     }
 }
 

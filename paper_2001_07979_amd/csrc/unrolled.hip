@@ -307,6 +307,9 @@ struct Run {
         int vpt = 0;
         kv = variable_kernel<float>(code->max_var_deg, &vpt);
         dv = Dims{code->E, n, M, ng, (n + vpt - 1) / vpt, 0, 0, 0.0, clip};
+        // the iteration kernels index their (group, tile) work items in 32 bits
+        if (static_cast<int64_t>(ng) * std::max(dc.ntiles, dv.ntiles) >= INT32_MAX)
+            return fail(MBP_EUNSUPPORTED, "unrolled: too many frame groups times tiles for one call");
         grid_c = grid_for(ctx, reinterpret_cast<const void *>(fwd), static_cast<int64_t>(ng) * dc.ntiles);
         grid_a = grid_for(ctx, reinterpret_cast<const void *>(adj), static_cast<int64_t>(ng) * dc.ntiles);
         grid_v = grid_for(ctx, reinterpret_cast<const void *>(kv),
