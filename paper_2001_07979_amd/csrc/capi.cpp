@@ -207,8 +207,58 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
         h_var_mptr[static_cast<size_t>(u) * n + i] = var_cnt[i + 1];
     }
 
+    // the run starts as a bitmask per variable (degrees are at most 64)
+    std::vector<uint64_t> h_var_runs(n, 0);
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = var_cnt[i]; k < var_cnt[i + 1]; ++k)
+            if (h_var_edge_f[k] < 0) h_var_runs[i] |= 1ull << (k - var_cnt[i]);
+    // degree classes: runs of consecutive variables by the slot count their
+    // degree needs; runs of fewer than 2048 variables merge into a neighbour
+    // (taking the larger count), and a code with many runs gets one class
+    auto cap_of = [](int32_t d) {
+        for (int32_t c : {8, 12, 16, 32})
+            if (d <= c) return c;
+        return 64;
+    };
+    std::vector<mbp_var_class> classes;
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t c = cap_of(var_cnt[i + 1] - var_cnt[i]);
+        if (classes.empty() || classes.back().dv != c)
+            classes.push_back({i, i + 1, c});
+        else
+            classes.back().i1 = i + 1;
+        if (classes.size() > 64) break;
+    }
+    if (classes.size() > 64) {
+        classes.assign(1, mbp_var_class{0, n, cap_of(maxvd)});
+    } else {
+        for (bool merged = true; merged && classes.size() > 1;) {
+            merged = false;
+            for (size_t k = 0; k < classes.size(); ++k) {
+                if (classes[k].i1 - classes[k].i0 >= 2048) continue;
+                const size_t o = k > 0 ? k - 1 : k + 1;  // the neighbour it joins
+                const size_t lo = std::min(k, o), hi = std::max(k, o);
+                classes[lo] = {classes[lo].i0, classes[hi].i1, std::max(classes[lo].dv, classes[hi].dv)};
+                classes.erase(classes.begin() + static_cast<std::ptrdiff_t>(hi));
+                merged = true;
+                break;
+            }
+            // neighbours that now share a slot count become one class
+            for (size_t k = 1; k < classes.size();) {
+                if (classes[k].dv == classes[k - 1].dv) {
+                    classes[k - 1].i1 = classes[k].i1;
+                    classes.erase(classes.begin() + static_cast<std::ptrdiff_t>(k));
+                } else {
+                    ++k;
+                }
+            }
+        }
+        if (classes.size() > 6) classes.assign(1, mbp_var_class{0, n, cap_of(maxvd)});
+    }
+
     mbp_code *code = new (std::nothrow) mbp_code();
     if (!code) return fail(MBP_ENOMEM, "mbp_code_create: out of host memory");
+    code->var_classes = classes;
     code->ctx = ctx;
     code->n = n;
     code->u = u;
@@ -229,6 +279,7 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
         (void)hipFree(code->d_var_edge);
         (void)hipFree(code->d_var_edge_f);
         (void)hipFree(code->d_var_mptr);
+        (void)hipFree(code->d_var_runs);
         delete code;
         return rc;
     };
@@ -241,7 +292,8 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
         (he = hipMalloc(&code->d_var_ptr, sizeof(int32_t) * (n + 1))) != hipSuccess ||
         (he = hipMalloc(&code->d_var_edge, sizeof(int32_t) * (E + mbp::kIndexPad))) != hipSuccess ||
         (he = hipMalloc(&code->d_var_edge_f, sizeof(int32_t) * (E + mbp::kIndexPad))) != hipSuccess ||
-        (he = hipMalloc(&code->d_var_mptr, sizeof(int32_t) * (u + 1) * n)) != hipSuccess)
+        (he = hipMalloc(&code->d_var_mptr, sizeof(int32_t) * (u + 1) * n)) != hipSuccess ||
+        (he = hipMalloc(&code->d_var_runs, sizeof(uint64_t) * n)) != hipSuccess)
         return cleanup(hip_fail(he, "mbp_code_create: hipMalloc"));
     // the kernels read edge indices in fixed-size blocks that may run past the
     // last edge; the padding holds valid (zero) indices
@@ -263,7 +315,9 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
         (he = hipMemcpy(code->d_var_edge_f, h_var_edge_f.data(), sizeof(int32_t) * (E + mbp::kIndexPad),
                         hipMemcpyHostToDevice)) != hipSuccess ||
         (he = hipMemcpy(code->d_var_mptr, h_var_mptr.data(), sizeof(int32_t) * (u + 1) * n,
-                        hipMemcpyHostToDevice)) != hipSuccess)
+                        hipMemcpyHostToDevice)) != hipSuccess ||
+        (he = hipMemcpy(code->d_var_runs, h_var_runs.data(), sizeof(uint64_t) * n, hipMemcpyHostToDevice)) !=
+            hipSuccess)
         return cleanup(hip_fail(he, "mbp_code_create: hipMemcpy"));
     ctx->live_codes++;
     *out = code;
@@ -282,6 +336,7 @@ void mbp_code_destroy(mbp_code *code) {
     (void)hipFree(code->d_var_edge);
     (void)hipFree(code->d_var_edge_f);
     (void)hipFree(code->d_var_mptr);
+    (void)hipFree(code->d_var_runs);
     mbp_ctx *ctx = code->ctx;
     delete code;
     if (--ctx->live_codes == 0 && ctx->closed) delete ctx;

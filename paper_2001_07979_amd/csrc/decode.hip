@@ -183,6 +183,29 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     Dims ds{E, n, M, ntot, (M + kBlock - 1) / kBlock, 0, 0, p->alpha, p->llr_clip, p->max_iter, ngroups,
             nspare};
     ds.live = &tail->live;
+    // FP32 flooding with the stacked graph: the variable pass per degree
+    // class, specialised (its buffer loads address a group's messages with
+    // 32-bit offsets)
+    struct VarLaunch {
+        VarFastFn fn;
+        Dims d;
+        int grid;
+    };
+    std::vector<VarLaunch> fast_v;
+    if (std::is_same<T, float>::value && !indep && E * G * static_cast<int64_t>(sizeof(float)) < INT32_MAX) {
+        for (const mbp_var_class &vc : code->var_classes) {
+            int vpt_k = 0;
+            const VarFastFn fn = from_bits ? variable_fast_kernel<true>(vc.dv, &vpt_k)
+                                           : variable_fast_kernel<false>(vc.dv, &vpt_k);
+            Dims d = dv;
+            d.vbeg = vc.i0;
+            d.vend = vc.i1;
+            d.ntiles = (vc.i1 - vc.i0 + vpt_k - 1) / vpt_k;
+            d.runs = code->d_var_runs;
+            fast_v.push_back({fn, d, grid_for(ctx, reinterpret_cast<const void *>(fn),
+                                              static_cast<int64_t>(ngroups) * d.ntiles)});
+        }
+    }
     // the iteration kernels index their (group, tile) work items in 32 bits
     if (static_cast<int64_t>(ntot) * std::max({dc.ntiles, dv.ntiles, dvs.ntiles}) >= INT32_MAX)
         return fail(MBP_EUNSUPPORTED, "decode: too many frame groups times tiles for one call");
@@ -267,8 +290,20 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
                 // serial iteration only the matrices visited so far count
                 Dims dvp = dv;
                 dvp.emax = t == 1 && phases.size() > 1 ? code->e_off[ph + 1] : -1;
-                LAUNCH_OR_FAIL(kVarNode, kv<<<grid_v, kBlock, 0, stream>>>(code->d_var_ptr, code->d_var_edge_f, c,
-                                                                           lam, Lp, words, Dout, dvp));
+                if (dvp.emax < 0 && !fast_v.empty()) {
+                    if constexpr (std::is_same<T, float>::value) {
+                        for (const VarLaunch &vl : fast_v) {
+                            Dims dk = vl.d;
+                            dk.t = t;
+                            LAUNCH_OR_FAIL(kVarNode, vl.fn<<<vl.grid, kBlock, 0, stream>>>(
+                                                         code->d_var_ptr, code->d_var_edge, c, lam, Lp, words, Dout,
+                                                         dk));
+                        }
+                    }
+                } else {
+                    LAUNCH_OR_FAIL(kVarNode, kv<<<grid_v, kBlock, 0, stream>>>(code->d_var_ptr, code->d_var_edge_f,
+                                                                               c, lam, Lp, words, Dout, dvp));
+                }
             }
         }
         if (!p->early_exit && t < p->max_iter) continue;

@@ -91,6 +91,12 @@ struct mbp_plan {
     int32_t *err_dev = nullptr;
 };
 
+// A run of consecutive variables whose degrees fit dv slots of the variable
+// pass (variables [i0, i1)).
+struct mbp_var_class {
+    int32_t i0, i1, dv;
+};
+
 struct mbp_code {
     mbp_ctx *ctx = nullptr;
     int32_t n = 0, u = 0, M = 0;
@@ -114,6 +120,10 @@ struct mbp_code {
     // position in var_edge of the first edge of matrix l at variable i, at
     // [l * n + i] for l = 0..u (row u: one past the variable's last edge)
     int32_t *d_var_mptr = nullptr;  // [(u + 1) n]
+    // per variable, the slots of its edge list that start the next matrix's
+    // edges (bit j: slot j), and the variables split into degree classes
+    uint64_t *d_var_runs = nullptr;  // [n]
+    std::vector<mbp_var_class> var_classes;
 };
 
 namespace mbp {

@@ -169,6 +169,11 @@ struct Dims {
     // rows of n * 64 values per group in the array holding the stored
     // per-matrix sums (psum, rows 0..u-1) and the posteriors (lm)
     int32_t prows = 0;
+    // variable pass (k_variable_fast): the variables [vbeg, vend) of one
+    // degree class, and per variable the slots of its edge list that start
+    // the next matrix's run (bit j: slot j, j >= 1)
+    int32_t vbeg = 0, vend = 0;
+    const uint64_t *runs = nullptr;
     // variable pass: visit the groups last to first. The check pass visits
     // them first to last, so the variable pass starts on the group whose
     // messages were written last (the likeliest still in the last-level
@@ -203,6 +208,44 @@ struct StopTail {
 // group g (at kStride * g) holds the frames still running, word kUnmet the
 // frames with an unmet check in the stopping test under way.
 constexpr int kRun = 0, kUnmet = 1;
+
+// Groups that still have running frames, as a bitmap in LDS that a block
+// fills at the start of an iteration kernel (the running sets do not change
+// while it runs); groups past the bitmap's capacity count as running. The
+// kernels' work-item cursors use it to jump over retired groups.
+constexpr int kLiveWords = 1024;  // 32768 groups
+__device__ __forceinline__ void load_live(uint32_t *bits, const uint64_t *act, int ngroups) {
+    const unsigned lane = threadIdx.x & 63u;
+    const int ng = min(ngroups, kLiveWords * 32);
+    for (int base = static_cast<int>(threadIdx.x >> 6) * 64; base < ng; base += kBlock) {
+        const int g = base + static_cast<int>(lane);
+        const uint64_t b = __ballot(g < ng && act[kStride * g + kRun] != 0);
+        if (lane == 0) {
+            bits[base / 32] = static_cast<uint32_t>(b);
+            if (base / 32 + 1 < kLiveWords) bits[base / 32 + 1] = static_cast<uint32_t>(b >> 32);
+        }
+    }
+    __syncthreads();
+}
+__device__ __forceinline__ bool is_live(const uint32_t *bits, int g) {
+    return g >= kLiveWords * 32 || ((bits[g >> 5] >> (g & 31)) & 1u);
+}
+// The block's first work item at or after w (items blockIdx.x + k gridDim.x,
+// ntiles per group, group index gw = w / ntiles, mapped to its group by
+// `group`) whose group is running; total or more if none.
+template <typename GroupOf>
+__device__ __forceinline__ uint32_t live_item(uint32_t w, uint32_t total, uint32_t ntiles, const uint32_t *bits,
+                                              GroupOf group) {
+    while (w < total) {
+        const uint32_t gw = w / ntiles;
+        if (is_live(bits, group(static_cast<int>(gw)))) return w;
+        // the block's first item in the next group
+        const uint32_t start = (gw + 1) * ntiles;
+        w += ((start - w + gridDim.x - 1) / gridDim.x) * gridDim.x;
+    }
+    return w;
+}
+
 
 // One check of the FP32 check pass, for the lanes of one wave (frames of
 // one group): v(j) gives the check's j-th variable index, wave-uniform (it is
@@ -395,30 +438,38 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
     const T clip = static_cast<T>(a.clip);
     const bool first = a.t == 1;
     const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
-    const int rend = a.row1 < 0 ? a.M : a.row1;
-    if constexpr (sizeof(T) == 4) {
-        // FP32: the wave's checks (kRowsPerWave per work item, items a grid
-        // stride apart) as one software-pipelined stream. While a check's
-        // gathers are in flight the wave loads the next check's column
-        // indices (one vector load: lane j holds column j) and the offsets,
-        // syndrome word and weight of the check after it, so no check waits
-        // on its own chain of index loads.
+    if constexpr (sizeof(T) == 4 && !BITS) {
+        // FP32 from messages: the wave's checks (kRowsPerWave per work item,
+        // items a grid stride apart, groups with running frames only) as one
+        // software-pipelined stream. While a check's gathers are in flight
+        // the wave loads the next check's column indices (one vector load:
+        // lane j holds column j) and the scalars of the one after (one
+        // per-lane gather), so no check waits on its own chain of index
+        // loads. (The first pass from Bob's bits gathers from cache and is
+        // bound by arithmetic; it takes the plain loop below.)
+        __shared__ uint32_t live[kLiveWords];
+        load_live(live, act, a.ngroups);
+        const int rend = a.row1 < 0 ? a.M : a.row1;
         // A check's scalars travel in one register (lane 0: row_ptr[r],
         // 1: row_ptr[r + 1], 2-3: the group's running set, 4-5: the check's
-        // syndrome word, 6: the group, 7: the check; r >= rend: none), read
-        // with one per-lane gather, so three checks in flight hold few
-        // scalar registers; its column indices in another (lane j < DMAX:
-        // col[row_ptr[r] + j], the array padded past E).
+        // syndrome word, 6: the group, 7: the check; r >= rend: none), so
+        // three checks in flight hold few scalar registers; its column
+        // indices in another (lane j < DMAX: col[row_ptr[r] + j], the array
+        // padded past E).
         struct Row {
             int32_t info, cols;
         };
-        const int64_t nrows = ((total - blockIdx.x + gridDim.x - 1) / gridDim.x) * kRowsPerWave;
-        auto meta = [&](int64_t q, Row &R) {
-            // total < 2^31 (the host checks): 32-bit division
-            const uint32_t w = blockIdx.x + static_cast<uint32_t>(q / kRowsPerWave) * gridDim.x;
-            const int g = static_cast<int>(w / static_cast<uint32_t>(a.ntiles));
-            const int tile = static_cast<int>(w % static_cast<uint32_t>(a.ntiles));
-            const int r = a.row0 + tile * kRowsPerTile + static_cast<int>(q % kRowsPerWave) * kWaves + wave;
+        // total < 2^31 (the host checks): 32-bit cursor over the block's work
+        // items of running groups, and the check within the item
+        const uint32_t tot = static_cast<uint32_t>(total), nt = static_cast<uint32_t>(a.ntiles);
+        auto same = [](int g) { return g; };
+        uint32_t cw = live_item(blockIdx.x, tot, nt, live, same);
+        int ck = 0;
+        auto meta = [&](Row &R) {
+            if (cw >= tot) return false;
+            const int g = static_cast<int>(cw / nt);
+            const int tile = static_cast<int>(cw % nt);
+            const int r = a.row0 + tile * kRowsPerTile + ck * kWaves + wave;
             const int rr = r < rend ? r : rend - 1;
             const int l = static_cast<int>(lane);
             const int32_t *src = l < 2 ? row_ptr + rr + l
@@ -427,21 +478,25 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                                        : row_ptr + rr;
             const int32_t got = *src;
             R.info = l == 6 ? g : l == 7 ? r : got;
+            if (++ck == kRowsPerWave) {
+                ck = 0;
+                cw = live_item(cw + gridDim.x, tot, nt, live, same);
+            }
+            return true;
         };
         auto cols = [&](Row &R) {
             R.cols = static_cast<int>(lane) < DMAX ? col[__builtin_amdgcn_readlane(R.info, 0) + static_cast<int>(lane)]
                                                    : 0;
         };
-        if (nrows <= 0) return;
         Row cur, nxt, nn;
-        meta(0, cur);
+        if (!meta(cur)) return;
         cols(cur);
-        if (nrows > 1) meta(1, nxt);
-        for (int64_t q = 0; q < nrows; ++q) {
-            const bool more = q + 1 < nrows, more2 = q + 2 < nrows;
+        bool has_nxt = meta(nxt);
+        for (;;) {
+            bool has_nn = false;
             auto prefetch = [&]() {
-                if (more) cols(nxt);
-                if (more2) meta(q + 2, nn);
+                if (has_nxt) cols(nxt);
+                has_nn = meta(nn);
             };
             const int r = __builtin_amdgcn_readlane(cur.info, 7);
             const uint64_t run = static_cast<uint32_t>(__builtin_amdgcn_readlane(cur.info, 2)) |
@@ -459,24 +514,22 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                 const T *Lg = Lp + static_cast<size_t>(g) * (a.lstride < 0 ? static_cast<int64_t>(a.n) * G : a.lstride);
                 // independent decoders: the posterior of the check's own matrix
                 const T *Lr = a.mstride ? Lg + row_mat[r] * a.mstride : Lg;
-                const uint64_t *yg = BITS ? a.ybits + static_cast<size_t>(g) * a.n : nullptr;
-                const float ym = BITS ? static_cast<const float *>(a.ymag)[static_cast<size_t>(g) * G + lane] : 0.0f;
                 uint32_t *st = CST ? static_cast<uint32_t *>(a.cstate) + (static_cast<size_t>(g) * a.M + r) * kStateRows * G
                                    : nullptr;
                 const int32_t cs = cur.cols;
                 auto v = [cs](int j) { return __builtin_amdgcn_readlane(cs, j); };
-                check_row_f32<ALGO, DMAX, BITS, CST>(v, d, zbit, alpha, clip, first,
-                                                     BITS ? buf_rsrc(yg, kBufAll) : buf_rsrc(Lr, kBufAll),
-                                                     c_in + cb, c_out + cb, lane, ym, st, prefetch, on);
+                check_row_f32<ALGO, DMAX, false, CST>(v, d, zbit, alpha, clip, first, buf_rsrc(Lr, kBufAll),
+                                                      c_in + cb, c_out + cb, lane, 0.0f, st, prefetch, on);
             } else {
                 prefetch();
             }
+            if (!has_nxt) break;
             cur = nxt;
             nxt = nn;
+            has_nxt = has_nn;
         }
         return;
-    } else {
-    // FP64: one check after another
+    }
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
         const int g = static_cast<int>(w / a.ntiles);
         const int tile = static_cast<int>(w % a.ntiles);
@@ -504,7 +557,15 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
             int v[DMAX];
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) v[j] = col[e0 + j];
-            if (on) {
+            if constexpr (sizeof(T) == 4) {
+                uint32_t *st = CST ? static_cast<uint32_t *>(a.cstate) +
+                                         (static_cast<size_t>(g) * a.M + r) * kStateRows * G
+                                   : nullptr;
+                if (on)
+                    check_row_f32<ALGO, DMAX, BITS, CST>(
+                        [&v](int j) { return v[j]; }, d, static_cast<uint32_t>(zbit), alpha, clip, first,
+                        BITS ? buf_rsrc(yg, kBufAll) : buf_rsrc(Lr, kBufAll), ci, cg, lane, ym, st);
+            } else if (on) {
                 // issue every gather of the check before using any of them
                 T q[DMAX], co[DMAX];
                 uint32_t yh[DMAX];
@@ -594,7 +655,6 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                 }
             }
         }
-    }
     }
 }
 
@@ -912,155 +972,211 @@ __global__ __launch_bounds__(kBlock) void k_output_slots(const T *Lp, const int3
 // (summed from 0 in check order). var_edge is the flagged list: an entry
 // with bit 31 set starts the next matrix's run of the variable's edges, where
 // the running matrix sum is added to L and restarted. Each wave takes VPW
-// consecutive variables of degree at most DV and issues all their gathers
-// before summing any. D, if not null, receives the decision word of each
-// variable (bit k set when frame 64g+k decides 1, i.e. L < 0; frames not
-// running leave 0).
-//
-// The work items a wave visits are software-pipelined. A wave's VPW
-// variables have consecutive offsets and, together, at most 64 consecutive
-// edge-list entries, so each comes in one vector load (lane l holds offset
-// l, resp. entry l, and a wave-uniform copy is read from its lane where
-// needed). While one item's message gathers are in flight, the wave loads
-// the next item's edge lists and the offsets of the item after it, so no item
-// waits on its own chain of index loads (offsets, then edge lists, then
-// messages).
+// variables of degree at most DV and issues all their gathers before summing
+// any. D, if not null, receives the decision word of
+// each variable (bit k set when frame 64g+k decides 1, i.e. L < 0; frames
+// not running leave 0).
 template <typename T, int DV, int VPW, bool BITS = false>
 __global__ __launch_bounds__(kBlock) void k_variable(
     const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_edge,
     const T *__restrict__ c, const T *__restrict__ lam, T *__restrict__ Lp,
     const uint64_t *__restrict__ act, uint64_t *__restrict__ D, const Dims a) {
-    static_assert(DV * VPW <= 64, "a wave's edge lists fit its lanes");
     if (a.live && *a.live == 0) return;  // every frame retired
     const unsigned lane = lane_id();
     const int wave = wave_id();
     const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
-    // emax >= 0 restricts the sum to stacked edges below it: the matrices
-    // whose check messages exist so far in the first iteration of the
-    // matrix-serial schedule
-    const int64_t lim = a.emax < 0 ? INT64_MAX : a.emax;
-    struct Item {
-        int g, i0;      // group; first variable of the wave
-        uint64_t run;   // frames of the group still running
-        int32_t off;    // lane l <= VPW: var_ptr[min(i0 + l, n)]
-        int32_t edges;  // lane l: var_edge[var_ptr[i0] + l] (the list is padded past E)
-    };
-    auto meta = [&](int64_t w, Item &it) {
-        // total < 2^31 (the host checks): 32-bit division
-        const uint32_t w32 = static_cast<uint32_t>(w);
-        const int gw = static_cast<int>(w32 / static_cast<uint32_t>(a.ntiles));
-        it.g = a.reverse ? a.ngroups - 1 - gw : gw;
-        const int tile = static_cast<int>(w32 % static_cast<uint32_t>(a.ntiles));
-        it.i0 = (tile * kWaves + wave) * VPW;
-        it.run = act[kStride * it.g + kRun];
-        it.off = var_ptr[min(it.i0 + min(static_cast<int>(lane), VPW), a.n)];
-    };
-    auto edges = [&](Item &it) {
-        it.edges = var_edge[__builtin_amdgcn_readlane(it.off, 0) + static_cast<int>(lane)];
-    };
-    int64_t w = blockIdx.x;
-    if (w >= total) return;
-    Item cur, nxt, nn;
-    meta(w, cur);
-    edges(cur);
-    bool more = w + gridDim.x < total;
-    if (more) meta(w + gridDim.x, nxt);
-    for (;;) {
-        const bool on = (cur.run >> lane) & 1;
-        const int g = cur.g;
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        const int gw = static_cast<int>(w / a.ntiles);
+        const int g = a.reverse ? a.ngroups - 1 - gw : gw;
+        const int tile = static_cast<int>(w % a.ntiles);
+        const uint64_t run = act[kStride * g + kRun];
+        if (run == 0) continue;
+        const bool on = (run >> lane) & 1;
         const size_t gb = static_cast<size_t>(g) * a.n * G;
         const T *cg = c + static_cast<size_t>(g) * a.E * G;
-        // per variable: its index, first list position (relative to the
-        // wave's first) and degree; past n the offsets repeat E, degree 0
-        const int k0 = __builtin_amdgcn_readlane(cur.off, 0);
-        int i[VPW], p0[VPW], deg[VPW];
+        const uint64_t *yg = BITS ? a.ybits + static_cast<size_t>(g) * a.n : nullptr;
+        const T ym = BITS ? static_cast<const T *>(a.ymag)[static_cast<size_t>(g) * G + lane] : T(0);
+        int i[VPW], k0[VPW], deg[VPW];
         bool in[VPW];
 #pragma unroll
         for (int v = 0; v < VPW; ++v) {
-            i[v] = cur.i0 + v;
+            i[v] = (tile * VPW + v) * kWaves + wave;
             in[v] = i[v] < a.n;
-            p0[v] = __builtin_amdgcn_readlane(cur.off, v) - k0;
-            deg[v] = __builtin_amdgcn_readlane(cur.off, v + 1) - k0 - p0[v];
+            const int ii = in[v] ? i[v] : a.n - 1;
+            k0[v] = var_ptr[ii];
+            deg[v] = in[v] ? var_ptr[ii + 1] - k0[v] : 0;
         }
-        // entry j of variable v (wave-uniform), read where it is used
-        auto entry = [&](int v, int j) { return __builtin_amdgcn_readlane(cur.edges, min(p0[v] + j, 63)); };
         T x[VPW][DV], s[VPW];
-        uint32_t yh[VPW];
-        if (cur.run != 0 && on) {
-            const uint64_t *yg = BITS ? a.ybits + static_cast<size_t>(g) * a.n : nullptr;
+        if (on) {
+            // emax >= 0 restricts the sum to stacked edges below it: the
+            // matrices whose check messages exist so far in the first
+            // iteration of the matrix-serial schedule
+            const int64_t lim = a.emax < 0 ? INT64_MAX : a.emax;
+            int ev[VPW][DV];
+            bool fl[VPW][DV];
+            uint32_t yh[VPW];
 #pragma unroll
             for (int v = 0; v < VPW; ++v) {
+#pragma unroll
+                for (int j = 0; j < DV; ++j) {
+                    const int raw = var_edge[k0[v] + j];
+                    fl[v][j] = raw < 0;
+                    ev[v][j] = raw & 0x7fffffff;
+                }
                 if constexpr (BITS)
                     yh[v] = in[v] ? bit_half(yg, i[v], lane) : 0u;
                 else
                     s[v] = in[v] ? (lam + gb + static_cast<size_t>(i[v]) * G)[lane] : T(0);
 #pragma unroll
+                for (int j = 0; j < DV; ++j)
+                    if (j < deg[v] && ev[v][j] < lim) x[v][j] = (cg + static_cast<size_t>(ev[v][j]) * G)[lane];
+            }
+            if constexpr (BITS) {
+#pragma unroll
+                for (int v = 0; v < VPW; ++v) s[v] = in[v] ? lam_of_half(yh[v], lane, ym) : T(0);
+            }
+            // independent decoders: each matrix's posterior lambda + its sum
+            T *lmg = static_cast<T *>(a.lm);
+            if (lmg) lmg += static_cast<size_t>(g) * a.prows * a.n * G;
+#pragma unroll
+            for (int v = 0; v < VPW; ++v) {
+                T acc = T(0);  // the running matrix's sum
+                const T lam_v = s[v];
+                int mrun = 0;  // the running matrix
+                bool any = false;
+#pragma unroll
                 for (int j = 0; j < DV; ++j) {
-                    const int e = entry(v, j) & 0x7fffffff;
-                    if (j < deg[v] && e < lim) x[v][j] = (cg + static_cast<size_t>(e) * G)[lane];
-                }
-            }
-        }
-        // the next item's edge lists and the offsets of the one after, in
-        // flight with this item's gathers
-        const bool more2 = more && w + 2 * static_cast<int64_t>(gridDim.x) < total;
-        if (more) edges(nxt);
-        if (more2) meta(w + 2 * static_cast<int64_t>(gridDim.x), nn);
-        if (cur.run != 0) {
-            if (on) {
-                if constexpr (BITS) {
-                    const T ym = static_cast<const T *>(a.ymag)[static_cast<size_t>(g) * G + lane];
-#pragma unroll
-                    for (int v = 0; v < VPW; ++v) s[v] = in[v] ? lam_of_half(yh[v], lane, ym) : T(0);
-                }
-                // independent decoders: each matrix's posterior lambda + its sum
-                T *lmg = static_cast<T *>(a.lm);
-                if (lmg) lmg += static_cast<size_t>(g) * a.prows * a.n * G;
-#pragma unroll
-                for (int v = 0; v < VPW; ++v) {
-                    T acc = T(0);  // the running matrix's sum
-                    const T lam_v = s[v];
-                    int mrun = 0;  // the running matrix
-                    bool any = false;
-#pragma unroll
-                    for (int j = 0; j < DV; ++j) {
-                        const int raw = entry(v, j);
-                        const bool fl = raw < 0;
-                        const int e = raw & 0x7fffffff;
-                        if (j < deg[v] && e < lim) {
-                            if (fl) {
-                                s[v] += acc;
-                                if (lmg && in[v])
-                                    (lmg + (static_cast<size_t>(mrun) * a.n + i[v]) * G)[lane] = lam_v + acc;
-                                acc = T(0);
-                            }
-                            if (lmg && (fl || !any))
-                                mrun = (e >= a.emat[0]) + (e >= a.emat[1]) + (e >= a.emat[2]);
-                            acc += x[v][j];
-                            any = true;
+                    if (j < deg[v] && ev[v][j] < lim) {
+                        if (fl[v][j]) {
+                            s[v] += acc;
+                            if (lmg && in[v])
+                                (lmg + (static_cast<size_t>(mrun) * a.n + i[v]) * G)[lane] = lam_v + acc;
+                            acc = T(0);
                         }
+                        if (lmg && (fl[v][j] || !any))
+                            mrun = (ev[v][j] >= a.emat[0]) + (ev[v][j] >= a.emat[1]) + (ev[v][j] >= a.emat[2]);
+                        acc += x[v][j];
+                        any = true;
                     }
-                    if (any) {
-                        s[v] += acc;
-                        if (lmg && in[v]) (lmg + (static_cast<size_t>(mrun) * a.n + i[v]) * G)[lane] = lam_v + acc;
-                    }
-                    if (in[v]) (Lp + gb + static_cast<size_t>(i[v]) * G)[lane] = s[v];
                 }
-            }
-            if (D) {
-#pragma unroll
-                for (int v = 0; v < VPW; ++v) {
-                    const uint64_t bits = __ballot(on && in[v] && s[v] < T(0));
-                    if (lane == 0 && in[v]) D[static_cast<size_t>(g) * a.n + i[v]] = bits;
+                if (any) {
+                    s[v] += acc;
+                    if (lmg && in[v]) (lmg + (static_cast<size_t>(mrun) * a.n + i[v]) * G)[lane] = lam_v + acc;
                 }
+                if (in[v]) (Lp + gb + static_cast<size_t>(i[v]) * G)[lane] = s[v];
             }
         }
-        if (!more) break;
-        cur = nxt;
-        nxt = nn;
-        more = more2;
-        w += gridDim.x;
+        if (D) {
+#pragma unroll
+            for (int v = 0; v < VPW; ++v) {
+                const uint64_t bits = __ballot(on && in[v] && s[v] < T(0));
+                if (lane == 0 && in[v]) D[static_cast<size_t>(g) * a.n + i[v]] = bits;
+            }
+        }
     }
+}
+
+// The variable pass of eq. (2) for FP32 flooding with the stacked graph
+// (and the matrix-serial schedule of one matrix), specialised for
+// instruction count. It runs over one degree class of variables [vbeg,
+// vend), whose degrees fit DV slots, so few slots are spent past a
+// variable's degree; each variable's matrix runs come as one precomputed
+// bitmask instead of a flag per edge; the edge indices are scalar loads
+// (one wave-uniform list per variable: a vector load read back lane by lane
+// would make every item wait for the previous item's stores). Its cursor
+// walks only the work items of groups with running frames. Same
+// summation as k_variable, so the same results bit for bit.
+template <int DV, int VPW, bool BITS>
+__global__ __launch_bounds__(kBlock) void k_variable_fast(
+    const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_edge,
+    const float *__restrict__ c, const float *__restrict__ lam, float *__restrict__ Lp,
+    const uint64_t *__restrict__ act, uint64_t *__restrict__ D, const Dims a) {
+    if (a.live && *a.live == 0) return;  // every frame retired
+    const unsigned lane = lane_id();
+    const int wave = wave_id();
+    __shared__ uint32_t live[kLiveWords];
+    load_live(live, act, a.ngroups);
+    // total < 2^31 (the host checks): a 32-bit cursor over the block's work
+    // items of running groups
+    const uint32_t tot = static_cast<uint32_t>(static_cast<int64_t>(a.ngroups) * a.ntiles);
+    const uint32_t nt = static_cast<uint32_t>(a.ntiles);
+    auto group = [&](int gw) { return a.reverse ? a.ngroups - 1 - gw : gw; };
+    for (uint32_t w = live_item(blockIdx.x, tot, nt, live, group); w < tot;
+         w = live_item(w + gridDim.x, tot, nt, live, group)) {
+        const int gw = static_cast<int>(w / nt);
+        const int g = group(gw);
+        const int tile = static_cast<int>(w % nt);
+        const uint64_t run = act[kStride * g + kRun];
+        const bool on = (run >> lane) & 1;
+        const size_t gb = static_cast<size_t>(g) * a.n * G;
+        const float *cg = c + static_cast<size_t>(g) * a.E * G;
+        int i[VPW], k0[VPW], deg[VPW];
+        bool in[VPW];
+        float x[VPW][DV], s[VPW];
+        uint32_t yh[VPW];
+        uint64_t rs[VPW];
+        const uint64_t *yg = BITS ? a.ybits + static_cast<size_t>(g) * a.n : nullptr;
+#pragma unroll
+        for (int v = 0; v < VPW; ++v) {
+            i[v] = a.vbeg + (tile * kWaves + wave) * VPW + v;
+            in[v] = i[v] < a.vend;
+            const int ii = in[v] ? i[v] : a.vend - 1;
+            k0[v] = var_ptr[ii];
+            deg[v] = in[v] ? var_ptr[ii + 1] - k0[v] : 0;
+            rs[v] = a.runs[ii];
+        }
+#pragma unroll
+        for (int v = 0; v < VPW; ++v) {
+            if constexpr (BITS)
+                yh[v] = in[v] ? bit_half(yg, i[v], lane) : 0u;
+            else
+                s[v] = in[v] ? (lam + gb + static_cast<size_t>(i[v]) * G)[lane] : 0.0f;
+#pragma unroll
+            for (int j = 0; j < DV; ++j)
+                if (j < deg[v]) x[v][j] = (cg + static_cast<size_t>(var_edge[k0[v] + j]) * G)[lane];
+        }
+        if constexpr (BITS) {
+            const float ym = static_cast<const float *>(a.ymag)[static_cast<size_t>(g) * G + lane];
+#pragma unroll
+            for (int v = 0; v < VPW; ++v) s[v] = in[v] ? lam_of_half(yh[v], lane, ym) : 0.0f;
+        }
+#pragma unroll
+        for (int v = 0; v < VPW; ++v) {
+            float acc = 0.0f;  // the running matrix's sum
+#pragma unroll
+            for (int j = 0; j < DV; ++j) {
+                if (j < deg[v]) {
+                    if ((rs[v] >> j) & 1) {
+                        s[v] += acc;
+                        acc = 0.0f;
+                    }
+                    acc += x[v][j];
+                }
+            }
+            if (deg[v] > 0) s[v] += acc;
+            if (in[v] && on) (Lp + gb + static_cast<size_t>(i[v]) * G)[lane] = s[v];
+        }
+        if (D) {
+#pragma unroll
+            for (int v = 0; v < VPW; ++v) {
+                const uint64_t bits = __ballot(on && in[v] && s[v] < 0.0f);
+                if (lane == 0 && in[v]) D[static_cast<size_t>(g) * a.n + i[v]] = bits;
+            }
+        }
+    }
+}
+
+// The degree classes of k_variable_fast: slots DV and variables per wave.
+using VarFastFn = void (*)(const int32_t *, const int32_t *, const float *, const float *, float *,
+                           const uint64_t *, uint64_t *, Dims);
+template <bool BITS>
+VarFastFn variable_fast_kernel(int dv, int *vars_per_tile) {
+    if (dv <= 8) { *vars_per_tile = 8 * kWaves; return &k_variable_fast<8, 8, BITS>; }
+    if (dv <= 12) { *vars_per_tile = 5 * kWaves; return &k_variable_fast<12, 5, BITS>; }
+    if (dv <= 16) { *vars_per_tile = 4 * kWaves; return &k_variable_fast<16, 4, BITS>; }
+    if (dv <= 32) { *vars_per_tile = 2 * kWaves; return &k_variable_fast<32, 2, BITS>; }
+    *vars_per_tile = kWaves;
+    return &k_variable_fast<64, 1, BITS>;
 }
 
 // Variable pass of phase l of the matrix-serial schedule, for codes of at
