@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <mutex>
 #include <unordered_map>
@@ -393,6 +394,38 @@ __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbi
             const float e = fabsf(ep[j]);
             q[j] = run;  // complement of the product before j
             run = fmaf(-run, e, run + e);
+        }
+        if constexpr (BITS) {
+            // Every complement is e_bits, so the suffix at slot j (over the
+            // d - 1 - j slots after it) is the prefix of d - 1 - j slots, and
+            // slots j and d - 1 - j merge the same two values (fma and the sum
+            // commute): their magnitudes are equal bit for bit. For a full or
+            // nearly full row (the common case) each pair's magnitude is formed
+            // once; other rows take the general suffix pass below.
+            auto full_row = [&](auto dd) {
+                constexpr int D = decltype(dd)::value;
+#pragma unroll
+                for (int j = 0; j <= D - 1 - j; ++j) {
+                    const int k = D - 1 - j;  // slot j's mirror
+                    const float mag = atanh2_of_complement(fmaf(-q[j], q[k], q[j] + q[k]));
+                    if (on) {
+                        const uint32_t sj = sign_word(__uint_as_float(sxb ^ __float_as_uint(ep[j])));
+                        buf_store((__float_as_uint(mag) & 0x7fffffffu) | sj, rout, lo, j * G * 4);
+                        if (k != j) {
+                            const uint32_t sk = sign_word(__uint_as_float(sxb ^ __float_as_uint(ep[k])));
+                            buf_store((__float_as_uint(mag) & 0x7fffffffu) | sk, rout, lo, k * G * 4);
+                        }
+                    }
+                }
+            };
+            if (d == DMAX) {
+                full_row(std::integral_constant<int, DMAX>());
+                return;
+            }
+            if (d == DMAX - 1) {
+                full_row(std::integral_constant<int, DMAX - 1>());
+                return;
+            }
         }
         float suf = 0.0f;
 #pragma unroll
