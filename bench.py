@@ -86,6 +86,22 @@ def h2(p):
     return -p * np.log2(p) - (1 - p) * np.log2(1 - p)
 
 
+def batched_roofline(codes, iters, seconds: float, algo: str) -> dict:
+    """HBM roofline of one launch of the persistent batched decode: the
+    algorithmic bytes of every check and variable pass its batches ran (the
+    plain decode's per-frame figures, LLR rows in, flooding), summed over the
+    frames each iteration advanced, over the wall time of one plan launch
+    (staging and outputs included, a few percent)."""
+    total = 0.0
+    for code, it in zip(codes, iters):
+        chk, vn = algorithmic_bytes(code, it, algo, "flooding", from_bits=False)
+        total += chk + vn
+    achieved = total / seconds / 1e9
+    return {"bound": "hbm", "kernel": "k_persistent (whole decode, one launch)", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "algorithmic_bytes_per_launch": int(total), "traffic": None}
+
+
 def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_only: bool = False,
                      algo: str = "spa"):
     """The heterogeneous queue (n, rate, u and p per frame) decoded three ways
@@ -146,11 +162,13 @@ def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_
     for (dc, lam, z), o in zip(items, outs_g):  # warm
         mbp.decode(ctx, dc, lam, z, algo=algo, max_iter=T, out=o)
     torch.cuda.synchronize()
+    log(f"bench: plain per code x{reps}")
     t0 = time.perf_counter()
-    for (dc, lam, z), o in zip(items, outs_g):
-        mbp.decode(ctx, dc, lam, z, algo=algo, max_iter=T, out=o)
+    for _ in range(reps):
+        for (dc, lam, z), o in zip(items, outs_g):
+            mbp.decode(ctx, dc, lam, z, algo=algo, max_iter=T, out=o)
     torch.cuda.synchronize()
-    t_grouped = time.perf_counter() - t0
+    t_grouped = (time.perf_counter() - t0) / reps
 
     # plain, one call per frame in arrival order
     where = {}
@@ -263,6 +281,8 @@ def batched_vs_plain(ctx, nframes: int, reps: int, arrival_load: float, batched_
         "speedup_vs_plain_per_frame": round(t_plain / t_batched, 2),
         "speedup_vs_plain_per_code": round(t_grouped / t_batched, 2),
         "identical_outputs": identical,
+        "roofline": batched_roofline([pool[c]["code"] for c in cells], [rb["iters"].numpy() for rb in res_b],
+                                     t_batched, algo),
         "decoder_successes": ok_frames, "frame_errors": err_frames,
         "qualifying_mbps": round(qual_bits / t_batched / 1e6, 1),
         "cells": fer_cells,
@@ -350,6 +370,8 @@ def qualifying_queue(ctx, frames_per_cell: int, reps: int, algo: str = "spa"):
             "plain_per_code_mbps": round(bits_total / t_g / 1e6, 1),
             "speedup_vs_plain_per_code": round(t_g / t_b, 2),
             "identical_outputs": identical,
+            "roofline": batched_roofline([code for code, _ in pool], [o["iters"].cpu().numpy() for o in outs_b],
+                                         t_b, algo),
             "qualifying_mbps": round(qual_bits / t_b / 1e6, 1),
             "cells": per_cell}
 
@@ -534,7 +556,7 @@ def host_info() -> dict:
     return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": aff}
 
 
-def algorithmic_bytes(code, iters, algo: str, schedule: str):
+def algorithmic_bytes(code, iters, algo: str, schedule: str, from_bits: bool = True):
     """Algorithmic HBM bytes of all check passes and of all variable passes of
     one step (FP32), summed over the frames each iteration advanced.
 
@@ -547,8 +569,10 @@ def algorithmic_bytes(code, iters, algo: str, schedule: str):
     the decision bits (n/8). Under the matrix-serial schedule each phase's
     check pass reads L (4n) and its matrix's c; its variable pass reads its
     matrix's messages and the other matrices' stored sums and writes L and
-    its matrix's sum."""
+    its matrix's sum. Decoding from stored LLR rows (from_bits False) reads
+    lambda as 4n bytes where the bit words take n/8."""
     s, n, E, M, u = 4, code.n, code.E, code.M, code.u
+    lam = n / 8 if from_bits else s * n
     serial = schedule == "serial"
     phases = u if serial else 1
     cst = algo == "nms" and max(int(np.diff(rp).max()) for rp in code.row_ptr) <= 24
@@ -558,14 +582,14 @@ def algorithmic_bytes(code, iters, algo: str, schedule: str):
     for t in range(1, int(iters.max()) + 1):
         full = int((iters >= t).sum())
         if t == 1:
-            chk += full * (s * E + n / 8 + s * n * (phases - 1) + (3 * s * M if cst else 0))
+            chk += full * (s * E + lam + s * n * (phases - 1) + (3 * s * M if cst else 0))
         else:
             chk += full * (s * E + old + s * n * phases)
         if stored:
             others = sum(l if t == 1 else u - 1 for l in range(u))
-            vn += full * (s * E + u * n / 8 + s * n * (2 * u + others) + n / 8)
+            vn += full * (s * E + u * lam + s * n * (2 * u + others) + n / 8)
         else:
-            vn += full * (phases * (s * E + n / 8 + s * n) + n / 8)
+            vn += full * (phases * (s * E + lam + s * n) + n / 8)
     return chk, vn
 
 

@@ -20,7 +20,8 @@
 // Work inside a phase is spread over the blocks per live group: the tiles of
 // the groups still running form one item space, which the blocks take either
 // interleaved (item = block + k * grid) or in contiguous runs, as the tuning
-// says; retired and unused groups cost one load.
+// says; the running groups are found 64 at a time, so retired and unused
+// groups cost little.
 //
 // The check rule is normalized min-sum or sum-product in FP32. Min-sum is
 // evaluated in chunks of the check's edges so any check degree up to 64
@@ -140,7 +141,7 @@ constexpr uint64_t kWaitTicks = 200000000ull;
 // so every block of the grid is resident at once.
 constexpr int kMaxBlocksPerCu = 4;
 
-__device__ bool grid_sync(Barrier *b) {
+__device__ __forceinline__ bool grid_sync(Barrier *b) {
     __shared__ int ok;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -175,45 +176,70 @@ __device__ __forceinline__ uint64_t run_of(const PArgs &a, int g) {
 }
 
 // Calls fn(g, desc, run, tile) for this block's share of the tiles of the
-// groups still running; tiles_of(gd, g) is the phase's tile count of group g.
-// Schedule 0 interleaves the live item space over the blocks; schedule 1
-// gives each block one contiguous run of it.
-template <typename TilesOf, typename Fn>
-__device__ void for_live_tiles(const PArgs &a, TilesOf tiles_of, Fn fn) {
+// groups still running; tile_field is the phase's tile count in GroupDesc.
+// Schedule 0 interleaves the live item space over the blocks (item w to
+// block w mod grid); schedule 1 gives each block one contiguous run of it.
+// The run words and tile counts of 64 groups at a time come in as one
+// vector load each, so finding the running groups costs a load per 64
+// groups rather than one per group.
+template <typename Fn>
+__device__ __forceinline__ void for_live_tiles(const PArgs &a, int32_t GroupDesc::*tile_field, Fn fn) {
     const int64_t grid = gridDim.x, b = blockIdx.x;
+    const unsigned lane = lane_id();
+    auto chunk = [&](int c0, uint64_t *run_l, int32_t *nt_l) {
+        const int g = c0 + static_cast<int>(lane);
+        *run_l = g < a.ngroups ? run_of(a, g) : 0;
+        *nt_l = *run_l ? ldg(&(a.gd[g].*tile_field), 0) : 0;
+    };
     int64_t per = 0;
     if (a.schedule == 1) {
         int64_t total = 0;
-        for (int g = 0; g < a.ngroups; ++g)
-            if (run_of(a, g)) total += tiles_of(a.gd, g);
+        for (int c0 = 0; c0 < a.ngroups; c0 += G) {
+            uint64_t run_l;
+            int32_t nt_l;
+            chunk(c0, &run_l, &nt_l);
+            int32_t s = nt_l;
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+            total += __builtin_amdgcn_readfirstlane(s);
+        }
         per = (total + grid - 1) / grid;
     }
     int64_t base = 0;
-    for (int g = 0; g < a.ngroups; ++g) {
-        const uint64_t run = run_of(a, g);
-        if (!run) continue;
-        const int64_t nt = tiles_of(a.gd, g);
-        int64_t j0, j1, step;
-        if (a.schedule == 0) {
-            j0 = ((b - base) % grid + grid) % grid;
-            j1 = nt;
-            step = grid;
-        } else {
-            j0 = b * per - base;
-            j1 = j0 + per;
-            j0 = j0 < 0 ? 0 : j0;
-            j1 = j1 > nt ? nt : j1;
-            step = 1;
+    for (int c0 = 0; c0 < a.ngroups; c0 += G) {
+        uint64_t run_l;
+        int32_t nt_l;
+        chunk(c0, &run_l, &nt_l);
+        for (uint64_t live = __ballot(run_l != 0); live; live &= live - 1) {
+            const int l = __ffsll(static_cast<unsigned long long>(live)) - 1;
+            const int g = c0 + l;
+            const int64_t nt = __builtin_amdgcn_readlane(nt_l, l);
+            int64_t j0, j1, step;
+            if (a.schedule == 0) {
+                j0 = ((b - base) % grid + grid) % grid;
+                j1 = nt;
+                step = grid;
+            } else {
+                j0 = b * per - base;
+                j1 = j0 + per;
+                j0 = j0 < 0 ? 0 : j0;
+                j1 = j1 > nt ? nt : j1;
+                step = 1;
+            }
+            base += nt;
+            if (j0 >= j1) continue;
+            const uint64_t run =
+                static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int32_t>(run_l), l))) |
+                (static_cast<uint64_t>(
+                     static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int32_t>(run_l >> 32), l)))
+                 << 32);
+            const GroupDesc G_ = load_desc(a.gd, g);
+            for (int64_t j = j0; j < j1; j += step) fn(g, G_, run, static_cast<int>(j));
         }
-        base += nt;
-        if (j0 >= j1) continue;
-        const GroupDesc G_ = load_desc(a.gd, g);
-        for (int64_t j = j0; j < j1; j += step) fn(g, G_, run, static_cast<int>(j));
     }
 }
 
 // Min-sum check pass over one tile of a group (rows_per_wave rows per wave).
-__device__ void cn_tile(const GroupDesc &G_, int tile, int t, const PArgs &a, uint64_t run) {
+__device__ __forceinline__ void cn_tile(const GroupDesc &G_, int tile, int t, const PArgs &a, uint64_t run) {
     const unsigned lane = lane_id();
     const int wave = wave_id();
     const bool on = (run >> lane) & 1;
@@ -273,11 +299,16 @@ __device__ void cn_tile(const GroupDesc &G_, int tile, int t, const PArgs &a, ui
     }
 }
 
-// Sum-product check rule of one check (row r of the group), through the
-// plain pass's check_row_f32 with DMAX slots: all gathers of the check in
-// flight, the complement prefix and suffix products in registers. The
-// column array is padded past E, so a full block of DMAX indices is always
-// in bounds.
+// Sum-product check pass over one tile of a group (rows_per_wave checks per
+// wave) with the plain pass's check_row_f32 and DMAX slots: all gathers of a
+// check in flight, the complement prefix and suffix products in registers.
+// The wave's checks form a software-pipelined stream: while a check's
+// gathers are in flight it loads the next check's column indices (one
+// vector load: lane j holds column j; the column array is padded past E, so
+// DMAX indices are always in bounds) and the scalars of the one after (one
+// per-lane gather: lanes 0-1 the row pointers, 2-3 the syndrome word). Every
+// lane runs the rule (a stopped frame's slots hold stale but readable
+// values) and only running frames store, so the loads stay uniform.
 template <int DMAX>
 __device__ __forceinline__ void spa_row(const GroupDesc &G_, int r, bool first, const PArgs &a, unsigned lane,
                                         bool on) {
@@ -288,32 +319,34 @@ __device__ __forceinline__ void spa_row(const GroupDesc &G_, int r, bool first, 
 #pragma unroll
     for (int j = 0; j < DMAX; ++j) v[j] = ldc(G_.col, e0 + j);
     float *cg = G_.c + static_cast<size_t>(e0) * G;
-    if (on)
-        check_row_f32<kSPA, DMAX, false>([&v](int j) { return v[j]; }, d, zbit, a.alpha, a.clip, first,
-                                         buf_rsrc(G_.Lp, kBufAll), cg, cg,
-                                         lane, 0.0f);
+    check_row_f32<kSPA, DMAX, false>([&v](int j) { return v[j]; }, d, zbit, a.alpha, a.clip, first,
+                                     buf_rsrc(G_.Lp, kBufAll), cg, cg, lane, 0.0f, nullptr, NoPrefetch(), on);
 }
-
-// Sum-product check pass over one tile of a group (rows_per_wave rows per
-// wave); the slot count is uniform over the group.
-__device__ void cn_tile_spa(const GroupDesc &G_, int tile, int t, const PArgs &a, uint64_t run) {
-    const unsigned lane = lane_id();
-    const int wave = wave_id();
-    const bool on = (run >> lane) & 1;
-    const bool first = t == 1;
+template <int DMAX>
+__device__ __forceinline__ void spa_tile(const GroupDesc &G_, int tile, bool first, const PArgs &a, unsigned lane,
+                                         bool on) {
     const int rpt = a.rows_per_wave * kWaves;
     for (int k = 0; k < a.rows_per_wave; ++k) {
-        const int r = tile * rpt + k * kWaves + wave;
+        const int r = tile * rpt + k * kWaves + wave_id();
         if (r >= G_.M) break;
-        switch (G_.dslots) {
-            case 8: spa_row<8>(G_, r, first, a, lane, on); break;
-            case 10: spa_row<10>(G_, r, first, a, lane, on); break;
-            case 16: spa_row<16>(G_, r, first, a, lane, on); break;
-            case 18: spa_row<18>(G_, r, first, a, lane, on); break;
-            case 24: spa_row<24>(G_, r, first, a, lane, on); break;
-            case 32: spa_row<32>(G_, r, first, a, lane, on); break;
-            default: spa_row<kBatchedSpaMaxDeg>(G_, r, first, a, lane, on); break;
-        }
+        spa_row<DMAX>(G_, r, first, a, lane, on);
+    }
+}
+
+// Sum-product check pass over one tile of a group; the slot count is
+// uniform over the group.
+__device__ __forceinline__ void cn_tile_spa(const GroupDesc &G_, int tile, int t, const PArgs &a, uint64_t run) {
+    const unsigned lane = lane_id();
+    const bool on = (run >> lane) & 1;
+    const bool first = t == 1;
+    switch (G_.dslots) {
+        case 8: spa_tile<8>(G_, tile, first, a, lane, on); break;
+        case 10: spa_tile<10>(G_, tile, first, a, lane, on); break;
+        case 16: spa_tile<16>(G_, tile, first, a, lane, on); break;
+        case 18: spa_tile<18>(G_, tile, first, a, lane, on); break;
+        case 24: spa_tile<24>(G_, tile, first, a, lane, on); break;
+        case 32: spa_tile<32>(G_, tile, first, a, lane, on); break;
+        default: spa_tile<kBatchedSpaMaxDeg>(G_, tile, first, a, lane, on); break;
     }
 }
 
@@ -328,7 +361,7 @@ __device__ __forceinline__ void vn_finish(const GroupDesc &G_, int i, float s, b
     if (lane == 0) stg(G_.D, i, bits);
 }
 
-__device__ void vn_tile(const GroupDesc &G_, int tile, const PArgs &a, uint64_t run) {
+__device__ __forceinline__ void vn_tile(const GroupDesc &G_, int tile, const PArgs &a, uint64_t run) {
     constexpr int VC = kVarChunk;
     const unsigned lane = lane_id();
     const int wave = wave_id();
@@ -391,7 +424,7 @@ __device__ void vn_tile(const GroupDesc &G_, int tile, const PArgs &a, uint64_t 
 // Stopping test over one tile of kBlock checks: one thread per check XORs
 // the check's decision words with its syndrome word; the frames whose
 // parity differs are ORed into the group's kUnmet word.
-__device__ void st_tile(const GroupDesc &G_, int g, int tile, const PArgs &a, uint64_t run,
+__device__ __forceinline__ void st_tile(const GroupDesc &G_, int g, int tile, const PArgs &a, uint64_t run,
                         uint32_t *sh_or) {
     const unsigned lane = lane_id();
     const int wave = wave_id();
@@ -433,7 +466,7 @@ __device__ void st_tile(const GroupDesc &G_, int g, int tile, const PArgs &a, ui
 
 // Settle of round t for one group (one wave): frames with no unmet check
 // stop at t with ok = 1; on the last iteration the others stop with ok = 0.
-__device__ void settle_group(const PArgs &a, int g, int t, int par) {
+__device__ __forceinline__ void settle_group(const PArgs &a, int g, int t, int par) {
     const unsigned lane = lane_id();
     uint64_t *w = a.words + static_cast<size_t>(kStride) * g;
     const uint64_t run = ld_fresh(&w[kRun]);
@@ -461,7 +494,7 @@ __device__ void settle_group(const PArgs &a, int g, int t, int par) {
 // Whether batch i compacts after round t: its running frames fit into at
 // most three quarters of the groups they occupy, enough spare groups remain,
 // and at least two iterations remain to profit from it. *K = groups needed.
-__device__ bool wants_compaction(const PArgs &a, int i, int t, int par, int *K) {
+__device__ __forceinline__ bool wants_compaction(const PArgs &a, int i, int t, int par, int *K) {
     if (!a.compact || t > a.T - 2) return false;
     ItemState *s = a.ist + i;
     const uint32_t R = __hip_atomic_load(&s->running[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -476,7 +509,7 @@ __device__ bool wants_compaction(const PArgs &a, int i, int t, int par, int *K) 
 // Compaction plan of batch i (one block): the running frames of its groups,
 // in group and lane order, go to consecutive slots of K fresh spare groups;
 // their old groups stop running.
-__device__ void plan_compaction(const PArgs &a, int i, int K, int par) {
+__device__ __forceinline__ void plan_compaction(const PArgs &a, int i, int K, int par) {
     __shared__ uint32_t scan[kBlock];
     __shared__ uint32_t sh_base;
     const int g0 = ldc(&a.items[i].g0, 0), ng = ldc(&a.items[i].ng, 0);
@@ -538,7 +571,7 @@ constexpr int kBatchMovePieces = 1024;
 
 // Fills piece p of a group a compaction filled: rows of c (E), L and lambda
 // (n each) and syndrome words (M), each lane from its source slot.
-__device__ void move_piece(const PArgs &a, int g, int p) {
+__device__ __forceinline__ void move_piece(const PArgs &a, int g, int p) {
     const unsigned lane = lane_id();
     const int wave = wave_id();
     const GroupDesc G_ = load_desc(a.gd, g);
@@ -595,11 +628,9 @@ __device__ void move_piece(const PArgs &a, int g, int p) {
     }
 }
 
-// One instance per check rule, so the min-sum decode keeps the register
-// budget (and resident blocks) of its chunked rule, and sum-product pays for
-// its unrolled slots alone.
+// The decode, one instance per check rule (one kernel each below).
 template <int ALGO>
-__global__ __launch_bounds__(kBlock) void k_persistent(PArgs a) {
+__device__ __forceinline__ void persistent_body(PArgs a) {
     __shared__ uint32_t sh_or[2 * kWaves];
     for (int t = 1; t <= a.T; ++t) {
         const int par = t & 1;
@@ -614,22 +645,19 @@ __global__ __launch_bounds__(kBlock) void k_persistent(PArgs a) {
                 a.bar->nnew[par ^ 1] = 0;
             }
         }
-        for_live_tiles(a, [](const GroupDesc *gd, int g) { return ldc(&gd[g].cn_tiles, 0); },
-                       [&](int, const GroupDesc &G_, uint64_t run, int tile) {
-                           if constexpr (ALGO == kSPA)
-                               cn_tile_spa(G_, tile, t, a, run);
-                           else
-                               cn_tile(G_, tile, t, a, run);
-                       });
+        for_live_tiles(a, &GroupDesc::cn_tiles, [&](int, const GroupDesc &G_, uint64_t run, int tile) {
+                      if constexpr (ALGO == kSPA)
+                          cn_tile_spa(G_, tile, t, a, run);
+                      else
+                          cn_tile(G_, tile, t, a, run);
+                  });
         if (!grid_sync(a.bar)) return;
-        for_live_tiles(a, [](const GroupDesc *gd, int g) { return ldc(&gd[g].vn_tiles, 0); },
-                       [&](int, const GroupDesc &G_, uint64_t run, int tile) { vn_tile(G_, tile, a, run); });
+        for_live_tiles(a, &GroupDesc::vn_tiles, [&](int, const GroupDesc &G_, uint64_t run, int tile) { vn_tile(G_, tile, a, run); });
         if (!grid_sync(a.bar)) return;
         if (!a.early_exit && t < a.T) continue;
-        for_live_tiles(a, [](const GroupDesc *gd, int g) { return ldc(&gd[g].st_tiles, 0); },
-                       [&](int g, const GroupDesc &G_, uint64_t run, int tile) {
-                           st_tile(G_, g, tile, a, run, sh_or);
-                       });
+        for_live_tiles(a, &GroupDesc::st_tiles, [&](int g, const GroupDesc &G_, uint64_t run, int tile) {
+                      st_tile(G_, g, tile, a, run, sh_or);
+                  });
         if (!grid_sync(a.bar)) return;
         for (int g = blockIdx.x * kWaves + wave_id(); g < a.ngroups; g += gridDim.x * kWaves)
             settle_group(a, g, t, par);
@@ -648,6 +676,11 @@ __global__ __launch_bounds__(kBlock) void k_persistent(PArgs a) {
         if (!grid_sync(a.bar)) return;
     }
 }
+
+// Min-sum keeps the register budget of its chunked rule, and sum-product
+// pays for its unrolled slots alone.
+__global__ __launch_bounds__(kBlock) void k_persistent_nms(PArgs a) { persistent_body<kNMS>(a); }
+__global__ __launch_bounds__(kBlock) void k_persistent_spa(PArgs a) { persistent_body<kSPA>(a); }
 
 __global__ void k_reset(Barrier *b, ItemState *ist, int32_t nitems) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -698,7 +731,15 @@ struct Built {
     std::vector<BatchPlace> place;
     size_t off_gd, off_items, off_ist, off_words, off_src, off_newg, off_fid, off_bar, off_err, total;
     int32_t ngroups;
+    int64_t nwork;  // work items of the largest phase over every group
 };
+
+// The persistent kernel indexes the tiles of a group with 32-bit integers.
+int check_items(const Built &B) {
+    if (B.nwork >= INT32_MAX)
+        return fail(MBP_EUNSUPPORTED, "batched decode: more than 2^31 work items in one phase");
+    return MBP_OK;
+}
 
 Built lay_out(int32_t nb, const mbp_batch *b, const mbp_tuning &tu) {
     Built B{};
@@ -765,6 +806,7 @@ Built lay_out(int32_t nb, const mbp_batch *b, const mbp_tuning &tu) {
             d.cn_tiles = (code->M + rpt - 1) / rpt;
             d.vn_tiles = (code->n + vpt - 1) / vpt;
             d.st_tiles = (code->M + kBlock - 1) / kBlock;
+            B.nwork += std::max({d.cn_tiles, d.vn_tiles, d.st_tiles});
             B.gd.push_back(d);
         }
         B.place.push_back(P);
@@ -784,8 +826,8 @@ void rebase(Built &B, char *base) {
 }
 
 const void *persistent_kernel(int algo) {
-    return algo == kSPA ? reinterpret_cast<const void *>(&k_persistent<kSPA>)
-                        : reinterpret_cast<const void *>(&k_persistent<kNMS>);
+    return algo == kSPA ? reinterpret_cast<const void *>(&k_persistent_spa)
+                        : reinterpret_cast<const void *>(&k_persistent_nms);
 }
 
 // Upload the group and batch descriptors (synchronous) after pointing them
@@ -884,8 +926,9 @@ int batched_decode(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_param
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     Built B = lay_out(nb, b, tu);
-    int rc = ensure_workspace(ctx, B.total);
+    int rc = check_items(B);
     if (rc != MBP_OK) return rc;
+    if ((rc = ensure_workspace(ctx, B.total)) != MBP_OK) return rc;
     char *base = static_cast<char *>(ctx->ws);
     // the previous user of the workspace may still be running on another stream
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
@@ -907,8 +950,9 @@ int batched_launch(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp_param
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     Built B = lay_out(nb, b, tu);
     char *base = static_cast<char *>(ws);
-    int rc = upload_descriptors(B, base);
+    int rc = check_items(B);
     if (rc != MBP_OK) return rc;
+    if ((rc = upload_descriptors(B, base)) != MBP_OK) return rc;
     if ((rc = enqueue_kernels(nb, b, p, tu, B, base, ctx->num_cus, stream, true)) != MBP_OK) return rc;
     *err_dev = reinterpret_cast<int32_t *>(base + B.off_err);
     return MBP_OK;
@@ -949,8 +993,9 @@ int batched_plan_capture(mbp_ctx *ctx, int32_t nb, const mbp_batch *b, const mbp
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     Built B = lay_out(nb, b, tu);
     char *base = static_cast<char *>(ws);
-    int rc = upload_descriptors(B, base);
+    int rc = check_items(B);
     if (rc != MBP_OK) return rc;
+    if ((rc = upload_descriptors(B, base)) != MBP_OK) return rc;
     hipStream_t cap;
     if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess)
         return hip_fail(e, "hipStreamCreate");
