@@ -20,8 +20,7 @@
 // Work inside a phase is spread over the blocks per live group: the tiles of
 // the groups still running form one item space, which the blocks take either
 // interleaved (item = block + k * grid) or in contiguous runs, as the tuning
-// says; the running groups are found 64 at a time, so retired and unused
-// groups cost little.
+// says; retired and unused groups cost one load.
 //
 // The check rule is normalized min-sum or sum-product in FP32. Min-sum is
 // evaluated in chunks of the check's edges so any check degree up to 64
@@ -179,62 +178,37 @@ __device__ __forceinline__ uint64_t run_of(const PArgs &a, int g) {
 // groups still running; tile_field is the phase's tile count in GroupDesc.
 // Schedule 0 interleaves the live item space over the blocks (item w to
 // block w mod grid); schedule 1 gives each block one contiguous run of it.
-// The run words and tile counts of 64 groups at a time come in as one
-// vector load each, so finding the running groups costs a load per 64
-// groups rather than one per group.
 template <typename Fn>
 __device__ __forceinline__ void for_live_tiles(const PArgs &a, int32_t GroupDesc::*tile_field, Fn fn) {
     const int64_t grid = gridDim.x, b = blockIdx.x;
-    const unsigned lane = lane_id();
-    auto chunk = [&](int c0, uint64_t *run_l, int32_t *nt_l) {
-        const int g = c0 + static_cast<int>(lane);
-        *run_l = g < a.ngroups ? run_of(a, g) : 0;
-        *nt_l = *run_l ? ldg(&(a.gd[g].*tile_field), 0) : 0;
-    };
     int64_t per = 0;
     if (a.schedule == 1) {
         int64_t total = 0;
-        for (int c0 = 0; c0 < a.ngroups; c0 += G) {
-            uint64_t run_l;
-            int32_t nt_l;
-            chunk(c0, &run_l, &nt_l);
-            int32_t s = nt_l;
-            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-            total += __builtin_amdgcn_readfirstlane(s);
-        }
+        for (int g = 0; g < a.ngroups; ++g)
+            if (run_of(a, g)) total += ldc(&(a.gd[g].*tile_field), 0);
         per = (total + grid - 1) / grid;
     }
     int64_t base = 0;
-    for (int c0 = 0; c0 < a.ngroups; c0 += G) {
-        uint64_t run_l;
-        int32_t nt_l;
-        chunk(c0, &run_l, &nt_l);
-        for (uint64_t live = __ballot(run_l != 0); live; live &= live - 1) {
-            const int l = __ffsll(static_cast<unsigned long long>(live)) - 1;
-            const int g = c0 + l;
-            const int64_t nt = __builtin_amdgcn_readlane(nt_l, l);
-            int64_t j0, j1, step;
-            if (a.schedule == 0) {
-                j0 = ((b - base) % grid + grid) % grid;
-                j1 = nt;
-                step = grid;
-            } else {
-                j0 = b * per - base;
-                j1 = j0 + per;
-                j0 = j0 < 0 ? 0 : j0;
-                j1 = j1 > nt ? nt : j1;
-                step = 1;
-            }
-            base += nt;
-            if (j0 >= j1) continue;
-            const uint64_t run =
-                static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int32_t>(run_l), l))) |
-                (static_cast<uint64_t>(
-                     static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int32_t>(run_l >> 32), l)))
-                 << 32);
-            const GroupDesc G_ = load_desc(a.gd, g);
-            for (int64_t j = j0; j < j1; j += step) fn(g, G_, run, static_cast<int>(j));
+    for (int g = 0; g < a.ngroups; ++g) {
+        const uint64_t run = run_of(a, g);
+        if (!run) continue;
+        const int64_t nt = ldc(&(a.gd[g].*tile_field), 0);
+        int64_t j0, j1, step;
+        if (a.schedule == 0) {
+            j0 = ((b - base) % grid + grid) % grid;
+            j1 = nt;
+            step = grid;
+        } else {
+            j0 = b * per - base;
+            j1 = j0 + per;
+            j0 = j0 < 0 ? 0 : j0;
+            j1 = j1 > nt ? nt : j1;
+            step = 1;
         }
+        base += nt;
+        if (j0 >= j1) continue;
+        const GroupDesc G_ = load_desc(a.gd, g);
+        for (int64_t j = j0; j < j1; j += step) fn(g, G_, run, static_cast<int>(j));
     }
 }
 
@@ -677,10 +651,13 @@ __device__ __forceinline__ void persistent_body(PArgs a) {
     }
 }
 
-// Min-sum keeps the register budget of its chunked rule, and sum-product
-// pays for its unrolled slots alone.
+// Min-sum keeps the register budget of its chunked rule (four waves per
+// SIMD); sum-product pays for its unrolled slots alone and is held to three
+// waves per SIMD.
 __global__ __launch_bounds__(kBlock) void k_persistent_nms(PArgs a) { persistent_body<kNMS>(a); }
-__global__ __launch_bounds__(kBlock) void k_persistent_spa(PArgs a) { persistent_body<kSPA>(a); }
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_persistent_spa(PArgs a) {
+    persistent_body<kSPA>(a);
+}
 
 __global__ void k_reset(Barrier *b, ItemState *ist, int32_t nitems) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;

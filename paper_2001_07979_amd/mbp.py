@@ -7,8 +7,10 @@ The binding fails loudly when the library has not been built.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -123,7 +125,25 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} has ABI version {L.mbp_version()}, this binding expects "
                                f"{ABI_VERSION}: rebuild it with __graft_entry__.build()")
         _lib = L
+        # library objects still open when the interpreter exits are closed
+        # while the HIP runtime is still up (before C-level exit handlers)
+        atexit.register(close_all)
     return _lib
+
+
+# Every open Plan, Queue, Code and Context, by kind, for close_all().
+_open = {kind: weakref.WeakSet() for kind in ("plan", "queue", "code", "ctx")}
+
+
+def close_all():
+    """Close every Plan and Queue, then every Code, then every Context that
+    is still open (each close is idempotent)."""
+    for kind in ("plan", "queue", "code", "ctx"):
+        for obj in list(_open[kind]):
+            try:
+                obj.close()
+            except Exception:  # noqa: BLE001 - teardown goes on with the rest
+                pass
 
 
 def last_error() -> str:
@@ -196,11 +216,13 @@ class Context:
         _check(lib().mbp_ctx_create(int(device), ctypes.byref(h)), "mbp_ctx_create")
         self.handle = h
         self.device = int(device)
+        _open["ctx"].add(self)
 
     def close(self):
         if self.handle:
             lib().mbp_ctx_destroy(self.handle)
             self.handle = None
+        _open["ctx"].discard(self)
 
     def __enter__(self):
         return self
@@ -261,6 +283,7 @@ class Code:
         self.M = int(m.sum())
         info = self.info()
         self.E, self.max_check_deg, self.max_var_deg = info["E"], info["max_check_deg"], info["max_var_deg"]
+        _open["code"].add(self)
 
     @classmethod
     def from_inputs(cls, ctx: Context, code) -> "Code":
@@ -279,6 +302,7 @@ class Code:
         if self.handle:
             lib().mbp_code_destroy(self.handle)
             self.handle = None
+        _open["code"].discard(self)
 
     def __enter__(self):
         return self
@@ -603,6 +627,7 @@ class Plan:
                "mbp_plan_create")
         self.handle = h
         self.ctx, self.items, self.outs = ctx, items, outs
+        _open["plan"].add(self)
 
     def launch(self, stream=None):
         _check(lib().mbp_plan_launch(self.handle, _stream_ptr(stream)), "mbp_plan_launch")
@@ -614,6 +639,7 @@ class Plan:
         if self.handle:
             lib().mbp_plan_destroy(self.handle)
             self.handle = None
+        _open["plan"].discard(self)
 
     def __enter__(self):
         return self
@@ -644,6 +670,7 @@ class Queue:
         self.handle = h
         self.ctx = ctx
         self._pending, self._flights, self._done = [], [], 0
+        _open["queue"].add(self)
 
     def submit(self, items, outs):
         """items: [(Code, llr [F, n] f32, synd [F, M] u8)], outs: batch_outputs(...) per item."""
@@ -677,6 +704,7 @@ class Queue:
             lib().mbp_queue_destroy(self.handle)
             self.handle = None
             self._flights = []
+        _open["queue"].discard(self)
 
     def __enter__(self):
         return self

@@ -133,3 +133,26 @@ def test_device_check_order_on_fake_cuda_tensors(monkeypatch):
         mbp._dev(a, "alpha", 0, (torch.float32,), (5, 2))
     with pytest.raises(TypeError):
         mbp._dev([1, 2], "a", 0)
+
+
+def test_close_all_order():
+    """close_all() closes plans and queues before codes and codes before
+    contexts, once each, and leaves nothing registered."""
+    from paper_2001_07979_amd import mbp
+
+    closed = []
+
+    class Obj:
+        def __init__(self, kind):
+            self.kind = kind
+
+        def close(self):
+            closed.append(self.kind)
+            mbp._open[self.kind].discard(self)
+
+    objs = [Obj(k) for k in ("ctx", "code", "plan", "queue", "code", "ctx")]
+    for o in objs:
+        mbp._open[o.kind].add(o)
+    mbp.close_all()
+    assert closed == ["plan", "queue", "code", "code", "ctx", "ctx"]
+    assert all(len(s) == 0 for s in mbp._open.values())
