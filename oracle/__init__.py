@@ -33,7 +33,7 @@ class _Params(ctypes.Structure):
                 ("early_exit", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("clip", ctypes.c_double), ("alpha_tl", ctypes.c_void_p),
                 ("margin", ctypes.c_double), ("schedule", ctypes.c_int32),
-                ("coupling", ctypes.c_int32)]
+                ("coupling", ctypes.c_int32), ("msg_half", ctypes.c_int32)]
 
 FLOODING, SERIAL = 0, 1  # schedules: flooding, matrix-serial
 JOINT, INDEPENDENT = 0, 1  # how the u matrices combine: one stacked graph, or u decoders joined by eq. (2)
@@ -70,6 +70,8 @@ def lib():
             + [ctypes.c_int32]
         L.oracle_default_threads.restype = ctypes.c_int32
         L.oracle_default_threads.argtypes = []
+        L.oracle_round_binary16.restype = ctypes.c_double
+        L.oracle_round_binary16.argtypes = [ctypes.c_double]
         _lib = L
     return _lib
 
@@ -95,6 +97,12 @@ def default_threads() -> int:
     return int(lib().oracle_default_threads())
 
 
+def round_binary16(x: float) -> float:
+    """The binary16 value nearest to x (ties to even), as the decode's
+    msg_half option stores check messages."""
+    return float(lib().oracle_round_binary16(float(x)))
+
+
 def llr_from_bits(y: np.ndarray, e) -> np.ndarray:
     """Channel LLRs [F, n] (FP64) from Bob's bits [F, n] and per-frame error rate."""
     y = np.ascontiguousarray(np.atleast_2d(y), dtype=np.uint8)
@@ -109,8 +117,10 @@ def llr_from_bits(y: np.ndarray, e) -> np.ndarray:
 def decode(code, llr: np.ndarray, synd: np.ndarray, algo: int = SPA, max_iter: int = 50,
            early_exit: bool = True, alpha: float = 0.75, clip: float = 20.0,
            alpha_tl: Optional[np.ndarray] = None, margin: float = 1e-3,
-           nthreads: int = 0, schedule: int = FLOODING, coupling: int = JOINT) -> dict:
-    """FP64 MBP decode of every frame; returns bits, iters, ok, L, flag."""
+           nthreads: int = 0, schedule: int = FLOODING, coupling: int = JOINT,
+           msg_half: bool = False) -> dict:
+    """FP64 MBP decode of every frame; returns bits, iters, ok, L, flag.
+    msg_half stores every check message rounded to binary16."""
     llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float64)
     synd = np.ascontiguousarray(np.atleast_2d(synd), dtype=np.uint8)
     F, n = llr.shape
@@ -121,7 +131,8 @@ def decode(code, llr: np.ndarray, synd: np.ndarray, algo: int = SPA, max_iter: i
         atl = np.ascontiguousarray(alpha_tl, dtype=np.float64)
         assert atl.shape == (max_iter, len(code.row_ptr))
     P = _Params(int(algo), int(max_iter), int(bool(early_exit)), float(alpha), float(clip),
-                atl.ctypes.data if atl is not None else None, float(margin), int(schedule), int(coupling))
+                atl.ctypes.data if atl is not None else None, float(margin), int(schedule), int(coupling),
+                int(bool(msg_half)))
     bits = np.zeros((F, n), dtype=np.uint8)
     iters = np.zeros(F, dtype=np.int32)
     ok = np.zeros(F, dtype=np.uint8)
@@ -139,8 +150,9 @@ def decode(code, llr: np.ndarray, synd: np.ndarray, algo: int = SPA, max_iter: i
 def decode_nms_f32(code, llr: np.ndarray, synd: np.ndarray, max_iter: int = 50,
                    early_exit: bool = True, alpha: float = 0.75, clip: float = 20.0,
                    alpha_tl: Optional[np.ndarray] = None, nthreads: int = 0,
-                   schedule: int = FLOODING, coupling: int = JOINT) -> dict:
-    """Normalized min-sum decode with every operation in binary32 (see the C source)."""
+                   schedule: int = FLOODING, coupling: int = JOINT, msg_half: bool = False) -> dict:
+    """Normalized min-sum decode with every operation in binary32 (see the C source);
+    msg_half stores every check message rounded to binary16."""
     llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float64)
     synd = np.ascontiguousarray(np.atleast_2d(synd), dtype=np.uint8)
     F, n = llr.shape
@@ -151,7 +163,8 @@ def decode_nms_f32(code, llr: np.ndarray, synd: np.ndarray, max_iter: int = 50,
         atl = np.ascontiguousarray(alpha_tl, dtype=np.float64)
         assert atl.shape == (max_iter, len(code.row_ptr))
     P = _Params(NMS, int(max_iter), int(bool(early_exit)), float(alpha), float(clip),
-                atl.ctypes.data if atl is not None else None, 1e-3, int(schedule), int(coupling))
+                atl.ctypes.data if atl is not None else None, 1e-3, int(schedule), int(coupling),
+                int(bool(msg_half)))
     bits = np.zeros((F, n), dtype=np.uint8)
     iters = np.zeros(F, dtype=np.int32)
     ok = np.zeros(F, dtype=np.uint8)

@@ -68,6 +68,9 @@ typedef struct {
     double margin;           /* delta for the near-tie flag */
     int32_t schedule;        /* 0 = flooding; 1 = matrix-serial (see phase_rows) */
     int32_t coupling;        /* 0 = one stacked graph; 1 = u independent decoders (see below) */
+    int32_t msg_half;        /* 1: every new check-to-variable message is stored rounded to
+                                binary16 (see round_binary16); its sender and every reader
+                                use the stored value */
 } oracle_params;
 
 /* ---------------------------------------------------------------------- */
@@ -171,6 +174,24 @@ static int graph_build(const oracle_code *c, graph *g) {
 }
 
 static double sgn(double x) { return x < 0.0 ? -1.0 : 1.0; }
+
+/* The binary16 value nearest to x, ties to even, as IEEE 754 defines the
+   format: 11 significant bits down to 2^-14, then a fixed quantum of 2^-24
+   (subnormals); magnitudes that round beyond the largest finite value 65504
+   become infinite. x / quantum is exact (a power-of-two scale), and nearbyint
+   rounds it to the nearest integer, ties to even, in the default mode. */
+static double round_binary16(double x) {
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    frexp(fabs(x), &e); /* |x| = f 2^e, f in [0.5, 1) */
+    int q = e - 11;
+    if (q < -24) q = -24;
+    double r = ldexp(nearbyint(ldexp(fabs(x), -q)), q);
+    if (r > 65504.0) r = INFINITY;
+    return copysign(r, x);
+}
+
+double oracle_round_binary16(double x) { return round_binary16(x); }
 
 static double clip_to(double x, double C) { return x > C ? C : (x < -C ? -C : x); }
 
@@ -386,7 +407,8 @@ static void decode_frame(const graph *g, const oracle_params *P, const double *l
                 else
                     check_rule_nms(d, b->q + e0, z[r], weight_of(P, t, g->row_matrix[r], g->u),
                                    P->clip, b->tmp);
-                for (int32_t k = 0; k < d; ++k) b->c[e0 + k] = b->tmp[k];
+                for (int32_t k = 0; k < d; ++k)
+                    b->c[e0 + k] = P->msg_half ? round_binary16(b->tmp[k]) : b->tmp[k];
             }
             /* eq. (2): soft decision = channel LLR + every incoming check
                message, a sum per matrix added in matrix order */
@@ -473,7 +495,8 @@ static void decode_frame_nms_f32(const graph *g, const oracle_params *P, const d
                     }
                     tmp[k] = zs * alpha * sg * mn;
                 }
-                for (int32_t k = 0; k < d; ++k) c[e0 + k] = tmp[k];
+                for (int32_t k = 0; k < d; ++k)
+                    c[e0 + k] = P->msg_half ? (float)round_binary16((double)tmp[k]) : tmp[k];
             }
             for (int32_t i = 0; i < n; ++i) L[i] = vsum_f(g, i, lam[i], c);
             if (P->coupling)

@@ -609,14 +609,16 @@ def test_syndrome_is_linear_and_agrees_with_the_residual_weight(small_peg):
 
 
 # --------------------------------------- binary32 rounding order (R16, R12)
-def _nms_f32_by_hand(Hs, lam, z, alpha, T, C=20.0, nested=True, alpha_in_double=False, independent=False):
+def _nms_f32_by_hand(Hs, lam, z, alpha, T, C=20.0, nested=True, alpha_in_double=False, independent=False,
+                     half=False):
     """T flooding min-sum iterations written out in numpy float32 for a tiny
     code: q = L - c; |q| capped at C; c = (-1)^z * alpha * prod sgn * min over
     the other edges; eq. (2) either with its nesting (each matrix's messages
     summed from 0 in check order, those sums added to lambda in matrix order)
     or flattened (every message added to lambda in turn). alpha_in_double
     forms alpha * min from the FP64 weight and rounds once, the mistake of
-    not rounding the weight to binary32 first."""
+    not rounding the weight to binary32 first. half stores every new message
+    rounded to binary16 (numpy's float16 conversion)."""
     f32 = np.float32
     rows = [(l, np.nonzero(h)[0]) for l, H in enumerate(Hs) for h in H]
     lam = lam.astype(f32)
@@ -635,7 +637,7 @@ def _nms_f32_by_hand(Hs, lam, z, alpha, T, C=20.0, nested=True, alpha_in_double=
                 zs = f32(-1) if z[k] else f32(1)
                 out[j] = f32(float(zs) * alpha * float(sg) * float(mn)) if alpha_in_double else \
                     zs * f32(alpha) * sg * mn
-            new.append(out)
+            new.append(out.astype(np.float16).astype(f32) if half else out)
         c = new
         L = np.zeros_like(lam)
         for i in range(lam.size):
@@ -683,6 +685,72 @@ def test_nms_f32_nesting_and_weight_rounding():
     # the binary32 unrolled forward rounds the same way
     L = oracle.nms_unrolled(code, 2, np.full((2, 2), 0.7), lam[None], z[None], binary32=True)[0]
     assert L.tolist() == _nms_f32_by_hand(Hs, lam, z, 0.7, 2).astype(np.float64).tolist()
+
+
+# ------------------------------------------------- binary16 message storage
+def test_round_binary16_is_numpys_float16():
+    """The oracle's binary16 rounding (ties to even, subnormals, overflow)
+    equals numpy's float64 -> float16 conversion on random values over the
+    whole range and on the boundary cases."""
+    rng = np.random.default_rng(16)
+    xs = rng.standard_normal(5000) * np.exp(rng.uniform(-22.0, 12.0, 5000))
+    edge = [0.0, -0.0, 1.0 + 2.0 ** -11, 1.0 + 3 * 2.0 ** -11, 2.0 ** -24, 2.0 ** -25, 3 * 2.0 ** -26,
+            6.1e-5, 65504.0, 65519.99, 65520.0, -65520.0, 1e9]
+    for x in np.concatenate([xs, edge]):
+        want = float(np.float64(x).astype(np.float16)) if abs(x) < 65520.0 else math.copysign(math.inf, x)
+        assert oracle.round_binary16(float(x)) == want, x
+
+
+def test_spa_degree2_passes_half_message():
+    """With binary16 message storage, a degree-2 check passes each variable
+    the other's LLR rounded to binary16: L = lambda_1 + f16(lambda_2) and
+    L = lambda_2 + f16(lambda_1) after one iteration (the values are far from
+    binary16 rounding boundaries, so the FP64 tanh round trip does not matter)."""
+    code = code_from_dense([np.array([[1, 1]])])
+    a, b = 1.2345, -0.7777
+    for z in (0, 1):
+        r = _dec(code, np.array([[a, b]]), np.array([[z]], np.uint8), algo=oracle.SPA, max_iter=1,
+                 early_exit=False, msg_half=True)
+        s = -1.0 if z else 1.0
+        f16 = lambda x: float(np.float16(x))  # noqa: E731
+        assert r["L"][0].tolist() == [a + s * f16(b), b + s * f16(a)]
+        full = _dec(code, np.array([[a, b]]), np.array([[z]], np.uint8), algo=oracle.SPA, max_iter=1,
+                    early_exit=False)["L"][0]
+        assert not np.array_equal(r["L"][0], full)
+
+
+def test_nms_f32_half_messages_by_hand():
+    """Binary32 min-sum with binary16 message storage on the non-dyadic u = 2
+    example: bit for bit the numpy float32 computation with every new message
+    rounded through numpy's float16, at T = 1, 2, 3, and different from the
+    same decode without the rounding."""
+    Hs = [np.array([[1, 1, 0, 0], [1, 0, 1, 0]]), np.array([[1, 0, 1, 1]])]
+    code = code_from_dense(Hs)
+    lam = np.array([-1.7725950479507446, -1.961043357849121, -0.43938955664634705, 0.036386072635650635])
+    z = np.array([1, 1, 1], np.uint8)
+    for T in (1, 2, 3):
+        want = _nms_f32_by_hand(Hs, lam, z, 0.7, T, half=True)
+        got = oracle.decode_nms_f32(code, lam[None], z[None], max_iter=T, early_exit=False, alpha=0.7,
+                                    msg_half=True)["L"][0]
+        assert got.tolist() == want.astype(np.float64).tolist(), T
+        assert not np.array_equal(want, _nms_f32_by_hand(Hs, lam, z, 0.7, T)), T
+
+
+def test_half_messages_stay_within_their_rounding_bound(small_peg):
+    """One iteration from the same LLRs: binary16 storage moves each soft
+    decision by at most the sum of the half-ulps of its incoming messages
+    (|c| 2^-11 each, and the subnormal quantum below 2^-14)."""
+    fr = bsc_frames(small_peg, 8, 0.03, seed=5)
+    lam = oracle.llr_from_bits(fr.y, fr.p)
+    for algo in (oracle.SPA, oracle.NMS):
+        a = _dec(small_peg, lam, fr.z, algo=algo, max_iter=1, early_exit=False)["L"]
+        b = _dec(small_peg, lam, fr.z, algo=algo, max_iter=1, early_exit=False, msg_half=True)["L"]
+        deg = np.zeros(small_peg.n)
+        for rp, ci in zip(small_peg.row_ptr, small_peg.col_idx):
+            np.add.at(deg, ci, 1)
+        bound = deg * 20.0 * 2.0 ** -11 + 1e-12
+        assert np.all(np.abs(a - b) <= bound[None, :])
+        assert np.any(a != b)
 
 
 # ------------------------------------------------------------ near-tie flag
