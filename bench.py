@@ -440,6 +440,50 @@ def other_schedule(ctx, wl, fr, dcode, y, e, z, steps: int, schedule: str):
             "max_iters": int(out["iters"].max().item())}
 
 
+def half_messages(ctx, wl, fr, dcode, y, e, z, steps: int):
+    """The headline step with binary16 message storage (msg="f16"): each
+    check message is stored rounded to binary16, half the message bytes of
+    every pass, at binary16's precision (not the FP32 decoder; the headline
+    stays FP32). Its check and variable passes are timed once more with the
+    library's per-launch events for their rooflines (algorithmic bytes at 2
+    bytes per message)."""
+    import torch
+    from paper_2001_07979_amd import mbp
+
+    code = wl.code
+
+    def step():
+        return mbp.decode_from_bits(ctx, dcode, y, e, z, dtype="f32", algo=wl.algo, max_iter=wl.max_iter,
+                                    alpha=wl.alpha, clip=wl.clip, msg="f16")
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    iters = out["iters"].cpu().numpy()
+    ctx.profile_enable(True, kernels=["check", "variable"])
+    ctx.profile_reset()
+    step()
+    torch.cuda.synchronize()
+    ctx.profile_enable(False)
+    chk, vn = algorithmic_bytes(code, iters, wl.algo, "flooding", msg_bytes=2)
+    roof = {}
+    for kern, total in (("check", chk), ("variable", vn)):
+        launches, ms = ctx.profile_get(kern)
+        achieved = total / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+        roof[kern] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_ms": round(ms / max(launches, 1), 5),
+                      "launches": launches, "algorithmic_bytes_per_launch": int(total / max(launches, 1))}
+    bits = out["bits"].cpu().numpy()
+    return {"workload": wl.name, "msg": "f16", "frames": fr.nframes,
+            "mbps": round(fr.nframes * code.n / dt / 1e6, 1), "ms_per_step": round(dt * 1e3, 4),
+            "fer": float(np.any(bits != fr.x, axis=1).mean()),
+            "avg_iters": float(iters.mean()), "max_iters": int(iters.max()), "roofline": roof}
+
+
 def alice_syndromes(ctx, wl, fr, dcode, steps: int):
     """Alice's side, eq. (1): the u syndromes of every frame of the main
     workload from her key bits (resident in HBM), per step."""
@@ -556,7 +600,7 @@ def host_info() -> dict:
     return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": aff}
 
 
-def algorithmic_bytes(code, iters, algo: str, schedule: str, from_bits: bool = True):
+def algorithmic_bytes(code, iters, algo: str, schedule: str, from_bits: bool = True, msg_bytes: int = 4):
     """Algorithmic HBM bytes of all check passes and of all variable passes of
     one step (FP32), summed over the frames each iteration advanced.
 
@@ -570,26 +614,29 @@ def algorithmic_bytes(code, iters, algo: str, schedule: str, from_bits: bool = T
     check pass reads L (4n) and its matrix's c; its variable pass reads its
     matrix's messages and the other matrices' stored sums and writes L and
     its matrix's sum. Decoding from stored LLR rows (from_bits False) reads
-    lambda as 4n bytes where the bit words take n/8."""
+    lambda as 4n bytes where the bit words take n/8. msg_bytes is the size of
+    a stored check message (2 with binary16 storage, which keeps no
+    compressed min-sum state)."""
     s, n, E, M, u = 4, code.n, code.E, code.M, code.u
+    sm = msg_bytes
     lam = n / 8 if from_bits else s * n
     serial = schedule == "serial"
     phases = u if serial else 1
-    cst = algo == "nms" and max(int(np.diff(rp).max()) for rp in code.row_ptr) <= 24
-    old = 2 * 3 * s * M if cst else s * E
+    cst = algo == "nms" and sm == 4 and max(int(np.diff(rp).max()) for rp in code.row_ptr) <= 24
+    old = 2 * 3 * s * M if cst else sm * E
     stored = serial and 1 < u <= 4
     chk = vn = 0.0
     for t in range(1, int(iters.max()) + 1):
         full = int((iters >= t).sum())
         if t == 1:
-            chk += full * (s * E + lam + s * n * (phases - 1) + (3 * s * M if cst else 0))
+            chk += full * (sm * E + lam + s * n * (phases - 1) + (3 * s * M if cst else 0))
         else:
-            chk += full * (s * E + old + s * n * phases)
+            chk += full * (sm * E + old + s * n * phases)
         if stored:
             others = sum(l if t == 1 else u - 1 for l in range(u))
-            vn += full * (s * E + u * lam + s * n * (2 * u + others) + n / 8)
+            vn += full * (sm * E + u * lam + s * n * (2 * u + others) + n / 8)
         else:
-            vn += full * (phases * (s * E + lam + s * n) + n / 8)
+            vn += full * (phases * (sm * E + lam + s * n) + n / 8)
     return chk, vn
 
 
@@ -815,6 +862,11 @@ def run(args, ctx, dcode, wl, fr, dev):
         log(f"bench: headline workload, {sched} schedule")
         other = other_schedule(ctx, wl, fr, dcode, y, e, z, 5, sched)
 
+    half = None
+    if not args.no_extras:
+        log("bench: headline workload, binary16 messages")
+        half = half_messages(ctx, wl, fr, dcode, y, e, z, 5)
+
     c2 = None
     if not args.no_n65536:
         log("bench: n=65536 workload, both schedules")
@@ -853,7 +905,7 @@ def run(args, ctx, dcode, wl, fr, dev):
         "f": round(m / (n * h), 4), "f_leak": round(code.u * m / (n * h), 4),
         "llr_rows_then_decode": two_calls,
         "roofline": roofline, "roofline_other_kernel": roofline_other, "cpu_baseline": cpu,
-        "other_schedule": other, "n65536": c2, "alice_syndromes": alice,
+        "other_schedule": other, "half_messages": half, "n65536": c2, "alice_syndromes": alice,
         "unrolled_training_step": unrolled,
         "batched_vs_plain": batched,
         "qualifying_queue": qualifying,

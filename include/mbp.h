@@ -90,6 +90,20 @@ typedef struct mbp_code mbp_code;
  *              only, codes of at most 4 matrices (else EUNSUPPORTED); the
  *              workspace holds another 64 g u n sizeof(dtype) bytes for each
  *              matrix's posterior at every variable.
+ *   msg_dtype  storage of the check-to-variable messages between passes.
+ *              MBP_MSG_F32 (value 0): the dtype itself. MBP_MSG_F16: each new
+ *              message (computed in FP32) is stored rounded to the nearest
+ *              binary16, ties to even, and every later read (the variable
+ *              pass, the next check pass's old message) uses the stored
+ *              value; soft decisions stay FP32. Half the message bytes of a
+ *              pass, at binary16's precision (2^-11 relative per message):
+ *              the fewer-bytes-per-edge option of Sec. 3B's memory
+ *              optimisation, not a way to the FP32 results. Requires dtype
+ *              MBP_F32, the flooding schedule and the joint coupling (else
+ *              EUNSUPPORTED) and codes of fewer than 2^23 stacked edges (else
+ *              EUNSUPPORTED at the call); mbp_decode and mbp_decode_from_bits
+ *              only (the batched calls refuse it).
+ *              Min-sum keeps no compressed check state in this mode.
  * Soft decisions (eq. (2)) are summed with the equation's nesting: each
  * matrix's check messages at a variable are summed first (in check order),
  * and those sums are added to the channel LLR in matrix order. */
@@ -97,6 +111,8 @@ typedef struct mbp_code mbp_code;
 #define MBP_MATRIX_SERIAL 1
 #define MBP_JOINT 0
 #define MBP_INDEPENDENT 1
+#define MBP_MSG_F32 0
+#define MBP_MSG_F16 1
 typedef struct {
     int32_t algo;
     int32_t dtype;
@@ -107,12 +123,14 @@ typedef struct {
     int32_t compact;
     int32_t schedule;
     int32_t coupling;
+    int32_t msg_dtype;
 } mbp_params;
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *mbp_last_error(void);
 
-/* ABI version of this library (currently 2: mbp_params has a coupling field). */
+/* ABI version of this library (currently 3: mbp_params has coupling and
+   msg_dtype fields). */
 int32_t mbp_version(void);
 
 /* Create a context on HIP device `device`; *out receives it.

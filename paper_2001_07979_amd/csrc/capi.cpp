@@ -54,6 +54,12 @@ int check_decode(const char *f, mbp_ctx *ctx, const mbp_code *code, const mbp_pa
         return fail(MBP_EINVAL, fn + ": unknown schedule");
     if (p->coupling != MBP_JOINT && p->coupling != MBP_INDEPENDENT)
         return fail(MBP_EINVAL, fn + ": unknown coupling");
+    if (p->msg_dtype != MBP_MSG_F32 && p->msg_dtype != MBP_MSG_F16)
+        return fail(MBP_EINVAL, fn + ": unknown msg_dtype");
+    if (p->msg_dtype == MBP_MSG_F16 &&
+        (p->dtype != MBP_F32 || p->schedule != MBP_FLOODING || p->coupling != MBP_JOINT))
+        return fail(MBP_EUNSUPPORTED, fn + ": binary16 messages need dtype F32, the flooding schedule and the "
+                                           "joint coupling");
     if (p->coupling == MBP_INDEPENDENT && code->u > mbp::kIndepMaxU)
         return fail(MBP_EUNSUPPORTED, fn + ": independent decoders take codes of at most " +
                                           std::to_string(mbp::kIndepMaxU) + " matrices");
@@ -74,7 +80,7 @@ extern "C" {
 
 const char *mbp_last_error(void) { return mbp::g_last_error.c_str(); }
 
-int32_t mbp_version(void) { return 2; }
+int32_t mbp_version(void) { return 3; }
 
 int mbp_ctx_create(int32_t device, mbp_ctx **out) {
     if (!out) return fail(MBP_EINVAL, "mbp_ctx_create: out is NULL");
@@ -484,6 +490,8 @@ static int check_batched_params(const char *fn, const mbp_params *p) {
         return fail(MBP_EUNSUPPORTED, f + ": the batched decode runs the flooding schedule only");
     if (p->coupling != MBP_JOINT)
         return fail(MBP_EUNSUPPORTED, f + ": the batched decode runs the joint (stacked) graph only");
+    if (p->msg_dtype != MBP_MSG_F32)
+        return fail(MBP_EUNSUPPORTED, f + ": the batched decode stores FP32 messages only");
     if (p->max_iter < 1 || p->max_iter > 10000) return fail(MBP_EINVAL, f + ": max_iter must be in [1, 10000]");
     if (p->early_exit != 0 && p->early_exit != 1) return fail(MBP_EINVAL, f + ": early_exit must be 0 or 1");
     if (!std::isfinite(p->llr_clip) || p->llr_clip <= 0.0)

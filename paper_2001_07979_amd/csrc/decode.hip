@@ -47,6 +47,27 @@ CheckFn<float> check_kernel_state(int dmax) {
     }
 }
 
+// FP32 instances with binary16 message storage.
+template <int ALGO, bool BITS>
+CheckFn<float> check_kernel_half(int dmax) {
+    switch (dmax) {
+        case 8: return &k_check<float, ALGO, 8, BITS, false, true>;
+        case 10: return &k_check<float, ALGO, 10, BITS, false, true>;
+        case 16: return &k_check<float, ALGO, 16, BITS, false, true>;
+        case 18: return &k_check<float, ALGO, 18, BITS, false, true>;
+        case 24: return &k_check<float, ALGO, 24, BITS, false, true>;
+        case 32: return &k_check<float, ALGO, 32, BITS, false, true>;
+        case 34: return &k_check<float, ALGO, 34, BITS, false, true>;
+        case 48: return &k_check<float, ALGO, 48, BITS, false, true>;
+        default: return &k_check<float, ALGO, 64, BITS, false, true>;
+    }
+}
+
+template <bool BITS>
+CheckFn<float> check_kernel_half_for(int algo, int dmax) {
+    return algo == MBP_ALGO_NMS ? check_kernel_half<kNMS, BITS>(dmax) : check_kernel_half<kSPA, BITS>(dmax);
+}
+
 // The channel of a decode: LLR rows [F][n] of the decode's element type, or
 // Bob's bits y [F][n] (bytes, nonzero = 1) with the error rate e [F] of each
 // frame, from which lambda = (1 - 2y) ln((1 - e)/e) is formed inside the
@@ -57,7 +78,9 @@ struct Channel {
     const double *e;
 };
 
-template <typename T>
+// H: the check messages are stored as binary16 (FP32 decode, flooding,
+// stacked graph; the caller has checked that).
+template <typename T, bool H = false>
 int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t F,
                const Channel &ch, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
                uint8_t *ok_out, void *llr_out, hipStream_t stream) {
@@ -70,7 +93,7 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     const int32_t nspare = p->compact && p->early_exit && ngroups >= 2 ? std::max(1, ngroups / 4) : 0;
     const int32_t ntot = ngroups + nspare;
     const size_t s = sizeof(T);
-    const size_t sz_c = align_up(static_cast<size_t>(ntot) * E * G * s);
+    const size_t sz_c = align_up(static_cast<size_t>(ntot) * E * G * (H ? 2 : s));
     const size_t sz_L = align_up(static_cast<size_t>(ntot) * n * G * s);
     const size_t sz_z = align_up(static_cast<size_t>(ntot) * M * sizeof(uint64_t));
     const size_t sz_d = align_up(static_cast<size_t>(ntot) * n * sizeof(uint64_t));
@@ -78,7 +101,8 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     const int dmax = dmax_for(code->max_check_deg);
     // FP32 min-sum keeps a compressed check state in place of re-reading
     // every old message (where the slot count allows one)
-    const bool with_state = std::is_same<T, float>::value && p->algo == MBP_ALGO_NMS && dmax <= kStateMaxDeg;
+    const bool with_state =
+        std::is_same<T, float>::value && !H && p->algo == MBP_ALGO_NMS && dmax <= kStateMaxDeg;
     const size_t sz_cs = with_state ? align_up(static_cast<size_t>(ntot) * M * kStateRows * G * sizeof(uint32_t))
                                     : 0;
     // the matrix-serial variable passes keep each matrix's sum at every
@@ -158,6 +182,10 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
             kc = check_kernel_state<false>(dmax);
             kc1 = from_bits ? check_kernel_state<true>(dmax) : kc;
         }
+        if (H) {
+            kc = check_kernel_half_for<false>(p->algo, dmax);
+            kc1 = from_bits ? check_kernel_half_for<true>(p->algo, dmax) : kc;
+        }
     }
     Dims dc{E, n, M, ntot, (M + kRowsPerTile - 1) / kRowsPerTile, 0, 0, p->alpha, p->llr_clip};
     int vpt = 0;
@@ -195,8 +223,8 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     if (std::is_same<T, float>::value && !indep && E * G * static_cast<int64_t>(sizeof(float)) < INT32_MAX) {
         for (const mbp_var_class &vc : code->var_classes) {
             int vpt_k = 0;
-            const VarFastFn fn = from_bits ? variable_fast_kernel<true>(vc.dv, &vpt_k)
-                                           : variable_fast_kernel<false>(vc.dv, &vpt_k);
+            const VarFastFn fn = from_bits ? variable_fast_kernel<true, H>(vc.dv, &vpt_k)
+                                           : variable_fast_kernel<false, H>(vc.dv, &vpt_k);
             Dims d = dv;
             d.vbeg = vc.i0;
             d.vend = vc.i1;
@@ -206,6 +234,9 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
                                               static_cast<int64_t>(ngroups) * d.ntiles)});
         }
     }
+    // binary16 messages are read by the per-class variable pass only
+    if (H && fast_v.empty())
+        return fail(MBP_EUNSUPPORTED, "binary16 messages: code too large for the per-class variable pass");
     // the iteration kernels index their (group, tile) work items in 32 bits
     if (static_cast<int64_t>(ntot) * std::max({dc.ntiles, dv.ntiles, dvs.ntiles}) >= INT32_MAX)
         return fail(MBP_EUNSUPPORTED, "decode: too many frame groups times tiles for one call");
@@ -219,7 +250,7 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     // others at the last-block counter (a fence and an atomic on one word)
     const int grid_s = std::min(ctx->num_cus, grid_for(ctx, reinterpret_cast<const void *>(&k_stop_test),
                                                        static_cast<int64_t>(ntot) * ds.ntiles));
-    const int grid_m = grid_for(ctx, reinterpret_cast<const void *>(&k_move<T>),
+    const int grid_m = grid_for(ctx, reinterpret_cast<const void *>(&k_move<T, H>),
                                 static_cast<int64_t>(std::max(nspare, 1)) * (E + 2 * n + M) / kMoveRows);
 
     if (ctx->poll_events.size() < 2) {
@@ -312,8 +343,8 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
                                       iters_out, ok_out, fid, src, tail, ds));
         // fills the spare groups the stopping test's compaction planned
         if (nspare && t <= p->max_iter - 2)
-            LAUNCH_OR_FAIL(kSyndrome, k_move<T><<<grid_m, kBlock, 0, stream>>>(c, Lp, lam, zb, yb, ymag, cs, ps, prows, src, tail, E,
-                                                                                n, M));
+            LAUNCH_OR_FAIL(kSyndrome, k_move<T, H><<<grid_m, kBlock, 0, stream>>>(
+                                          c, Lp, lam, zb, yb, ymag, cs, ps, prows, src, tail, E, n, M));
         if (p->early_exit) {
             if ((err = hipEventRecord(ctx->poll_events[t & 1], stream)) != hipSuccess)
                 return hip_fail(err, "hipEventRecord");
@@ -346,6 +377,9 @@ int decode_impl(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t
     hipError_t err = hipSetDevice(ctx->device);
     if (err != hipSuccess) return hip_fail(err, "hipSetDevice");
     const Channel ch{llr, y, e};
+    if (p->dtype == MBP_F32 && p->msg_dtype == MBP_MSG_F16)
+        return run_decode<float, true>(ctx, code, p, nframes, ch, synd, bits_out, iters_out, ok_out, llr_out,
+                                       stream);
     if (p->dtype == MBP_F32)
         return run_decode<float>(ctx, code, p, nframes, ch, synd, bits_out, iters_out, ok_out, llr_out, stream);
     return run_decode<double>(ctx, code, p, nframes, ch, synd, bits_out, iters_out, ok_out, llr_out, stream);

@@ -92,6 +92,17 @@ __device__ __forceinline__ uint32_t buf_load(BufRsrc r, int lane_off, int row_of
 __device__ __forceinline__ void buf_store(uint32_t x, BufRsrc r, int lane_off, int row_off) {
     __builtin_amdgcn_raw_buffer_store_b32(x, r, lane_off, row_off, 0);
 }
+// Binary16 message storage: a message is read back as the float it rounds
+// to, and stored rounded to the nearest binary16 (ties to even, the
+// conversion's default mode).
+__device__ __forceinline__ float buf_load_half(BufRsrc r, int lane_off, int row_off) {
+    return static_cast<float>(
+        __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, lane_off, row_off, 0)));
+}
+__device__ __forceinline__ void buf_store_half(float x, BufRsrc r, int lane_off, int row_off) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, static_cast<_Float16>(x)), r,
+                                          lane_off, row_off, 0);
+}
 
 // 2 atanh(1 - E) = ln((2 - E) / E) for a complement E in (0, 1], with two
 // hardware log2: no quotient is rounded, and nothing cancels where E is small
@@ -272,13 +283,18 @@ struct NoPrefetch {
     __device__ void operator()() const {}
 };
 
-template <int ALGO, int DMAX, bool BITS, bool CST = false, typename Cols, typename Prefetch = NoPrefetch>
+template <int ALGO, int DMAX, bool BITS, bool CST = false, bool H = false, typename Cols,
+          typename Prefetch = NoPrefetch>
 __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbit, float alpha,
-                                              float clip, bool first, BufRsrc src, const float *ci, float *cg,
+                                              float clip, bool first, BufRsrc src, const void *ci, void *cg,
                                               unsigned lane, float ym, uint32_t *st = nullptr,
                                               Prefetch prefetch = Prefetch(), bool on = true) {
     static_assert(!CST || (ALGO == kNMS && DMAX <= kStateMaxDeg), "compressed state: min-sum, small degree");
+    static_assert(!(CST && H), "binary16 messages keep no compressed state");
     const int lo = static_cast<int>(lane) * 4;
+    // messages: 4-byte floats, or (H) binary16 values in 2-byte slots
+    constexpr int ES = H ? 2 : 4;
+    const int lm = static_cast<int>(lane) * ES;
     // c^{t-1} of the check's edges (read only after the first iteration:
     // c^0 = 0). The descriptors' record counts are constants: a count chosen
     // at run time by a select can be formed in a vector register, and a
@@ -286,6 +302,13 @@ __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbi
     const BufRsrc rin = buf_rsrc(ci, kBufAll);
     const BufRsrc rout = buf_rsrc(cg, kBufAll);
     const BufRsrc rst = buf_rsrc(st, kBufAll);
+    // stores message j (its float bit pattern) into c^t
+    const auto put = [&](int j, uint32_t word) {
+        if constexpr (H)
+            buf_store_half(__uint_as_float(word), rout, lm, j * G * ES);
+        else
+            buf_store(word, rout, lo, j * G * 4);
+    };
     float q[DMAX];
     if constexpr (CST && !BITS) {
         // the old messages from the state (zeros at t = 1: nothing to read)
@@ -320,7 +343,10 @@ __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbi
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) {
                 q[j] = __uint_as_float(buf_load(src, lo, (j < d ? v(j) : 0) * G * 4));
-                co[j] = __uint_as_float(buf_load(rin, lo, (j < d ? j : 0) * G * 4));
+                if constexpr (H)
+                    co[j] = buf_load_half(rin, lm, (j < d ? j : 0) * G * ES);
+                else
+                    co[j] = __uint_as_float(buf_load(rin, lo, (j < d ? j : 0) * G * 4));
             }
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) q[j] -= co[j];
@@ -356,7 +382,7 @@ __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbi
             if constexpr (CST) signs |= (sw >> 31) << j;
             if (j < d && on) {
                 const float mag = j == i1 ? a2 : a1;  // >= 0
-                buf_store(__float_as_uint(mag) | sw, rout, lo, j * G * 4);
+                put(j, __float_as_uint(mag) | sw);
             }
         }
         if constexpr (CST) {
@@ -410,10 +436,10 @@ __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbi
                     const float mag = atanh2_of_complement(fmaf(-q[j], q[k], q[j] + q[k]));
                     if (on) {
                         const uint32_t sj = sign_word(__uint_as_float(sxb ^ __float_as_uint(ep[j])));
-                        buf_store((__float_as_uint(mag) & 0x7fffffffu) | sj, rout, lo, j * G * 4);
+                        put(j, (__float_as_uint(mag) & 0x7fffffffu) | sj);
                         if (k != j) {
                             const uint32_t sk = sign_word(__uint_as_float(sxb ^ __float_as_uint(ep[k])));
-                            buf_store((__float_as_uint(mag) & 0x7fffffffu) | sk, rout, lo, k * G * 4);
+                            put(k, (__float_as_uint(mag) & 0x7fffffffu) | sk);
                         }
                     }
                 }
@@ -434,12 +460,23 @@ __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbi
                 const float E = fmaf(-q[j], suf, q[j] + suf);
                 const float mag = atanh2_of_complement(E);
                 const uint32_t sb = sign_word(__uint_as_float(sxb ^ __float_as_uint(ep[j])));
-                buf_store((__float_as_uint(mag) & 0x7fffffffu) | sb, rout, lo, j * G * 4);
+                put(j, (__float_as_uint(mag) & 0x7fffffffu) | sb);
             }
             const float e = fabsf(ep[j]);
             suf = fmaf(-suf, e, suf + e);
         }
     }
+}
+
+// Address of element `off` of a message array: 4-byte floats (or T), or
+// (H) 2-byte binary16 slots.
+template <bool H, typename P>
+__device__ __forceinline__ P *msg_at(P *base, size_t off) {
+    using B = typename std::conditional<std::is_const<P>::value, const uint16_t, uint16_t>::type;
+    if constexpr (H)
+        return reinterpret_cast<P *>(reinterpret_cast<B *>(base) + off);
+    else
+        return base + off;
 }
 
 // Check-node pass, iteration t. Each wave handles kRowsPerWave checks of one
@@ -455,8 +492,9 @@ __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbi
 // Bob's bits instead of Lp (q = lambda, c^0 = 0): its gathers touch one
 // 8-byte bit word per edge rather than a 256-byte row. alpha_l, if not null,
 // gives the min-sum weight of each matrix for this iteration (row_mat maps a
-// check to its matrix); otherwise a.alpha applies to every check.
-template <typename T, int ALGO, int DMAX, bool BITS = false, bool CST = false>
+// check to its matrix); otherwise a.alpha applies to every check. With H
+// (FP32 only) c_in and c_out hold binary16 messages, two bytes per slot.
+template <typename T, int ALGO, int DMAX, bool BITS = false, bool CST = false, bool H = false>
 __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ row_ptr,
                                                   const int32_t *__restrict__ col,
                                                   const int32_t *__restrict__ row_mat,
@@ -551,8 +589,9 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                                    : nullptr;
                 const int32_t cs = cur.cols;
                 auto v = [cs](int j) { return __builtin_amdgcn_readlane(cs, j); };
-                check_row_f32<ALGO, DMAX, false, CST>(v, d, zbit, alpha, clip, first, buf_rsrc(Lr, kBufAll),
-                                                      c_in + cb, c_out + cb, lane, 0.0f, st, prefetch, on);
+                check_row_f32<ALGO, DMAX, false, CST, H>(v, d, zbit, alpha, clip, first, buf_rsrc(Lr, kBufAll),
+                                                         msg_at<H>(c_in, cb), msg_at<H>(c_out, cb), lane, 0.0f,
+                                                         st, prefetch, on);
             } else {
                 prefetch();
             }
@@ -595,9 +634,10 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                                          (static_cast<size_t>(g) * a.M + r) * kStateRows * G
                                    : nullptr;
                 if (on)
-                    check_row_f32<ALGO, DMAX, BITS, CST>(
+                    check_row_f32<ALGO, DMAX, BITS, CST, H>(
                         [&v](int j) { return v[j]; }, d, static_cast<uint32_t>(zbit), alpha, clip, first,
-                        BITS ? buf_rsrc(yg, kBufAll) : buf_rsrc(Lr, kBufAll), ci, cg, lane, ym, st);
+                        BITS ? buf_rsrc(yg, kBufAll) : buf_rsrc(Lr, kBufAll), msg_at<H>(c_in, cb),
+                        msg_at<H>(c_out, cb), lane, ym, st);
             } else if (on) {
                 // issue every gather of the check before using any of them
                 T q[DMAX], co[DMAX];
@@ -884,8 +924,9 @@ constexpr int kMovePerWave = kMoveRows / kWaves;
 // per-slot magnitudes move instead of the lambda rows; a compressed check
 // state (cs, kStateRows rows per check) and stored per-matrix sums (ps, u
 // rows per variable) move with the messages. Work items are runs of
-// kMoveRows rows of one region of one group.
-template <typename T>
+// kMoveRows rows of one region of one group. With H the messages are
+// binary16 (two bytes per slot) and there is no state or stored sum.
+template <typename T, bool H = false>
 __global__ __launch_bounds__(kBlock) void k_move(T *c, T *Lp, T *lam, uint64_t *zb, uint64_t *yb, T *ymag,
                                                  T *cs, T *ps, int32_t prows, const int32_t *src,
                                                  const StopTail *tail, int64_t E, int32_t n, int32_t M) {
@@ -909,7 +950,21 @@ __global__ __launch_bounds__(kBlock) void k_move(T *c, T *Lp, T *lam, uint64_t *
         const int32_t s = src[g * G + lane];
         const bool has = s >= 0;
         const int64_t sg = has ? s / G : g, sl = has ? s % G : 0;
-        if (item < ic) {
+        if (H && item < ic) {
+            const int64_t r0 = item * kMoveRows + wave * kMovePerWave;
+            uint16_t *ch = reinterpret_cast<uint16_t *>(c);
+            uint16_t v[kMovePerWave];
+#pragma unroll
+            for (int j = 0; j < kMovePerWave; ++j) {
+                const int64_t r = r0 + j;
+                if (has && r < E) v[j] = ch[(sg * E + r) * G + sl];
+            }
+#pragma unroll
+            for (int j = 0; j < kMovePerWave; ++j) {
+                const int64_t r = r0 + j;
+                if (has && r < E) ch[(g * E + r) * G + lane] = v[j];
+            }
+        } else if (item < ic) {
             const int64_t r0 = item * kMoveRows + wave * kMovePerWave;
             // row r of a group: its array, rows per group and row within
             auto at = [&](int64_t grp, int64_t r) -> T * {
@@ -1119,7 +1174,7 @@ __global__ __launch_bounds__(kBlock) void k_variable(
 // would make every item wait for the previous item's stores). Its cursor
 // walks only the work items of groups with running frames. Same
 // summation as k_variable, so the same results bit for bit.
-template <int DV, int VPW, bool BITS>
+template <int DV, int VPW, bool BITS, bool H = false>
 __global__ __launch_bounds__(kBlock) void k_variable_fast(
     const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_edge,
     const float *__restrict__ c, const float *__restrict__ lam, float *__restrict__ Lp,
@@ -1142,7 +1197,7 @@ __global__ __launch_bounds__(kBlock) void k_variable_fast(
         const uint64_t run = act[kStride * g + kRun];
         const bool on = (run >> lane) & 1;
         const size_t gb = static_cast<size_t>(g) * a.n * G;
-        const float *cg = c + static_cast<size_t>(g) * a.E * G;
+        const float *cg = msg_at<H>(c, static_cast<size_t>(g) * a.E * G);
         int i[VPW], k0[VPW], deg[VPW];
         bool in[VPW];
         float x[VPW][DV], s[VPW];
@@ -1165,8 +1220,17 @@ __global__ __launch_bounds__(kBlock) void k_variable_fast(
             else
                 s[v] = in[v] ? (lam + gb + static_cast<size_t>(i[v]) * G)[lane] : 0.0f;
 #pragma unroll
-            for (int j = 0; j < DV; ++j)
-                if (j < deg[v]) x[v][j] = (cg + static_cast<size_t>(var_edge[k0[v] + j]) * G)[lane];
+            for (int j = 0; j < DV; ++j) {
+                if (j < deg[v]) {
+                    const size_t at = static_cast<size_t>(var_edge[k0[v] + j]) * G + lane;
+                    // binary16: the raw bits now, converted in the sum below
+                    // (converting here would wait for each load in turn)
+                    if constexpr (H)
+                        x[v][j] = __uint_as_float(static_cast<uint32_t>(reinterpret_cast<const uint16_t *>(cg)[at]));
+                    else
+                        x[v][j] = cg[at];
+                }
+            }
         }
         if constexpr (BITS) {
             const float ym = static_cast<const float *>(a.ymag)[static_cast<size_t>(g) * G + lane];
@@ -1183,7 +1247,11 @@ __global__ __launch_bounds__(kBlock) void k_variable_fast(
                         s[v] += acc;
                         acc = 0.0f;
                     }
-                    acc += x[v][j];
+                    if constexpr (H)
+                        acc += static_cast<float>(
+                            __builtin_bit_cast(_Float16, static_cast<uint16_t>(__float_as_uint(x[v][j]))));
+                    else
+                        acc += x[v][j];
                 }
             }
             if (deg[v] > 0) s[v] += acc;
@@ -1202,14 +1270,14 @@ __global__ __launch_bounds__(kBlock) void k_variable_fast(
 // The degree classes of k_variable_fast: slots DV and variables per wave.
 using VarFastFn = void (*)(const int32_t *, const int32_t *, const float *, const float *, float *,
                            const uint64_t *, uint64_t *, Dims);
-template <bool BITS>
+template <bool BITS, bool H = false>
 VarFastFn variable_fast_kernel(int dv, int *vars_per_tile) {
-    if (dv <= 8) { *vars_per_tile = 8 * kWaves; return &k_variable_fast<8, 8, BITS>; }
-    if (dv <= 12) { *vars_per_tile = 5 * kWaves; return &k_variable_fast<12, 5, BITS>; }
-    if (dv <= 16) { *vars_per_tile = 4 * kWaves; return &k_variable_fast<16, 4, BITS>; }
-    if (dv <= 32) { *vars_per_tile = 2 * kWaves; return &k_variable_fast<32, 2, BITS>; }
+    if (dv <= 8) { *vars_per_tile = 8 * kWaves; return &k_variable_fast<8, 8, BITS, H>; }
+    if (dv <= 12) { *vars_per_tile = 5 * kWaves; return &k_variable_fast<12, 5, BITS, H>; }
+    if (dv <= 16) { *vars_per_tile = 4 * kWaves; return &k_variable_fast<16, 4, BITS, H>; }
+    if (dv <= 32) { *vars_per_tile = 2 * kWaves; return &k_variable_fast<32, 2, BITS, H>; }
     *vars_per_tile = kWaves;
-    return &k_variable_fast<64, 1, BITS>;
+    return &k_variable_fast<64, 1, BITS, H>;
 }
 
 // Variable pass of phase l of the matrix-serial schedule, for codes of at

@@ -24,8 +24,10 @@ MBP_ALGO_SPA, MBP_ALGO_NMS = 0, 1
 MBP_F32, MBP_F64 = 0, 1
 MBP_FLOODING, MBP_MATRIX_SERIAL = 0, 1
 MBP_JOINT, MBP_INDEPENDENT = 0, 1
-ABI_VERSION = 2  # mbp_version() of the library this binding marshals for
+MBP_MSG_F32, MBP_MSG_F16 = 0, 1
+ABI_VERSION = 3  # mbp_version() of the library this binding marshals for
 _COUPLINGS = {"joint": MBP_JOINT, "independent": MBP_INDEPENDENT}
+_MSGS = {"f32": MBP_MSG_F32, "f16": MBP_MSG_F16}
 KERNEL_IDS = {"check": 0, "variable": 1, "syndrome": 2, "staging": 3}
 
 _lib = None
@@ -58,7 +60,7 @@ class mbp_params(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("early_exit", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("llr_clip", ctypes.c_double),
                 ("compact", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("coupling", ctypes.c_int32)]
+                ("coupling", ctypes.c_int32), ("msg_dtype", ctypes.c_int32)]
 
 
 def lib():
@@ -348,13 +350,15 @@ def llr_from_bits(ctx: Context, y, e, dtype="f32", out=None, stream=None):
     return out
 
 
-def _params(algo, dt, max_iter, early_exit, alpha, clip, compact, schedule, coupling="joint"):
+def _params(algo, dt, max_iter, early_exit, alpha, clip, compact, schedule, coupling="joint", msg="f32"):
     if coupling not in _COUPLINGS:
         raise ValueError(f"unknown coupling {coupling!r}")
+    if msg not in _MSGS:
+        raise ValueError(f"unknown message storage {msg!r}")
     return mbp_params(MBP_ALGO_SPA if algo == "spa" else MBP_ALGO_NMS, dt, int(max_iter),
                       int(bool(early_exit)), float(alpha), float(clip), int(bool(compact)),
                       {"flooding": MBP_FLOODING, "serial": MBP_MATRIX_SERIAL}[schedule],
-                      _COUPLINGS[coupling])
+                      _COUPLINGS[coupling], _MSGS[msg])
 
 
 def _decode_outputs(F, n, dtype, dev, want_llr):
@@ -396,12 +400,14 @@ def syndrome_noalloc(ctx: Context, code: Code, x, out, stream=None):
 def decode(ctx: Context, code: Code, llr, synd, algo: str = "spa", max_iter: int = 50,
            early_exit: bool = True, alpha: float = 0.75, clip: float = 20.0,
            want_llr: bool = True, out: Optional[dict] = None, stream=None,
-           compact: bool = True, schedule: str = "flooding", coupling: str = "joint") -> dict:
+           compact: bool = True, schedule: str = "flooding", coupling: str = "joint",
+           msg: str = "f32") -> dict:
     """Decode every frame: llr [F, n] (float32/float64, GPU), synd [F, M] (uint8, GPU).
 
     schedule: "flooding" or "serial" (Algorithm 1's per-matrix loop);
     coupling: "joint" (one stacked graph) or "independent" (one decoder per
-    matrix, joined by eq. (2)).
+    matrix, joined by eq. (2)); msg: "f32", or "f16" to store the check
+    messages as binary16 (FP32 flooding joint decodes only).
     Returns dict(bits [F, n] uint8, iters [F] int32, ok [F] uint8, llr [F, n] or None).
     """
     import torch
@@ -414,7 +420,7 @@ def decode(ctx: Context, code: Code, llr, synd, algo: str = "spa", max_iter: int
     if out is None:
         out = _decode_outputs(F, code.n, llr.dtype, llr.device, want_llr)
     pb, pi, pk, plo = _out_ptrs(out, ctx.device, F, code.n, llr.dtype)
-    p = _params(algo, dt, max_iter, early_exit, alpha, clip, compact, schedule, coupling)
+    p = _params(algo, dt, max_iter, early_exit, alpha, clip, compact, schedule, coupling, msg)
     _check(lib().mbp_decode(ctx.handle, code.handle, ctypes.byref(p), F, pl, pz, pb, pi, pk, plo,
                             _stream_ptr(stream)), "mbp_decode")
     return out
@@ -424,7 +430,7 @@ def decode_from_bits(ctx: Context, code: Code, y, e, synd, dtype: str = "f32", a
                      max_iter: int = 50, early_exit: bool = True, alpha: float = 0.75,
                      clip: float = 20.0, want_llr: bool = True, out: Optional[dict] = None,
                      stream=None, compact: bool = True, schedule: str = "flooding",
-                     coupling: str = "joint") -> dict:
+                     coupling: str = "joint", msg: str = "f32") -> dict:
     """decode() with the channel given as Bob's bits y [F, n] (uint8, GPU) and
     error rates e [F] (float64, GPU); the LLRs are formed inside the decoder.
     Same outputs as llr_from_bits followed by decode, bit for bit."""
@@ -439,7 +445,7 @@ def decode_from_bits(ctx: Context, code: Code, y, e, synd, dtype: str = "f32", a
     if out is None:
         out = _decode_outputs(F, code.n, tdt, y.device, want_llr)
     pb, pi, pk, plo = _out_ptrs(out, ctx.device, F, code.n, tdt)
-    p = _params(algo, _dtype_code(tdt), max_iter, early_exit, alpha, clip, compact, schedule, coupling)
+    p = _params(algo, _dtype_code(tdt), max_iter, early_exit, alpha, clip, compact, schedule, coupling, msg)
     _check(lib().mbp_decode_from_bits(ctx.handle, code.handle, ctypes.byref(p), F, py, pe, pz, pb, pi, pk,
                                       plo, _stream_ptr(stream)), "mbp_decode_from_bits")
     return out

@@ -57,7 +57,7 @@ _COUPLINGS = {"joint": oracle.JOINT, "independent": oracle.INDEPENDENT}
 
 
 def gpu_run(ctx, dcode, frames, algo, dtype, max_iter, early_exit=True, alpha=0.75,
-            clip=20.0, llr=None, schedule="flooding", coupling="joint", compact=True):
+            clip=20.0, llr=None, schedule="flooding", coupling="joint", compact=True, msg="f32"):
     import torch
     from paper_2001_07979_amd import mbp
     dev = torch.device("cuda", ctx.device)
@@ -69,7 +69,7 @@ def gpu_run(ctx, dcode, frames, algo, dtype, max_iter, early_exit=True, alpha=0.
         llr = torch.from_numpy(llr).to(dev)
     z = torch.from_numpy(frames.z).to(dev)
     out = mbp.decode(ctx, dcode, llr, z, algo=algo, max_iter=max_iter, early_exit=early_exit,
-                     alpha=alpha, clip=clip, schedule=schedule, coupling=coupling, compact=compact)
+                     alpha=alpha, clip=clip, schedule=schedule, coupling=coupling, compact=compact, msg=msg)
     torch.cuda.synchronize()
     return dict(llr_in=llr.cpu().numpy(), bits=out["bits"].cpu().numpy(),
                 iters=out["iters"].cpu().numpy(), ok=out["ok"].cpu().numpy(),
@@ -84,7 +84,7 @@ def oracle_llr(frames, dtype):
 
 
 def oracle_run(code, frames, algo, dtype, max_iter, early_exit=True, alpha=0.75, clip=20.0,
-               idx=None, lam=None, schedule="flooding", coupling="joint"):
+               idx=None, lam=None, schedule="flooding", coupling="joint", msg="f32"):
     if lam is None:
         lam = oracle_llr(frames, dtype)
     z = frames.z
@@ -92,7 +92,7 @@ def oracle_run(code, frames, algo, dtype, max_iter, early_exit=True, alpha=0.75,
         lam, z = lam[idx], z[idx]
     r = oracle.decode(code, lam, z, algo=oracle.SPA if algo == "spa" else oracle.NMS,
                       max_iter=max_iter, early_exit=early_exit, alpha=alpha, clip=clip,
-                      schedule=_SCHEDULES[schedule], coupling=_COUPLINGS[coupling])
+                      schedule=_SCHEDULES[schedule], coupling=_COUPLINGS[coupling], msg_half=msg == "f16")
     r["llr_in"] = lam
     return r
 
@@ -160,7 +160,7 @@ def compare(gpu, orc, max_iter, rtol, idx=None, exact_all=False, atol=0.0, long_
 
 
 def oracle_f32_run(code, frames, max_iter, early_exit=True, alpha=0.75, clip=20.0, idx=None,
-                   lam=None, schedule="flooding", coupling="joint"):
+                   lam=None, schedule="flooding", coupling="joint", msg="f32"):
     if lam is None:
         lam = oracle_llr(frames, "f32")
     z = frames.z
@@ -168,7 +168,7 @@ def oracle_f32_run(code, frames, max_iter, early_exit=True, alpha=0.75, clip=20.
         lam, z = lam[idx], z[idx]
     return oracle.decode_nms_f32(code, lam, z, max_iter=max_iter, early_exit=early_exit,
                                  alpha=alpha, clip=clip, schedule=_SCHEDULES[schedule],
-                                 coupling=_COUPLINGS[coupling])
+                                 coupling=_COUPLINGS[coupling], msg_half=msg == "f16")
 
 
 def assert_bitwise(gpu, ref, idx=None):

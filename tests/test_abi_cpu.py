@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_error_paths_without_device():
     from paper_2001_07979_amd import mbp
     L = mbp.lib()
-    assert L.mbp_version() == 2
+    assert L.mbp_version() == 3
     h = ctypes.c_void_p()
     assert L.mbp_ctx_create(0, None) == mbp.MBP_EINVAL
     assert "NULL" in mbp.last_error()
