@@ -664,6 +664,9 @@ def main():
     ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled training step")
     ap.add_argument("--no-two-call", action="store_true",
                     help="skip timing the same step as two calls (LLR rows stored, then decoded)")
+    ap.add_argument("--msg", choices=["f32", "f16"], default="f32",
+                    help="message storage of the timed step (f16: binary16, an extra mode for profiling "
+                         "it; the reported metric is the f32 step)")
     ap.add_argument("--schedule", choices=["serial", "flooding"], default="flooding",
                     help="schedule of the timed step (flooding: every matrix's checks from the previous "
                          "iteration's messages; serial: Algorithm 1's per-matrix loop)")
@@ -731,7 +734,7 @@ def run(args, ctx, dcode, wl, fr, dev):
         # the decoder (the same outputs as llr_from_bits then decode)
         mbp.decode_from_bits(ctx, dcode, y, e, z, dtype="f32", algo=wl.algo, max_iter=wl.max_iter,
                              early_exit=wl.early_exit, alpha=wl.alpha, clip=wl.clip, out=out,
-                             stream=stream, schedule=args.schedule)
+                             stream=stream, schedule=args.schedule, msg=args.msg)
 
     if args.copy_probe_mib:
         src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
@@ -810,7 +813,7 @@ def run(args, ctx, dcode, wl, fr, dev):
 
     roofline = roofline_other = None
     if profile:
-        chk, vn = algorithmic_bytes(code, iters, wl.algo, args.schedule)
+        chk, vn = algorithmic_bytes(code, iters, wl.algo, args.schedule, msg_bytes=2 if args.msg == "f16" else 4)
         stored = args.schedule == "serial" and 1 < code.u <= 4
 
         def line(which, per_step, kernel):
@@ -820,7 +823,8 @@ def run(args, ctx, dcode, wl, fr, dev):
             achieved = per_launch / (avg_ms * 1e-3) / 1e9
             return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": stored_traffic(wl.algo, args.schedule, which), "kernel": kernel,
+                    "traffic": stored_traffic(wl.algo, args.schedule, which) if args.msg == "f32" else None,
+                    "kernel": kernel,
                     "avg_launch_ms": round(avg_ms, 5), "launches": n_k,
                     "algorithmic_bytes_per_launch": int(per_launch)}
 
@@ -898,7 +902,8 @@ def run(args, ctx, dcode, wl, fr, dev):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "frames": F, "n": n, "u": code.u, "m": m, "E": E,
                    "rate": 1 - m / n, "p": p, "algo": wl.algo, "max_iter": wl.max_iter,
-                   "early_exit": wl.early_exit, "schedule": args.schedule, "peg": code.name},
+                   "early_exit": wl.early_exit, "schedule": args.schedule, "peg": code.name,
+                   "messages": args.msg},
         "fer": fer, "frame_errors": int(frame_err.sum()), "decoder_failures": int((ok == 0).sum()),
         "fer_bound_95": round(3.0 / F, 5) if not frame_err.any() else None,
         "avg_iters": float(iters.mean()), "max_iters": int(iters.max()),
