@@ -211,6 +211,32 @@ int mbp_syndrome(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, const uint
 int mbp_syndrome_noalloc(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, const uint8_t *x,
                          uint8_t *synd_out, void *stream);
 
+/* Progressive edge-growth construction of u parity-check matrices (Sec. 2:
+ * the u matrices are generated by PEG, after Hu, Eleftheriou and Arnold),
+ * one workgroup per matrix. Variables are taken in index order; a
+ * variable's first edge goes to a check of lowest current degree; each
+ * further edge goes to a lowest-degree check among those that a
+ * breadth-first expansion from the variable reaches last, or, when the
+ * expansion stops growing or reaches max_depth levels, among the checks it
+ * never reached. Ties are broken by a hash of the seed, the edge and the
+ * check (random picks in a degree bucket first), so the matrices depend only
+ * on the arguments; they are not those of the host generator, which draws
+ * its ties sequentially. With depth bound b >= 0 no edge closes a cycle
+ * shorter than 2 (b + 2).
+ *   n, m       variables and checks per matrix
+ *   u          number of matrices; matrix l uses seeds[l]
+ *   var_deg    host [n] variable degrees, non-decreasing, in [1, min(m, 1024)]
+ *   max_depth  expansion bound in levels (< 0: unbounded)
+ *   row_ptr    host [u][m + 1] out: CSR row offsets of each matrix, from 0
+ *   col_idx    host [u][E] out (E = sum of var_deg): columns, ascending in
+ *              each row
+ * Synchronous; allocates and frees its own device memory.
+ * Errors: EINVAL (sizes, degrees, null buffers, or a variable left with no
+ * check for an edge), EUNSUPPORTED (a check degree would pass ceil(E/m) +
+ * 32), ENOMEM, EDEVICE. */
+int mbp_peg_build(mbp_ctx *ctx, int32_t n, int32_t m, int32_t u, const int32_t *var_deg, const uint64_t *seeds,
+                  int32_t max_depth, int32_t *row_ptr, int32_t *col_idx);
+
 /* Decode nframes frames of one code (Sec. 2; Algorithm 1).
  *   llr       device [nframes][n] channel LLRs of p->dtype, finite
  *   synd      device [nframes][M] syndrome bytes (0 / nonzero), the u

@@ -29,7 +29,7 @@ HIP_FLAGS = [
 OBJ_DIR = os.path.join(PKG, "_build")
 
 HIP_SOURCES = ["csrc/capi.cpp", "csrc/decode.hip", "csrc/unrolled.hip", "csrc/batched.hip",
-               "csrc/syndrome.hip"]
+               "csrc/syndrome.hip", "csrc/peg.hip"]
 
 
 def _run(cmd, cwd=None):

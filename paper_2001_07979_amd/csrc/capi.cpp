@@ -394,6 +394,23 @@ int mbp_syndrome_noalloc(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, co
     return mbp::syndrome_noalloc_impl(ctx, code, nframes, x, synd_out, (hipStream_t)stream);
 }
 
+int mbp_peg_build(mbp_ctx *ctx, int32_t n, int32_t m, int32_t u, const int32_t *var_deg, const uint64_t *seeds,
+                  int32_t max_depth, int32_t *row_ptr, int32_t *col_idx) {
+    if (!ctx) return fail(MBP_EINVAL, "mbp_peg_build: null ctx");
+    if (n < 1 || m < 1 || u < 1) return fail(MBP_EINVAL, "mbp_peg_build: n, m and u must be >= 1");
+    if (!var_deg || !seeds || !row_ptr || !col_idx) return fail(MBP_EINVAL, "mbp_peg_build: null buffer");
+    int64_t E = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (var_deg[i] < 1 || var_deg[i] > m || var_deg[i] > 1024)
+            return fail(MBP_EINVAL, "mbp_peg_build: variable degrees must be in [1, min(m, 1024)]");
+        if (i > 0 && var_deg[i] < var_deg[i - 1])
+            return fail(MBP_EINVAL, "mbp_peg_build: variable degrees must be non-decreasing");
+        E += var_deg[i];
+    }
+    if (E >= INT32_MAX / 2) return fail(MBP_EINVAL, "mbp_peg_build: too many edges");
+    return mbp::peg_build_impl(ctx, n, m, u, var_deg, seeds, max_depth, row_ptr, col_idx);
+}
+
 int mbp_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,
                const void *llr, const uint8_t *synd, uint8_t *bits_out, int32_t *iters_out,
                uint8_t *ok_out, void *llr_out, void *stream) {

@@ -146,6 +146,8 @@ int syndrome_noalloc_impl(mbp_ctx *ctx, const mbp_code *code, int32_t nframes, c
                           hipStream_t stream);
 int llr_impl(mbp_ctx *ctx, int32_t nframes, int32_t n, const uint8_t *y, const double *e,
              int32_t dtype, void *llr_out, hipStream_t stream);
+int peg_build_impl(mbp_ctx *ctx, int32_t n, int32_t m, int32_t u, const int32_t *var_deg, const uint64_t *seeds,
+                   int32_t max_depth, int32_t *row_ptr, int32_t *col_idx);
 
 // Batched persistent decode (batched.hip).
 mbp_tuning default_tuning();

@@ -88,6 +88,7 @@ def lib():
             "mbp_decode_from_bits": (ctypes.c_int, [vp, vp, ctypes.POINTER(mbp_params), i32] + [vp] * 8),
             "mbp_syndrome": (ctypes.c_int, [vp, vp, i32, vp, vp, vp]),
             "mbp_syndrome_noalloc": (ctypes.c_int, [vp, vp, i32, vp, vp, vp]),
+            "mbp_peg_build": (ctypes.c_int, [vp, i32, i32, i32, vp, vp, i32, vp, vp]),
             "mbp_unrolled_workspace_bytes": (ctypes.c_int, [vp, i32, i32, i32,
                                                              ctypes.POINTER(ctypes.c_uint64)]),
             "mbp_nms_unrolled_fwd": (ctypes.c_int, [vp, vp, i32, i32, i32, ctypes.c_double] + [vp] * 5
@@ -395,6 +396,22 @@ def syndrome_noalloc(ctx: Context, code: Code, x, out, stream=None):
     _check(lib().mbp_syndrome_noalloc(ctx.handle, code.handle, F, px, po, _stream_ptr(stream)),
            "mbp_syndrome_noalloc")
     return out
+
+
+def peg_build(ctx: Context, n: int, m: int, var_deg, seeds, max_depth: int = -1):
+    """u PEG matrices built on the GPU (mbp_peg_build), matrix l from
+    seeds[l]: returns ([row_ptr] * u, [col_idx] * u) as int32 numpy arrays."""
+    dv = np.ascontiguousarray(var_deg, dtype=np.int32)
+    if dv.shape != (int(n),):
+        raise ValueError("var_deg must have n entries")
+    sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64).reshape(-1))
+    u = int(sd.size)
+    E = int(dv.sum())
+    rp = np.zeros((u, int(m) + 1), dtype=np.int32)
+    ci = np.zeros((u, E), dtype=np.int32)
+    _check(lib().mbp_peg_build(ctx.handle, int(n), int(m), u, dv.ctypes.data, sd.ctypes.data, int(max_depth),
+                               rp.ctypes.data, ci.ctypes.data), "mbp_peg_build")
+    return [rp[l] for l in range(u)], [ci[l] for l in range(u)]
 
 
 def decode(ctx: Context, code: Code, llr, synd, algo: str = "spa", max_iter: int = 50,

@@ -48,6 +48,10 @@ def test_version_and_error_paths_without_device():
     assert L.mbp_llr_from_bits(None, 1, 1, None, None, 0, None, None) == mbp.MBP_EINVAL
     assert L.mbp_decode_from_bits(None, None, ctypes.byref(p), 1, *([None] * 8)) == mbp.MBP_EINVAL
     assert "mbp_decode_from_bits" in mbp.last_error()
+    dv = (ctypes.c_int32 * 4)(2, 2, 2, 2)
+    seeds = (ctypes.c_uint64 * 1)(1)
+    assert L.mbp_peg_build(None, 4, 2, 1, dv, seeds, 1, None, None) == mbp.MBP_EINVAL
+    assert "mbp_peg_build" in mbp.last_error()
     assert L.mbp_syndrome(None, None, 1, None, None, None) == mbp.MBP_EINVAL
     qh = ctypes.c_void_p()
     assert L.mbp_queue_create(None, ctypes.byref(p), None, ctypes.byref(qh)) == mbp.MBP_EINVAL
