@@ -27,6 +27,7 @@ namespace {
 constexpr int kPegBlock = 1024;
 constexpr int kPegWaves = kPegBlock / 64;
 constexpr int kPegTries = 24;  // random picks in a degree bucket before scanning it
+constexpr int kPegSegMax = 4096;  // degree buckets held in LDS: cap + 2 at most
 
 // splitmix64's output function (Steele, Lea and Flood, 2014) applied to a
 // counter: the k-th value of the stream seeded with `seed`.
@@ -37,10 +38,10 @@ __device__ __forceinline__ uint64_t sm64_at(uint64_t seed, uint64_t k) {
     return z ^ (z >> 31);
 }
 
-// Per-matrix state, all in device memory. Check c's variables are
+// Per-matrix state, in device memory. Check c's variables are
 // adj[c * cap + i], i < len[c] (ascending: variables arrive in index order);
-// order[] lists the checks by degree, seg[d] is where degree d starts in it
-// and pos[c] is c's index there.
+// order[] lists the checks by degree and pos[c] is c's index there; where
+// degree d starts in order[] (seg[d]) is kept in LDS by the kernel.
 struct PegState {
     const int32_t *var_off;  // [n + 1], shared by the u matrices
     int32_t *var_cnt;        // [n]
@@ -48,7 +49,6 @@ struct PegState {
     int32_t *len;            // [m]
     int32_t *adj;            // [m * cap]
     int32_t *order, *pos;    // [m]
-    int32_t *seg;            // [cap + 2]
     int32_t *cstamp;         // [m]
     int32_t *vstamp;         // [n]
     int32_t *front, *next;   // [m] each
@@ -82,24 +82,13 @@ __device__ __forceinline__ uint64_t cand_key(const PegState &S, int c, int deg, 
 // Lowest-degree check not reached by the current search (cstamp != stamp):
 // first a few random picks in each degree bucket (as a sequential PEG
 // would), then the lowest key over the bucket's unreached checks. -1 if
-// every check is reached.
-// Every value that steers the block's control flow is read by thread 0 and
-// handed to all threads through LDS, so all take the same path to each
-// barrier.
+// every check is reached. The degree buckets (seg) and the lowest degree
+// with a check (d0) live in LDS, where every thread reads the same values,
+// so all take the same path to each barrier.
 __device__ int pick_unreached(const PegState &S, int cap, int stamp, uint64_t edge, uint64_t *draw,
-                              uint64_t *sh_min, int *sh_pick, int *sh_bounds) {
-    if (threadIdx.x == 0) sh_bounds[2] = S.len[S.order[0]];  // the lowest degree
-    __syncthreads();
-    const int d0 = sh_bounds[2];
-    __syncthreads();
+                              uint64_t *sh_min, int *sh_pick, const int *seg, int d0) {
     for (int d = d0; d <= cap; ++d) {
-        if (threadIdx.x == 0) {
-            sh_bounds[0] = S.seg[d];
-            sh_bounds[1] = S.seg[d + 1];
-        }
-        __syncthreads();
-        const int lo = sh_bounds[0], hi = sh_bounds[1];
-        __syncthreads();
+        const int lo = seg[d], hi = seg[d + 1];
         if (hi <= lo) continue;
         if (threadIdx.x == 0) {
             int got = -1;
@@ -128,16 +117,18 @@ __device__ int pick_unreached(const PegState &S, int cap, int stamp, uint64_t ed
     return -1;
 }
 
-// Raise check c's degree by one, keeping order[] sorted by degree (thread 0).
-__device__ void bump_degree(const PegState &S, int c) {
+// Raise check c's degree by one, keeping order[] sorted by degree, and the
+// lowest degree with a check (thread 0).
+__device__ void bump_degree(const PegState &S, int c, int *seg, int *d0) {
     const int d = S.len[c];
-    const int last = S.seg[d + 1] - 1;
+    const int last = seg[d + 1] - 1;
     const int pc = S.pos[c], other = S.order[last];
     S.order[pc] = other;
     S.pos[other] = pc;
     S.order[last] = c;
     S.pos[c] = last;
-    S.seg[d + 1] = last;
+    seg[d + 1] = last;
+    while (seg[*d0] == seg[*d0 + 1]) ++*d0;
 }
 
 __global__ __launch_bounds__(kPegBlock) void k_peg(PegArgs a, int32_t matrix0) {
@@ -147,7 +138,8 @@ __global__ __launch_bounds__(kPegBlock) void k_peg(PegArgs a, int32_t matrix0) {
     const int tid = static_cast<int>(threadIdx.x);
     const int wave = tid >> 6, lane = tid & 63;
     __shared__ uint64_t sh_min;
-    __shared__ int sh_pick, sh_nlen, sh_stop, sh_bounds[3];
+    __shared__ int sh_pick, sh_nlen, sh_stop, sh_d0;
+    __shared__ int seg[kPegSegMax];
     // all checks start at degree 0
     for (int c = tid; c < m; c += kPegBlock) {
         S.order[c] = c;
@@ -159,8 +151,11 @@ __global__ __launch_bounds__(kPegBlock) void k_peg(PegArgs a, int32_t matrix0) {
         S.var_cnt[i] = 0;
         S.vstamp[i] = 0;
     }
-    for (int d = tid; d < cap + 2; d += kPegBlock) S.seg[d] = d == 0 ? 0 : m;
-    if (tid == 0) sh_stop = 0;
+    for (int d = tid; d < cap + 2; d += kPegBlock) seg[d] = d == 0 ? 0 : m;
+    if (tid == 0) {
+        sh_stop = 0;
+        sh_d0 = 0;
+    }
     __syncthreads();
     int stamp = 0;
     uint64_t edge = 0, draw = 0;  // draw: position in the tie-break stream (thread 0)
@@ -170,7 +165,7 @@ __global__ __launch_bounds__(kPegBlock) void k_peg(PegArgs a, int32_t matrix0) {
             ++stamp;
             int c = -1;
             if (k == 0) {
-                c = pick_unreached(S, cap, stamp, edge, &draw, &sh_min, &sh_pick, sh_bounds);
+                c = pick_unreached(S, cap, stamp, edge, &draw, &sh_min, &sh_pick, seg, sh_d0);
             } else {
                 // level 0: the variable's checks
                 if (tid < k) {
@@ -187,7 +182,7 @@ __global__ __launch_bounds__(kPegBlock) void k_peg(PegArgs a, int32_t matrix0) {
                 __syncthreads();
                 for (int level = 0;; ++level) {
                     if (a.max_depth >= 0 && level >= a.max_depth) {
-                        c = pick_unreached(S, cap, stamp, edge, &draw, &sh_min, &sh_pick, sh_bounds);
+                        c = pick_unreached(S, cap, stamp, edge, &draw, &sh_min, &sh_pick, seg, sh_d0);
                         break;
                     }
                     // the next level: unvisited variables of the frontier's
@@ -209,7 +204,7 @@ __global__ __launch_bounds__(kPegBlock) void k_peg(PegArgs a, int32_t matrix0) {
                     const int nlen = sh_nlen;
                     __syncthreads();
                     if (nlen == 0) {
-                        c = pick_unreached(S, cap, stamp, edge, &draw, &sh_min, &sh_pick, sh_bounds);
+                        c = pick_unreached(S, cap, stamp, edge, &draw, &sh_min, &sh_pick, seg, sh_d0);
                         break;
                     }
                     if (count + nlen == m) {
@@ -240,7 +235,7 @@ __global__ __launch_bounds__(kPegBlock) void k_peg(PegArgs a, int32_t matrix0) {
                     *S.err = 1;
                     sh_stop = 1;
                 } else {
-                    bump_degree(S, c);
+                    bump_degree(S, c, seg, &sh_d0);
                     S.adj[static_cast<size_t>(c) * cap + S.len[c]] = v;
                     S.len[c] += 1;
                     S.var_adj[off + S.var_cnt[v]] = c;
@@ -298,8 +293,10 @@ int peg_build_impl(mbp_ctx *ctx, int32_t n, int32_t m, int32_t u, const int32_t 
     // check degrees stay near E / m (each edge goes to a lowest-degree
     // candidate); a check that would pass this bound stops the build
     const int32_t cap = static_cast<int32_t>((E + m - 1) / m) + 32;
+    if (cap + 2 > kPegSegMax)
+        return fail(MBP_EUNSUPPORTED, "mbp_peg_build: average check degree above " + std::to_string(kPegSegMax - 34));
     const size_t per = (2 * static_cast<size_t>(n) + E + 6 * static_cast<size_t>(m) +
-                        static_cast<size_t>(m) * cap + cap + 2 + 1) * sizeof(int32_t);
+                        static_cast<size_t>(m) * cap + 1) * sizeof(int32_t);
     char *ws = nullptr;
     const size_t total = (static_cast<size_t>(n) + 1) * sizeof(int32_t) + per * u +
                          (static_cast<size_t>(m) + 1) * sizeof(int32_t) + E * sizeof(int32_t);
@@ -330,7 +327,6 @@ int peg_build_impl(mbp_ctx *ctx, int32_t n, int32_t m, int32_t u, const int32_t 
         S.front = take(m);
         S.next = take(m);
         S.adj = take(static_cast<size_t>(m) * cap);
-        S.seg = take(static_cast<size_t>(cap) + 2);
         S.err = take(1);
         S.seed = seeds[l];
     }
