@@ -194,9 +194,18 @@ __global__ __launch_bounds__(kPegBlock) void k_peg(PegArgs a, int32_t matrix0) {
                             const int w = S.adj[static_cast<size_t>(f) * cap + i];
                             if (atomicExch(&S.vstamp[w], stamp) == stamp) continue;
                             const int wo = S.var_off[w], wc = S.var_cnt[w];
-                            for (int b = 0; b < wc; ++b) {
-                                const int c2 = S.var_adj[wo + b];
-                                if (atomicExch(&S.cstamp[c2], stamp) != stamp) next[atomicAdd(&sh_nlen, 1)] = c2;
+                            // the variable's checks eight at a time: all loads,
+                            // then all claims, then the pushes, so the round
+                            // trips overlap instead of chaining
+                            for (int b0 = 0; b0 < wc; b0 += 8) {
+                                int c2[8], old[8];
+#pragma unroll
+                                for (int j = 0; j < 8; ++j) c2[j] = b0 + j < wc ? S.var_adj[wo + b0 + j] : -1;
+#pragma unroll
+                                for (int j = 0; j < 8; ++j) old[j] = c2[j] >= 0 ? atomicExch(&S.cstamp[c2[j]], stamp) : stamp;
+#pragma unroll
+                                for (int j = 0; j < 8; ++j)
+                                    if (old[j] != stamp) next[atomicAdd(&sh_nlen, 1)] = c2[j];
                             }
                         }
                     }
