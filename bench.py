@@ -464,14 +464,18 @@ def half_messages(ctx, wl, fr, dcode, y, e, z, steps: int):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     iters = out["iters"].cpu().numpy()
-    ctx.profile_enable(True, kernels=["check", "variable"])
+    ctx.profile_enable(True, kernels=["check", "variable", "first", "second"])
     ctx.profile_reset()
     step()
     torch.cuda.synchronize()
     ctx.profile_enable(False)
-    chk, vn = algorithmic_bytes(code, iters, wl.algo, "flooding", msg_bytes=2)
+    closed = closed_first(code, wl.algo, "flooding", msg_bytes=2)
+    chk, vn = algorithmic_bytes(code, iters, wl.algo, "flooding", msg_bytes=2, closed=closed)
     roof = {}
-    for kern, total in (("check", chk), ("variable", vn)):
+    kernels = (("check", chk), ("variable", vn))
+    if closed:
+        kernels += (("first", first_iteration_bytes(code, iters)), ("second", second_check_bytes(code, iters, 2)))
+    for kern, total in kernels:
         launches, ms = ctx.profile_get(kern)
         achieved = total / (ms / 1e3) / 1e9 if ms > 0 else 0.0
         roof[kern] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -600,7 +604,37 @@ def host_info() -> dict:
     return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": aff}
 
 
-def algorithmic_bytes(code, iters, algo: str, schedule: str, from_bits: bool = True, msg_bytes: int = 4):
+def closed_first(code, algo: str, schedule: str, msg_bytes: int = 4, from_bits: bool = True) -> bool:
+    """Whether the decoder runs the first iteration in closed form (the
+    library's condition: FP32 from Bob's bits, one check pass per iteration,
+    no compressed min-sum state, the per-class variable pass, fewer than
+    2^20 checks)."""
+    dmax = max(int(np.diff(rp).max()) for rp in code.row_ptr)
+    cst = algo == "nms" and msg_bytes == 4 and dmax <= 24
+    return (from_bits and (schedule == "flooding" or code.u == 1) and not cst
+            and code.E * 64 * 4 < 2**31 - 1 and code.M < 2**20)
+
+
+def first_iteration_bytes(code, iters) -> float:
+    """Algorithmic bytes of the first iteration in closed form, all frames:
+    the parity words (Bob's bit words n/8 and syndrome words M/8 read, M/8
+    written) and the variable pass (bit words and parity words read, L^1
+    and the decision bits written)."""
+    n, M = code.n, code.M
+    return float(len(iters)) * (n / 8 + 2 * M / 8 + n / 8 + M / 8 + 4 * n + n / 8)
+
+
+def second_check_bytes(code, iters, msg_bytes: int = 4) -> float:
+    """Algorithmic bytes of the check pass that follows a closed-form first
+    iteration, over the frames it advanced: L^1 (4n), Bob's bit words (n/8)
+    and the parity words (M/8) read, c^2 written; the old messages are
+    rebuilt, not read."""
+    full = int((iters >= 2).sum())
+    return float(full) * (msg_bytes * code.E + code.n / 8 + code.M / 8 + 4 * code.n)
+
+
+def algorithmic_bytes(code, iters, algo: str, schedule: str, from_bits: bool = True, msg_bytes: int = 4,
+                      closed: bool = False):
     """Algorithmic HBM bytes of all check passes and of all variable passes of
     one step (FP32), summed over the frames each iteration advanced.
 
@@ -616,7 +650,10 @@ def algorithmic_bytes(code, iters, algo: str, schedule: str, from_bits: bool = T
     its matrix's sum. Decoding from stored LLR rows (from_bits False) reads
     lambda as 4n bytes where the bit words take n/8. msg_bytes is the size of
     a stored check message (2 with binary16 storage, which keeps no
-    compressed min-sum state)."""
+    compressed min-sum state). With the first iteration in closed form
+    (closed) neither pass runs in the first iteration (first_iteration_bytes
+    counts its kernels), and the second iteration's check pass, a kernel of
+    its own, is left to second_check_bytes."""
     s, n, E, M, u = 4, code.n, code.E, code.M, code.u
     sm = msg_bytes
     lam = n / 8 if from_bits else s * n
@@ -628,9 +665,11 @@ def algorithmic_bytes(code, iters, algo: str, schedule: str, from_bits: bool = T
     chk = vn = 0.0
     for t in range(1, int(iters.max()) + 1):
         full = int((iters >= t).sum())
+        if closed and t == 1:
+            continue
         if t == 1:
             chk += full * (sm * E + lam + s * n * (phases - 1) + (3 * s * M if cst else 0))
-        else:
+        elif not (closed and t == 2):
             chk += full * (sm * E + old + s * n * phases)
         if stored:
             others = sum(l if t == 1 else u - 1 for l in range(u))
@@ -773,8 +812,9 @@ def run(args, ctx, dcode, wl, fr, dev):
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     mbps = F * n / ((t1 - t0) / args.steps) / 1e6
     if profile:
-        # the other iteration kernel, timed over the same number of steps after the timed region
-        ctx.profile_enable(True, kernels=[other_kernel])
+        # the other iteration kernel and the closed-form first iteration, timed
+        # over the same number of steps after the timed region
+        ctx.profile_enable(True, kernels=[other_kernel, "first", "second"])
         for _ in range(args.steps):
             step()
         torch.cuda.synchronize()
@@ -811,9 +851,11 @@ def run(args, ctx, dcode, wl, fr, dev):
     h = float(h2(p))
     m = code.m[0]
 
-    roofline = roofline_other = None
+    roofline = roofline_other = first_line = second_line = None
     if profile:
-        chk, vn = algorithmic_bytes(code, iters, wl.algo, args.schedule, msg_bytes=2 if args.msg == "f16" else 4)
+        closed = closed_first(code, wl.algo, args.schedule, msg_bytes=2 if args.msg == "f16" else 4)
+        chk, vn = algorithmic_bytes(code, iters, wl.algo, args.schedule, msg_bytes=2 if args.msg == "f16" else 4,
+                                    closed=closed)
         stored = args.schedule == "serial" and 1 < code.u <= 4
 
         def line(which, per_step, kernel):
@@ -832,6 +874,13 @@ def run(args, ctx, dcode, wl, fr, dev):
         r_vn = line("variable", vn, "k_variable_phase (variable-node pass)" if stored
                     else "k_variable (variable-node pass)")
         roofline, roofline_other = (r_chk, r_vn) if dominant == "check" else (r_vn, r_chk)
+        if closed:
+            first_line = line("first", first_iteration_bytes(code, iters),
+                              "k_first_table, k_first_parity, k_variable_first (first iteration in closed form)")
+            first_line["traffic"] = None
+            second_line = line("second", second_check_bytes(code, iters, 2 if args.msg == "f16" else 4),
+                               "k_check, second iteration (old messages rebuilt, not read)")
+            second_line["traffic"] = None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -909,7 +958,9 @@ def run(args, ctx, dcode, wl, fr, dev):
         "avg_iters": float(iters.mean()), "max_iters": int(iters.max()),
         "f": round(m / (n * h), 4), "f_leak": round(code.u * m / (n * h), 4),
         "llr_rows_then_decode": two_calls,
-        "roofline": roofline, "roofline_other_kernel": roofline_other, "cpu_baseline": cpu,
+        "roofline": roofline, "roofline_other_kernel": roofline_other, "first_iteration": first_line,
+        "second_check_pass": second_line,
+        "cpu_baseline": cpu,
         "other_schedule": other, "half_messages": half, "n65536": c2, "alice_syndromes": alice,
         "unrolled_training_step": unrolled,
         "batched_vs_plain": batched,

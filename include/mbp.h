@@ -269,12 +269,22 @@ int mbp_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
  * mbp_llr_from_bits followed by mbp_decode, bit for bit. The LLRs are never
  * stored as rows: the kernels read 64-frame bit words and one magnitude per
  * frame, which saves the first iteration's LLR gathers and the LLR reads of
- * every variable pass.
+ * every variable pass. In FP32 with one check pass per iteration (flooding,
+ * or u = 1) and no compressed min-sum state, the first iteration's messages
+ * are not stored either: with every |lambda| of a frame equal, the message
+ * from slot j of a check of degree d has a magnitude set by (d, j) and the
+ * frame, and a sign set by the check's parity and the variable's bit, so the
+ * first variable pass and the second check pass rebuild each message from a
+ * small table and two bits (the same values, bit for bit). Error rates
+ * outside (0, 1) give NaN outputs that may differ from the two-call path in
+ * their NaN bits.
  *   y     device [nframes][n] bytes, 0 = bit 0, nonzero = bit 1
  *   e     device [nframes] FP64 error rates, each in (0, 0.5]
  * Every other argument, the output contract and the errors are those of
  * mbp_decode (the workspace holds 8 g n bytes of bit words and 64 g
- * magnitudes in place of the 64 g n LLRs). Error rates are not read on the
+ * magnitudes in place of the 64 g n LLRs; with the first iteration in
+ * closed form, also 8 g M bytes of parity words and 256 g R bytes of table,
+ * R = the sum of the code's distinct check degrees). Error rates are not read on the
  * host; a value outside (0, 0.5] gives non-finite or sign-flipped LLRs. */
 int mbp_decode_from_bits(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t nframes,
                          const uint8_t *y, const double *e, const uint8_t *synd, uint8_t *bits_out,
@@ -427,14 +437,17 @@ void mbp_queue_destroy(mbp_queue *q);
  * selected by the mask with HIP events on the decode's stream and adds the
  * elapsed times to per-kernel totals. Kernel ids: 0 = check-node pass,
  * 1 = variable-node pass, 2 = stopping test, 3 = staging and output
- * transposes. Events between launches cost a few microseconds each, so
- * timing only the kernel of interest disturbs the run least.
+ * transposes, 4 = the first iteration in closed form (decoding from Bob's
+ * bits: its check parity words, magnitude table and variable pass), 5 = the
+ * check pass after it (which rebuilds the first iteration's messages).
+ * Events between launches cost a few microseconds each, so timing only the
+ * kernel of interest disturbs the run least.
  *   mbp_profile_enable  mask: bit k times kernel id k (0 = off,
- *                       MBP_PROFILE_ALL = every kernel); EINVAL outside 0..15
+ *                       MBP_PROFILE_ALL = every kernel); EINVAL outside 0..63
  *   mbp_profile_reset   zero the totals
  *   mbp_profile_get     totals of kernel id `which`: launches and summed
  *                       milliseconds. */
-#define MBP_PROFILE_ALL 0xF
+#define MBP_PROFILE_ALL 0x3F
 int mbp_profile_enable(mbp_ctx *ctx, int32_t enable);
 int mbp_profile_reset(mbp_ctx *ctx);
 int mbp_profile_get(const mbp_ctx *ctx, int32_t which, int64_t *launches, double *total_ms);

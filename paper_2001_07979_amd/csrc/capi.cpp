@@ -286,6 +286,8 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
         (void)hipFree(code->d_var_edge_f);
         (void)hipFree(code->d_var_mptr);
         (void)hipFree(code->d_var_runs);
+        (void)hipFree(code->d_var_rt);
+        (void)hipFree(code->d_first_rowdj);
         delete code;
         return rc;
     };
@@ -301,6 +303,36 @@ int mbp_code_create(mbp_ctx *ctx, int32_t n, int32_t u, const int32_t *m,
         (he = hipMalloc(&code->d_var_mptr, sizeof(int32_t) * (u + 1) * n)) != hipSuccess ||
         (he = hipMalloc(&code->d_var_runs, sizeof(uint64_t) * n)) != hipSuccess)
         return cleanup(hip_fail(he, "mbp_code_create: hipMalloc"));
+    // each variable edge's check and its row of the first-iteration
+    // magnitude table: one row per slot of every check degree present
+    if (M < mbp::kRtMaxChecks) {
+        std::vector<int32_t> first_row(65, -1);
+        std::vector<uint32_t> rowdj;
+        std::vector<char> present(65, 0);
+        for (int64_t rr = 0; rr < M; ++rr) present[h_row_ptr[rr + 1] - h_row_ptr[rr]] = 1;
+        for (int32_t d = 1; d <= 64; ++d) {
+            if (!present[d]) continue;
+            first_row[d] = static_cast<int32_t>(rowdj.size());
+            for (int32_t j = 0; j < d; ++j) rowdj.push_back(static_cast<uint32_t>(d << 8 | j));
+        }
+        std::vector<uint32_t> h_var_rt(E + mbp::kIndexPad, 0);
+        std::vector<int32_t> edge_row(E);
+        for (int64_t rr = 0; rr < M; ++rr)
+            for (int32_t k = h_row_ptr[rr]; k < h_row_ptr[rr + 1]; ++k) edge_row[k] = static_cast<int32_t>(rr);
+        for (int64_t k = 0; k < E; ++k) {
+            const int32_t ek = h_var_edge[k], rr = edge_row[ek];
+            const int32_t d = h_row_ptr[rr + 1] - h_row_ptr[rr], j = ek - h_row_ptr[rr];
+            h_var_rt[k] = (static_cast<uint32_t>(rr) << mbp::kRtShift) | static_cast<uint32_t>(first_row[d] + j);
+        }
+        code->first_rows = static_cast<int32_t>(rowdj.size());
+        if ((he = hipMalloc(&code->d_var_rt, sizeof(uint32_t) * (E + mbp::kIndexPad))) != hipSuccess ||
+            (he = hipMemcpy(code->d_var_rt, h_var_rt.data(), sizeof(uint32_t) * (E + mbp::kIndexPad),
+                            hipMemcpyHostToDevice)) != hipSuccess ||
+            (he = hipMalloc(&code->d_first_rowdj, sizeof(uint32_t) * rowdj.size())) != hipSuccess ||
+            (he = hipMemcpy(code->d_first_rowdj, rowdj.data(), sizeof(uint32_t) * rowdj.size(),
+                            hipMemcpyHostToDevice)) != hipSuccess)
+            return cleanup(hip_fail(he, "mbp_code_create: first-iteration rows"));
+    }
     // the kernels read edge indices in fixed-size blocks that may run past the
     // last edge; the padding holds valid (zero) indices
     h_col.resize(E + mbp::kIndexPad, 0);
@@ -343,6 +375,8 @@ void mbp_code_destroy(mbp_code *code) {
     (void)hipFree(code->d_var_edge_f);
     (void)hipFree(code->d_var_mptr);
     (void)hipFree(code->d_var_runs);
+    (void)hipFree(code->d_var_rt);
+    (void)hipFree(code->d_first_rowdj);
     mbp_ctx *ctx = code->ctx;
     delete code;
     if (--ctx->live_codes == 0 && ctx->closed) delete ctx;
@@ -804,7 +838,7 @@ int mbp_autotune(mbp_ctx *ctx, int32_t nbatches, const mbp_batch *batches, const
 
 int mbp_profile_enable(mbp_ctx *ctx, int32_t enable) {
     if (!ctx) return fail(MBP_EINVAL, "mbp_profile_enable: ctx is NULL");
-    if (enable < 0 || enable > 0xF) return fail(MBP_EINVAL, "mbp_profile_enable: mask outside 0..15");
+    if (enable < 0 || enable > MBP_PROFILE_ALL) return fail(MBP_EINVAL, "mbp_profile_enable: mask outside 0..63");
     ctx->profiling = enable;
     return MBP_OK;
 }

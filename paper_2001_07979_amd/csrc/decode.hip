@@ -68,6 +68,34 @@ CheckFn<float> check_kernel_half_for(int algo, int dmax) {
     return algo == MBP_ALGO_NMS ? check_kernel_half<kNMS, BITS>(dmax) : check_kernel_half<kSPA, BITS>(dmax);
 }
 
+// FP32 instances of the second iteration after a first in closed form: the
+// old messages rebuilt from the magnitude table and the sign bits.
+template <int ALGO, bool H>
+CheckFn<float> check_kernel_short(int dmax) {
+    switch (dmax) {
+        case 8: return &k_check<float, ALGO, 8, false, false, H, true>;
+        case 10: return &k_check<float, ALGO, 10, false, false, H, true>;
+        case 16: return &k_check<float, ALGO, 16, false, false, H, true>;
+        case 18: return &k_check<float, ALGO, 18, false, false, H, true>;
+        case 24: return &k_check<float, ALGO, 24, false, false, H, true>;
+        case 32: return &k_check<float, ALGO, 32, false, false, H, true>;
+        case 34: return &k_check<float, ALGO, 34, false, false, H, true>;
+        case 48: return &k_check<float, ALGO, 48, false, false, H, true>;
+        default: return &k_check<float, ALGO, 64, false, false, H, true>;
+    }
+}
+
+template <bool H>
+CheckFn<float> check_kernel_short_for(int algo, int dmax) {
+    return algo == MBP_ALGO_NMS ? check_kernel_short<kNMS, H>(dmax) : check_kernel_short<kSPA, H>(dmax);
+}
+
+using FirstTableFn = void (*)(float *, const uint32_t *, Dims);
+template <bool H>
+FirstTableFn first_table_kernel(int algo) {
+    return algo == MBP_ALGO_NMS ? &k_first_table<kNMS, H> : &k_first_table<kSPA, H>;
+}
+
 // The channel of a decode: LLR rows [F][n] of the decode's element type, or
 // Bob's bits y [F][n] (bytes, nonzero = 1) with the error rate e [F] of each
 // frame, from which lambda = (1 - 2y) ln((1 - e)/e) is formed inside the
@@ -114,11 +142,26 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     const int32_t lm0 = phase_sums ? code->u : 0;
     const int32_t prows = lm0 + (indep ? code->u : 0);
     const size_t sz_ps = prows ? align_up(static_cast<size_t>(ntot) * prows * n * G * s) : 0;
+    // FP32 flooding with the stacked graph: the variable pass per degree
+    // class (its buffer loads address a group's messages with 32-bit offsets)
+    const bool per_class = std::is_same<T, float>::value && !indep && E * G * static_cast<int64_t>(sizeof(float)) < INT32_MAX;
+    // From Bob's bits, FP32 flooding (one phase), the per-class variable pass
+    // and no compressed state: the first iteration in closed form (its
+    // messages rebuilt from a table of magnitudes and the checks' parity
+    // words, never stored)
+    const bool closed1 = std::is_same<T, float>::value && from_bits && per_class && !with_state &&
+                         (p->schedule != MBP_MATRIX_SERIAL || code->u == 1) && code->d_var_rt != nullptr &&
+                         static_cast<int64_t>(ntot) * n < INT32_MAX;
+    const int32_t mrows = closed1 ? code->first_rows : 0;
+    const size_t sz_sp = closed1 ? align_up(static_cast<size_t>(ntot) * M * sizeof(uint64_t)) +
+                                       align_up(static_cast<size_t>(ntot) * 2 * sizeof(uint64_t)) +
+                                       align_up(static_cast<size_t>(ngroups) * mrows * G * sizeof(float))
+                                 : 0;
     // lambda: rows like L, or Bob's bit words and one magnitude per slot
     const size_t sz_lam = from_bits ? sz_d + align_up(static_cast<size_t>(ntot) * G * s) : sz_L;
     // status words, one 256-byte line per group, then the stopping-test counters
     const size_t sz_m = align_up(static_cast<size_t>(ntot) * kStride * sizeof(uint64_t)) + 256;
-    int rc = ensure_workspace(ctx, sz_c + sz_L + sz_lam + sz_z + sz_d + 2 * sz_f + sz_m + sz_cs + sz_ps);
+    int rc = ensure_workspace(ctx, sz_c + sz_L + sz_lam + sz_z + sz_d + 2 * sz_f + sz_m + sz_cs + sz_ps + sz_sp);
     if (rc != MBP_OK) return rc;
     if ((rc = ensure_status(ctx, ntot)) != MBP_OK) return rc;
     char *base = static_cast<char *>(ctx->ws);
@@ -148,6 +191,13 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     T *cs = with_state ? reinterpret_cast<T *>(carve(sz_cs)) : nullptr;
     T *ps = prows ? reinterpret_cast<T *>(carve(sz_ps)) : nullptr;
     T *lm = indep ? ps + static_cast<size_t>(lm0) * n * G : nullptr;
+    uint64_t *spar = nullptr, *smask = nullptr;
+    float *mtab = nullptr;
+    if (closed1) {
+        spar = reinterpret_cast<uint64_t *>(carve(align_up(static_cast<size_t>(ntot) * M * sizeof(uint64_t))));
+        smask = reinterpret_cast<uint64_t *>(carve(align_up(static_cast<size_t>(ntot) * 2 * sizeof(uint64_t))));
+        mtab = reinterpret_cast<float *>(carve(align_up(static_cast<size_t>(ngroups) * mrows * G * sizeof(float))));
+    }
 
     Timer tm{ctx, stream, {}, 0};
     hipError_t err;
@@ -187,6 +237,12 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
             kc1 = from_bits ? check_kernel_half_for<true>(p->algo, dmax) : kc;
         }
     }
+    // with the first iteration in closed form, the second iteration's check
+    // pass rebuilds the old messages
+    CheckFn<T> kc2 = kc;
+    if constexpr (std::is_same<T, float>::value) {
+        if (closed1) kc2 = check_kernel_short_for<H>(p->algo, dmax);
+    }
     Dims dc{E, n, M, ntot, (M + kRowsPerTile - 1) / kRowsPerTile, 0, 0, p->alpha, p->llr_clip};
     int vpt = 0;
     const VarFn<T> kv = from_bits ? variable_kernel<T, true>(code->max_var_deg, &vpt)
@@ -196,6 +252,11 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     dc.ybits = dv.ybits = yb;
     dc.ymag = dv.ymag = ymag;
     dc.cstate = cs;
+    dc.spar = dv.spar = spar;
+    dc.smask = dv.smask = smask;
+    dc.mtab = dv.mtab = mtab;
+    dc.mrows = dv.mrows = mrows;
+    dv.var_rt = code->d_var_rt;
     dv.reverse = 1;
     dv.lm = lm;
     dv.prows = prows;
@@ -220,7 +281,13 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
         int grid;
     };
     std::vector<VarLaunch> fast_v;
-    if (std::is_same<T, float>::value && !indep && E * G * static_cast<int64_t>(sizeof(float)) < INT32_MAX) {
+    struct VarFirstLaunch {
+        VarFirstFn fn;
+        Dims d;
+        int grid;
+    };
+    std::vector<VarFirstLaunch> first_v;
+    if (per_class) {
         for (const mbp_var_class &vc : code->var_classes) {
             int vpt_k = 0;
             const VarFastFn fn = from_bits ? variable_fast_kernel<true, H>(vc.dv, &vpt_k)
@@ -232,6 +299,12 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
             d.runs = code->d_var_runs;
             fast_v.push_back({fn, d, grid_for(ctx, reinterpret_cast<const void *>(fn),
                                               static_cast<int64_t>(ngroups) * d.ntiles)});
+            if (closed1) {
+                const VarFirstFn f1 = variable_first_kernel(vc.dv, &vpt_k);
+                d.ntiles = (vc.i1 - vc.i0 + vpt_k - 1) / vpt_k;
+                first_v.push_back({f1, d, grid_for(ctx, reinterpret_cast<const void *>(f1),
+                                                   static_cast<int64_t>(ngroups) * d.ntiles)});
+            }
         }
     }
     // binary16 messages are read by the per-class variable pass only
@@ -288,10 +361,36 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
     // per phase; then, with early exit or on the last iteration, the
     // stopping test, which retires the frames whose decisions meet every
     // syndrome.
+    Dims dfp = ds;  // the first iteration's parity words: one thread per check
+    dfp.ybits = yb;
+    dfp.ymag = ymag;
+    Dims dtab = dc;  // its magnitude table, for the groups holding frames
+    dtab.ngroups = ngroups;
+    const int grid_fp = closed1 ? grid_for(ctx, reinterpret_cast<const void *>(&k_first_parity),
+                                           static_cast<int64_t>(ntot) * dfp.ntiles)
+                                : 0;
+    const int grid_tab = static_cast<int>(std::min<int64_t>(
+        4 * static_cast<int64_t>(ctx->num_cus), (static_cast<int64_t>(ngroups) * mrows * G + kBlock - 1) / kBlock));
     for (int32_t t = 1; t <= p->max_iter; ++t) {
         dv.t = ds.t = t;
         ds.flag = t == p->max_iter ? 1 : 0;
-        for (size_t ph = 0; ph < phases.size(); ++ph) {
+        const bool closed_now = closed1 && t == 1;
+        if (closed_now) {
+            // the first check pass in closed form: the magnitude table and the
+            // checks' parity words; then the variable pass rebuilds each message
+            if constexpr (std::is_same<T, float>::value) {
+                LAUNCH_OR_FAIL(kFirst, first_table_kernel<H>(p->algo)<<<std::max(grid_tab, 1), kBlock, 0, stream>>>(
+                                           mtab, code->d_first_rowdj, dtab));
+                LAUNCH_OR_FAIL(kFirst, k_first_parity<<<grid_fp, kBlock, 0, stream>>>(
+                                           code->d_row_ptr, code->d_col, zb, words, spar, smask, dfp));
+                for (const VarFirstLaunch &vl : first_v) {
+                    Dims dk = vl.d;
+                    dk.t = t;
+                    LAUNCH_OR_FAIL(kFirst, vl.fn<<<vl.grid, kBlock, 0, stream>>>(code->d_var_ptr, Lp, words, D, dk));
+                }
+            }
+        }
+        for (size_t ph = 0; ph < phases.size() && !closed_now; ++ph) {
             Dims d = phases[ph].d;
             d.t = t;
             // L^0 = lambda until the first variable pass has run; each
@@ -302,7 +401,9 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
                 d.lstride = static_cast<int64_t>(prows) * n * G;
                 d.mstride = static_cast<int64_t>(n) * G;
             }
-            LAUNCH_OR_FAIL(kCheckNode, (start ? kc1 : kc)<<<phases[ph].grid, kBlock, 0, stream>>>(
+            const bool second = closed1 && t == 2;
+            const CheckFn<T> kct = start ? kc1 : second ? kc2 : kc;
+            LAUNCH_OR_FAIL(second ? kSecond : kCheckNode, kct<<<phases[ph].grid, kBlock, 0, stream>>>(
                                            code->d_row_ptr, code->d_col, code->d_row_mat, nullptr, zb, words, Lin,
                                            c, c, d));
             // decision words only after the iteration's last phase
@@ -338,11 +439,15 @@ int run_decode(mbp_ctx *ctx, const mbp_code *code, const mbp_params *p, int32_t 
             }
         }
         if (!p->early_exit && t < p->max_iter) continue;
+        // no compaction after a first iteration in closed form: its messages
+        // exist only as the groups' tables and parity words, which stay put
+        Dims dst = ds;
+        if (closed_now) dst.nspare = 0;
         LAUNCH_OR_FAIL(kSyndrome, k_stop_test<<<grid_s, kBlock, 0, stream>>>(
                                       code->d_row_ptr, code->d_col, zb, D, words, ctx->status_dev,
-                                      iters_out, ok_out, fid, src, tail, ds));
+                                      iters_out, ok_out, fid, src, tail, dst));
         // fills the spare groups the stopping test's compaction planned
-        if (nspare && t <= p->max_iter - 2)
+        if (nspare && t <= p->max_iter - 2 && !closed_now)
             LAUNCH_OR_FAIL(kSyndrome, k_move<T, H><<<grid_m, kBlock, 0, stream>>>(
                                           c, Lp, lam, zb, yb, ymag, cs, ps, prows, src, tail, E, n, M));
         if (p->early_exit) {

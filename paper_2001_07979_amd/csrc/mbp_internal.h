@@ -28,8 +28,21 @@ constexpr int kIndepMaxU = 4;
 // indices in fixed blocks (up to 64 + 32 entries) past the end.
 constexpr int kIndexPad = 128;
 
+// Packing of d_var_rt: the table row (below 64 * 65 / 2 = 2080) in the low
+// kRtShift bits, the check above them.
+constexpr int kRtShift = 12;
+constexpr int64_t kRtMaxChecks = int64_t(1) << (32 - kRtShift);
+
 // Per-kernel timing totals (see mbp_profile_get).
-enum KernelId { kCheckNode = 0, kVarNode = 1, kSyndrome = 2, kStaging = 3, kNumKernels = 4 };
+enum KernelId {
+    kCheckNode = 0,
+    kVarNode = 1,
+    kSyndrome = 2,
+    kStaging = 3,
+    kFirst = 4,   // the first iteration in closed form
+    kSecond = 5,  // the check pass after it, which rebuilds the old messages
+    kNumKernels = 6
+};
 
 struct KernelStat {
     int64_t launches = 0;
@@ -123,6 +136,15 @@ struct mbp_code {
     // per variable, the slots of its edge list that start the next matrix's
     // edges (bit j: slot j), and the variables split into degree classes
     uint64_t *d_var_runs = nullptr;  // [n]
+    // var_edge again, each entry as (check << kRtShift) | (row of the
+    // first-iteration magnitude table) for its edge: the table has one row
+    // per slot of every check degree the code has (degrees ascending, slot j
+    // of degree d at first_row(d) + j), first_rows rows in all, and
+    // d_first_rowdj gives each row's (d << 8) | j. Null when the code has
+    // kRtMaxChecks checks or more.
+    uint32_t *d_var_rt = nullptr;       // [E + kIndexPad]
+    uint32_t *d_first_rowdj = nullptr;  // [first_rows]
+    int32_t first_rows = 0;
     std::vector<mbp_var_class> var_classes;
 };
 

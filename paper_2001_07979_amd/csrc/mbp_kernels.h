@@ -186,6 +186,18 @@ struct Dims {
     // the next matrix's run (bit j: slot j, j >= 1)
     int32_t vbeg = 0, vend = 0;
     const uint64_t *runs = nullptr;
+    // First iteration in closed form (from Bob's bits; k_first_parity,
+    // k_first_table, k_variable_first and the SHORT check pass): per group
+    // the checks' parity words ([g][M]), the lane masks of frames whose
+    // lambda is negative for bit 0 and of frames with a nonzero lambda
+    // ([g][2]), and the table of first-iteration message magnitudes
+    // ([g][mrows][64], row d (d - 1) / 2 + j: slot j of a check of degree
+    // d); per variable edge its check and table row (kRtShift packing).
+    const uint64_t *spar = nullptr;
+    const uint64_t *smask = nullptr;
+    const float *mtab = nullptr;
+    int32_t mrows = 0;
+    const uint32_t *var_rt = nullptr;
     // variable pass: visit the groups last to first. The check pass visits
     // them first to last, so the variable pass starts on the group whose
     // messages were written last (the likeliest still in the last-level
@@ -279,16 +291,97 @@ __device__ __forceinline__ uint32_t live_item(uint32_t w, uint32_t total, uint32
 // (bits 26-31). Every old message is rebuilt from them bit for bit, so the
 // pass reads 3 rows per check instead of one per edge; it still writes
 // every message (the variable pass reads them) and the new state.
+//
+// With SHORT (the second iteration after a first one in closed form) the old
+// messages are not read from ci: message j of the first iteration has the
+// magnitude first_mags forms for (d, j) and the sign S_r XOR s_j, S_r the
+// check's parity bit and s_j the lambda sign bit of the slot's variable (its
+// bit XOR flip, or 0 where lambda is zero), which is the message the check
+// pass from bits would have stored, bit for bit.
 struct NoPrefetch {
     __device__ void operator()() const {}
 };
 
-template <int ALGO, int DMAX, bool BITS, bool CST = false, bool H = false, typename Cols,
+struct FirstMsgs {
+    uint32_t ylo, yhi;  // lane j < DMAX: the bit word of slot j's variable (low, high half)
+    float ym;           // this frame's lambda magnitude
+    uint32_t sbit;      // S_r in this lane's frame (0 or 1)
+    uint32_t flip;      // 1 if this frame's lambda is negative for bit 0
+    uint32_t nz;        // 1 if this frame's lambda is nonzero
+};
+
+// The magnitudes of the first iteration's messages of a check of degree d
+// when every lambda of the frame has the magnitude |ym| (decoding from Bob's
+// bits), slot by slot, with the operations of the check pass from bits in
+// the same order: sum-product merges the complements' prefix and suffix
+// chains (mirrored slot pairs for a full or nearly full row, where both
+// chains are the prefix chain), min-sum takes alpha times the smaller of
+// |ym| and the clip (the second minimum, +inf, at slot 0 of a degree-1
+// check). With H each is rounded to binary16, as the stored message is
+// (the rounding is symmetric in the sign). Slots past d are left 0.
+//
+// No multiply-add contraction here: the complement e is a product, and
+// fusing it into the chain's sums (which the check pass from bits cannot do,
+// as its e passes through a sign-bit merge) would round differently.
+template <int ALGO, int DMAX, bool H>
+__device__ __forceinline__ void first_mags(int d, float ym, float clip, float alpha, float (&m)[DMAX]) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int j = 0; j < DMAX; ++j) m[j] = 0.0f;
+    if constexpr (ALGO == kNMS) {
+        const float m1 = fminf(fabsf(ym), clip);
+        const float m2 = d >= 2 ? m1 : INFINITY;
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) m[j] = j == 0 ? alpha * m2 : alpha * m1;
+    } else {
+        const float e = tanh_complement(fminf(fabsf(ym), clip));
+        float pre[DMAX];
+        float run = 0.0f;
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            pre[j] = run;
+            run = fmaf(-run, e, run + e);
+        }
+        auto mag = [](float x, float y) {
+            return __uint_as_float(__float_as_uint(atanh2_of_complement(fmaf(-x, y, x + y))) & 0x7fffffffu);
+        };
+        auto full_row = [&](auto dd) {
+            constexpr int D = decltype(dd)::value;
+#pragma unroll
+            for (int j = 0; j <= D - 1 - j; ++j) {
+                const float v = mag(pre[j], pre[D - 1 - j]);
+                m[j] = v;
+                m[D - 1 - j] = v;
+            }
+        };
+        if (d == DMAX) {
+            full_row(std::integral_constant<int, DMAX>());
+        } else if (d == DMAX - 1) {
+            full_row(std::integral_constant<int, DMAX - 1>());
+        } else {
+            float suf = 0.0f;
+#pragma unroll
+            for (int j = DMAX - 1; j >= 0; --j) {
+                if (j < d) m[j] = mag(pre[j], suf);
+                const float ej = j < d ? e : 0.0f;
+                suf = fmaf(-suf, ej, suf + ej);
+            }
+        }
+    }
+    if constexpr (H) {
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) m[j] = static_cast<float>(static_cast<_Float16>(m[j]));
+    }
+}
+
+template <int ALGO, int DMAX, bool BITS, bool CST = false, bool H = false, bool SHORT = false, typename Cols,
           typename Prefetch = NoPrefetch>
 __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbit, float alpha,
                                               float clip, bool first, BufRsrc src, const void *ci, void *cg,
                                               unsigned lane, float ym, uint32_t *st = nullptr,
-                                              Prefetch prefetch = Prefetch(), bool on = true) {
+                                              Prefetch prefetch = Prefetch(), bool on = true,
+                                              const FirstMsgs &fm = FirstMsgs()) {
+    static_assert(!SHORT || (!BITS && !CST), "closed-form old messages: the FP32 pass from messages");
     static_assert(!CST || (ALGO == kNMS && DMAX <= kStateMaxDeg), "compressed state: min-sum, small degree");
     static_assert(!(CST && H), "binary16 messages keep no compressed state");
     const int lo = static_cast<int>(lane) * 4;
@@ -338,6 +431,19 @@ __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbi
         if (first) {
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) q[j] = __uint_as_float(buf_load(src, lo, (j < d ? v(j) : 0) * G * 4));
+        } else if constexpr (SHORT) {
+            // the old messages' magnitudes, then the gathers
+            float om[DMAX];
+            first_mags<ALGO, DMAX, H>(d, fm.ym, clip, alpha, om);
+#pragma unroll
+            for (int j = 0; j < DMAX; ++j) q[j] = __uint_as_float(buf_load(src, lo, (j < d ? v(j) : 0) * G * 4));
+#pragma unroll
+            for (int j = 0; j < DMAX; ++j) {
+                const uint32_t wlo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(fm.ylo), j));
+                const uint32_t whi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(fm.yhi), j));
+                const uint32_t sj = (((lane < 32 ? wlo : whi) >> (lane & 31u)) ^ fm.flip) & fm.nz & 1u;
+                q[j] -= __uint_as_float(__float_as_uint(om[j]) | ((fm.sbit ^ sj) << 31));
+            }
         } else {
             float co[DMAX];
 #pragma unroll
@@ -494,8 +600,8 @@ __device__ __forceinline__ P *msg_at(P *base, size_t off) {
 // gives the min-sum weight of each matrix for this iteration (row_mat maps a
 // check to its matrix); otherwise a.alpha applies to every check. With H
 // (FP32 only) c_in and c_out hold binary16 messages, two bytes per slot.
-template <typename T, int ALGO, int DMAX, bool BITS = false, bool CST = false, bool H = false>
-__global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ row_ptr,
+template <typename T, int ALGO, int DMAX, bool BITS = false, bool CST = false, bool H = false, bool SHORT = false>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SHORT && DMAX <= 34 ? 4 : 1))) void k_check(const int32_t *__restrict__ row_ptr,
                                                   const int32_t *__restrict__ col,
                                                   const int32_t *__restrict__ row_mat,
                                                   const float *__restrict__ alpha_l,
@@ -543,10 +649,15 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
             const int r = a.row0 + tile * kRowsPerTile + ck * kWaves + wave;
             const int rr = r < rend ? r : rend - 1;
             const int l = static_cast<int>(lane);
+            // (SHORT: 8-9 the check's parity word, 10-11 and 12-13 the
+            // group's lambda sign masks)
             const int32_t *src = l < 2 ? row_ptr + rr + l
                                : l < 4 ? reinterpret_cast<const int32_t *>(act + kStride * g + kRun) + (l - 2)
                                : l < 6 ? reinterpret_cast<const int32_t *>(zb + static_cast<size_t>(g) * a.M + rr) + (l - 4)
-                                       : row_ptr + rr;
+                               : !SHORT || l < 8 ? row_ptr + rr
+                               : l < 10 ? reinterpret_cast<const int32_t *>(a.spar + static_cast<size_t>(g) * a.M + rr) + (l - 8)
+                               : l < 14 ? reinterpret_cast<const int32_t *>(a.smask + 2 * static_cast<size_t>(g)) + (l - 10)
+                                        : row_ptr + rr;
             const int32_t got = *src;
             R.info = l == 6 ? g : l == 7 ? r : got;
             if (++ck == kRowsPerWave) {
@@ -589,9 +700,23 @@ __global__ __launch_bounds__(kBlock) void k_check(const int32_t *__restrict__ ro
                                    : nullptr;
                 const int32_t cs = cur.cols;
                 auto v = [cs](int j) { return __builtin_amdgcn_readlane(cs, j); };
-                check_row_f32<ALGO, DMAX, false, CST, H>(v, d, zbit, alpha, clip, first, buf_rsrc(Lr, kBufAll),
-                                                         msg_at<H>(c_in, cb), msg_at<H>(c_out, cb), lane, 0.0f,
-                                                         st, prefetch, on);
+                FirstMsgs fm;
+                if constexpr (SHORT) {
+                    auto bit = [&](int k) {
+                        const uint32_t lo32 = static_cast<uint32_t>(__builtin_amdgcn_readlane(cur.info, k));
+                        const uint32_t hi32 = static_cast<uint32_t>(__builtin_amdgcn_readlane(cur.info, k + 1));
+                        return ((lane < 32 ? lo32 : hi32) >> (lane & 31u)) & 1u;
+                    };
+                    // lane j: the bit word of slot j's variable (the column
+                    // indices of lanes past the degree are in range too)
+                    const uint2 yw = reinterpret_cast<const uint2 *>(a.ybits + static_cast<size_t>(g) * a.n)[cs];
+                    const float ym = static_cast<const float *>(a.ymag)[static_cast<size_t>(g) * G + lane];
+                    fm = FirstMsgs{yw.x, yw.y, ym, bit(8), bit(10), bit(12)};
+                }
+                check_row_f32<ALGO, DMAX, false, CST, H, SHORT>(v, d, zbit, alpha, clip, first,
+                                                                buf_rsrc(Lr, kBufAll), msg_at<H>(c_in, cb),
+                                                                msg_at<H>(c_out, cb), lane, 0.0f, st, prefetch,
+                                                                on, fm);
             } else {
                 prefetch();
             }
@@ -1278,6 +1403,213 @@ VarFastFn variable_fast_kernel(int dv, int *vars_per_tile) {
     if (dv <= 32) { *vars_per_tile = 2 * kWaves; return &k_variable_fast<32, 2, BITS, H>; }
     *vars_per_tile = kWaves;
     return &k_variable_fast<64, 1, BITS, H>;
+}
+
+// The first iteration in closed form, when the channel is Bob's bits. Every
+// lambda of a frame then has the same magnitude |ym|, so the first check
+// pass's message from slot j of a check of degree d has a magnitude that
+// depends only on (d, j) and the frame, and its sign is the check's syndrome
+// bit times the signs of the check's other lambdas: S_r XOR s_j, with S_r the
+// syndrome bit XOR every lambda sign bit of the check (its parity word) and
+// s_j the sign bit of slot j's lambda. So that pass need not run: the
+// variable pass of the first iteration and the check pass of the second
+// rebuild each message from the table and two bits instead of moving the
+// messages through HBM.
+//
+// k_first_table forms the magnitudes for every degree up to the code's
+// largest, for each frame, with the operations of the check pass from bits
+// in the same order (sum-product: the complements' prefix and suffix chains,
+// merged per slot; min-sum: alpha times the smaller of |ym| and the clip,
+// the second minimum +inf for a degree-1 check), so a rebuilt message
+// equals the stored one bit for bit. With H each entry is rounded to
+// binary16, as a stored message would be (the rounding is symmetric in the
+// sign). Row r of group g, lane k: slot j of degree d in the frame of slot
+// k, with rowdj[r] = (d << 8) | j (a row per slot of every check degree of
+// the code).
+template <int ALGO, bool H>
+__device__ __forceinline__ void first_entry(float *__restrict__ tab, const uint32_t *__restrict__ rowdj,
+                                            const Dims &a, int g, int idx) {
+#pragma clang fp contract(off)  // as in first_mags
+    const int row = idx / G, lane = idx % G;
+    const int d = static_cast<int>(rowdj[row] >> 8), j = static_cast<int>(rowdj[row] & 0xffu), k = d - 1 - j;
+    const float ym = static_cast<const float *>(a.ymag)[static_cast<size_t>(g) * G + lane];
+    const float clip = static_cast<float>(a.clip);
+    uint32_t bits;
+    if constexpr (ALGO == kNMS) {
+        const float alpha = static_cast<float>(a.alpha);
+        const float m1 = fminf(fabsf(ym), clip);
+        const float m2 = d >= 2 ? m1 : INFINITY;
+        bits = __float_as_uint(j == 0 ? alpha * m2 : alpha * m1);
+    } else {
+        const float e = tanh_complement(fminf(fabsf(ym), clip));
+        float run = 0.0f, pj = 0.0f, pk = 0.0f;
+        for (int i = 0; i <= max(j, k); ++i) {
+            if (i == j) pj = run;
+            if (i == k) pk = run;
+            run = fmaf(-run, e, run + e);
+        }
+        bits = __float_as_uint(atanh2_of_complement(fmaf(-pj, pk, pj + pk))) & 0x7fffffffu;
+    }
+    if constexpr (H) bits = __float_as_uint(static_cast<float>(static_cast<_Float16>(__uint_as_float(bits))));
+    tab[(static_cast<size_t>(g) * a.mrows + row) * G + lane] = __uint_as_float(bits);
+}
+
+template <int ALGO, bool H>
+__global__ __launch_bounds__(kBlock) void k_first_table(float *__restrict__ tab, const uint32_t *__restrict__ rowdj,
+                                                        const Dims a) {
+    const int64_t total = static_cast<int64_t>(a.ngroups) * a.mrows * G;
+    for (int64_t idx = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; idx < total;
+         idx += static_cast<int64_t>(gridDim.x) * kBlock)
+        first_entry<ALGO, H>(tab, rowdj, a, static_cast<int>(idx / (static_cast<int64_t>(a.mrows) * G)),
+                             static_cast<int>(idx % (static_cast<int64_t>(a.mrows) * G)));
+}
+
+// The checks' parity words of the first iteration: S[g][r] = z_r XOR the
+// lambda sign bits of the check's variables, for the 64 frames at once. The
+// sign bit of lambda = (1 - 2y)|ym| as the check pass sees it (after adding
+// +0) is y XOR flip where lambda is nonzero and 0 where it is zero, with
+// flip the sign of ym; per group the lanes with flip and with a nonzero ym
+// are two masks (smask[g][0], [1]), formed here by a ballot. One thread per
+// check, as the stopping test; only groups holding frames.
+__global__ __launch_bounds__(kBlock) void k_first_parity(const int32_t *__restrict__ row_ptr,
+                                                         const int32_t *__restrict__ col,
+                                                         const uint64_t *__restrict__ zb,
+                                                         const uint64_t *__restrict__ act,
+                                                         uint64_t *__restrict__ spar, uint64_t *__restrict__ smask,
+                                                         const Dims a) {
+    const unsigned lane = lane_id();
+    const int64_t total = static_cast<int64_t>(a.ngroups) * a.ntiles;
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        const int g = static_cast<int>(w / a.ntiles);
+        const int tile = static_cast<int>(w % a.ntiles);
+        if (act[kStride * g + kRun] == 0) continue;
+        const float ym = static_cast<const float *>(a.ymag)[static_cast<size_t>(g) * G + lane];
+        const uint64_t flip = __ballot(__float_as_uint(ym) >> 31);
+        const uint64_t nz = __ballot(ym != 0.0f);
+        if (tile == 0 && threadIdx.x == 0) {
+            smask[2 * static_cast<size_t>(g)] = flip;
+            smask[2 * static_cast<size_t>(g) + 1] = nz;
+        }
+        const int r = tile * kBlock + static_cast<int>(threadIdx.x);
+        if (r >= a.M) continue;
+        const uint64_t *yg = a.ybits + static_cast<size_t>(g) * a.n;
+        uint64_t par = 0;
+        const int e0 = row_ptr[r], e1 = row_ptr[r + 1];
+        // indices, then words, kStopChunk at a time (col is padded past E)
+        for (int e = e0; e < e1; e += kStopChunk) {
+            int v[kStopChunk];
+#pragma unroll
+            for (int j = 0; j < kStopChunk; ++j) v[j] = col[e + j];
+            uint64_t yw[kStopChunk];
+#pragma unroll
+            for (int j = 0; j < kStopChunk; ++j) yw[j] = e + j < e1 ? yg[v[j]] : 0;
+#pragma unroll
+            for (int j = 0; j < kStopChunk; ++j) par ^= yw[j];
+        }
+        // XOR over the edges of (y XOR flip) AND nz
+        if ((e1 - e0) & 1) par ^= flip;
+        spar[static_cast<size_t>(g) * a.M + r] = zb[static_cast<size_t>(g) * a.M + r] ^ (par & nz);
+    }
+}
+
+// Variable pass of the first iteration in closed form: L^1 = lambda + the
+// first check pass's messages, each rebuilt from its table entry (row from
+// var_rt) and its sign S_r XOR s_v (S_r gathered from the parity words, s_v
+// the variable's own lambda sign bit), summed exactly as k_variable_fast
+// sums the stored messages (so L^1 and the decision words are the same, bit
+// for bit). Per edge two gathers from cache (the table and the parity words
+// are small: a 256-byte table row and 8 bytes per wave) in place of one
+// 256-byte message row from HBM; half as many variables per wave as
+// k_variable_fast for the same registers. (Staging a group's table in LDS
+// was slower: the copy each time a block's work moves to another group cost
+// more than the cache reads it saved.)
+template <int DV, int VPW>
+__global__ __launch_bounds__(kBlock) void k_variable_first(const int32_t *__restrict__ var_ptr,
+                                                           float *__restrict__ Lp, const uint64_t *__restrict__ act,
+                                                           uint64_t *__restrict__ D, const Dims a) {
+    if (a.live && *a.live == 0) return;  // every frame retired
+    const unsigned lane = lane_id();
+    const int wave = wave_id();
+    __shared__ uint32_t live[kLiveWords];
+    load_live(live, act, a.ngroups);
+    const uint32_t tot = static_cast<uint32_t>(static_cast<int64_t>(a.ngroups) * a.ntiles);
+    const uint32_t nt = static_cast<uint32_t>(a.ntiles);
+    auto group = [&](int gw) { return a.reverse ? a.ngroups - 1 - gw : gw; };
+    for (uint32_t w = live_item(blockIdx.x, tot, nt, live, group); w < tot;
+         w = live_item(w + gridDim.x, tot, nt, live, group)) {
+        const int g = group(static_cast<int>(w / nt));
+        const int tile = static_cast<int>(w % nt);
+        const uint64_t run = act[kStride * g + kRun];
+        const bool on = (run >> lane) & 1;
+        const size_t gb = static_cast<size_t>(g) * a.n * G;
+        const uint32_t *tg = reinterpret_cast<const uint32_t *>(a.mtab) + static_cast<size_t>(g) * a.mrows * G;
+        const uint32_t *sg = reinterpret_cast<const uint32_t *>(a.spar + static_cast<size_t>(g) * a.M);
+        const uint64_t *yg = a.ybits + static_cast<size_t>(g) * a.n;
+        int i[VPW], k0[VPW], deg[VPW];
+        bool in[VPW];
+        uint32_t m[VPW][DV], sp[VPW][DV], yh[VPW];
+        uint64_t rs[VPW];
+#pragma unroll
+        for (int v = 0; v < VPW; ++v) {
+            i[v] = a.vbeg + (tile * kWaves + wave) * VPW + v;
+            in[v] = i[v] < a.vend;
+            const int ii = in[v] ? i[v] : a.vend - 1;
+            k0[v] = var_ptr[ii];
+            deg[v] = in[v] ? var_ptr[ii + 1] - k0[v] : 0;
+            rs[v] = a.runs[ii];
+        }
+#pragma unroll
+        for (int v = 0; v < VPW; ++v) {
+            yh[v] = in[v] ? bit_half(yg, i[v], lane) : 0u;
+#pragma unroll
+            for (int j = 0; j < DV; ++j) {
+                if (j < deg[v]) {
+                    const uint32_t rt = a.var_rt[k0[v] + j];
+                    m[v][j] = tg[(rt & ((1u << kRtShift) - 1u)) * G + lane];
+                    sp[v][j] = sg[(rt >> kRtShift) * 2 + (lane >> 5)];
+                }
+            }
+        }
+        const float ym = static_cast<const float *>(a.ymag)[static_cast<size_t>(g) * G + lane];
+        const uint32_t flip = __float_as_uint(ym) >> 31, nz = ym != 0.0f ? 1u : 0u;
+        float s[VPW];
+#pragma unroll
+        for (int v = 0; v < VPW; ++v) {
+            s[v] = in[v] ? lam_of_half(yh[v], lane, ym) : 0.0f;
+            const uint32_t sv = ((yh[v] >> (lane & 31u)) ^ flip) & nz & 1u;
+            float acc = 0.0f;  // the running matrix's sum
+#pragma unroll
+            for (int j = 0; j < DV; ++j) {
+                if (j < deg[v]) {
+                    if ((rs[v] >> j) & 1) {
+                        s[v] += acc;
+                        acc = 0.0f;
+                    }
+                    const uint32_t sb = ((sp[v][j] >> (lane & 31u)) & 1u) ^ sv;
+                    acc += __uint_as_float(m[v][j] | (sb << 31));
+                }
+            }
+            if (deg[v] > 0) s[v] += acc;
+            if (in[v] && on) (Lp + gb + static_cast<size_t>(i[v]) * G)[lane] = s[v];
+        }
+        if (D) {
+#pragma unroll
+            for (int v = 0; v < VPW; ++v) {
+                const uint64_t bits = __ballot(on && in[v] && s[v] < 0.0f);
+                if (lane == 0 && in[v]) D[static_cast<size_t>(g) * a.n + i[v]] = bits;
+            }
+        }
+    }
+}
+
+using VarFirstFn = void (*)(const int32_t *, float *, const uint64_t *, uint64_t *, Dims);
+inline VarFirstFn variable_first_kernel(int dv, int *vars_per_tile) {
+    if (dv <= 8) { *vars_per_tile = 4 * kWaves; return &k_variable_first<8, 4>; }
+    if (dv <= 12) { *vars_per_tile = 3 * kWaves; return &k_variable_first<12, 3>; }
+    if (dv <= 16) { *vars_per_tile = 2 * kWaves; return &k_variable_first<16, 2>; }
+    if (dv <= 32) { *vars_per_tile = kWaves; return &k_variable_first<32, 1>; }
+    *vars_per_tile = kWaves;
+    return &k_variable_first<64, 1>;
 }
 
 // Variable pass of phase l of the matrix-serial schedule, for codes of at

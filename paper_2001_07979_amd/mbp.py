@@ -28,7 +28,7 @@ MBP_MSG_F32, MBP_MSG_F16 = 0, 1
 ABI_VERSION = 3  # mbp_version() of the library this binding marshals for
 _COUPLINGS = {"joint": MBP_JOINT, "independent": MBP_INDEPENDENT}
 _MSGS = {"f32": MBP_MSG_F32, "f16": MBP_MSG_F16}
-KERNEL_IDS = {"check": 0, "variable": 1, "syndrome": 2, "staging": 3}
+KERNEL_IDS = {"check": 0, "variable": 1, "syndrome": 2, "staging": 3, "first": 4, "second": 5}
 
 _lib = None
 
@@ -245,7 +245,7 @@ class Context:
         if not on:
             mask = 0
         elif kernels is None:
-            mask = 0xF
+            mask = 0x3F
         else:
             mask = 0
             for k in kernels:

@@ -305,7 +305,7 @@ def test_profiling_counts_launches(ctx, ragged_code):
     ctx.profile_enable(False)
     assert ctx.profile_get("check")[0] == n_c and ctx.profile_get("variable")[0] == 0
     from paper_2001_07979_amd import mbp
-    assert mbp.lib().mbp_profile_enable(ctx.handle, 16) == mbp.MBP_EINVAL
+    assert mbp.lib().mbp_profile_enable(ctx.handle, 64) == mbp.MBP_EINVAL
 
 
 def test_context_may_go_before_its_codes(ragged_code):

@@ -153,3 +153,39 @@ def test_from_bits_n65536_full_batch(ctx, algo, schedule):
     assert s["oracle_ok"] == 256
     okf = a["ok"] == 1
     assert okf.mean() > 0.99 and np.array_equal(a["bits"][okf], fr.x[okf])
+
+
+@pytest.fixture(scope="module")
+def dense_code():
+    """Checks of degree 33-34 (u = 2, n = 2000, 150 checks per matrix): above
+    the compressed min-sum state's degree limit, like the n = 2^18 rate-0.85
+    codes."""
+    return peg_code(2000, 150, 2, {2: 0.5, 3: 0.5}, seed_base=7900, name="peg-n2000-dense")
+
+
+@pytest.mark.parametrize("msg", ["f32", "f16"])
+@pytest.mark.parametrize("algo", ["spa", "nms"])
+def test_closed_form_first_iteration(ctx, codes, dense_code, algo, msg):
+    """FP32 flooding from Bob's bits never stores the first iteration's
+    messages: it rebuilds them from a table of magnitudes per (check degree,
+    slot) and the checks' parity words. Every output equals the LLR path,
+    which stores and reads every message: at T = 1, 2 and 3 without early
+    exit (the closed-form variable pass, then the check pass that rebuilds
+    the old messages), with early exit, on codes with and without the
+    compressed min-sum state, and for error rates whose lambda is zero
+    (e = 0.5) or negative for bit 0 (e > 0.5) beside ordinary ones."""
+    from paper_2001_07979_amd import mbp
+    for code in (dense_code, codes[3]):
+        dc = mbp.Code.from_inputs(ctx, code)
+        F = 130
+        fr = bsc_frames(code, F, np.linspace(0.002, 0.03, F), seed=77)
+        fr.p[5] = 0.5
+        fr.p[70] = 0.5
+        fr.p[9] = 0.6
+        fr.p[100] = 0.93
+        for T in (1, 2, 3):
+            a, b = _both(ctx, dc, fr, algo=algo, max_iter=T, early_exit=False, msg=msg)
+            _same(a, b)
+        a, b = _both(ctx, dc, fr, algo=algo, max_iter=40, msg=msg)
+        _same(a, b)
+        assert a["ok"].sum() >= 20 and a["iters"].min() < 40
