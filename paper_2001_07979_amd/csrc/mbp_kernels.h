@@ -294,17 +294,21 @@ __device__ __forceinline__ uint32_t live_item(uint32_t w, uint32_t total, uint32
 //
 // With SHORT (the second iteration after a first one in closed form) the old
 // messages are not read from ci: message j of the first iteration has the
-// magnitude first_mags forms for (d, j) and the sign S_r XOR s_j, S_r the
-// check's parity bit and s_j the lambda sign bit of the slot's variable (its
-// bit XOR flip, or 0 where lambda is zero), which is the message the check
-// pass from bits would have stored, bit for bit.
+// magnitude oldmag(j) (first_mags of the check's degree, formed by the
+// caller) and the sign S_r XOR s_j, S_r the check's parity bit and s_j the
+// lambda sign bit of the slot's variable (its bit XOR flip, or 0 where
+// lambda is zero), which is the message the check pass from bits would have
+// stored, bit for bit.
 struct NoPrefetch {
     __device__ void operator()() const {}
 };
 
+struct NoOldMag {
+    __device__ float operator()(int) const { return 0.0f; }
+};
+
 struct FirstMsgs {
     uint32_t ylo, yhi;  // lane j < DMAX: the bit word of slot j's variable (low, high half)
-    float ym;           // this frame's lambda magnitude
     uint32_t sbit;      // S_r in this lane's frame (0 or 1)
     uint32_t flip;      // 1 if this frame's lambda is negative for bit 0
     uint32_t nz;        // 1 if this frame's lambda is nonzero
@@ -313,74 +317,53 @@ struct FirstMsgs {
 // The magnitudes of the first iteration's messages of a check of degree d
 // when every lambda of the frame has the magnitude |ym| (decoding from Bob's
 // bits), slot by slot, with the operations of the check pass from bits in
-// the same order: sum-product merges the complements' prefix and suffix
-// chains (mirrored slot pairs for a full or nearly full row, where both
-// chains are the prefix chain), min-sum takes alpha times the smaller of
-// |ym| and the clip (the second minimum, +inf, at slot 0 of a degree-1
-// check). With H each is rounded to binary16, as the stored message is
-// (the rounding is symmetric in the sign). Slots past d are left 0.
+// the same order: sum-product merges the complements' prefix chain P_j with
+// the suffix chain, which for equal complements is P_{d-1-j} (so slots j and
+// d-1-j share one magnitude); min-sum takes alpha times the smaller of |ym|
+// and the clip (the second minimum, +inf, at slot 0 of a degree-1 check).
+// With H each is rounded to binary16, as the stored message is (the rounding
+// is symmetric in the sign). Written to om[j * 64 + lane], j < d, in place:
+// the chain first, then each pair of mirrored slots from its two chain
+// values, so no register array is held.
 //
 // No multiply-add contraction here: the complement e is a product, and
 // fusing it into the chain's sums (which the check pass from bits cannot do,
 // as its e passes through a sign-bit merge) would round differently.
-template <int ALGO, int DMAX, bool H>
-__device__ __forceinline__ void first_mags(int d, float ym, float clip, float alpha, float (&m)[DMAX]) {
+template <int ALGO, bool H>
+__device__ __forceinline__ void first_mags(int d, float ym, float clip, float alpha, float *om, unsigned lane) {
 #pragma clang fp contract(off)
-#pragma unroll
-    for (int j = 0; j < DMAX; ++j) m[j] = 0.0f;
+    auto put = [&](int j, float v) {
+        if constexpr (H) v = static_cast<float>(static_cast<_Float16>(v));
+        om[j * G + lane] = v;
+    };
     if constexpr (ALGO == kNMS) {
         const float m1 = fminf(fabsf(ym), clip);
         const float m2 = d >= 2 ? m1 : INFINITY;
-#pragma unroll
-        for (int j = 0; j < DMAX; ++j) m[j] = j == 0 ? alpha * m2 : alpha * m1;
+        for (int j = 0; j < d; ++j) put(j, j == 0 ? alpha * m2 : alpha * m1);
     } else {
         const float e = tanh_complement(fminf(fabsf(ym), clip));
-        float pre[DMAX];
         float run = 0.0f;
-#pragma unroll
-        for (int j = 0; j < DMAX; ++j) {
-            pre[j] = run;
+        for (int j = 0; j < d; ++j) {
+            om[j * G + lane] = run;
             run = fmaf(-run, e, run + e);
         }
-        auto mag = [](float x, float y) {
-            return __uint_as_float(__float_as_uint(atanh2_of_complement(fmaf(-x, y, x + y))) & 0x7fffffffu);
-        };
-        auto full_row = [&](auto dd) {
-            constexpr int D = decltype(dd)::value;
-#pragma unroll
-            for (int j = 0; j <= D - 1 - j; ++j) {
-                const float v = mag(pre[j], pre[D - 1 - j]);
-                m[j] = v;
-                m[D - 1 - j] = v;
-            }
-        };
-        if (d == DMAX) {
-            full_row(std::integral_constant<int, DMAX>());
-        } else if (d == DMAX - 1) {
-            full_row(std::integral_constant<int, DMAX - 1>());
-        } else {
-            float suf = 0.0f;
-#pragma unroll
-            for (int j = DMAX - 1; j >= 0; --j) {
-                if (j < d) m[j] = mag(pre[j], suf);
-                const float ej = j < d ? e : 0.0f;
-                suf = fmaf(-suf, ej, suf + ej);
-            }
+        for (int j = 0; j <= d - 1 - j; ++j) {
+            const int k = d - 1 - j;
+            const float x = om[j * G + lane], y = om[k * G + lane];
+            const float v = __uint_as_float(__float_as_uint(atanh2_of_complement(fmaf(-x, y, x + y))) & 0x7fffffffu);
+            put(j, v);
+            put(k, v);
         }
-    }
-    if constexpr (H) {
-#pragma unroll
-        for (int j = 0; j < DMAX; ++j) m[j] = static_cast<float>(static_cast<_Float16>(m[j]));
     }
 }
 
 template <int ALGO, int DMAX, bool BITS, bool CST = false, bool H = false, bool SHORT = false, typename Cols,
-          typename Prefetch = NoPrefetch>
+          typename Prefetch = NoPrefetch, typename OldMag = NoOldMag>
 __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbit, float alpha,
                                               float clip, bool first, BufRsrc src, const void *ci, void *cg,
                                               unsigned lane, float ym, uint32_t *st = nullptr,
                                               Prefetch prefetch = Prefetch(), bool on = true,
-                                              const FirstMsgs &fm = FirstMsgs()) {
+                                              const FirstMsgs &fm = FirstMsgs(), const OldMag &oldmag = OldMag()) {
     static_assert(!SHORT || (!BITS && !CST), "closed-form old messages: the FP32 pass from messages");
     static_assert(!CST || (ALGO == kNMS && DMAX <= kStateMaxDeg), "compressed state: min-sum, small degree");
     static_assert(!(CST && H), "binary16 messages keep no compressed state");
@@ -432,9 +415,6 @@ __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbi
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) q[j] = __uint_as_float(buf_load(src, lo, (j < d ? v(j) : 0) * G * 4));
         } else if constexpr (SHORT) {
-            // the old messages' magnitudes, then the gathers
-            float om[DMAX];
-            first_mags<ALGO, DMAX, H>(d, fm.ym, clip, alpha, om);
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) q[j] = __uint_as_float(buf_load(src, lo, (j < d ? v(j) : 0) * G * 4));
 #pragma unroll
@@ -442,7 +422,7 @@ __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbi
                 const uint32_t wlo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(fm.ylo), j));
                 const uint32_t whi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(fm.yhi), j));
                 const uint32_t sj = (((lane < 32 ? wlo : whi) >> (lane & 31u)) ^ fm.flip) & fm.nz & 1u;
-                q[j] -= __uint_as_float(__float_as_uint(om[j]) | ((fm.sbit ^ sj) << 31));
+                q[j] -= __uint_as_float(__float_as_uint(oldmag(j)) | ((fm.sbit ^ sj) << 31));
             }
         } else {
             float co[DMAX];
@@ -671,6 +651,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SHORT &&
                                                    : 0;
         };
         Row cur, nxt, nn;
+        // SHORT: the old messages' magnitudes of the wave's last (group,
+        // degree), in the wave's own part of LDS (each lane its column)
+        __shared__ float om[SHORT ? kWaves * DMAX * G : 1];
+        int om_key = -1;
         if (!meta(cur)) return;
         cols(cur);
         bool has_nxt = meta(nxt);
@@ -710,13 +694,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SHORT &&
                     // lane j: the bit word of slot j's variable (the column
                     // indices of lanes past the degree are in range too)
                     const uint2 yw = reinterpret_cast<const uint2 *>(a.ybits + static_cast<size_t>(g) * a.n)[cs];
-                    const float ym = static_cast<const float *>(a.ymag)[static_cast<size_t>(g) * G + lane];
-                    fm = FirstMsgs{yw.x, yw.y, ym, bit(8), bit(10), bit(12)};
+                    fm = FirstMsgs{yw.x, yw.y, bit(8), bit(10), bit(12)};
+                    // the old magnitudes depend on the group and the degree
+                    // only: formed again when either changes (a wave's
+                    // stream stays in one group for many checks, and most
+                    // checks of a PEG code share one degree)
+                    const int key = g * 128 + d;
+                    if (key != om_key) {
+                        const float ym = static_cast<const float *>(a.ymag)[static_cast<size_t>(g) * G + lane];
+                        first_mags<ALGO, H>(d, ym, clip, alpha, om + wave * DMAX * G, lane);
+                        om_key = key;
+                    }
                 }
+                auto oldmag = [&](int j) { return om[(wave * DMAX + j) * G + lane]; };
                 check_row_f32<ALGO, DMAX, false, CST, H, SHORT>(v, d, zbit, alpha, clip, first,
                                                                 buf_rsrc(Lr, kBufAll), msg_at<H>(c_in, cb),
                                                                 msg_at<H>(c_out, cb), lane, 0.0f, st, prefetch,
-                                                                on, fm);
+                                                                on, fm, oldmag);
             } else {
                 prefetch();
             }
