@@ -307,11 +307,20 @@ struct NoOldMag {
     __device__ float operator()(int) const { return 0.0f; }
 };
 
+// The sign of old message j in this lane's frame, as bit 31: S_r where
+// lambda is zero, else S_r XOR flip XOR the frame's bit of slot j's
+// variable, taken from that variable's bit word (word j of yrow, the
+// 32-bit half holding the lane's bit) moved up to bit 31 by a shift.
 struct FirstMsgs {
-    uint32_t ylo, yhi;  // lane j < DMAX: the bit word of slot j's variable (low, high half)
-    uint32_t sbit;      // S_r in this lane's frame (0 or 1)
-    uint32_t flip;      // 1 if this frame's lambda is negative for bit 0
-    uint32_t nz;        // 1 if this frame's lambda is nonzero
+    const uint32_t *yrow;  // the check's bit words in LDS: [slot][low, high half]
+    uint32_t shift;        // 31 - (lane mod 32)
+    uint32_t k31;          // (S_r XOR flip) << 31
+    uint32_t nz31;         // 1 << 31 where lambda is nonzero, else 0
+    uint32_t z31;          // S_r << 31 where lambda is zero, else 0
+    __device__ uint32_t sign(int j, unsigned lane) const {
+        const uint32_t w = yrow[2 * j + static_cast<int>(lane >> 5)];
+        return (((w << shift) ^ k31) & nz31) | z31;
+    }
 };
 
 // The magnitudes of the first iteration's messages of a check of degree d
@@ -418,12 +427,8 @@ __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbi
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) q[j] = __uint_as_float(buf_load(src, lo, (j < d ? v(j) : 0) * G * 4));
 #pragma unroll
-            for (int j = 0; j < DMAX; ++j) {
-                const uint32_t wlo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(fm.ylo), j));
-                const uint32_t whi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(fm.yhi), j));
-                const uint32_t sj = (((lane < 32 ? wlo : whi) >> (lane & 31u)) ^ fm.flip) & fm.nz & 1u;
-                q[j] -= __uint_as_float(__float_as_uint(oldmag(j)) | ((fm.sbit ^ sj) << 31));
-            }
+            for (int j = 0; j < DMAX; ++j)
+                q[j] -= __uint_as_float(__float_as_uint(oldmag(j)) | fm.sign(j, lane));
         } else {
             float co[DMAX];
 #pragma unroll
@@ -654,6 +659,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SHORT &&
         // SHORT: the old messages' magnitudes of the wave's last (group,
         // degree), in the wave's own part of LDS (each lane its column)
         __shared__ float om[SHORT ? kWaves * DMAX * G : 1];
+        __shared__ uint32_t ysh[SHORT ? kWaves * 2 * DMAX : 1];
         int om_key = -1;
         if (!meta(cur)) return;
         cols(cur);
@@ -692,9 +698,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SHORT &&
                         return ((lane < 32 ? lo32 : hi32) >> (lane & 31u)) & 1u;
                     };
                     // lane j: the bit word of slot j's variable (the column
-                    // indices of lanes past the degree are in range too)
+                    // indices of lanes past the degree are in range too),
+                    // put in the wave's part of LDS for every lane to read
                     const uint2 yw = reinterpret_cast<const uint2 *>(a.ybits + static_cast<size_t>(g) * a.n)[cs];
-                    fm = FirstMsgs{yw.x, yw.y, bit(8), bit(10), bit(12)};
+                    uint32_t *yrow = ysh + wave * 2 * DMAX;
+                    // (the wave's LDS accesses run in order; the barriers
+                    // keep the compiler from moving them across each other)
+                    __builtin_amdgcn_wave_barrier();
+                    if (static_cast<int>(lane) < DMAX) {
+                        yrow[2 * lane] = yw.x;
+                        yrow[2 * lane + 1] = yw.y;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    const uint32_t sbit = bit(8), flip = bit(10), nz = bit(12);
+                    fm = FirstMsgs{yrow, 31u - (lane & 31u), (sbit ^ flip) << 31, nz << 31, nz ? 0u : sbit << 31};
                     // the old magnitudes depend on the group and the degree
                     // only: formed again when either changes (a wave's
                     // stream stays in one group for many checks, and most
