@@ -293,8 +293,10 @@ __device__ __forceinline__ void spa_row(const GroupDesc &G_, int r, bool first, 
 #pragma unroll
     for (int j = 0; j < DMAX; ++j) v[j] = ldc(G_.col, e0 + j);
     float *cg = G_.c + static_cast<size_t>(e0) * G;
-    check_row_f32<kSPA, DMAX, false>([&v](int j) { return v[j]; }, d, zbit, a.alpha, a.clip, first,
-                                     buf_rsrc(G_.Lp, kBufAll), cg, cg, lane, 0.0f, nullptr, NoPrefetch(), on);
+    // default caching of the message rows (NT false)
+    check_row_f32<kSPA, DMAX, false, false, false, false, false>([&v](int j) { return v[j]; }, d, zbit, a.alpha,
+                                                                  a.clip, first, buf_rsrc(G_.Lp, kBufAll), cg, cg,
+                                                                  lane, 0.0f, nullptr, NoPrefetch(), on);
 }
 template <int DMAX>
 __device__ __forceinline__ void spa_tile(const GroupDesc &G_, int tile, bool first, const PArgs &a, unsigned lane,

@@ -297,6 +297,10 @@ __device__ __forceinline__ uint32_t live_item(uint32_t w, uint32_t total, uint32
 // computes (so the caller's prefetched values stay wave-uniform); only lanes
 // with `on` (frames still running) store.
 //
+// NT: the message rows with the non-temporal cache policy (the plain
+// decode; the batched decode's cells are small enough that a pass's messages
+// can stay in the Infinity Cache for the next pass, so it keeps the default).
+//
 // With CST (min-sum only, DMAX <= kStateMaxDeg) the check's state `st`
 // replaces its old messages: row 0 holds alpha m1, row 1 alpha m2, row 2 the
 // sign of each outgoing message (bit j) and the position of the minimum
@@ -378,8 +382,8 @@ __device__ __forceinline__ void first_mags(int d, float ym, float clip, float al
     }
 }
 
-template <int ALGO, int DMAX, bool BITS, bool CST = false, bool H = false, bool SHORT = false, typename Cols,
-          typename Prefetch = NoPrefetch, typename OldMag = NoOldMag>
+template <int ALGO, int DMAX, bool BITS, bool CST = false, bool H = false, bool SHORT = false, bool NT = true,
+          typename Cols, typename Prefetch = NoPrefetch, typename OldMag = NoOldMag>
 __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbit, float alpha,
                                               float clip, bool first, BufRsrc src, const void *ci, void *cg,
                                               unsigned lane, float ym, uint32_t *st = nullptr,
@@ -403,8 +407,10 @@ __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbi
     const auto put = [&](int j, uint32_t word) {
         if constexpr (H)
             buf_store_half(__uint_as_float(word), rout, lm, j * G * ES);
-        else
+        else if constexpr (NT)
             buf_store_nt(word, rout, lo, j * G * 4);
+        else
+            buf_store(word, rout, lo, j * G * 4);
     };
     float q[DMAX];
     if constexpr (CST && !BITS) {
@@ -449,7 +455,8 @@ __device__ __forceinline__ void check_row_f32(const Cols &v, int d, uint32_t zbi
                 if constexpr (H)
                     co[j] = buf_load_half(rin, lm, (j < d ? j : 0) * G * ES);
                 else
-                    co[j] = __uint_as_float(buf_load_nt(rin, lo, (j < d ? j : 0) * G * 4));
+                    co[j] = __uint_as_float(NT ? buf_load_nt(rin, lo, (j < d ? j : 0) * G * 4)
+                                               : buf_load(rin, lo, (j < d ? j : 0) * G * 4));
             }
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) q[j] -= co[j];
